@@ -1,0 +1,237 @@
+"""Cartesian Taylor FMM matrix-vector product for the Galerkin PB operator
+(Sec. 2.4: moments, MtM, MtL, LtL, LtP and the six-step algorithm).
+
+Readings (one choice, used everywhere):
+  * order convention: |alpha| <= p_l for locals and |alpha| + |beta| <= p_l in
+    MtL (the truncation written in the MtL formula; its (-1)^beta is read as
+    (-1)^|beta|, which follows from G(x, y) = f(x - y));
+  * LtL sums over alpha >= beta (componentwise), |alpha| <= p_l;
+  * variable order: MtM builds a parent's moments up to p_l from its children's
+    moments of order p_{l+1} (missing terms are zero); LtL truncates the
+    shifted parent locals to the child order;
+  * the interaction phase runs over c in C_l and c' in I(c) for
+    l = l_min..L;
+  * leaf moments of a panel use the same 3-point rule as the regular near field;
+  * only two expansion channels are needed.  With phi, dphi the two unknown
+    blocks and m_s / m_d the single / double layer moments,
+        M0 = m_s(dphi) - m_d(phi)        (Coulomb kernel G0)
+        Mk = -m_s(dphi) + eps m_d(phi)   (screened kernel Gk)
+    row 1 of the far field is -(lambda0 + lambdak) tested with m_s, row 2 is
+    -(lambda0 + lambdak/eps) tested with m_d (the kernels K1..K4 of Sec. 2.2).
+"""
+import numpy as np
+from math import comb, factorial
+from types import SimpleNamespace
+
+from . import taylor
+from .kernels import combine
+from .pairs import pair_integrals
+
+FOUR_PI = 4.0 * np.pi
+
+
+def _mi(p):
+    mi = taylor.multi_indices(p)
+    return mi, {k: n for n, k in enumerate(mi)}
+
+
+def panel_moments(P, ids, centers, p):
+    """Single- and double-layer moments of the basis functions psi_i about the
+    given centres with the 3-point rule:  m_s^b = sum_q w_q (y_q - x_c)^b,
+    m_d^b = sum_q w_q n . grad (y - x_c)^b at y_q.  Returns [n, T], [n, T]."""
+    mi, _ = _mi(p)
+    d = P.qp[ids] - centers[:, None, :]              # [n,3,3] (q, dim)
+    pw = np.ones((len(ids), 3, 3, p + 1))            # [n, q, dim, power]
+    for e in range(1, p + 1):
+        pw[..., e] = pw[..., e - 1] * d
+    nrm = P.normal[ids]
+    w = P.qw[ids]
+    ms = np.zeros((len(ids), len(mi)))
+    md = np.zeros((len(ids), len(mi)))
+    for t, (a, b, c) in enumerate(mi):
+        mono = pw[:, :, 0, a] * pw[:, :, 1, b] * pw[:, :, 2, c]
+        ms[:, t] = (w * mono).sum(1)
+        g = np.zeros_like(mono)
+        if a:
+            g += a * nrm[:, 0, None] * pw[:, :, 0, a - 1] * pw[:, :, 1, b] * pw[:, :, 2, c]
+        if b:
+            g += b * nrm[:, 1, None] * pw[:, :, 0, a] * pw[:, :, 1, b - 1] * pw[:, :, 2, c]
+        if c:
+            g += c * nrm[:, 2, None] * pw[:, :, 0, a] * pw[:, :, 1, b] * pw[:, :, 2, c - 1]
+        md[:, t] = (w * g).sum(1)
+    return ms, md
+
+
+def shift_matrix(dvec, p_big, p_small):
+    """S[alpha, beta] = C(alpha, beta) d^(alpha - beta) for beta <= alpha,
+    |alpha| <= p_big, |beta| <= p_small.  MtM: M_parent = S M_child;
+    LtL: lambda_child = S^T lambda_parent (multivariate binomial formula)."""
+    ma, _ = _mi(p_big)
+    mb, _ = _mi(p_small)
+    S = np.zeros((len(ma), len(mb)))
+    for i, al in enumerate(ma):
+        for j, be in enumerate(mb):
+            if all(be[k] <= al[k] for k in range(3)):
+                v = 1.0
+                for k in range(3):
+                    v *= comb(al[k], be[k]) * dvec[k] ** (al[k] - be[k])
+                S[i, j] = v
+    return S
+
+
+def m2l_matrix(x0, kappa, p):
+    """T[alpha, beta] = (alpha+beta)!/(alpha! beta!) (-1)^|beta| F_{alpha+beta}(x0)/(4 pi)
+    for |alpha| + |beta| <= p (the MtL translation, x0 = x_c - x_c')."""
+    mi, pos = _mi(p)
+    F = taylor.coefficients(np.asarray(x0)[None, :], kappa, p)
+    T = np.zeros((len(mi), len(mi)))
+    for i, al in enumerate(mi):
+        for j, be in enumerate(mi):
+            if sum(al) + sum(be) <= p:
+                g = (al[0] + be[0], al[1] + be[1], al[2] + be[2])
+                T[i, j] = (taylor.mfact(g) / (taylor.mfact(al) * taylor.mfact(be))
+                           * (-1.0) ** sum(be) * F[g][0] / FOUR_PI)
+    return T
+
+
+def setup(P, tree, eps, kappa, p_leaf=4, adaptive=False, p_max=8,
+          near_ratio=2.0, n_duffy=7, with_near=True):
+    """Precompute panel moments and the near-field blocks (per leaf c and each
+    c' in N(c), the combined 4-entry blocks of every panel pair)."""
+    from .tree import orders
+    L = tree.L
+    pl = orders(tree, p_leaf, adaptive, p_max)
+    leaf = tree.levels[L]
+    perm = tree.perm
+    owner = np.repeat(np.arange(leaf.n), leaf.end - leaf.start)   # tree order
+    ms, md = panel_moments(P, perm, leaf.center[owner], pl[L])
+    F = SimpleNamespace(P=P, tree=tree, eps=eps, kappa=kappa, orders=pl,
+                        ms=ms, md=md, owner=owner)
+    if with_near:
+        ii, jj = [], []
+        for c in range(leaf.n):
+            tgt = perm[leaf.start[c]:leaf.end[c]]
+            for c2 in leaf.nbr[c]:
+                src = perm[leaf.start[c2]:leaf.end[c2]]
+                a, b = np.meshgrid(tgt, src, indexing="ij")
+                ii.append(a.ravel())
+                jj.append(b.ravel())
+        ii = np.concatenate(ii)
+        jj = np.concatenate(jj)
+        I, cls = pair_integrals(P, ii, jj, kappa, near_ratio, n_duffy)
+        F.near_i, F.near_j, F.near_B, F.near_cls = ii, jj, combine(I, eps), cls
+    return F
+
+
+def matvec(F, x, far=True, near=True):
+    """y = A x, x = [phi (N); dphi (N)] in panel order."""
+    P, tree, eps, kappa = F.P, F.tree, F.eps, F.kappa
+    N = P.n
+    phi, dphi = x[:N], x[N:]
+    y1 = 0.5 * (1.0 + eps) * P.area * phi
+    y2 = 0.5 * (1.0 + 1.0 / eps) * P.area * dphi
+    if near:
+        B = F.near_B
+        y1 = y1 + np.bincount(F.near_i, B[:, 0] * phi[F.near_j] + B[:, 1] * dphi[F.near_j],
+                              minlength=N)
+        y2 = y2 + np.bincount(F.near_i, B[:, 2] * phi[F.near_j] + B[:, 3] * dphi[F.near_j],
+                              minlength=N)
+    if far and tree.lmin <= tree.L:
+        f1, f2 = far_field(F, phi, dphi)
+        y1 = y1 + f1
+        y2 = y2 + f2
+    return np.concatenate([y1, y2])
+
+
+def far_field(F, phi, dphi):
+    P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
+    L, perm = tree.L, tree.perm
+    levels = tree.levels
+    # step 2: leaf moments (two channels)
+    a = phi[perm]
+    b = dphi[perm]
+    c0 = F.ms * b[:, None] - F.md * a[:, None]
+    ck = -F.ms * b[:, None] + eps * F.md * a[:, None]
+    leaf = levels[L]
+    M0 = {L: np.zeros((leaf.n, F.ms.shape[1]))}
+    Mk = {L: np.zeros((leaf.n, F.ms.shape[1]))}
+    np.add.at(M0[L], F.owner, c0)
+    np.add.at(Mk[L], F.owner, ck)
+    # step 3: upward pass
+    for l in range(L - 1, tree.lmin - 1, -1):
+        ch, pa = levels[l + 1], levels[l]
+        T = len(_mi(pl[l])[0])
+        M0[l] = np.zeros((pa.n, T))
+        Mk[l] = np.zeros((pa.n, T))
+        octant = ch.idx & 1
+        for o in np.unique(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2]):
+            sel = np.nonzero(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2] == o)[0]
+            dvec = (np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1]) - 0.5) * ch.h
+            S = shift_matrix(dvec, pl[l], pl[l + 1])
+            np.add.at(M0[l], ch.parent[sel], M0[l + 1][sel] @ S.T)
+            np.add.at(Mk[l], ch.parent[sel], Mk[l + 1][sel] @ S.T)
+    # step 4: interaction phase
+    lam0, lamk = {}, {}
+    for l in range(tree.lmin, L + 1):
+        cl = levels[l]
+        T = len(_mi(pl[l])[0])
+        lam0[l] = np.zeros((cl.n, T))
+        lamk[l] = np.zeros((cl.n, T))
+        tgt = np.concatenate([np.full(len(s), c) for c, s in enumerate(cl.inter)]).astype(np.int64)
+        src = np.concatenate(cl.inter).astype(np.int64)
+        if len(tgt) == 0:
+            continue
+        off = cl.idx[tgt] - cl.idx[src]              # x_c - x_c' = off * h
+        uo, inv = np.unique(off, axis=0, return_inverse=True)
+        inv = inv.ravel()
+        for k in range(len(uo)):
+            sel = np.nonzero(inv == k)[0]
+            x0 = uo[k] * cl.h
+            T0 = m2l_matrix(x0, 0.0, pl[l])
+            Tk = m2l_matrix(x0, kappa, pl[l])
+            np.add.at(lam0[l], tgt[sel], M0[l][src[sel]] @ T0.T)
+            np.add.at(lamk[l], tgt[sel], Mk[l][src[sel]] @ Tk.T)
+    # step 5: downward pass
+    for l in range(tree.lmin, L):
+        ch = levels[l + 1]
+        octant = ch.idx & 1
+        for o in np.unique(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2]):
+            sel = np.nonzero(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2] == o)[0]
+            dvec = (np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1]) - 0.5) * ch.h
+            S = shift_matrix(dvec, pl[l], pl[l + 1])
+            lam0[l + 1][sel] += lam0[l][ch.parent[sel]] @ S
+            lamk[l + 1][sel] += lamk[l][ch.parent[sel]] @ S
+    # step 6: evaluation
+    l0 = lam0[L][F.owner]
+    lk = lamk[L][F.owner]
+    f1 = -((l0 + lk) * F.ms).sum(1)
+    f2 = -((l0 + lk / eps) * F.md).sum(1)
+    y1 = np.zeros(P.n)
+    y2 = np.zeros(P.n)
+    y1[perm] = f1
+    y2[perm] = f2
+    return y1, y2
+
+
+def coverage(tree):
+    """Count, for every ordered leaf pair, how many times the near field or a
+    far-field translation (at any level) accounts for it.  Returns [nleaf,
+    nleaf] counts (each must be exactly one)."""
+    L = tree.L
+    leaf = tree.levels[L]
+    C = np.zeros((leaf.n, leaf.n), np.int64)
+    # descendants at leaf level of each cluster per level
+    desc = {L: [np.array([c]) for c in range(leaf.n)]}
+    for l in range(L - 1, -1, -1):
+        pa = tree.levels[l]
+        desc[l] = [np.concatenate([desc[l + 1][k] for k in
+                                   range(pa.child_start[c], pa.child_end[c])])
+                   for c in range(pa.n)]
+    for c in range(leaf.n):
+        C[c, leaf.nbr[c]] += 1
+    for l in range(L + 1):
+        cl = tree.levels[l]
+        for c in range(cl.n):
+            for c2 in cl.inter[c]:
+                C[np.ix_(desc[l][c], desc[l][c2])] += 1
+    return C

@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms,
+finite differences, symbolic derivatives, invariants and the paper's printed
+Kirkwood-sphere values.  CPU only."""
+import numpy as np
+import pytest
+
+from analytic import composite_outer, potential_1_over_r, solid_angle
+from oracle import dense, fmm, kirkwood, pairs, solve, taylor
+from oracle import tree as otree
+from oracle.geometry import panels
+from oracle.kernels import kernel6
+from synth import icosphere
+
+
+def _golden(name):
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, n, v = line.split()
+            out[(k, n)] = float(v)
+    return out
+
+
+def _three_panels():
+    verts = np.array([[0, 0, 0], [1.0, 0, 0], [0.4, 0.8, 0.1], [0.5, -0.7, 0.3],
+                      [-0.6, 0.5, -0.2]])
+    tris = np.array([[0, 1, 2], [1, 0, 3], [0, 4, 2]])
+    return panels(verts, tris)
+
+
+def _g0_kernels(r, nx, ny, kappa):
+    rr = np.sqrt((r * r).sum(-1))
+    return np.stack([1.0 / (4 * np.pi * rr), (r * ny).sum(-1) / (4 * np.pi * rr ** 3)], -1)
+
+
+def _reference(P, i, j):
+    """outer composite rule at two refinements, Richardson-extrapolated (the
+    outer integrand is smooth inside but its gradient is log-singular at the
+    panel edges, so the composite error falls by about 4 per level)"""
+    vals = []
+    for lev in (4, 5):
+        pts, w = composite_outer(P.corners[i], lev, 8)
+        s = np.sum(w * potential_1_over_r(pts, P.corners[j])) / (4 * np.pi)
+        d = -np.sum(w * solid_angle(pts, P.corners[j])) / (4 * np.pi)
+        vals.append((s, d))
+    (s4, d4), (s5, d5) = vals
+    return s5 + (s5 - s4) / 3.0, d5 + (d5 - d4) / 3.0
+
+
+def test_gauss_legendre_exactness():
+    g, w = pairs.gauss01(7)
+    for k in range(14):
+        assert abs((w * g ** k).sum() - 1.0 / (k + 1)) < 1e-14
+
+
+def test_three_point_rule_exact_for_quadratics():
+    P = panels(np.array([[0, 0, 0], [2.0, 0, 0], [0.5, 1.5, 0]]), np.array([[0, 1, 2]]))
+    # int x^2 over the triangle by a fine composite rule as the check
+    pts, w = composite_outer(P.corners[0], 3, 6)
+    for f in (lambda p: p[..., 0] ** 2, lambda p: p[..., 0] * p[..., 1], lambda p: p[..., 1]):
+        ref = (w * f(pts)).sum()
+        got = (P.qw[0] * f(P.qp[0])).sum()
+        assert abs(got - ref) < 1e-12 * max(1, abs(ref))
+
+
+@pytest.mark.parametrize("case", ["ident", "edge01", "edge10", "edge02", "vertex12"])
+def test_singular_rules_match_closed_forms(case):
+    """Single layer against the Wilton closed form, double layer against the
+    Van Oosterom-Strackee solid angle (outer integral by a fine composite rule)."""
+    P = _three_panels()
+    spec = {"ident": (0, 0), "edge01": (0, 1), "edge10": (1, 0), "edge02": (0, 2),
+            "vertex12": (1, 2)}[case]
+    i, j = np.array([spec[0]]), np.array([spec[1]])
+    if case == "ident":
+        I = pairs.ident(P, i, 0.0, 7, kern=_g0_kernels)[0]
+    elif case.startswith("edge"):
+        I = pairs.edge(P, i, j, 0.0, 7, kern=_g0_kernels)[0]
+    else:
+        I = pairs.vertex(P, i, j, 0.0, 7, kern=_g0_kernels)[0]
+    s, d = _reference(P, spec[0], spec[1])
+    assert abs(I[0] - s) < 2e-8 * abs(s)
+    if case != "ident":      # the solid angle is two-valued on the panel itself
+        assert abs(I[1] - d) < 1e-7 * abs(d)
+    else:
+        assert I[1] == pytest.approx(0.0, abs=1e-12)
+
+
+def test_kernel6_matches_finite_differences():
+    """k2..k6 are normal derivatives of G0/Gk: check against central differences."""
+    rng = np.random.default_rng(1)
+    kappa = 0.37
+    x = rng.standard_normal(3)
+    y = rng.standard_normal(3) + np.array([1.5, 0, 0])
+    nx = rng.standard_normal(3); nx /= np.linalg.norm(nx)
+    ny = rng.standard_normal(3); ny /= np.linalg.norm(ny)
+
+    def G(a, b, k):
+        r = np.linalg.norm(a - b)
+        return np.exp(-k * r) / (4 * np.pi * r)
+
+    h = 1e-4
+    dy = lambda k: (G(x, y + h * ny, k) - G(x, y - h * ny, k)) / (2 * h)
+    dx = lambda k: (G(x + h * nx, y, k) - G(x - h * nx, y, k)) / (2 * h)
+
+    def dxy(k):
+        f = lambda a, b: G(x + a * nx, y + b * ny, k)
+        return (f(h, h) - f(h, -h) - f(-h, h) + f(-h, -h)) / (4 * h * h)
+
+    K = kernel6(x - y, nx, ny, kappa)
+    ref = [G(x, y, 0) - G(x, y, kappa), dy(0), dy(kappa), dx(0), dx(kappa), dxy(kappa) - dxy(0)]
+    for m in range(6):
+        assert abs(K[m] - ref[m]) < 1e-6 * max(abs(ref[m]), 1e-3), m
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.4])
+def test_taylor_recurrence_matches_sympy(kappa):
+    import sympy as sp
+    X, Y, Z = sp.symbols("X Y Z", real=True)
+    r = sp.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    f = sp.exp(-sp.Rational(kappa).limit_denominator(1000) * r) / r
+    x0 = np.array([0.7, -1.1, 0.4])
+    F = taylor.coefficients(x0, float(sp.Rational(kappa).limit_denominator(1000)), 5)
+    sub = {X: sp.Rational(7, 10), Y: sp.Rational(-11, 10), Z: sp.Rational(2, 5)}
+    for k in taylor.multi_indices(5):
+        d = sp.diff(f, X, k[0], Y, k[1], Z, k[2]) if sum(k) else f
+        ref = float(d.subs(sub).evalf(30)) / taylor.mfact(k)
+        assert abs(F[k][0] - ref) < 1e-12 * max(abs(ref), 1e-8), k
+
+
+def test_shift_matrices_are_exact_translations():
+    """MtM of moments equals the moments taken about the new centre, and LtL
+    of a local expansion evaluates to the same polynomial (binomial formula)."""
+    rng = np.random.default_rng(2)
+    p = 5
+    mi = taylor.multi_indices(p)
+    pts = rng.standard_normal((20, 3)) * 0.3
+    w = rng.standard_normal(20)
+    c1 = np.array([0.1, -0.2, 0.05])
+    c2 = c1 + np.array([0.25, -0.25, 0.25])
+    mom = lambda c: np.array([(w * np.prod((pts - c) ** np.array(a), 1)).sum() for a in mi])
+    S = fmm.shift_matrix(c1 - c2, p, p)
+    assert np.allclose(S @ mom(c1), mom(c2), rtol=1e-12, atol=1e-14)
+    lam = rng.standard_normal(len(mi))
+    x = rng.standard_normal(3) * 0.2
+    ev = lambda l, c: sum(l[t] * np.prod((x - c) ** np.array(a)) for t, a in enumerate(mi))
+    S2 = fmm.shift_matrix(c2 - c1, p, p)   # parent c1 -> child c2
+    assert abs(ev(S2.T @ lam, c2) - ev(lam, c1)) < 1e-12
+
+
+def test_m2l_converges_to_direct_sum():
+    rng = np.random.default_rng(3)
+    src = rng.uniform(-0.5, 0.5, (30, 3))
+    tgt = rng.uniform(-0.5, 0.5, (10, 3)) + np.array([3.0, 0, 0])
+    q = rng.standard_normal(30)
+    kappa = 0.3
+    cs, ct = np.zeros(3), np.array([3.0, 0, 0])
+    direct = np.array([(q * np.exp(-kappa * np.linalg.norm(t - src, axis=1))
+                        / (4 * np.pi * np.linalg.norm(t - src, axis=1))).sum() for t in tgt])
+    errs = []
+    for p in (2, 4, 6, 8):
+        mi = taylor.multi_indices(p)
+        M = np.array([(q * np.prod((src - cs) ** np.array(a), 1)).sum() for a in mi])
+        lam = fmm.m2l_matrix(ct - cs, kappa, p) @ M
+        approx = np.array([sum(lam[t] * np.prod((x - ct) ** np.array(a)) for t, a in enumerate(mi))
+                           for x in tgt])
+        errs.append(np.abs(approx - direct).max() / np.abs(direct).max())
+    assert all(errs[k + 1] < 0.5 * errs[k] for k in range(3)), errs
+    assert errs[-1] < 1e-4
+
+
+@pytest.fixture(scope="module")
+def sphere320():
+    v, t = icosphere(2, 2.0)
+    P = panels(v, t)
+    I, cls = dense.integrals(P, 0.1257)
+    return P, I
+
+
+def test_gauss_double_layer_identity(sphere320):
+    """sum_j int_i int_j dG0/dn_y = -A_i/2 on a closed surface (Gauss)."""
+    P, I = sphere320
+    s = I[..., 1].sum(1) / P.area
+    assert np.abs(s + 0.5).max() < 2e-3
+
+
+def test_pair_symmetries(sphere320):
+    P, I = sphere320
+    # exact for the symmetric rules; the edge rule treats its two panels
+    # differently, so swapping them moves the result by its quadrature error
+    for a, b in ((0, 0), (5, 5), (3, 1), (4, 2)):
+        scale = np.abs(I[..., a]).max()
+        assert np.abs(I[..., a] - I[..., b].T).max() < 1e-8 * scale
+
+
+def test_sphere_constant_density_operators(sphere320):
+    """Unit density on a sphere of radius a: int G0 = a, int Gk = (1 - e^{-2 k a})/(2k),
+    int dGk/dn = -(1 - e^{-2ka}(1+ka))/(2ka); flat 320-panel sphere agrees to O(h^2)."""
+    P, I = sphere320
+    a, k = 2.0, 0.1257
+    V0 = a
+    Vk = (1 - np.exp(-2 * k * a)) / (2 * k)
+    Kk = -(1 - np.exp(-2 * k * a) * (1 + k * a)) / (2 * k * a)
+    A = P.area
+    assert abs((I[..., 0].sum(1) / A).mean() - (V0 - Vk)) < 0.02 * (V0 - Vk)
+    assert abs((I[..., 2].sum(1) / A).mean() - Kk) < 0.01 * abs(Kk)
+
+
+def test_born_and_kirkwood_series_agree():
+    for kap in (0.0, 0.1257):
+        assert kirkwood.energy(np.zeros((1, 3)), [1.0], 2.0, 1.0, 80.0, kap) == pytest.approx(
+            kirkwood.born(1.0, 2.0, 1.0, 80.0, kap), rel=1e-13)
+    g = _golden("kirkwood_paper_table2.txt")
+    assert kirkwood.born(50.0, 50.0, 1.0, 40.0, 0.1257) == pytest.approx(g[("exact", "inf")], abs=0.02)
+
+
+def test_kirkwood_series_properties():
+    from scipy.special import spherical_kn
+    x = 0.8
+    for n in range(6):
+        Rn = x * spherical_kn(n, x, derivative=True) / spherical_kn(n, x)
+        # reaction factor from the library's Bessel ratio
+        C = (80.0 * Rn + 2.0 * (n + 1)) / (2.0 * n - 80.0 * Rn)
+        assert kirkwood.reaction_factors(x / 0.4, 2.0, 80.0, 0.4, 5)[n] == pytest.approx(C, rel=1e-12)
+    # kappa = 0 reduces to the classical (n+1)(e1-e2)/(n e1 + (n+1) e2)
+    C0 = kirkwood.reaction_factors(3.0, 2.0, 80.0, 0.0, 5)
+    for n in range(6):
+        assert C0[n] == pytest.approx((n + 1) * (2.0 - 80.0) / (n * 2.0 + (n + 1) * 80.0), rel=1e-14)
+    rng = np.random.default_rng(4)
+    xq = rng.uniform(-1, 1, (5, 3))
+    q = rng.standard_normal(5)
+    e1 = kirkwood.energy(xq, q, 3.0, 1.0, 80.0, 0.1)
+    p = rng.permutation(5)
+    assert kirkwood.energy(xq[p], q[p], 3.0, 1.0, 80.0, 0.1) == pytest.approx(e1, rel=1e-13)
+
+
+def test_paper_sphere_energy_matches_table2():
+    """Dense oracle on the paper's sphere (R=50, q=50, eps 1/40) with 320 panels
+    lands within 0.05% of the paper's high-order quadrature value."""
+    g = _golden("kirkwood_paper_table2.txt")
+    v, t = icosphere(2, 50.0)
+    P = panels(v, t)
+    A = dense.assemble(P, 40.0, 0.1257)
+    b = solve.rhs(P, np.zeros((1, 3)), np.array([50.0]), 1.0)
+    x, it, _ = solve.gmres(lambda z: A @ z, b, 1e-10)
+    E = solve.energy(P, x, np.zeros((1, 3)), np.array([50.0]), 40.0, 0.1257)
+    assert abs(E - g[("table2_order4", "320")]) < 5e-4 * abs(E)
+    assert abs(E - g[("table2_order3", "320")]) < 5e-4 * abs(E)
+    # and the discretisation error is below the paper's one-point-rule error
+    assert abs(E - g[("exact", "inf")]) < abs(g[("table1_order1", "320")] - g[("exact", "inf")])
+
+
+def test_born_surface_values():
+    """Solved surface potential/derivative vs the exact Born values on C1-like sphere."""
+    v, t = icosphere(2, 2.0)
+    P = panels(v, t)
+    eps, kap = 80.0, 0.1257
+    A = dense.assemble(P, eps, kap)
+    b = solve.rhs(P, np.zeros((1, 3)), np.array([1.0]), 1.0)
+    x, it, _ = solve.gmres(lambda z: A @ z, b, 1e-10)
+    N = P.n
+    phi_ex = 1.0 / (4 * np.pi * 2.0 * eps * (1 + kap * 2.0))
+    dphi_ex = -1.0 / (4 * np.pi * 4.0)
+    assert np.abs(x[:N] / phi_ex - 1).max() < 0.05
+    # flat panels sit inside the sphere (centroid radius ~1.5% short at 320
+    # panels), so the flux density is a few percent high
+    assert np.abs(x[N:] / dphi_ex - 1).max() < 0.05
+    assert np.linalg.norm(A @ x - b) < 1e-9 * np.linalg.norm(b)
+
+
+def test_tree_coverage_and_fmm_convergence():
+    v, t = icosphere(3, 2.0)
+    P = panels(v, t)
+    tr = otree.build(P, 32, 0.8)
+    assert (fmm.coverage(tr) == 1).all()
+    # a deeper tree on a smaller leaf size also covers every pair once
+    tr8 = otree.build(P, 8, 0.8)
+    assert tr8.L > tr.L and (fmm.coverage(tr8) == 1).all()
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(2 * P.n)
+    F = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=2, with_near=False)
+    near = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=2)
+    ref = dense.assemble(P, 80.0, 0.1257) @ x
+    errs = []
+    for p in (2, 4, 6):
+        F = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=p, with_near=False)
+        F.near_i, F.near_j, F.near_B = near.near_i, near.near_j, near.near_B
+        errs.append(np.linalg.norm(fmm.matvec(F, x) - ref) / np.linalg.norm(ref))
+    assert errs[1] < 0.5 * errs[0] and errs[2] < 0.5 * errs[1], errs
+    # far field off + every pair near (eta0 = 0) is the dense operator exactly
+    tr0 = otree.build(P, 32, 0.0)
+    F0 = fmm.setup(P, tr0, 80.0, 0.1257, p_leaf=2)
+    assert np.linalg.norm(fmm.matvec(F0, x) - ref) < 1e-13 * np.linalg.norm(ref)
+
+
+def test_gmres_matches_direct_solve():
+    rng = np.random.default_rng(6)
+    A = np.eye(40) * 3 + rng.standard_normal((40, 40)) * 0.2
+    b = rng.standard_normal(40)
+    x, it, _ = solve.gmres(lambda z: A @ z, b, 1e-12, 40)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
+    D = np.diag(A)
+    x2, it2, _ = solve.gmres(lambda z: A @ z, b, 1e-12, 40, precond=lambda z: z / D)
+    assert np.allclose(x2, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
