@@ -1,0 +1,180 @@
+/*
+ * fagbi.h - C ABI of the MI355X Galerkin boundary-integral Poisson-Boltzmann
+ * operator and solver (Cartesian Taylor FMM + stored Galerkin near field).
+ *
+ * Problem (paper Sec. 2.1-2.3): a closed, conforming, outward-oriented surface
+ * of N flat triangles separates a solute (dielectric eps_in, point charges
+ * q_k at x_k) from a solvent (eps_out, inverse Debye length kappa).  The
+ * unknowns are the piecewise-constant surface potential phi and its normal
+ * derivative dphi (box-function Galerkin discretisation of the derivative
+ * boundary integral equations), stacked as x = [phi_1..phi_N, dphi_1..dphi_N]
+ * in the caller's panel order.  A x = b is the Galerkin system of Sec. 2.3:
+ *   A11 = (1+eps)/2 M - (eps I3 - I2),  A12 = -I1,
+ *   A21 = -I6,                          A22 = (1+1/eps)/2 M - (I4 - I5/eps),
+ * eps = eps_out/eps_in, M = diag(panel areas), I1..I6 the panel-pair integrals
+ * of G0 - Gk, dG0/dn_y, dGk/dn_y, dG0/dn_x, dGk/dn_x, d2(Gk - G0)/dn_x dn_y
+ * (G0 = 1/(4 pi r), Gk = exp(-kappa r)/(4 pi r)).
+ *
+ * Conventions for every call:
+ *   - return value: 0 = ok, < 0 = error (message in fagbi_last_error(), which
+ *     is per calling thread), > 0 = warning (e.g. FAGBI_W_NOT_CONVERGED);
+ *   - mesh and charge arrays are HOST pointers, read during the call and not
+ *     retained; solution/vector arrays are DEVICE pointers of the current HIP
+ *     device, owned by the caller, of 2N doubles unless stated otherwise;
+ *   - `stream` is a hipStream_t (NULL = the default stream); asynchronous calls
+ *     are ordered on it, calls documented as synchronising wait for it;
+ *   - a handle owns all of its device memory, is bound to the device current
+ *     at fagbi_create, and is not thread-safe; calls on one handle must not
+ *     overlap.
+ */
+#ifndef FAGBI_H
+#define FAGBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FAGBI_OK = 0,
+  FAGBI_E_ARG = -1,      /* bad argument or parameter value */
+  FAGBI_E_MESH = -2,     /* open/non-manifold/degenerate/inward mesh */
+  FAGBI_E_STATE = -3,    /* call out of order (e.g. matvec before assembly) */
+  FAGBI_E_OOM = -4,      /* device allocation failed */
+  FAGBI_E_HIP = -5,      /* HIP runtime error */
+  FAGBI_E_NUMERIC = -6,  /* NaN/Inf met, singular preconditioner block */
+  FAGBI_W_NOT_CONVERGED = 1
+};
+
+enum { FAGBI_FP64 = 0, FAGBI_MIXED = 1 };
+enum { FAGBI_PRECOND_NONE = 0, FAGBI_PRECOND_DIAG = 1, FAGBI_PRECOND_BLOCK = 2 };
+enum { FAGBI_MLP_OFF = 0, FAGBI_MLP_PRECOND = 1, FAGBI_MLP_GATED = 2 };
+/* parts of the operator for fagbi_matvec_parts */
+enum { FAGBI_PART_NEAR = 1, FAGBI_PART_FAR = 2, FAGBI_PART_ALL = 3 };
+
+typedef struct fagbi_params {
+  /* physics (Sec. 2.1): dielectric constants and inverse Debye length [1/A] */
+  double eps_in, eps_out, kappa;
+  /* cluster tree and FMM (Sec. 2.4): clusters c, c' of one level are
+     neighbours iff 2 rho_l / |x_c - x_c'| > eta0; uniform depth with at most
+     leaf_size panels per leaf cube; expansion order p_leaf at the leaves,
+     p_l = min(p_leaf + L - l, p_max) per level when adaptive != 0 */
+  double eta0;
+  int32_t leaf_size, p_leaf, adaptive, p_max;
+  /* near-field quadrature: Gauss points per dimension of the singular and
+     close-pair rules; pairs closer than near_ratio*max(h_i, h_j) (centroid
+     distance, h = sqrt(area)) use the close-pair rule */
+  int32_t quad_duffy;
+  double near_ratio;
+  /* solve: FAGBI_FP64 (GMRES on the FP64 operator) or FAGBI_MIXED (flexible
+     GMRES with the FP64 operator around inner GMRES on the FP32 operator) */
+  int32_t precision;
+  int32_t precond;             /* FAGBI_PRECOND_* */
+  double tol;                  /* relative true residual ||b - Ax||/||b|| */
+  int32_t max_iter;            /* Krylov basis size (no restart) */
+  int32_t max_outer;           /* outer iterations in FAGBI_MIXED */
+  double inner_tol;            /* inner relative tolerance in FAGBI_MIXED */
+  int32_t mlp_mode;            /* FAGBI_MLP_* (needs fagbi_mlp_set_weights) */
+  double mlp_gate_tol;         /* gated near field: max estimated rel. error */
+} fagbi_params;
+
+typedef struct fagbi_tree_info {
+  int64_t n_panels, n_leaves;
+  int32_t levels;              /* leaf level L (levels are 0..L) */
+  int32_t lmin;                /* coarsest level with interactions (L+1: none) */
+  int64_t near_pairs;          /* stored near-field panel pairs */
+  int64_t m2l_pairs;           /* cluster pairs over all interaction lists */
+  int64_t m2l_flops_fp;        /* M2L multiply-adds per matvec, both channels */
+  int64_t singular_pairs[4];   /* identical, edge, vertex, close */
+  int32_t order_leaf, order_root;
+  double rho_leaf, h_leaf;
+} fagbi_tree_info;
+
+typedef struct fagbi_solve_info {
+  int32_t outer_iterations;    /* FGMRES steps (FAGBI_MIXED) or 1 */
+  int32_t inner_iterations;    /* total Krylov iterations */
+  int32_t matvecs_fp64, matvecs_fp32;
+  double rel_residual;         /* true ||b - A64 x|| / ||b|| at exit */
+  double t_rhs_ms, t_solve_ms;
+} fagbi_solve_info;
+
+typedef struct fagbi_handle fagbi_handle;
+
+/* Fill *p with the defaults: eps 1/80, kappa 0.1257, eta0 0.8, leaf 32,
+   p_leaf 4 fixed order, p_max 8, quad_duffy 7, near_ratio 2, FP64, block
+   preconditioner, tol 1e-6, max_iter 200, max_outer 5, inner_tol 1e-4. */
+int fagbi_default_params(fagbi_params* p);
+
+/* Create a handle on the current device.  *out receives the handle. */
+int fagbi_create(const fagbi_params* p, fagbi_handle** out);
+
+/* Geometry and cluster tree (Sec. 2.3 panels; Sec. 2.4 cluster tree,
+   separation ratio, neighbour and interaction lists).  verts: host f64[nv*3],
+   tris: host i32[nt*3] (0-based, counter-clockwise seen from the solvent).
+   Rejects open, non-manifold, degenerate (zero-area) and inward meshes with
+   FAGBI_E_MESH.  Synchronises. */
+int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv,
+                     const int32_t* tris, int64_t nt);
+
+/* Near-field Galerkin blocks for every leaf pair (c, c') with c' in N(c)
+   (Sec. 2.3 linear system entries; singular pairs by Sauter-Schwab-type
+   relative-coordinate cubature, Sec. 2.3 last paragraph), their FP32 copy,
+   the FMM translation tables and the block-diagonal preconditioner factors
+   (Sec. 2.6).  Requires fagbi_build_tree.  Synchronises. */
+int fagbi_assemble_nearfield(fagbi_handle* h, void* stream);
+
+/* y = A x (Sec. 2.4 six-step FMM: near field, moments, upward pass,
+   interaction phase, downward pass, evaluation).  precision FAGBI_FP64: FP64
+   throughout; FAGBI_MIXED: FP32 near-field entries and FP32 expansions with
+   FP64 accumulation of y.  x, y: device f64[2N], caller order, must not
+   alias.  Asynchronous on stream. */
+int fagbi_matvec(fagbi_handle* h, const double* x, double* y, int32_t precision,
+                 void* stream);
+
+/* As fagbi_matvec but restricted to parts (FAGBI_PART_* bit mask). */
+int fagbi_matvec_parts(fagbi_handle* h, const double* x, double* y,
+                       int32_t precision, int32_t parts, void* stream);
+
+/* y = M^{-1} z for the block-diagonal preconditioner of Sec. 2.6 (leaf-level
+   blocks [phi_c; dphi_c], LU with partial pivoting, FP64).  With
+   precond = FAGBI_PRECOND_DIAG the diagonal of A is used instead.  z, y:
+   device f64[2N] (may alias).  Asynchronous on stream. */
+int fagbi_precond_apply(fagbi_handle* h, const double* z, double* y, void* stream);
+
+/* Right-hand side b (Sec. 2.2 source terms S1, S2 tested with the box
+   functions): xq host f64[nc*3] charge positions [A], q host f64[nc] charges
+   [e]; b device f64[2N].  Asynchronous on stream (arguments copied before
+   return). */
+int fagbi_rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
+              double* b, void* stream);
+
+/* Solve A x = b(charges) by right-preconditioned GMRES (FP64) or flexible
+   GMRES around FP32 inner solves (FAGBI_MIXED).  x: device f64[2N], the
+   initial guess on entry (zeros: pass zeros), the solution on exit.  info may
+   be NULL.  Returns FAGBI_W_NOT_CONVERGED with the best x if the tolerance is
+   not met.  Synchronises. */
+int fagbi_solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
+                double* x, fagbi_solve_info* info, void* stream);
+
+/* Solvation energy (Sec. 2.3 discrete E_sol times 4 pi 332.0716, Sec. 3) in
+   kcal/mol from a solution x (device f64[2N]).  FP64 direct sum over charges
+   and panel quadrature points.  Synchronises. */
+int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
+                           const double* q, int64_t nc, double* E_kcal,
+                           void* stream);
+
+/* Tree statistics (after fagbi_build_tree; near-field counts after assembly). */
+int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info);
+
+/* Tree order: perm[k] = caller panel index of the k-th panel in tree (Morton)
+   order; perm host i32[N]. */
+int fagbi_get_permutation(fagbi_handle* h, int32_t* perm);
+
+void fagbi_destroy(fagbi_handle* h);
+const char* fagbi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAGBI_H */

@@ -136,19 +136,17 @@ def ident(P, i, kappa, n, kern=None):
 
 
 def _reorder_edge(P, i, j):
-    """Per pair: P, Q (shared edge) and the opposite vertices R_i, R_j."""
+    """Per pair: P, Q (the shared edge, in the order they appear in triangle
+    i) and the opposite vertices R_i, R_j."""
     ti, tj = P.tris[i], P.tris[j]
     in_j = (ti[:, :, None] == tj[:, None, :]).any(2)   # [p,3] which of ti shared
     in_i = (tj[:, :, None] == ti[:, None, :]).any(2)
-    Pp, Qp, Ri, Rj = [], [], [], []
-    for k in range(len(i)):
-        sh = ti[k][in_j[k]]
-        Pp.append(sh[0])
-        Qp.append(sh[1])
-        Ri.append(ti[k][~in_j[k]][0])
-        Rj.append(tj[k][~in_i[k]][0])
+    oi = np.argsort(~in_j, axis=1, kind="stable")       # shared first, in order
+    oj = np.argsort(in_i, axis=1, kind="stable")        # unshared first
+    r = np.arange(len(i))
     V = P.verts
-    return V[Pp], V[Qp], V[Ri], V[Rj]
+    return (V[ti[r, oi[:, 0]]], V[ti[r, oi[:, 1]]], V[ti[r, oi[:, 2]]],
+            V[tj[r, oj[:, 0]]])
 
 
 def edge(P, i, j, kappa, n, kern=None):
@@ -181,17 +179,17 @@ def edge(P, i, j, kappa, n, kern=None):
 
 
 def _reorder_vertex(P, i, j):
+    """Per pair: the shared vertex S and the other two vertices of each
+    triangle in their order of appearance."""
     ti, tj = P.tris[i], P.tris[j]
-    S, Vi, Wi, Vj, Wj = [], [], [], [], []
-    for k in range(len(i)):
-        common = np.intersect1d(ti[k], tj[k])[0]
-        oi = [x for x in ti[k] if x != common]
-        oj = [x for x in tj[k] if x != common]
-        S.append(common)
-        Vi.append(oi[0]); Wi.append(oi[1])
-        Vj.append(oj[0]); Wj.append(oj[1])
+    in_j = (ti[:, :, None] == tj[:, None, :]).any(2)
+    in_i = (tj[:, :, None] == ti[:, None, :]).any(2)
+    oi = np.argsort(~in_j, axis=1, kind="stable")
+    oj = np.argsort(~in_i, axis=1, kind="stable")
+    r = np.arange(len(i))
     V = P.verts
-    return V[S], V[Vi], V[Wi], V[Vj], V[Wj]
+    return (V[ti[r, oi[:, 0]]], V[ti[r, oi[:, 1]]], V[ti[r, oi[:, 2]]],
+            V[tj[r, oj[:, 1]]], V[tj[r, oj[:, 2]]])
 
 
 def vertex(P, i, j, kappa, n, kern=None):
@@ -223,8 +221,8 @@ def pair_integrals(P, i, j, kappa, near_ratio=2.0, n=7, cls=None, chunk=2048):
     out = np.zeros((len(i), 6))
     rules = {REGULAR: (lambda a, b: regular(P, a, b, kappa), 65536),
              IDENT: (lambda a, b: ident(P, a, kappa, n), 4096),
-             EDGE: (lambda a, b: edge(P, a, b, kappa, n), 512),
-             VERTEX: (lambda a, b: vertex(P, a, b, kappa, n), 128),
+             EDGE: (lambda a, b: edge(P, a, b, kappa, n), 1024),
+             VERTEX: (lambda a, b: vertex(P, a, b, kappa, n), 256),
              CLOSE: (lambda a, b: close(P, a, b, kappa, n), 128)}
     for c, (fn, ch) in rules.items():
         sel = np.nonzero(cls == c)[0]

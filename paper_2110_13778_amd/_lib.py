@@ -1,0 +1,207 @@
+"""ctypes binding of libfagbi.so (the C ABI in include/fagbi.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device arrays are torch CUDA tensors (float64, contiguous); host
+arrays are numpy arrays.  Errors raise FagbiError with the library message.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libfagbi.so")
+
+OK, E_ARG, E_MESH, E_STATE, E_OOM, E_HIP, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+W_NOT_CONVERGED = 1
+FP64, MIXED = 0, 1
+PRECOND_NONE, PRECOND_DIAG, PRECOND_BLOCK = 0, 1, 2
+MLP_OFF, MLP_PRECOND, MLP_GATED = 0, 1, 2
+PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
+
+EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
+           "fagbi_assemble_nearfield", "fagbi_matvec", "fagbi_matvec_parts",
+           "fagbi_precond_apply", "fagbi_rhs", "fagbi_solve",
+           "fagbi_solvation_energy", "fagbi_get_tree_info",
+           "fagbi_get_permutation", "fagbi_destroy", "fagbi_last_error"]
+
+
+class Params(C.Structure):
+    _fields_ = [("eps_in", C.c_double), ("eps_out", C.c_double), ("kappa", C.c_double),
+                ("eta0", C.c_double),
+                ("leaf_size", C.c_int32), ("p_leaf", C.c_int32), ("adaptive", C.c_int32),
+                ("p_max", C.c_int32),
+                ("quad_duffy", C.c_int32), ("near_ratio", C.c_double),
+                ("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("max_outer", C.c_int32), ("inner_tol", C.c_double),
+                ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_panels", C.c_int64), ("n_leaves", C.c_int64), ("levels", C.c_int32),
+                ("lmin", C.c_int32), ("near_pairs", C.c_int64), ("m2l_pairs", C.c_int64),
+                ("m2l_flops_fp", C.c_int64), ("singular_pairs", C.c_int64 * 4),
+                ("order_leaf", C.c_int32), ("order_root", C.c_int32),
+                ("rho_leaf", C.c_double), ("h_leaf", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_iterations", C.c_int32), ("inner_iterations", C.c_int32),
+                ("matvecs_fp64", C.c_int32), ("matvecs_fp32", C.c_int32),
+                ("rel_residual", C.c_double), ("t_rhs_ms", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+
+class FagbiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fagbi error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libfagbi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError("libfagbi.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(LIBPATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "fagbi_default_params": [C.POINTER(Params)],
+        "fagbi_create": [C.POINTER(Params), C.POINTER(vp)],
+        "fagbi_build_tree": [vp, vp, i64, vp, i64],
+        "fagbi_assemble_nearfield": [vp, vp],
+        "fagbi_matvec": [vp, vp, vp, i32, vp],
+        "fagbi_matvec_parts": [vp, vp, vp, i32, i32, vp],
+        "fagbi_precond_apply": [vp, vp, vp, vp],
+        "fagbi_rhs": [vp, vp, vp, i64, vp, vp],
+        "fagbi_solve": [vp, vp, vp, i64, vp, C.POINTER(SolveInfo), vp],
+        "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
+        "fagbi_get_tree_info": [vp, C.POINTER(TreeInfo)],
+        "fagbi_get_permutation": [vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.fagbi_destroy.argtypes = [vp]
+    lib.fagbi_destroy.restype = None
+    lib.fagbi_last_error.argtypes = []
+    lib.fagbi_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code < 0:
+        raise FagbiError(code, _lib.fagbi_last_error().decode())
+    return code
+
+
+def default_params(**kw):
+    lib = load()
+    p = Params()
+    _check(lib.fagbi_default_params(C.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _dev(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+class Handle:
+    """One operator/solver instance (owns its device memory)."""
+
+    def __init__(self, params=None, **kw):
+        self.lib = load()
+        self.params = params if params is not None else default_params(**kw)
+        h = C.c_void_p()
+        _check(self.lib.fagbi_create(C.byref(self.params), C.byref(h)))
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fagbi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_tree(self, verts, tris):
+        v, vp = _host(verts, np.float64)
+        t, tp = _host(tris, np.int32)
+        _check(self.lib.fagbi_build_tree(self.h, vp, len(v), tp, len(t)))
+        self.n = len(t)
+        return self
+
+    def assemble_nearfield(self, stream=None):
+        _check(self.lib.fagbi_assemble_nearfield(self.h, _stream(stream)))
+        return self
+
+    def matvec(self, x, y, precision=FP64, parts=PART_ALL, stream=None):
+        _check(self.lib.fagbi_matvec_parts(self.h, _dev(x), _dev(y), precision, parts,
+                                           _stream(stream)))
+        return y
+
+    def precond_apply(self, z, y, stream=None):
+        _check(self.lib.fagbi_precond_apply(self.h, _dev(z), _dev(y), _stream(stream)))
+        return y
+
+    def rhs(self, xq, q, b, stream=None):
+        xq_, xqp = _host(xq, np.float64)
+        q_, qp = _host(q, np.float64)
+        _check(self.lib.fagbi_rhs(self.h, xqp, qp, len(q_), _dev(b), _stream(stream)))
+        return b
+
+    def solve(self, xq, q, x, stream=None):
+        xq_, xqp = _host(xq, np.float64)
+        q_, qp = _host(q, np.float64)
+        info = SolveInfo()
+        code = _check(self.lib.fagbi_solve(self.h, xqp, qp, len(q_), _dev(x), C.byref(info),
+                                           _stream(stream)))
+        return code, info
+
+    def solvation_energy(self, x, xq, q, stream=None):
+        xq_, xqp = _host(xq, np.float64)
+        q_, qp = _host(q, np.float64)
+        e = C.c_double()
+        _check(self.lib.fagbi_solvation_energy(self.h, _dev(x), xqp, qp, len(q_), C.byref(e),
+                                               _stream(stream)))
+        return e.value
+
+    def tree_info(self):
+        ti = TreeInfo()
+        _check(self.lib.fagbi_get_tree_info(self.h, C.byref(ti)))
+        return ti
+
+    def permutation(self):
+        p = np.zeros(self.n, np.int32)
+        _check(self.lib.fagbi_get_permutation(self.h, p.ctypes.data_as(C.c_void_p)))
+        return p

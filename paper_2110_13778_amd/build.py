@@ -1,0 +1,54 @@
+"""Build libfagbi.so (HIP for gfx950) in the package directory.
+
+hipcc compiles each .hip file to an object (device code for gfx950 only,
+packed FP32 instructions disabled), the host-only tree builder is compiled
+with FP contraction off, and everything is linked into one shared library.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libfagbi.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I" + os.path.join(HERE, "..", "include")]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("command failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return r
+
+
+def build(verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = []
+    for f in sorted(os.listdir(CSRC)):
+        src = os.path.join(CSRC, f)
+        obj = os.path.join(BUILD, f + ".o")
+        if f.endswith(".hip"):
+            jobs.append([HIPCC, "-c", src, "-o", obj] + HIP_FLAGS)
+        elif f.endswith(".cpp"):
+            jobs.append(["g++", "-c", src, "-o", obj, "-O2", "-std=c++17", "-fPIC",
+                         "-ffp-contract=off", "-I" + os.path.join(HERE, "..", "include")])
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        list(ex.map(_run, jobs))
+    objs = [j[4] for j in jobs]
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-o", tmp, "--offload-arch=" + ARCH, "-fPIC"] + objs)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

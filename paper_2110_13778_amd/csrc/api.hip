@@ -1,0 +1,400 @@
+// C ABI entry points, handle lifetime, error reporting and tree upload.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "tree.h"
+
+namespace fagbi {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// Gauss-Legendre rule on [0,1] by Newton iteration on P_n from the Chebyshev
+// initial guesses (three-term recurrence for P_n and P_n').
+void gauss_legendre01(int n, double* x, double* w) {
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+    }
+    x[n - 1 - i] = 0.5 * (z + 1.0);
+    w[n - 1 - i] = 1.0 / ((1 - z * z) * dp * dp);   // (2/((1-z^2)P'^2)) / 2
+  }
+}
+
+}  // namespace fagbi
+
+using namespace fagbi;
+
+int Tmp::alloc(size_t n) {
+  release();
+  if (n == 0) return 0;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return set_error(FAGBI_E_OOM, "device allocation of %zu bytes failed: %s", n, hipGetErrorString(e));
+  }
+  bytes = n;
+  return 0;
+}
+
+// (re)allocate a handle-owned buffer; every DBuf passed here is a member of
+// the handle (or of one of its levels), registered once for free_all()
+int fagbi_handle::alloc(DBuf& b, size_t bytes) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  bool known = false;
+  for (DBuf* o : owned) known |= (o == &b);
+  if (!known) owned.push_back(&b);
+  if (bytes == 0) return 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return set_error(FAGBI_E_OOM, "device allocation of %zu bytes failed: %s", bytes,
+                     hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return 0;
+}
+
+int fagbi_handle::upload(DBuf& b, const void* host, size_t bytes) {
+  FAGBI_TRY(alloc(b, bytes));
+  if (bytes) FAGBI_HIP(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+void fagbi_handle::free_all() {
+  for (DBuf* b : owned) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+  owned.clear();
+}
+
+extern "C" {
+
+const char* fagbi_last_error(void) { return g_err.c_str(); }
+
+int fagbi_default_params(fagbi_params* p) {
+  if (!p) return set_error(FAGBI_E_ARG, "null params");
+  memset(p, 0, sizeof *p);
+  p->eps_in = 1.0;
+  p->eps_out = 80.0;
+  p->kappa = 0.1257;
+  p->eta0 = 0.8;
+  p->leaf_size = 32;
+  p->p_leaf = 4;
+  p->adaptive = 0;
+  p->p_max = 8;
+  p->quad_duffy = 7;
+  p->near_ratio = 2.0;
+  p->precision = FAGBI_FP64;
+  p->precond = FAGBI_PRECOND_BLOCK;
+  p->tol = 1e-6;
+  p->max_iter = 200;
+  p->max_outer = 5;
+  p->inner_tol = 1e-4;
+  p->mlp_mode = FAGBI_MLP_OFF;
+  p->mlp_gate_tol = 1e-3;
+  return 0;
+}
+
+static int check_params(const fagbi_params* p) {
+  if (!(p->eps_in > 0) || !(p->eps_out > 0) || !(p->kappa >= 0))
+    return set_error(FAGBI_E_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
+  if (!(p->eta0 >= 0) || p->leaf_size < 1)
+    return set_error(FAGBI_E_ARG, "eta0 must be >= 0 and leaf_size >= 1");
+  if (p->leaf_size > 32)
+    return set_error(FAGBI_E_ARG, "leaf_size must be <= 32 (preconditioner blocks <= 64)");
+  if (p->p_leaf < 0 || p->p_leaf > PMAX || p->p_max < p->p_leaf || p->p_max > PMAX)
+    return set_error(FAGBI_E_ARG, "need 0 <= p_leaf <= p_max <= %d", PMAX);
+  if (p->quad_duffy < 1 || p->quad_duffy > 16)
+    return set_error(FAGBI_E_ARG, "quad_duffy must be in [1, 16]");
+  if (!(p->near_ratio >= 0)) return set_error(FAGBI_E_ARG, "near_ratio must be >= 0");
+  if (p->precision != FAGBI_FP64 && p->precision != FAGBI_MIXED)
+    return set_error(FAGBI_E_ARG, "precision must be FAGBI_FP64 or FAGBI_MIXED");
+  if (p->precond < 0 || p->precond > 2) return set_error(FAGBI_E_ARG, "bad precond");
+  if (!(p->tol > 0) || p->max_iter < 1 || p->max_iter > 2000 || p->max_outer < 1 ||
+      !(p->inner_tol > 0))
+    return set_error(FAGBI_E_ARG, "bad solver tolerances/iteration limits");
+  if (p->mlp_mode < 0 || p->mlp_mode > 2) return set_error(FAGBI_E_ARG, "bad mlp_mode");
+  return 0;
+}
+
+int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
+  if (!p || !out) return set_error(FAGBI_E_ARG, "null argument");
+  *out = nullptr;
+  FAGBI_TRY(check_params(p));
+  fagbi_handle* h = new (std::nothrow) fagbi_handle();
+  if (!h) return set_error(FAGBI_E_OOM, "host allocation failed");
+  h->prm = *p;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return set_error(FAGBI_E_HIP, "no HIP device");
+  }
+  // Gauss-Legendre nodes and weights of the singular/close rules
+  std::vector<double> gl(32, 0.0);
+  gauss_legendre01(p->quad_duffy, gl.data(), gl.data() + 16);
+  int r = h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double));
+  if (r < 0) {
+    h->free_all();
+    delete h;
+    return r;
+  }
+  *out = h;
+  return 0;
+}
+
+void fagbi_destroy(fagbi_handle* h) {
+  if (!h) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  h->free_all();
+  (void)hipSetDevice(cur);
+  delete h;
+}
+
+int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* tris,
+                     int64_t nt) {
+  if (!h || !verts || !tris) return set_error(FAGBI_E_ARG, "null argument");
+  if (nt > (int64_t)1 << 30) return set_error(FAGBI_E_ARG, "too many panels");
+  TreeOut T;
+  std::string err;
+  int r = build_tree_host(verts, nv, tris, nt, h->prm.leaf_size, h->prm.eta0, T, err);
+  if (r < 0) return set_error(r, "%s", err.c_str());
+  h->near_ready = false;
+  h->tree_ready = false;
+  // a new mesh replaces every device buffer (level buffers live inside
+  // h->lev, which is rebuilt below)
+  FAGBI_HIP(hipDeviceSynchronize());
+  h->free_all();
+  {
+    std::vector<double> gl(32, 0.0);
+    gauss_legendre01(h->prm.quad_duffy, gl.data(), gl.data() + 16);
+    FAGBI_TRY(h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double)));
+  }
+  h->N = nt;
+  h->nv = nv;
+  h->L = T.L;
+  h->lmin = T.lmin;
+  h->side = T.side;
+  for (int d = 0; d < 3; ++d) h->corner[d] = T.corner[d];
+  h->perm = T.perm;
+  const int64_t N = nt;
+  FAGBI_TRY(h->upload(h->d_perm, T.perm.data(), N * 4));
+  FAGBI_TRY(h->upload(h->d_pv, T.corners.data(), 9 * N * 8));
+  FAGBI_TRY(h->upload(h->d_pn, T.normal.data(), 3 * N * 8));
+  FAGBI_TRY(h->upload(h->d_pa, T.area.data(), N * 8));
+  FAGBI_TRY(h->upload(h->d_ptri, T.tri.data(), 3 * N * 4));
+  // levels
+  h->lev.assign(T.L + 1, Level());
+  for (int l = 0; l <= T.L; ++l) {
+    TreeLevel& S = T.lev[l];
+    Level& D = h->lev[l];
+    D.n = S.n;
+    D.h = S.h;
+    D.rho = S.rho;
+    D.order = h->prm.adaptive ? std::min(h->prm.p_leaf + T.L - l, h->prm.p_max) : h->prm.p_leaf;
+    D.T = nterms(D.order);
+    D.idx = S.idx;
+    D.parent = S.parent;
+    D.child_start = S.child_start;
+    D.child_end = S.child_end;
+    D.nbr_off = S.nbr_off;
+    D.nbr = S.nbr;
+    D.inter_off = S.inter_off;
+    D.inter_src = S.inter_src;
+    D.inter_oid = S.inter_oid;
+    D.off_xyz = S.off_xyz;
+    D.n_off = (int)(S.off_xyz.size() / 3);
+    FAGBI_TRY(h->upload(D.d_idx, D.idx.data(), D.idx.size() * 4));
+    FAGBI_TRY(h->upload(D.d_parent, D.parent.data(), D.parent.size() * 4));
+    FAGBI_TRY(h->upload(D.d_child_start, D.child_start.data(), D.child_start.size() * 4));
+    FAGBI_TRY(h->upload(D.d_child_end, D.child_end.data(), D.child_end.size() * 4));
+    FAGBI_TRY(h->upload(D.d_inter_off, D.inter_off.data(), D.inter_off.size() * 4));
+    FAGBI_TRY(h->upload(D.d_inter_src, D.inter_src.data(), D.inter_src.size() * 4));
+    FAGBI_TRY(h->upload(D.d_inter_oid, D.inter_oid.data(), D.inter_oid.size() * 4));
+  }
+  // leaf-level near-field layout: per leaf c, the source panels of every
+  // c' in N(c), and n_c x S_c entries stored row by row
+  const TreeLevel& LF = T.lev[T.L];
+  const int nl = LF.n;
+  h->leaf_start.assign(LF.start.begin(), LF.start.end());
+  h->leaf_cnt.resize(nl);
+  h->max_leaf = 0;
+  for (int c = 0; c < nl; ++c) {
+    h->leaf_cnt[c] = LF.end[c] - LF.start[c];
+    h->max_leaf = std::max(h->max_leaf, h->leaf_cnt[c]);
+  }
+  h->src_off.assign(nl + 1, 0);
+  h->ent_off.assign(nl + 1, 0);
+  h->self_col.assign(nl, -1);
+  for (int c = 0; c < nl; ++c) {
+    int64_t s = 0;
+    for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
+      if (LF.nbr[q] == c) h->self_col[c] = (int32_t)s;
+      s += h->leaf_cnt[LF.nbr[q]];
+    }
+    h->src_off[c + 1] = h->src_off[c] + s;
+    h->ent_off[c + 1] = h->ent_off[c] + s * h->leaf_cnt[c];
+  }
+  h->n_src = h->src_off[nl];
+  h->n_ent = h->ent_off[nl];
+  std::vector<int32_t> src_tree(h->n_src), src_user(h->n_src), leaf_of(N);
+  for (int c = 0; c < nl; ++c) {
+    int64_t k = h->src_off[c];
+    for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
+      const int c2 = LF.nbr[q];
+      for (int j = LF.start[c2]; j < LF.end[c2]; ++j) {
+        src_tree[k] = j;
+        src_user[k] = T.perm[j];
+        ++k;
+      }
+    }
+    for (int i = LF.start[c]; i < LF.end[c]; ++i) leaf_of[i] = c;
+  }
+  FAGBI_TRY(h->upload(h->d_leaf_start, h->leaf_start.data(), nl * 4));
+  FAGBI_TRY(h->upload(h->d_leaf_cnt, h->leaf_cnt.data(), nl * 4));
+  FAGBI_TRY(h->upload(h->d_src_off, h->src_off.data(), (nl + 1) * 8));
+  FAGBI_TRY(h->upload(h->d_ent_off, h->ent_off.data(), (nl + 1) * 8));
+  FAGBI_TRY(h->upload(h->d_self_col, h->self_col.data(), nl * 4));
+  FAGBI_TRY(h->upload(h->d_src_tree, src_tree.data(), h->n_src * 4));
+  FAGBI_TRY(h->upload(h->d_src_user, src_user.data(), h->n_src * 4));
+  FAGBI_TRY(h->upload(h->d_leaf_of, leaf_of.data(), N * 4));
+  h->tree_ready = true;
+  return 0;
+}
+
+int fagbi_assemble_nearfield(fagbi_handle* h, void* stream) {
+  if (!h) return set_error(FAGBI_E_ARG, "null handle");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "assemble_nearfield before build_tree");
+  hipStream_t s = (hipStream_t)stream;
+  h->near_ready = false;
+  FAGBI_TRY(fagbi::assemble_nearfield(h, s));
+  FAGBI_TRY(fagbi::fmm_setup(h, s));
+  FAGBI_TRY(fagbi::precond_setup(h, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  h->near_ready = true;
+  return 0;
+}
+
+int fagbi_matvec_parts(fagbi_handle* h, const double* x, double* y, int32_t precision,
+                       int32_t parts, void* stream) {
+  if (!h || !x || !y) return set_error(FAGBI_E_ARG, "null argument");
+  if (!h->near_ready) return set_error(FAGBI_E_STATE, "matvec before assemble_nearfield");
+  if (precision != FAGBI_FP64 && precision != FAGBI_MIXED)
+    return set_error(FAGBI_E_ARG, "bad precision");
+  if (x == y) return set_error(FAGBI_E_ARG, "x and y must not alias");
+  return fagbi::matvec(h, x, y, precision, parts & FAGBI_PART_ALL, (hipStream_t)stream);
+}
+
+int fagbi_matvec(fagbi_handle* h, const double* x, double* y, int32_t precision,
+                 void* stream) {
+  return fagbi_matvec_parts(h, x, y, precision, FAGBI_PART_ALL, stream);
+}
+
+int fagbi_precond_apply(fagbi_handle* h, const double* z, double* y, void* stream) {
+  if (!h || !z || !y) return set_error(FAGBI_E_ARG, "null argument");
+  if (!h->near_ready) return set_error(FAGBI_E_STATE, "precond_apply before assemble_nearfield");
+  return fagbi::precond_apply(h, z, y, (hipStream_t)stream);
+}
+
+int fagbi_rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b,
+              void* stream) {
+  if (!h || !xq || !q || !b || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "rhs before build_tree");
+  return fagbi::rhs(h, xq, q, nc, b, (hipStream_t)stream);
+}
+
+int fagbi_solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
+                fagbi_solve_info* info, void* stream) {
+  if (!h || !xq || !q || !x || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (!h->near_ready) return set_error(FAGBI_E_STATE, "solve before assemble_nearfield");
+  return fagbi::solve(h, xq, q, nc, x, info, (hipStream_t)stream);
+}
+
+int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq, const double* q,
+                           int64_t nc, double* E_kcal, void* stream) {
+  if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "energy before build_tree");
+  return fagbi::energy(h, x, xq, q, nc, E_kcal, (hipStream_t)stream);
+}
+
+int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
+  if (!h || !info) return set_error(FAGBI_E_ARG, "null argument");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "no tree");
+  memset(info, 0, sizeof *info);
+  info->n_panels = h->N;
+  info->n_leaves = h->lev[h->L].n;
+  info->levels = h->L;
+  info->lmin = h->lmin;
+  info->near_pairs = h->n_ent;
+  int64_t pairs = 0, macs = 0;
+  for (int l = 0; l <= h->L; ++l) {
+    const Level& D = h->lev[l];
+    const int64_t np = (int64_t)D.inter_src.size();
+    pairs += np;
+    int64_t per = 0;   // sum over alpha of T(p - |alpha|)
+    for (int d = 0; d <= D.order; ++d) per += (int64_t)((d + 1) * (d + 2) / 2) * nterms(D.order - d);
+    macs += 2 * np * per;
+  }
+  info->m2l_pairs = pairs;
+  info->m2l_flops_fp = macs;
+  for (int k = 0; k < 4; ++k) info->singular_pairs[k] = h->singular_count[k];
+  info->order_leaf = h->lev[h->L].order;
+  info->order_root = h->lev[0].order;
+  info->rho_leaf = h->lev[h->L].rho;
+  info->h_leaf = h->lev[h->L].h;
+  return 0;
+}
+
+int fagbi_get_permutation(fagbi_handle* h, int32_t* perm) {
+  if (!h || !perm) return set_error(FAGBI_E_ARG, "null argument");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "no tree");
+  memcpy(perm, h->perm.data(), h->N * 4);
+  return 0;
+}
+
+}  // extern "C"

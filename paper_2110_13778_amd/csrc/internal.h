@@ -1,0 +1,173 @@
+// Internal state and device helpers of the fagbi library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fagbi.h"
+
+namespace fagbi {
+
+constexpr int PMAX = 10;                       // highest supported expansion order
+constexpr int TMAX = (PMAX + 1) * (PMAX + 2) * (PMAX + 3) / 6;   // 286 terms
+constexpr double FOUR_PI = 12.566370614359172953850573533118;
+constexpr double UNIT_KCAL = 4.0 * 3.14159265358979323846264338327950288 * 332.0716;
+
+__host__ __device__ inline int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+int set_error(int code, const char* fmt, ...);
+
+#define FAGBI_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::fagbi::set_error(FAGBI_E_HIP, "%s failed: %s (%s:%d)", #call,         \
+                                hipGetErrorString(e_), __FILE__, __LINE__);          \
+  } while (0)
+
+#define FAGBI_TRY(call)                  \
+  do {                                   \
+    int r_ = (call);                     \
+    if (r_ < 0) return r_;               \
+  } while (0)
+
+// device allocation owned by the handle
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// scratch device memory owned by a scope (freed on destruction)
+struct Tmp {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Tmp() = default;
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+  ~Tmp() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int alloc(size_t n);
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Level {
+  int n = 0;          // clusters on this level
+  int order = 0;      // expansion order p_l
+  int T = 0;          // terms of order p_l
+  double h = 0, rho = 0;
+  std::vector<int32_t> idx;          // 3n cube indices
+  std::vector<int32_t> parent;       // n
+  std::vector<int32_t> child_start, child_end;  // n (children on level+1)
+  std::vector<int32_t> nbr_off, nbr;            // CSR neighbour lists
+  std::vector<int32_t> inter_off, inter_src, inter_oid;  // CSR interaction lists
+  std::vector<int32_t> off_xyz;      // 3 * n_off distinct offsets (c - c')
+  int n_off = 0;
+  // device
+  DBuf d_idx, d_parent, d_child_start, d_child_end, d_inter_off, d_inter_src, d_inter_oid;
+  DBuf d_F64[2], d_F32[2];           // Taylor tables per offset [n_off][T], G0 / Gk
+  DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
+  DBuf d_M32[2], d_L32[2];
+};
+
+}  // namespace fagbi
+
+struct fagbi_handle {
+  fagbi_params prm;
+  int device = 0;
+  // ---- mesh / tree (host copies) ----
+  int64_t N = 0, nv = 0;
+  int L = -1, lmin = 0;
+  double corner[3] = {0, 0, 0}, side = 0;
+  std::vector<int32_t> perm;          // tree position -> caller panel index
+  std::vector<fagbi::Level> lev;      // 0..L
+  // leaf-level near field layout
+  std::vector<int32_t> leaf_start, leaf_cnt;
+  std::vector<int64_t> src_off, ent_off;
+  std::vector<int32_t> self_col;
+  int64_t n_src = 0, n_ent = 0;
+  int max_leaf = 0;
+  bool tree_ready = false, near_ready = false;
+  int64_t singular_count[4] = {0, 0, 0, 0};
+  // ---- device buffers ----
+  fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
+  fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
+  fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
+  fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
+  fagbi::DBuf d_coef64, d_coef32, d_gidx, d_mi; // translation tables
+  fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner
+  fagbi::DBuf d_gl;                   // Gauss-Legendre nodes/weights on [0,1]
+  fagbi::DBuf d_work;                 // scratch for reductions
+  // Krylov workspace
+  fagbi::DBuf d_V, d_Z, d_w, d_r, d_b, d_x0, d_dots, d_t1, d_t2;
+  int krylov_m = 0;
+  std::vector<fagbi::DBuf*> owned;
+  int alloc(fagbi::DBuf& b, size_t bytes);
+  int upload(fagbi::DBuf& b, const void* host, size_t bytes);
+  void free_all();
+};
+
+namespace fagbi {
+// stages implemented in the .hip files
+int assemble_nearfield(fagbi_handle* h, hipStream_t s);
+int fmm_setup(fagbi_handle* h, hipStream_t s);
+int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts,
+           hipStream_t s);
+int precond_setup(fagbi_handle* h, hipStream_t s);
+int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s);
+int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b,
+        hipStream_t s);
+int energy(fagbi_handle* h, const double* x, const double* xq, const double* q,
+           int64_t nc, double* E, hipStream_t s);
+int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
+          fagbi_solve_info* info, hipStream_t s);
+void gauss_legendre01(int n, double* x, double* w);
+}  // namespace fagbi
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+namespace fagbi {
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// the six pair integrands at separation r = x - y with normals nx (target),
+// ny (source): G0-Gk, dG0/dny, dGk/dny, dG0/dnx, dGk/dnx, d2(Gk-G0)/dnx dny
+__device__ inline void kernel6(double rx, double ry, double rz, const double* nx,
+                               const double* ny, double kappa, double* k) {
+  const double r2 = rx * rx + ry * ry + rz * rz;
+  const double r = sqrt(r2);
+  const double u = kappa * r;
+  const double em1 = expm1(-u);
+  const double E = em1 + 1.0;
+  const double i4pr = 1.0 / (FOUR_PI * r);
+  const double i4pr3 = i4pr / r2;
+  const double rny = rx * ny[0] + ry * ny[1] + rz * ny[2];
+  const double rnx = rx * nx[0] + ry * nx[1] + rz * nx[2];
+  const double nn = nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2];
+  const double e1u = E * (1.0 + u);
+  k[0] = -em1 * i4pr;
+  k[1] = rny * i4pr3;
+  k[2] = e1u * rny * i4pr3;
+  k[3] = -rnx * i4pr3;
+  k[4] = -e1u * rnx * i4pr3;
+  const double c1 = em1 + u * E;
+  const double c2 = 3.0 * em1 + 3.0 * u * E + u * u * E;
+  k[5] = (c1 * nn - c2 * rnx * rny / r2) * i4pr3;
+}
+
+}  // namespace fagbi

@@ -1,0 +1,521 @@
+// Near-field Galerkin assembly (paper Sec. 2.3: linear-system entries over
+// panel pairs of neighbouring leaf clusters; singular pairs by the
+// singularity-removing relative-coordinate cubature of Sauter and Schwab) and
+// the block-diagonal preconditioner of Sec. 2.6.
+//
+// Storage: for leaf c with n_c panels and S_c source panels (all panels of
+// every c' in N(c), in list order), entries[ent_off[c] + i*S_c + k] holds the
+// four operator blocks of the pair (target i of c, source k) as
+// {B11, B12, B21, B22} with B11 = -(eps I3 - I2), B12 = -I1, B21 = -I6,
+// B22 = -(I4 - I5/eps), plus the identity terms (1+eps)/2 A_i and
+// (1+1/eps)/2 A_i on the diagonal.
+//
+// Pair classes: IDENT (same panel), EDGE (two shared vertices), VERTEX (one),
+// CLOSE (centroid distance < near_ratio * max(sqrt(A_i), sqrt(A_j))), REGULAR.
+//   REGULAR: 3 x 3 product of the symmetric 3-point rule.
+//   CLOSE:   Duffy-collapsed n x n Gauss rule on each triangle.
+//   IDENT:   the integrand depends on z = y - x only; the x-integral is the
+//            area of a shrunken reference triangle, (1 - sigma(z))^2 / 2, and
+//            the hexagon of z splits into six triangles with radial
+//            coordinate xi: n^2 points per sector.
+//   EDGE:    depends on (y1 - x1, x2, y2); four pyramids in those variables
+//            with radial coordinate xi (Jacobian xi^2, times s on the two
+//            Duffy-collapsed triangular faces) and weight (1 - sigma):
+//            n^3 points per pyramid.
+//   VERTEX:  Duffy on each triangle, the (x1, y1) square split on its
+//            diagonal and collapsed to the shared vertex: 2 n^4 points.
+// Each panel is parameterised as chi(x) = u + x1 (v - u) + x2 (w - v) on
+// {0 <= x2 <= x1 <= 1}.  Every singular pair is integrated by one wavefront
+// (lanes over quadrature points, fixed-order reduction), so FP64 results do
+// not depend on scheduling.
+#include "internal.h"
+
+namespace fagbi {
+
+enum { C_REGULAR = 0, C_IDENT = 1, C_EDGE = 2, C_VERTEX = 3, C_CLOSE = 4 };
+
+struct Item {
+  int32_t i, j;       // tree-order panels (target, source)
+  int64_t ent;        // entry index
+};
+
+struct NearArgs {
+  const double* pv;     // corners [N][9]
+  const double* pn;     // normals [N][3]
+  const double* pa;     // areas [N]
+  const int32_t* ptri;  // vertex ids [N][3]
+  const int32_t* leaf_start;
+  const int32_t* leaf_cnt;
+  const int64_t* src_off;
+  const int64_t* ent_off;
+  const int32_t* src_tree;
+  double kappa, eps, near_ratio;
+};
+
+__device__ inline int classify(const NearArgs& a, int i, int j) {
+  if (i == j) return C_IDENT;
+  int shared = 0;
+  for (int p = 0; p < 3; ++p) {
+    const int vi = a.ptri[3 * i + p];
+    shared += (vi == a.ptri[3 * j]) + (vi == a.ptri[3 * j + 1]) + (vi == a.ptri[3 * j + 2]);
+  }
+  if (shared == 2) return C_EDGE;
+  if (shared == 1) return C_VERTEX;
+  // centroid distance, evaluated without contraction so the test is the
+  // IEEE result of the written expression
+  double s[3];
+  for (int d = 0; d < 3; ++d) {
+    const double ci = __dadd_rn(__dadd_rn(a.pv[9 * i + d], a.pv[9 * i + 3 + d]), a.pv[9 * i + 6 + d]) / 3.0;
+    const double cj = __dadd_rn(__dadd_rn(a.pv[9 * j + d], a.pv[9 * j + 3 + d]), a.pv[9 * j + 6 + d]) / 3.0;
+    s[d] = __dadd_rn(ci, -cj);
+  }
+  const double dist = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(s[0], s[0]), __dmul_rn(s[1], s[1])),
+                                     __dmul_rn(s[2], s[2])));
+  const double hm = fmax(sqrt(a.pa[i]), sqrt(a.pa[j]));
+  return dist < __dmul_rn(a.near_ratio, hm) ? C_CLOSE : C_REGULAR;
+}
+
+__device__ inline void regular_pair(const NearArgs& a, int i, int j, double* I) {
+  double qi[9], qj[9];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) {
+      qi[3 * k + d] = (2.0 / 3.0) * a.pv[9 * i + 3 * k + d] +
+                      (1.0 / 6.0) * (a.pv[9 * i + 3 * ((k + 1) % 3) + d] + a.pv[9 * i + 3 * ((k + 2) % 3) + d]);
+      qj[3 * k + d] = (2.0 / 3.0) * a.pv[9 * j + 3 * k + d] +
+                      (1.0 / 6.0) * (a.pv[9 * j + 3 * ((k + 1) % 3) + d] + a.pv[9 * j + 3 * ((k + 2) % 3) + d]);
+    }
+  const double* ni = a.pn + 3 * i;
+  const double* nj = a.pn + 3 * j;
+  for (int m = 0; m < 6; ++m) I[m] = 0;
+  double k6[6];
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q) {
+      kernel6(qi[3 * p] - qj[3 * q], qi[3 * p + 1] - qj[3 * q + 1], qi[3 * p + 2] - qj[3 * q + 2], ni, nj,
+              a.kappa, k6);
+      for (int m = 0; m < 6; ++m) I[m] += k6[m];
+    }
+  const double w = (a.pa[i] / 3.0) * (a.pa[j] / 3.0);
+  for (int m = 0; m < 6; ++m) I[m] *= w;
+}
+
+__device__ inline double4 combine(const double* I, double eps) {
+  return make_double4(-(eps * I[2] - I[1]), -I[0], -I[5], -(I[3] - I[4] / eps));
+}
+
+// pass 0: count singular pairs per class; pass 1: regular entries + worklists
+template <int PASS>
+__global__ void __launch_bounds__(256) k_near_classify(NearArgs a, unsigned long long* counters,
+                                                       const unsigned long long* capacity,
+                                                       Item* w_ident, Item* w_edge, Item* w_vertex,
+                                                       Item* w_close, double4* ent) {
+  const int c = blockIdx.x;
+  const int nc = a.leaf_cnt[c];
+  const int i0 = a.leaf_start[c];
+  const int64_t so = a.src_off[c];
+  const int S = (int)(a.src_off[c + 1] - so);
+  const int64_t eo = a.ent_off[c];
+  const int64_t total = (int64_t)nc * S;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = 0; base < total; base += blockDim.x) {
+    const int64_t e = base + threadIdx.x;
+    const bool valid = e < total;
+    int cls = -1, i = 0, j = 0;
+    if (valid) {
+      const int il = (int)(e / S);
+      const int k = (int)(e - (int64_t)il * S);
+      i = i0 + il;
+      j = a.src_tree[so + k];
+      cls = classify(a, i, j);
+      if (PASS == 1 && cls == C_REGULAR) {
+        double I[6];
+        regular_pair(a, i, j, I);
+        ent[eo + e] = combine(I, a.eps);
+      }
+    }
+#pragma unroll
+    for (int C = 1; C <= 4; ++C) {
+      const unsigned long long mask = __ballot(cls == C);
+      if (mask == 0) continue;
+      const int cnt = __popcll(mask);
+      const int leader = __ffsll((long long)mask) - 1;
+      unsigned long long basepos = 0;
+      if (lane == leader) basepos = atomicAdd(&counters[C - 1], (unsigned long long)cnt);
+      basepos = __shfl(basepos, leader, 64);
+      if (PASS == 1 && cls == C) {
+        const unsigned long long pos = basepos + __popcll(mask & ((1ull << lane) - 1ull));
+        Item it{i, j, eo + e};
+        Item* wl = C == C_IDENT ? w_ident : C == C_EDGE ? w_edge : C == C_VERTEX ? w_vertex : w_close;
+        if (pos < capacity[C - 1]) wl[pos] = it;
+      }
+    }
+  }
+}
+
+// one wavefront per singular / close pair
+template <int CLS>
+__global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* items, int64_t n_items,
+                                                       const double* gl, int n, double4* ent) {
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (it >= n_items) return;
+  const Item item = items[it];
+  const int i = item.i, j = item.j;
+  const double* gx = gl;
+  const double* gw = gl + 16;
+  const double* ci = a.pv + 9 * i;
+  const double* cj = a.pv + 9 * j;
+  const double* ni = a.pn + 3 * i;
+  const double* nj = a.pn + 3 * j;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double k6[6];
+  const int n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  if (CLS == C_IDENT) {
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+      e1[d] = ci[3 + d] - ci[d];
+      e2[d] = ci[6 + d] - ci[3 + d];
+    }
+    // hexagon sectors (P_s, Q_s)
+    const int HP[6][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}};
+    const int HQ[6][2] = {{1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, 0}};
+    for (int p = lane; p < 6 * n2; p += 64) {
+      const int s = p / n2, rem = p - s * n2, ia = rem / n, ib = rem - ia * n;
+      const double xi = gx[ia], t = gx[ib];
+      const double w = gw[ia] * gw[ib] * 0.5 * (1.0 - xi) * (1.0 - xi) * xi;
+      const double z1 = xi * ((1.0 - t) * HP[s][0] + t * HQ[s][0]);
+      const double z2 = xi * ((1.0 - t) * HP[s][1] + t * HQ[s][1]);
+      kernel6(-(z1 * e1[0] + z2 * e2[0]), -(z1 * e1[1] + z2 * e2[1]), -(z1 * e1[2] + z2 * e2[2]), ni, ni,
+              a.kappa, k6);
+      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+    }
+  } else if (CLS == C_EDGE) {
+    // shared vertices P, Q in the order they appear in triangle i
+    int pid[2], np_ = 0, ri = 0, rj = 0;
+    for (int p = 0; p < 3; ++p) {
+      const int v = a.ptri[3 * i + p];
+      const bool sh = v == a.ptri[3 * j] || v == a.ptri[3 * j + 1] || v == a.ptri[3 * j + 2];
+      if (sh) pid[np_++] = p; else ri = p;
+    }
+    for (int p = 0; p < 3; ++p) {
+      const int v = a.ptri[3 * j + p];
+      const bool sh = v == a.ptri[3 * i] || v == a.ptri[3 * i + 1] || v == a.ptri[3 * i + 2];
+      if (!sh) rj = p;
+    }
+    double e[3], av[3], bv[3];
+    for (int d = 0; d < 3; ++d) {
+      const double P = ci[3 * pid[0] + d], Q = ci[3 * pid[1] + d];
+      e[d] = Q - P;
+      av[d] = ci[3 * ri + d] - Q;
+      bv[d] = cj[3 * rj + d] - Q;
+    }
+    for (int p = lane; p < 4 * n3; p += 64) {
+      const int piece = p / n3, rem = p - piece * n3;
+      const int ia = rem / n2, ib = (rem / n) % n, ic = rem % n;
+      const double xi = gx[ia], w1 = gx[ib], w2 = gx[ic];
+      double w = gw[ia] * gw[ib] * gw[ic] * (1.0 - xi) * xi * xi;
+      double z1, x2, y2;
+      if (piece == 0) {
+        z1 = xi * w1; x2 = xi * (1 - w1); y2 = xi * w2;
+      } else if (piece == 1) {
+        z1 = xi * w1 * (1 - w2); x2 = xi * w1 * w2; y2 = xi; w *= w1;
+      } else if (piece == 2) {
+        z1 = -xi * w1 * (1 - w2); x2 = xi; y2 = xi * w1 * w2; w *= w1;
+      } else {
+        z1 = -xi * w1; x2 = xi * w2; y2 = xi * (1 - w1);
+      }
+      kernel6(-z1 * e[0] + x2 * av[0] - y2 * bv[0], -z1 * e[1] + x2 * av[1] - y2 * bv[1],
+              -z1 * e[2] + x2 * av[2] - y2 * bv[2], ni, nj, a.kappa, k6);
+      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+    }
+  } else if (CLS == C_VERTEX) {
+    int si = 0, sj = 0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q)
+        if (a.ptri[3 * i + p] == a.ptri[3 * j + q]) { si = p; sj = q; }
+    // the other two vertices in order of appearance
+    const int vi = si == 0 ? 1 : 0, wi = si == 2 ? 1 : 2;
+    const int vj = sj == 0 ? 1 : 0, wj = sj == 2 ? 1 : 2;
+    double S[3], A0[3], A1[3], B0[3], B1[3];
+    for (int d = 0; d < 3; ++d) {
+      S[d] = ci[3 * si + d];
+      A0[d] = ci[3 * vi + d] - S[d];
+      A1[d] = ci[3 * wi + d] - ci[3 * vi + d];
+      B0[d] = cj[3 * vj + d] - S[d];
+      B1[d] = cj[3 * wj + d] - cj[3 * vj + d];
+    }
+    for (int p = lane; p < 2 * n4; p += 64) {
+      const int piece = p / n4, rem = p - piece * n4;
+      const int ia = rem / n3, ib = (rem / n2) % n, ic = (rem / n) % n, id = rem % n;
+      const double xi = gx[ia], eta = gx[ib], t1 = gx[ic], t2 = gx[id];
+      const double w = gw[ia] * gw[ib] * gw[ic] * gw[id] * xi * xi * xi * eta;
+      const double sa = piece == 0 ? xi : xi * eta;
+      const double sb = piece == 0 ? xi * eta : xi;
+      double r[3];
+      for (int d = 0; d < 3; ++d) r[d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
+      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
+      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+    }
+  } else {  // CLOSE
+    const double tai = 2.0 * a.pa[i], taj = 2.0 * a.pa[j];
+    for (int p = lane; p < n4; p += 64) {
+      const int ia = p / n3, ib = (p / n2) % n, ic = (p / n) % n, id = p % n;
+      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic], t2 = gx[id];
+      const double w = tai * s1 * gw[ia] * gw[ib] * taj * s2 * gw[ic] * gw[id];
+      double r[3];
+      for (int d = 0; d < 3; ++d) {
+        const double x = ci[d] + s1 * (ci[3 + d] - ci[d]) + s1 * t1 * (ci[6 + d] - ci[3 + d]);
+        const double y = cj[d] + s2 * (cj[3 + d] - cj[d]) + s2 * t2 * (cj[6 + d] - cj[3 + d]);
+        r[d] = x - y;
+      }
+      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
+      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+    }
+  }
+  for (int m = 0; m < 6; ++m) acc[m] = wave_sum(acc[m]);
+  if (lane == 0) {
+    double scale = 1.0;
+    if (CLS == C_IDENT) scale = 4.0 * a.pa[i] * a.pa[i];
+    else if (CLS == C_EDGE || CLS == C_VERTEX) scale = 4.0 * a.pa[i] * a.pa[j];
+    for (int m = 0; m < 6; ++m) acc[m] *= scale;
+    if (CLS == C_IDENT) {
+      acc[1] = acc[2] = acc[3] = acc[4] = 0.0;   // r.n = 0 on a flat panel
+    }
+    double4 v = combine(acc, a.eps);
+    if (CLS == C_IDENT) {
+      v.x += 0.5 * (1.0 + a.eps) * a.pa[i];
+      v.w += 0.5 * (1.0 + 1.0 / a.eps) * a.pa[i];
+    }
+    ent[item.ent] = v;
+  }
+}
+
+__global__ void k_to_f32(const double4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double4 v = src[e];
+    dst[e] = make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+  }
+}
+
+static NearArgs near_args(fagbi_handle* h) {
+  NearArgs a;
+  a.pv = h->d_pv.as<double>();
+  a.pn = h->d_pn.as<double>();
+  a.pa = h->d_pa.as<double>();
+  a.ptri = h->d_ptri.as<int32_t>();
+  a.leaf_start = h->d_leaf_start.as<int32_t>();
+  a.leaf_cnt = h->d_leaf_cnt.as<int32_t>();
+  a.src_off = h->d_src_off.as<int64_t>();
+  a.ent_off = h->d_ent_off.as<int64_t>();
+  a.src_tree = h->d_src_tree.as<int32_t>();
+  a.kappa = h->prm.kappa;
+  a.eps = h->prm.eps_out / h->prm.eps_in;
+  a.near_ratio = h->prm.near_ratio;
+  return a;
+}
+
+int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
+  const int nl = h->lev[h->L].n;
+  NearArgs a = near_args(h);
+  FAGBI_TRY(h->alloc(h->d_E64, (size_t)h->n_ent * sizeof(double4)));
+  FAGBI_TRY(h->alloc(h->d_E32, (size_t)h->n_ent * sizeof(float4)));
+  Tmp cnt, cap;
+  FAGBI_TRY(cnt.alloc(4 * sizeof(unsigned long long)));
+  FAGBI_TRY(cap.alloc(4 * sizeof(unsigned long long)));
+  FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(unsigned long long), s));
+  k_near_classify<0><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), nullptr, nullptr, nullptr,
+                                        nullptr, nullptr, nullptr);
+  FAGBI_HIP(hipGetLastError());
+  unsigned long long c[4];
+  FAGBI_HIP(hipMemcpyAsync(c, cnt.p, sizeof c, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < 4; ++k) h->singular_count[k] = (int64_t)c[k];
+  Tmp wl[4];
+  for (int k = 0; k < 4; ++k) FAGBI_TRY(wl[k].alloc((size_t)std::max<unsigned long long>(c[k], 1) * sizeof(Item)));
+  FAGBI_HIP(hipMemcpyAsync(cap.p, c, sizeof c, hipMemcpyHostToDevice, s));
+  FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(unsigned long long), s));
+  k_near_classify<1><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), cap.as<unsigned long long>(), wl[0].as<Item>(),
+                                        wl[1].as<Item>(), wl[2].as<Item>(), wl[3].as<Item>(),
+                                        h->d_E64.as<double4>());
+  FAGBI_HIP(hipGetLastError());
+  const int n = h->prm.quad_duffy;
+  const double* gl = h->d_gl.as<double>();
+  double4* E = h->d_E64.as<double4>();
+  auto grid = [](unsigned long long m) { return (unsigned)((m + 3) / 4); };
+  if (c[0]) k_near_singular<C_IDENT><<<grid(c[0]), 256, 0, s>>>(a, wl[0].as<Item>(), c[0], gl, n, E);
+  if (c[1]) k_near_singular<C_EDGE><<<grid(c[1]), 256, 0, s>>>(a, wl[1].as<Item>(), c[1], gl, n, E);
+  if (c[2]) k_near_singular<C_VERTEX><<<grid(c[2]), 256, 0, s>>>(a, wl[2].as<Item>(), c[2], gl, n, E);
+  if (c[3]) k_near_singular<C_CLOSE><<<grid(c[3]), 256, 0, s>>>(a, wl[3].as<Item>(), c[3], gl, n, E);
+  FAGBI_HIP(hipGetLastError());
+  k_to_f32<<<2048, 256, 0, s>>>(E, h->d_E32.as<float4>(), h->n_ent);
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// block-diagonal preconditioner (Sec. 2.6): for each leaf c the 2n_c x 2n_c
+// block of A between its own panels, ordered [phi_c; dphi_c], inverted by
+// Gauss-Jordan elimination with partial pivoting (one wavefront per leaf,
+// matrix in LDS).  The inverse is stored transposed for coalesced apply.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__ ent,
+                                                     const int32_t* leaf_cnt, const int64_t* src_off,
+                                                     const int64_t* ent_off, const int32_t* self_col,
+                                                     const int64_t* inv_off, double* inv, int* bad) {
+  __shared__ double A[64][65];
+  __shared__ int swp[64];
+  const int c = blockIdx.x;
+  const int nc = leaf_cnt[c];
+  const int m = 2 * nc;
+  const int S = (int)(src_off[c + 1] - src_off[c]);
+  const int64_t eo = ent_off[c];
+  const int sc = self_col[c];
+  const int r = threadIdx.x;
+  if (r < m) {
+    const int il = r < nc ? r : r - nc;
+    for (int col = 0; col < m; ++col) {
+      const int jl = col < nc ? col : col - nc;
+      const double4 e = ent[eo + (int64_t)il * S + sc + jl];
+      A[r][col] = r < nc ? (col < nc ? e.x : e.y) : (col < nc ? e.z : e.w);
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    // pivot: largest |A[i][k]|, i >= k, smallest index on ties
+    double v = (r >= k && r < m) ? fabs(A[r][k]) : -1.0;
+    int vi = r;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(vi, o, 64);
+      if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
+    }
+    if (r == 0) swp[k] = vi;
+    if (!(v > 0.0)) {
+      if (r == 0) atomicExch(bad, 1);
+      return;
+    }
+    if (vi != k && r < m) {
+      const double t = A[k][r];
+      A[k][r] = A[vi][r];
+      A[vi][r] = t;
+    }
+    __syncthreads();
+    const double d = 1.0 / A[k][k];
+    __syncthreads();
+    if (r < m) A[k][r] = (r == k ? 1.0 : A[k][r]) * d;
+    __syncthreads();
+    if (r < m && r != k) {
+      const double f = A[r][k];
+      A[r][k] = 0.0;
+      for (int j = 0; j < m; ++j) A[r][j] -= f * A[k][j];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = m - 1; k >= 0; --k) {
+    const int p = swp[k];
+    if (p != k && r < m) {
+      const double t = A[r][k];
+      A[r][k] = A[r][p];
+      A[r][p] = t;
+    }
+    __syncthreads();
+  }
+  if (r < m) {
+    double* out = inv + inv_off[c];
+    for (int b = 0; b < m; ++b) out[(int64_t)b * m + r] = A[r][b];
+  }
+}
+
+__global__ void __launch_bounds__(64) k_block_apply(const double* __restrict__ inv,
+                                                    const int64_t* inv_off, const int32_t* leaf_start,
+                                                    const int32_t* leaf_cnt, const int32_t* perm,
+                                                    int64_t N, const double* z, double* y) {
+  __shared__ double zb[64];
+  const int c = blockIdx.x;
+  const int nc = leaf_cnt[c];
+  const int m = 2 * nc;
+  const int i0 = leaf_start[c];
+  const int r = threadIdx.x;
+  int64_t row = 0;
+  if (r < m) {
+    const int p = perm[i0 + (r < nc ? r : r - nc)];
+    row = r < nc ? (int64_t)p : N + p;
+    zb[r] = z[row];
+  }
+  __syncthreads();
+  if (r < m) {
+    const double* T = inv + inv_off[c];
+    double acc = 0;
+    for (int b = 0; b < m; ++b) acc += T[(int64_t)b * m + r] * zb[b];
+    y[row] = acc;
+  }
+}
+
+__global__ void k_diag_extract(const double4* __restrict__ ent, const int32_t* leaf_start,
+                               const int32_t* leaf_cnt, const int64_t* src_off, const int64_t* ent_off,
+                               const int32_t* self_col, const int32_t* perm, int64_t N, double* diag) {
+  const int c = blockIdx.x;
+  const int nc = leaf_cnt[c];
+  const int S = (int)(src_off[c + 1] - src_off[c]);
+  for (int il = threadIdx.x; il < nc; il += blockDim.x) {
+    const double4 e = ent[ent_off[c] + (int64_t)il * S + self_col[c] + il];
+    const int p = perm[leaf_start[c] + il];
+    diag[p] = e.x;
+    diag[N + p] = e.w;
+  }
+}
+
+__global__ void k_diag_apply(const double* diag, const double* z, double* y, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = z[e] / diag[e];
+}
+
+int precond_setup(fagbi_handle* h, hipStream_t s) {
+  const int nl = h->lev[h->L].n;
+  FAGBI_TRY(h->alloc(h->d_diag, 2 * h->N * sizeof(double)));
+  k_diag_extract<<<nl, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_leaf_start.as<int32_t>(),
+                                   h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
+                                   h->d_ent_off.as<int64_t>(), h->d_self_col.as<int32_t>(),
+                                   h->d_perm.as<int32_t>(), h->N, h->d_diag.as<double>());
+  FAGBI_HIP(hipGetLastError());
+  std::vector<int64_t> off(nl + 1, 0);
+  for (int c = 0; c < nl; ++c) off[c + 1] = off[c] + 4LL * h->leaf_cnt[c] * h->leaf_cnt[c];
+  FAGBI_TRY(h->upload(h->d_lu_off, off.data(), off.size() * 8));
+  FAGBI_TRY(h->alloc(h->d_lu, (size_t)off[nl] * sizeof(double)));
+  Tmp bad;
+  FAGBI_TRY(bad.alloc(sizeof(int)));
+  FAGBI_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  k_block_invert<<<nl, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_leaf_cnt.as<int32_t>(),
+                                   h->d_src_off.as<int64_t>(), h->d_ent_off.as<int64_t>(),
+                                   h->d_self_col.as<int32_t>(), h->d_lu_off.as<int64_t>(),
+                                   h->d_lu.as<double>(), bad.as<int>());
+  FAGBI_HIP(hipGetLastError());
+  int hb = 0;
+  FAGBI_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  if (hb) return set_error(FAGBI_E_NUMERIC, "singular block in the block-diagonal preconditioner");
+  return 0;
+}
+
+int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s) {
+  if (h->prm.precond == FAGBI_PRECOND_NONE) {
+    if (z != y) FAGBI_HIP(hipMemcpyAsync(y, z, 2 * h->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return 0;
+  }
+  if (h->prm.precond == FAGBI_PRECOND_DIAG) {
+    k_diag_apply<<<1024, 256, 0, s>>>(h->d_diag.as<double>(), z, y, 2 * h->N);
+    FAGBI_HIP(hipGetLastError());
+    return 0;
+  }
+  const int nl = h->lev[h->L].n;
+  k_block_apply<<<nl, 64, 0, s>>>(h->d_lu.as<double>(), h->d_lu_off.as<int64_t>(),
+                                  h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
+                                  h->d_perm.as<int32_t>(), h->N, z, y);
+  FAGBI_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace fagbi
