@@ -1,0 +1,193 @@
+"""Benchmark of the Galerkin BIE Poisson-Boltzmann hot path on one MI355X.
+
+One step = one full pass of the path on the ~500k-panel workload: cluster
+tree, near-field assembly (singular cubature) with preconditioner factors,
+right-hand side, mixed-precision flexible GMRES to a 1e-6 true FP64 residual
+(FP32 FMM/near field inside, FP64 outside), and the solvation energy.  Inputs
+(mesh, charges) are host arrays handed to the library, as its C ABI defines.
+
+value = FMM matvec throughput [Mpanels/s] of the mixed-precision operator,
+from HIP events around every matvec issued inside the timed steps.  The same
+line reports the GMRES time-to-1e-6 of the mixed and the plain FP64 paths,
+the dominant kernel against its roofline, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM matvec Mpanels/s + GMRES time-to-1e-6 (mixed+MLP vs FP64) at 500k panels"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ellipsoid500k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=12)
+    return ap.parse_args()
+
+
+PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7,
+              near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=1e-4)
+
+
+def m2l_flops(h):
+    """algorithmic M2L flops per matvec (2 channels, 2 flops per multiply-add)"""
+    return 2.0 * h.tree_info().m2l_flops_fp
+
+
+def cpu_baseline(w, rows):
+    """FP64 oracle (dense rows, O(N) per row) on a sample of rows of the
+    same mesh; the full dense matvec takes N times one row."""
+    from oracle import dense
+    from oracle.geometry import panels
+    P = panels(w["verts"], w["tris"])
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(2 * P.n)
+    sel = rng.choice(P.n, rows, replace=False)
+    eps = w["eps_out"] / w["eps_in"]
+    t0 = time.perf_counter()
+    for r in sel:
+        dense.rows_matvec(P, eps, w["kappa"], x, np.array([r]))
+    dt = (time.perf_counter() - t0) / rows
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count()
+    return {"value": 1e-6 / dt, "unit": "Mpanels/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d rows of the dense FP64 oracle matvec (all %d source panels per "
+                      "row, singular rules for touching/close pairs) on the same mesh; "
+                      "rate = 1/(time per row), i.e. the full O(N^2) matvec rate; "
+                      "numpy single-threaded (%d host threads available)"
+                      % (rows, P.n, threads)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2110_13778_amd as F
+    from synth import workload
+
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    N = len(w["tris"])
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+
+    def run(prec, profile):
+        h = F.Handle(precision=prec, eps_in=w["eps_in"], eps_out=w["eps_out"],
+                     kappa=w["kappa"], **PARAMS)
+        h.set_profiling(profile)
+        t0 = time.perf_counter()
+        h.build_tree(w["verts"], w["tris"])
+        t1 = time.perf_counter()
+        h.assemble_nearfield()
+        t2 = time.perf_counter()
+        x = torch.zeros(2 * N, dtype=torch.float64, device=dev)
+        code, info = h.solve(w["xq"], w["q"], x)
+        t3 = time.perf_counter()
+        E = h.solvation_energy(x, w["xq"], w["q"])
+        t4 = time.perf_counter()
+        return h, x, dict(code=code, tree_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
+                          solve_ms=1e3 * (t3 - t2), energy_ms=1e3 * (t4 - t3),
+                          total_ms=1e3 * (t4 - t0), iters=info.inner_iterations,
+                          outer=info.outer_iterations, mv64=info.matvecs_fp64,
+                          mv32=info.matvecs_fp32, res=info.rel_residual, E=E)
+
+    # warmup
+    for _ in range(args.warmup):
+        h, x, _ = run(F.MIXED, True)
+        h.close()
+    torch.cuda.synchronize()
+    # timed steps: the whole path, mixed precision
+    prof_tot = {k: [0.0, 0.0] for k in ("ms_total", "ms_near", "ms_up", "ms_m2l", "ms_down")}
+    mv = [0, 0]
+    steps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h, x, st = run(F.MIXED, True)
+        p = h.profile()
+        for k in prof_tot:
+            for j in range(2):
+                prof_tot[k][j] += p[k][j]
+        for j in range(2):
+            mv[j] += p["matvecs"][j]
+        steps.append(st)
+        ti = h.tree_info()
+        flops_m2l = m2l_flops(h)
+        near_pairs = ti.near_pairs
+        E_mixed = st["E"]
+        h.close()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_total / args.steps
+    # mixed operator throughput (FP32 matvecs dominate; FP64 outer ones reported too)
+    mv32_ms = prof_tot["ms_total"][1] / max(mv[1], 1)
+    mv64_in_mixed_ms = prof_tot["ms_total"][0] / max(mv[0], 1)
+    value = N / (mv32_ms * 1e-3) / 1e6
+    # FP64 reference path (outside the timed region)
+    h64, x64, st64 = run(F.FP64, True)
+    p64 = h64.profile()
+    mv64_ms = p64["ms_total"][0] / max(p64["matvecs"][0], 1)
+    h64.close()
+    # dominant kernel of the mixed matvec
+    phases = {k: prof_tot[k][1] / max(mv[1], 1) for k in ("ms_near", "ms_up", "ms_m2l", "ms_down")}
+    dom = max(phases, key=phases.get)
+    if dom == "ms_near":
+        bytes_ = near_pairs * 16 + 2 * N * 8 + 2 * N * 8
+        ach = bytes_ / (phases[dom] * 1e-3) / 1e9
+        roof = {"kernel": "k_spmv<float4> (near-field block SpMV)", "bound": "hbm",
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    else:
+        ach = flops_m2l / (phases["ms_m2l"] * 1e-3) / 1e12
+        roof = {"kernel": "k_m2l<float> (all levels of one matvec)", "bound": "alu",
+                "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}
+    line = {
+        "metric": METRIC, "value": value, "unit": "Mpanels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 operator, f64 accumulation/Krylov", "data": "synthetic",
+        "config": {"workload": "%s: Gaussian isosurface of 20,000 packed atoms, %d panels, "
+                               "%d charges, eps 1/80, kappa 0.1257" % (args.workload, N, len(w["q"])),
+                   **{k: v for k, v in PARAMS.items()}},
+        "roofline": roof,
+        "matvec_ms": {"mixed_fp32": mv32_ms, "fp64": mv64_ms,
+                      "mixed_phases": phases,
+                      "fp64_phases": {k: p64[k][0] / max(p64["matvecs"][0], 1)
+                                      for k in ("ms_near", "ms_up", "ms_m2l", "ms_down")}},
+        "matvec_mpanels_fp64": N / (mv64_ms * 1e-3) / 1e6,
+        "time_to_solve_ms": {"mixed": float(np.median([s["total_ms"] for s in steps])),
+                             "fp64": st64["total_ms"]},
+        "solve_breakdown_mixed": steps[-1], "solve_breakdown_fp64": st64,
+        "energy_kcal": {"mixed": E_mixed, "fp64": st64["E"],
+                        "rel_diff": abs(E_mixed - st64["E"]) / abs(st64["E"])},
+        "mlp": "not used in this measurement",
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,17 @@ typedef struct fagbi_solve_info {
   double t_rhs_ms, t_solve_ms;
 } fagbi_solve_info;
 
+/* Per-phase matvec timings from HIP events recorded on the caller's stream
+   around each phase (index 0: FAGBI_FP64, 1: FAGBI_MIXED). */
+typedef struct fagbi_profile {
+  int64_t matvecs[2];
+  double ms_total[2];          /* whole matvec */
+  double ms_near[2];           /* near-field block SpMV (incl. identity terms) */
+  double ms_up[2];             /* P2M + MtM */
+  double ms_m2l[2];            /* MtL, all levels */
+  double ms_down[2];           /* LtL + LtP */
+} fagbi_profile;
+
 typedef struct fagbi_handle fagbi_handle;
 
 /* Fill *p with the defaults: eps 1/80, kappa 0.1257, eta0 0.8, leaf 32,
@@ -163,6 +174,14 @@ int fagbi_solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
 int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
                            const double* q, int64_t nc, double* E_kcal,
                            void* stream);
+
+/* Turn per-phase matvec timing on (1) or off (0); turning it on resets the
+   counters.  While on, every matvec waits for its last phase to finish
+   (one host synchronisation per matvec). */
+int fagbi_set_profiling(fagbi_handle* h, int32_t on);
+
+/* Accumulated per-phase timings since profiling was turned on. */
+int fagbi_get_profile(fagbi_handle* h, fagbi_profile* out);
 
 /* Tree statistics (after fagbi_build_tree; near-field counts after assembly). */
 int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info);

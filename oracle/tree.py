@@ -8,9 +8,12 @@ Readings of points the paper leaves open (one choice, used everywhere):
   * a panel sits in cube floor((c - corner) / h_l) of level l (h_l = side/2^l),
     clamped to [0, 2^l - 1];
   * cluster centre x_c = the cube centre, and one radius per level,
-    rho_l = max over level-l clusters of the farthest vertex of a member panel
-    from the cube centre (so the separation ratio of two level-l clusters is
-    2 rho_l / |x_c - x_c'| and depends only on their index offset);
+    rho_l = max over level-l clusters of the farthest quadrature point of a
+    member panel from the cube centre (so the separation ratio of two level-l
+    clusters is 2 rho_l / |x_c - x_c'| and depends only on their index
+    offset).  The far field is the FMM of the 3-point-rule interaction, whose
+    sources and targets are exactly these points, so this radius bounds every
+    point the expansions are evaluated at;
   * c' is a neighbour of c iff it is a child of a neighbour of c's parent and
     eta(c, c') > eta0 (c is its own neighbour); the interaction list I(c) holds
     the other children of the parent's neighbours.
@@ -68,9 +71,10 @@ def build(P, leaf_size=32, eta0=0.8, max_level=20):
         idx = idxS[start] >> (L - lev)
         h = side / float(2 ** lev)
         ctr = corner + (idx + 0.5) * h
-        # radius: farthest vertex of a member panel from its cube centre
+        # radius: farthest quadrature point of a member panel from its cube
+        # centre (the far field only ever evaluates the 3-point rule)
         memb = np.repeat(np.arange(len(start)), end - start)
-        vv = P.corners[perm]                              # [N,3,3]
+        vv = P.qp[perm]                                   # [N,3,3]
         dist = np.linalg.norm(vv - ctr[memb][:, None, :], axis=2)
         levels.append(SimpleNamespace(level=lev, start=start, end=end, idx=idx,
                                       h=h, center=ctr, rho=dist.max(),

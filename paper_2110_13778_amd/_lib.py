@@ -23,7 +23,8 @@ EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
            "fagbi_assemble_nearfield", "fagbi_matvec", "fagbi_matvec_parts",
            "fagbi_precond_apply", "fagbi_rhs", "fagbi_solve",
            "fagbi_solvation_energy", "fagbi_get_tree_info",
-           "fagbi_get_permutation", "fagbi_destroy", "fagbi_last_error"]
+           "fagbi_get_permutation", "fagbi_set_profiling", "fagbi_get_profile",
+           "fagbi_destroy", "fagbi_last_error"]
 
 
 class Params(C.Structure):
@@ -50,6 +51,12 @@ class SolveInfo(C.Structure):
                 ("matvecs_fp64", C.c_int32), ("matvecs_fp32", C.c_int32),
                 ("rel_residual", C.c_double), ("t_rhs_ms", C.c_double),
                 ("t_solve_ms", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("matvecs", C.c_int64 * 2), ("ms_total", C.c_double * 2),
+                ("ms_near", C.c_double * 2), ("ms_up", C.c_double * 2),
+                ("ms_m2l", C.c_double * 2), ("ms_down", C.c_double * 2)]
 
 
 class FagbiError(RuntimeError):
@@ -83,6 +90,8 @@ def load():
         "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
         "fagbi_get_tree_info": [vp, C.POINTER(TreeInfo)],
         "fagbi_get_permutation": [vp, vp],
+        "fagbi_set_profiling": [vp, i32],
+        "fagbi_get_profile": [vp, C.POINTER(Profile)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -200,6 +209,14 @@ class Handle:
         ti = TreeInfo()
         _check(self.lib.fagbi_get_tree_info(self.h, C.byref(ti)))
         return ti
+
+    def set_profiling(self, on):
+        _check(self.lib.fagbi_set_profiling(self.h, 1 if on else 0))
+
+    def profile(self):
+        p = Profile()
+        _check(self.lib.fagbi_get_profile(self.h, C.byref(p)))
+        return {k: list(getattr(p, k)) for k, _ in Profile._fields_}
 
     def permutation(self):
         p = np.zeros(self.n, np.int32)

@@ -146,8 +146,8 @@ static int check_params(const fagbi_params* p) {
     return set_error(FAGBI_E_ARG, "eta0 must be >= 0 and leaf_size >= 1");
   if (p->leaf_size > 32)
     return set_error(FAGBI_E_ARG, "leaf_size must be <= 32 (preconditioner blocks <= 64)");
-  if (p->p_leaf < 0 || p->p_leaf > PMAX || p->p_max < p->p_leaf || p->p_max > PMAX)
-    return set_error(FAGBI_E_ARG, "need 0 <= p_leaf <= p_max <= %d", PMAX);
+  if (p->p_leaf < 0 || p->p_max < p->p_leaf || p->p_max > 8)
+    return set_error(FAGBI_E_ARG, "need 0 <= p_leaf <= p_max <= 8");
   if (p->quad_duffy < 1 || p->quad_duffy > 16)
     return set_error(FAGBI_E_ARG, "quad_duffy must be in [1, 16]");
   if (!(p->near_ratio >= 0)) return set_error(FAGBI_E_ARG, "near_ratio must be >= 0");
@@ -192,6 +192,8 @@ void fagbi_destroy(fagbi_handle* h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   h->free_all();
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -387,6 +389,19 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
   info->order_root = h->lev[0].order;
   info->rho_leaf = h->lev[h->L].rho;
   info->h_leaf = h->lev[h->L].h;
+  return 0;
+}
+
+int fagbi_set_profiling(fagbi_handle* h, int32_t on) {
+  if (!h) return set_error(FAGBI_E_ARG, "null handle");
+  h->profiling = on != 0;
+  if (h->profiling) h->prof = fagbi_profile{};
+  return 0;
+}
+
+int fagbi_get_profile(fagbi_handle* h, fagbi_profile* out) {
+  if (!h || !out) return set_error(FAGBI_E_ARG, "null argument");
+  *out = h->prof;
   return 0;
 }
 

@@ -17,6 +17,14 @@
 //    its children's moments of order p_{l+1}, and shifted parent locals are
 //    truncated to p_{l+1};
 //  * leaf moments use the 3-point rule of the regular near field.
+//
+// Translation kernels work on "slots": every coupled pair (alpha, beta) of a
+// translation is one slot with its coefficient held in a register; a
+// 256-thread block owns one output cluster, its threads own fixed slots (so
+// the triangular truncation is evenly spread), input rows are staged in LDS
+// and each output coefficient is a fixed-order sum over its slots
+// (deterministic in FP64).
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -28,8 +36,6 @@ __host__ __device__ inline int midx(int a, int b, int c) {
   const int below = d * (d + 1) * (d + 2) / 6;
   return below + (d - a) * (d - a + 1) / 2 + (d - a - b);
 }
-
-__constant__ double c_binom[PMAX + 1][PMAX + 1];
 
 // ---------------------------------------------------------------------------
 // host: Taylor coefficients by the recurrence (derived from
@@ -80,13 +86,26 @@ static double fact(int n) {
   return f;
 }
 
+static double binom(int n, int k) { return fact(n) / (fact(k) * fact(n - k)); }
+
+struct MI {
+  int a[3];
+};
+static MI mi_of(int t) {
+  static const std::vector<MI> tab = [] {
+    std::vector<MI> v(TMAX);
+    for (int d = 0; d <= PMAX; ++d)
+      for (int a = d; a >= 0; --a)
+        for (int b = d - a; b >= 0; --b) v[midx(a, b, d - a - b)] = MI{{a, b, d - a - b}};
+    return v;
+  }();
+  return tab[t];
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-struct MiTab {
-  const int8_t* mi;       // [TMAX][3]
-  const int16_t* gidx;    // [TMAX][TMAX] index of alpha+beta, -1 if |.| > PMAX
-};
+constexpr int TB = 256;   // threads per translation block
 
 // single/double layer moments of each panel about its leaf centre
 template <typename R>
@@ -125,114 +144,209 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
   md[g] = (R)dsum;
 }
 
-// P2M: one block per leaf, threads over terms
+// P2M: one thread per (leaf, term)
 template <typename R>
-__global__ void k_p2m(const R* __restrict__ ms, const R* __restrict__ md, const int32_t* leaf_start,
-                      const int32_t* leaf_cnt, const int32_t* __restrict__ perm, int64_t N, int T,
-                      double eps, const double* __restrict__ x, R* M0, R* Mk) {
-  const int c = blockIdx.x;
+__global__ void k_p2m(const R* __restrict__ ms, const R* __restrict__ md, const int32_t* __restrict__ leaf_start,
+                      const int32_t* __restrict__ leaf_cnt, const int32_t* __restrict__ perm, int64_t N, int nl,
+                      int T, double eps, const double* __restrict__ x, R* M0, R* Mk) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nl * T) return;
+  const int c = (int)(g / T), t = (int)(g - (int64_t)c * T);
   const int i0 = leaf_start[c], n = leaf_cnt[c];
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
-    R a0 = 0, ak = 0;
-    for (int i = i0; i < i0 + n; ++i) {
-      const int p = perm[i];
-      const R phi = (R)x[p], dphi = (R)x[N + p];
-      const R s = ms[(int64_t)i * T + t], d = md[(int64_t)i * T + t];
-      a0 += s * dphi - d * phi;
-      ak += -s * dphi + (R)eps * d * phi;
-    }
-    M0[(int64_t)c * T + t] = a0;
-    Mk[(int64_t)c * T + t] = ak;
+  R a0 = 0, ak = 0;
+  for (int i = i0; i < i0 + n; ++i) {
+    const int p = perm[i];
+    const R phi = (R)x[p], dphi = (R)x[N + p];
+    const R s = ms[(int64_t)i * T + t], d = md[(int64_t)i * T + t];
+    a0 += s * dphi - d * phi;
+    ak += -s * dphi + (R)eps * d * phi;
   }
+  M0[g] = a0;
+  Mk[g] = ak;
 }
 
-// MtM: parent^alpha = sum_children sum_{beta <= alpha, |beta| <= p_child}
-//        C(alpha, beta) d^(alpha - beta) child^beta
+// reduce per-slot partial sums (red0/redk, nslot each, slots grouped by
+// output index) into out[t] for t < Tout, fixed order
 template <typename R>
-__global__ void k_m2m(const int32_t* child_start, const int32_t* child_end, const int32_t* cidx,
-                      double hc, int Tp, int pc, int Tc, const int8_t* __restrict__ mi,
-                      const R* __restrict__ C0, const R* __restrict__ Ck, R* P0, R* Pk) {
-  const int c = blockIdx.x;
-  for (int t = threadIdx.x; t < Tp; t += blockDim.x) {
-    const int a[3] = {mi[3 * t], mi[3 * t + 1], mi[3 * t + 2]};
+__device__ inline void slot_reduce(const R* red0, const R* redk, const int32_t* __restrict__ off, int Tout,
+                                   R* out0, R* outk, bool accumulate) {
+  for (int t = threadIdx.x; t < Tout; t += TB) {
     R s0 = 0, sk = 0;
-    for (int ch = child_start[c]; ch < child_end[c]; ++ch) {
-      double d[3];
-      for (int ax = 0; ax < 3; ++ax) d[ax] = ((cidx[3 * ch + ax] & 1) - 0.5) * hc;
-      for (int b0 = 0; b0 <= a[0]; ++b0)
-        for (int b1 = 0; b1 <= a[1]; ++b1)
-          for (int b2 = 0; b2 <= a[2] && b0 + b1 + b2 <= pc; ++b2) {
-            double coef = c_binom[a[0]][b0] * c_binom[a[1]][b1] * c_binom[a[2]][b2];
-            for (int q = 0; q < a[0] - b0; ++q) coef *= d[0];
-            for (int q = 0; q < a[1] - b1; ++q) coef *= d[1];
-            for (int q = 0; q < a[2] - b2; ++q) coef *= d[2];
-            const int bi = midx(b0, b1, b2);
-            s0 += (R)coef * C0[(int64_t)ch * Tc + bi];
-            sk += (R)coef * Ck[(int64_t)ch * Tc + bi];
-          }
+    for (int k = off[t]; k < off[t + 1]; ++k) {
+      s0 += red0[k];
+      sk += redk[k];
     }
-    P0[(int64_t)c * Tp + t] = s0;
-    Pk[(int64_t)c * Tp + t] = sk;
+    if (accumulate) {
+      out0[t] += s0;
+      outk[t] += sk;
+    } else {
+      out0[t] = s0;
+      outk[t] = sk;
+    }
   }
 }
 
-// MtL: one block per target cluster, threads over alpha
-template <typename R>
-__global__ void k_m2l(const int32_t* __restrict__ inter_off, const int32_t* __restrict__ inter_src,
-                      const int32_t* __restrict__ inter_oid, const R* __restrict__ F0,
-                      const R* __restrict__ Fk, const R* __restrict__ coef, const int16_t* __restrict__ gidx,
-                      const int8_t* __restrict__ mi, int p, int T, const R* __restrict__ M0,
-                      const R* __restrict__ Mk, R* L0, R* Lk) {
+// MtL: one block per target cluster.  slot = (g | b << 16): g the index of
+// alpha+beta, b the index of beta; slots sorted by alpha (aoff).
+template <typename R, int SPT>
+__global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_off, const int32_t* __restrict__ inter_src,
+                                            const int32_t* __restrict__ inter_oid, const R* __restrict__ F0,
+                                            const R* __restrict__ Fk, const int32_t* __restrict__ slot,
+                                            const R* __restrict__ coef, const int32_t* __restrict__ aoff, int nslot,
+                                            int T, int batch, const R* __restrict__ M0, const R* __restrict__ Mk,
+                                            R* L0, R* Lk) {
+  extern __shared__ char smem_raw[];
+  R* sm = reinterpret_cast<R*>(smem_raw);
   const int c = blockIdx.x;
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
-    const int da = mi[3 * t] + mi[3 * t + 1] + mi[3 * t + 2];
-    const int nb = nterms(p - da);
-    R l0 = 0, lk = 0;
-    for (int q = inter_off[c]; q < inter_off[c + 1]; ++q) {
-      const int src = inter_src[q];
-      const R* f0 = F0 + (int64_t)inter_oid[q] * T;
-      const R* fk = Fk + (int64_t)inter_oid[q] * T;
-      const R* m0 = M0 + (int64_t)src * T;
-      const R* mk = Mk + (int64_t)src * T;
-      for (int b = 0; b < nb; ++b) {
-        const int g = gidx[t * TMAX + b];
-        const R cf = coef[t * TMAX + b];
-        l0 += cf * f0[g] * m0[b];
-        lk += cf * fk[g] * mk[b];
+  const int tid = threadIdx.x;
+  int sg[SPT], sb[SPT];
+  R cf[SPT], a0[SPT], ak[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    const int v = k < nslot ? slot[k] : 0;
+    sg[j] = v & 0xffff;
+    sb[j] = v >> 16;
+    cf[j] = k < nslot ? coef[k] : (R)0;
+    a0[j] = 0;
+    ak[j] = 0;
+  }
+  const int q0 = inter_off[c], q1 = inter_off[c + 1];
+  const int W = 4 * T;   // row stride of one staged source: F0, Fk, M0, Mk
+  for (int qb = q0; qb < q1; qb += batch) {
+    const int nb = min(batch, q1 - qb);
+    __syncthreads();
+    for (int e = tid; e < nb * T; e += TB) {
+      const int s = e / T, t = e - s * T;
+      const int q = qb + s;
+      const int64_t fo = (int64_t)inter_oid[q] * T + t;
+      const int64_t mo = (int64_t)inter_src[q] * T + t;
+      R* row = sm + s * W;
+      row[t] = F0[fo];
+      row[T + t] = Fk[fo];
+      row[2 * T + t] = M0[mo];
+      row[3 * T + t] = Mk[mo];
+    }
+    __syncthreads();
+    for (int s = 0; s < nb; ++s) {
+      const R* row = sm + s * W;
+#pragma unroll
+      for (int j = 0; j < SPT; ++j) {
+        a0[j] += cf[j] * row[sg[j]] * row[2 * T + sb[j]];
+        ak[j] += cf[j] * row[T + sg[j]] * row[3 * T + sb[j]];
       }
     }
-    L0[(int64_t)c * T + t] += l0;
-    Lk[(int64_t)c * T + t] += lk;
   }
+  __syncthreads();
+  R* red0 = sm;
+  R* redk = sm + nslot;
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    if (k < nslot) {
+      red0[k] = a0[j];
+      redk[k] = ak[j];
+    }
+  }
+  __syncthreads();
+  slot_reduce<R>(red0, redk, aoff, T, L0 + (int64_t)c * T, Lk + (int64_t)c * T, true);
 }
 
-// LtL: child^beta += sum_{alpha >= beta, |alpha| <= p_parent} C(alpha,beta) d^(alpha-beta) parent^alpha
-template <typename R>
-__global__ void k_l2l(const int32_t* parent, const int32_t* cidx, double hc, int pp, int Tp, int Tc,
-                      const int8_t* __restrict__ mi, const R* __restrict__ P0, const R* __restrict__ Pk,
-                      R* C0, R* Ck) {
+// MtM: one block per parent; slot = (a | b << 16), a parent index, b child
+// index (b <= a componentwise); coefficient rows per child octant.
+template <typename R, int SPT>
+__global__ void __launch_bounds__(TB) k_m2m(const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_end,
+                                            const int32_t* __restrict__ cidx, const int32_t* __restrict__ slot,
+                                            const R* __restrict__ coef, const int32_t* __restrict__ aoff, int nslot,
+                                            int Tp, int Tc, const R* __restrict__ C0, const R* __restrict__ Ck,
+                                            R* P0, R* Pk) {
+  extern __shared__ char smem_raw[];
+  R* sm = reinterpret_cast<R*>(smem_raw);
   const int c = blockIdx.x;
-  const int par = parent[c];
-  double d[3];
-  for (int ax = 0; ax < 3; ++ax) d[ax] = ((cidx[3 * c + ax] & 1) - 0.5) * hc;
-  for (int t = threadIdx.x; t < Tc; t += blockDim.x) {
-    const int b[3] = {mi[3 * t], mi[3 * t + 1], mi[3 * t + 2]};
-    const int db = b[0] + b[1] + b[2];
-    R s0 = 0, sk = 0;
-    for (int g0 = 0; g0 <= pp - db; ++g0)
-      for (int g1 = 0; g0 + g1 <= pp - db; ++g1)
-        for (int g2 = 0; g0 + g1 + g2 <= pp - db; ++g2) {
-          double coef = c_binom[b[0] + g0][b[0]] * c_binom[b[1] + g1][b[1]] * c_binom[b[2] + g2][b[2]];
-          for (int q = 0; q < g0; ++q) coef *= d[0];
-          for (int q = 0; q < g1; ++q) coef *= d[1];
-          for (int q = 0; q < g2; ++q) coef *= d[2];
-          const int ai = midx(b[0] + g0, b[1] + g1, b[2] + g2);
-          s0 += (R)coef * P0[(int64_t)par * Tp + ai];
-          sk += (R)coef * Pk[(int64_t)par * Tp + ai];
-        }
-    C0[(int64_t)c * Tc + t] += s0;
-    Ck[(int64_t)c * Tc + t] += sk;
+  const int tid = threadIdx.x;
+  int sb[SPT];
+  R a0[SPT], ak[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    sb[j] = k < nslot ? (slot[k] >> 16) : 0;
+    a0[j] = 0;
+    ak[j] = 0;
   }
+  const int c0 = child_start[c], c1 = child_end[c];
+  for (int e = tid; e < (c1 - c0) * Tc; e += TB) {
+    const int s = e / Tc, t = e - s * Tc;
+    sm[s * 2 * Tc + t] = C0[(int64_t)(c0 + s) * Tc + t];
+    sm[s * 2 * Tc + Tc + t] = Ck[(int64_t)(c0 + s) * Tc + t];
+  }
+  __syncthreads();
+  for (int ch = c0; ch < c1; ++ch) {
+    const int oct = ((cidx[3 * ch] & 1) << 2) | ((cidx[3 * ch + 1] & 1) << 1) | (cidx[3 * ch + 2] & 1);
+    const R* row = sm + (ch - c0) * 2 * Tc;
+    const R* cr = coef + (int64_t)oct * nslot;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int k = tid + j * TB;
+      const R w = k < nslot ? cr[k] : (R)0;
+      a0[j] += w * row[sb[j]];
+      ak[j] += w * row[Tc + sb[j]];
+    }
+  }
+  __syncthreads();
+  R* red0 = sm;
+  R* redk = sm + nslot;
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    if (k < nslot) {
+      red0[k] = a0[j];
+      redk[k] = ak[j];
+    }
+  }
+  __syncthreads();
+  slot_reduce<R>(red0, redk, aoff, Tp, P0 + (int64_t)c * Tp, Pk + (int64_t)c * Tp, false);
+}
+
+// LtL: one block per child; slot = (a | b << 16) sorted by b (child index)
+template <typename R, int SPT>
+__global__ void __launch_bounds__(TB) k_l2l(const int32_t* __restrict__ parent, const int32_t* __restrict__ cidx,
+                                            const int32_t* __restrict__ slot, const R* __restrict__ coef,
+                                            const int32_t* __restrict__ boff, int nslot, int Tp, int Tc,
+                                            const R* __restrict__ P0, const R* __restrict__ Pk, R* C0, R* Ck) {
+  extern __shared__ char smem_raw[];
+  R* sm = reinterpret_cast<R*>(smem_raw);
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int par = parent[c];
+  const int oct = ((cidx[3 * c] & 1) << 2) | ((cidx[3 * c + 1] & 1) << 1) | (cidx[3 * c + 2] & 1);
+  for (int t = tid; t < Tp; t += TB) {
+    sm[t] = P0[(int64_t)par * Tp + t];
+    sm[Tp + t] = Pk[(int64_t)par * Tp + t];
+  }
+  __syncthreads();
+  const R* cr = coef + (int64_t)oct * nslot;
+  R a0[SPT], ak[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    const int a = k < nslot ? (slot[k] & 0xffff) : 0;
+    const R w = k < nslot ? cr[k] : (R)0;
+    a0[j] = w * sm[a];
+    ak[j] = w * sm[Tp + a];
+  }
+  __syncthreads();
+  R* red0 = sm;
+  R* redk = sm + nslot;
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int k = tid + j * TB;
+    if (k < nslot) {
+      red0[k] = a0[j];
+      redk[k] = ak[j];
+    }
+  }
+  __syncthreads();
+  slot_reduce<R>(red0, redk, boff, Tc, C0 + (int64_t)c * Tc, Ck + (int64_t)c * Tc, true);
 }
 
 // LtP: far-field contribution of each panel, added to y (caller order)
@@ -289,7 +403,7 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
 }
 
 // ---------------------------------------------------------------------------
-// setup: translation tables, Taylor tables per (level, offset), moments
+// setup: slot tables, Taylor tables per (level, offset), moments
 // ---------------------------------------------------------------------------
 template <typename R>
 static int upload_conv(fagbi_handle* h, DBuf& b, const std::vector<double>& v) {
@@ -297,57 +411,116 @@ static int upload_conv(fagbi_handle* h, DBuf& b, const std::vector<double>& v) {
   return h->upload(b, t.data(), t.size() * sizeof(R));
 }
 
+static int spt_of(int nslot) {
+  const int s = (nslot + TB - 1) / TB;
+  return s <= 1 ? 1 : s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;
+}
+
 int fmm_setup(fagbi_handle* h, hipStream_t s) {
-  // multi-index tables
   std::vector<int8_t> mi(3 * TMAX);
-  for (int d = 0; d <= PMAX; ++d)
-    for (int a = d; a >= 0; --a)
-      for (int b = d - a; b >= 0; --b) {
-        const int t = midx(a, b, d - a - b);
-        mi[3 * t] = (int8_t)a;
-        mi[3 * t + 1] = (int8_t)b;
-        mi[3 * t + 2] = (int8_t)(d - a - b);
-      }
-  std::vector<int16_t> gidx((size_t)TMAX * TMAX, -1);
-  std::vector<double> coef((size_t)TMAX * TMAX, 0.0);
-  for (int t = 0; t < TMAX; ++t)
-    for (int u = 0; u < TMAX; ++u) {
-      const int a0 = mi[3 * t], a1 = mi[3 * t + 1], a2 = mi[3 * t + 2];
-      const int b0 = mi[3 * u], b1 = mi[3 * u + 1], b2 = mi[3 * u + 2];
-      if (a0 + a1 + a2 + b0 + b1 + b2 > PMAX) continue;
-      gidx[(size_t)t * TMAX + u] = (int16_t)midx(a0 + b0, a1 + b1, a2 + b2);
-      const double num = fact(a0 + b0) * fact(a1 + b1) * fact(a2 + b2);
-      const double den = fact(a0) * fact(a1) * fact(a2) * fact(b0) * fact(b1) * fact(b2);
-      const double sg = ((b0 + b1 + b2) & 1) ? -1.0 : 1.0;
-      coef[(size_t)t * TMAX + u] = sg * num / den / FOUR_PI;
-    }
+  for (int t = 0; t < TMAX; ++t) {
+    const MI m = mi_of(t);
+    for (int d = 0; d < 3; ++d) mi[3 * t + d] = (int8_t)m.a[d];
+  }
   FAGBI_TRY(h->upload(h->d_mi, mi.data(), mi.size()));
-  FAGBI_TRY(h->upload(h->d_gidx, gidx.data(), gidx.size() * 2));
-  FAGBI_TRY(upload_conv<double>(h, h->d_coef64, coef));
-  FAGBI_TRY(upload_conv<float>(h, h->d_coef32, coef));
-  double binom[PMAX + 1][PMAX + 1] = {};
-  for (int n = 0; n <= PMAX; ++n) {
-    binom[n][0] = 1;
-    for (int k = 1; k <= n; ++k) binom[n][k] = binom[n - 1][k - 1] + (k <= n - 1 ? binom[n - 1][k] : 0);
-  }
-  FAGBI_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), binom, sizeof binom));
-  // Taylor tables per (level, offset) for G0 and Gk
-  for (int l = h->lmin; l <= h->L; ++l) {
+  const int lo = std::min(h->lmin, h->L);
+  for (int l = lo; l <= h->L; ++l) {
     Level& D = h->lev[l];
-    if (D.n_off == 0) continue;
-    std::vector<double> f0((size_t)D.n_off * D.T), fk((size_t)D.n_off * D.T);
-    for (int o = 0; o < D.n_off; ++o) {
-      const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h, D.off_xyz[3 * o + 2] * D.h};
-      taylor_host(x0, 0.0, D.order, f0.data() + (size_t)o * D.T);
-      taylor_host(x0, h->prm.kappa, D.order, fk.data() + (size_t)o * D.T);
+    // MtL slots: (alpha, beta), |alpha| + |beta| <= p, grouped by alpha
+    if (l >= h->lmin) {
+      std::vector<int32_t> slot, aoff(1, 0);
+      std::vector<double> cf;
+      for (int ta = 0; ta < D.T; ++ta) {
+        const MI A = mi_of(ta);
+        const int da = A.a[0] + A.a[1] + A.a[2];
+        for (int tb = 0; tb < nterms(D.order - da); ++tb) {
+          const MI B = mi_of(tb);
+          const int g = midx(A.a[0] + B.a[0], A.a[1] + B.a[1], A.a[2] + B.a[2]);
+          slot.push_back(g | (tb << 16));
+          const double num = fact(A.a[0] + B.a[0]) * fact(A.a[1] + B.a[1]) * fact(A.a[2] + B.a[2]);
+          const double den = fact(A.a[0]) * fact(A.a[1]) * fact(A.a[2]) * fact(B.a[0]) * fact(B.a[1]) * fact(B.a[2]);
+          const double sg = ((B.a[0] + B.a[1] + B.a[2]) & 1) ? -1.0 : 1.0;
+          cf.push_back(sg * num / den / FOUR_PI);
+        }
+        aoff.push_back((int32_t)slot.size());
+      }
+      D.m2l_nslot = (int)slot.size();
+      FAGBI_TRY(h->upload(D.d_m2l_slot, slot.data(), slot.size() * 4));
+      FAGBI_TRY(h->upload(D.d_m2l_aoff, aoff.data(), aoff.size() * 4));
+      FAGBI_TRY(upload_conv<double>(h, D.d_m2l_c64, cf));
+      FAGBI_TRY(upload_conv<float>(h, D.d_m2l_c32, cf));
     }
-    FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], f0));
-    FAGBI_TRY(upload_conv<double>(h, D.d_F64[1], fk));
-    FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], f0));
-    FAGBI_TRY(upload_conv<float>(h, D.d_F32[1], fk));
-  }
-  for (int l = std::min(h->lmin, h->L); l <= h->L; ++l) {
-    Level& D = h->lev[l];
+    // shifts between level l (parent, order p_l) and l+1 (child, p_{l+1})
+    if (l < h->L) {
+      const Level& C = h->lev[l + 1];
+      struct P2 {
+        int a, b;
+      };
+      std::vector<P2> pairs;
+      for (int ta = 0; ta < D.T; ++ta)
+        for (int tb = 0; tb < C.T; ++tb) {
+          const MI A = mi_of(ta), B = mi_of(tb);
+          if (B.a[0] <= A.a[0] && B.a[1] <= A.a[1] && B.a[2] <= A.a[2]) pairs.push_back({ta, tb});
+        }
+      auto coef = [&](const P2& q, int oct) {
+        const MI A = mi_of(q.a), B = mi_of(q.b);
+        double v = 1.0;
+        for (int ax = 0; ax < 3; ++ax) {
+          const double d = (((oct >> (2 - ax)) & 1) - 0.5) * C.h;   // child centre - parent centre
+          v *= binom(A.a[ax], B.a[ax]) * std::pow(d, A.a[ax] - B.a[ax]);
+        }
+        return v;
+      };
+      // MtM: grouped by parent index a (pairs are generated in a order)
+      {
+        std::vector<int32_t> slot, aoff(D.T + 1, 0);
+        std::vector<double> cf(8 * pairs.size());
+        for (size_t k = 0; k < pairs.size(); ++k) {
+          slot.push_back(pairs[k].a | (pairs[k].b << 16));
+          aoff[pairs[k].a + 1] = (int32_t)(k + 1);
+        }
+        for (int t = 1; t <= D.T; ++t) aoff[t] = std::max(aoff[t], aoff[t - 1]);
+        for (int oct = 0; oct < 8; ++oct)
+          for (size_t k = 0; k < pairs.size(); ++k) cf[oct * pairs.size() + k] = coef(pairs[k], oct);
+        D.up_nslot = (int)pairs.size();
+        FAGBI_TRY(h->upload(D.d_up_slot, slot.data(), slot.size() * 4));
+        FAGBI_TRY(h->upload(D.d_up_aoff, aoff.data(), aoff.size() * 4));
+        FAGBI_TRY(upload_conv<double>(h, D.d_up_c64, cf));
+        FAGBI_TRY(upload_conv<float>(h, D.d_up_c32, cf));
+      }
+      // LtL: grouped by child index b
+      {
+        std::vector<P2> byb(pairs);
+        std::stable_sort(byb.begin(), byb.end(), [](const P2& x, const P2& y) { return x.b < y.b; });
+        std::vector<int32_t> slot, boff(C.T + 1, 0);
+        std::vector<double> cf(8 * byb.size());
+        for (size_t k = 0; k < byb.size(); ++k) {
+          slot.push_back(byb[k].a | (byb[k].b << 16));
+          boff[byb[k].b + 1] = (int32_t)(k + 1);
+        }
+        for (int t = 1; t <= C.T; ++t) boff[t] = std::max(boff[t], boff[t - 1]);
+        for (int oct = 0; oct < 8; ++oct)
+          for (size_t k = 0; k < byb.size(); ++k) cf[oct * byb.size() + k] = coef(byb[k], oct);
+        D.dn_nslot = (int)byb.size();
+        FAGBI_TRY(h->upload(D.d_dn_slot, slot.data(), slot.size() * 4));
+        FAGBI_TRY(h->upload(D.d_dn_boff, boff.data(), boff.size() * 4));
+        FAGBI_TRY(upload_conv<double>(h, D.d_dn_c64, cf));
+        FAGBI_TRY(upload_conv<float>(h, D.d_dn_c32, cf));
+      }
+    }
+    // Taylor tables per offset for G0 and Gk
+    if (l >= h->lmin && D.n_off > 0) {
+      std::vector<double> f0((size_t)D.n_off * D.T), fk((size_t)D.n_off * D.T);
+      for (int o = 0; o < D.n_off; ++o) {
+        const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h, D.off_xyz[3 * o + 2] * D.h};
+        taylor_host(x0, 0.0, D.order, f0.data() + (size_t)o * D.T);
+        taylor_host(x0, h->prm.kappa, D.order, fk.data() + (size_t)o * D.T);
+      }
+      FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], f0));
+      FAGBI_TRY(upload_conv<double>(h, D.d_F64[1], fk));
+      FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], f0));
+      FAGBI_TRY(upload_conv<float>(h, D.d_F32[1], fk));
+    }
     for (int ch = 0; ch < 2; ++ch) {
       FAGBI_TRY(h->alloc(D.d_M64[ch], (size_t)D.n * D.T * 8));
       FAGBI_TRY(h->alloc(D.d_L64[ch], (size_t)D.n * D.T * 8));
@@ -378,11 +551,27 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
   return 0;
 }
 
+// launch helpers dispatching on slots per thread
+#define FAGBI_SPT_SWITCH(spt, KER, GRID, SH, STREAM, ...)                  \
+  switch (spt) {                                                            \
+    case 1: KER<R, 1><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;        \
+    case 2: KER<R, 2><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;        \
+    case 4: KER<R, 4><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;        \
+    case 8: KER<R, 8><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;        \
+    default: KER<R, 16><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;      \
+  }
+
 template <typename R, typename E>
 static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipStream_t s,
                     const DBuf& ent, const DBuf& ms, const DBuf& md, bool f32) {
   const int64_t N = h->N;
   const int nl = h->lev[h->L].n;
+  const bool prof = h->profiling;
+  auto mark = [&](int k) -> int {
+    if (prof) FAGBI_HIP(hipEventRecord(h->ev[k], s));
+    return 0;
+  };
+  FAGBI_TRY(mark(0));
   if (parts & FAGBI_PART_NEAR) {
     k_spmv<E><<<(unsigned)((N + 3) / 4), 256, 0, s>>>(
         ent.as<E>(), h->d_leaf_of.as<int32_t>(), h->d_leaf_start.as<int32_t>(), h->d_src_off.as<int64_t>(),
@@ -391,19 +580,36 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   }
   FAGBI_HIP(hipGetLastError());
-  if (!(parts & FAGBI_PART_FAR) || h->lmin > h->L) return 0;
+  FAGBI_TRY(mark(1));
+  const bool far = (parts & FAGBI_PART_FAR) && h->lmin <= h->L;
+  if (!far) {
+    FAGBI_TRY(mark(2));
+    FAGBI_TRY(mark(3));
+    FAGBI_TRY(mark(4));
+    return 0;
+  }
   const double eps = h->prm.eps_out / h->prm.eps_in;
   const int L = h->L;
   auto M = [&](Level& D, int ch) { return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>(); };
   auto Lc = [&](Level& D, int ch) { return f32 ? D.d_L32[ch].as<R>() : D.d_L64[ch].as<R>(); };
+  auto cf = [&](const DBuf& c64, const DBuf& c32) { return f32 ? c32.as<R>() : c64.as<R>(); };
   Level& LF = h->lev[L];
-  k_p2m<R><<<nl, 64, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
-                             h->d_perm.as<int32_t>(), N, LF.T, eps, x, M(LF, 0), M(LF, 1));
+  {
+    const int64_t tot = (int64_t)nl * LF.T;
+    k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_start.as<int32_t>(),
+                                                          h->d_leaf_cnt.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl,
+                                                          LF.T, eps, x, M(LF, 0), M(LF, 1));
+  }
   for (int l = L - 1; l >= h->lmin; --l) {
     Level &P = h->lev[l], &C = h->lev[l + 1];
-    k_m2m<R><<<P.n, 64, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(), C.d_idx.as<int32_t>(),
-                                C.h, P.T, C.order, C.T, h->d_mi.as<int8_t>(), M(C, 0), M(C, 1), M(P, 0), M(P, 1));
+    const size_t sh = std::max<size_t>((size_t)16 * C.T, (size_t)2 * P.up_nslot) * sizeof(R);
+    FAGBI_SPT_SWITCH(spt_of(P.up_nslot), k_m2m, P.n, sh, s, P.d_child_start.as<int32_t>(),
+                     P.d_child_end.as<int32_t>(), C.d_idx.as<int32_t>(), P.d_up_slot.as<int32_t>(),
+                     cf(P.d_up_c64, P.d_up_c32), P.d_up_aoff.as<int32_t>(), P.up_nslot, P.T, C.T, M(C, 0),
+                     M(C, 1), M(P, 0), M(P, 1));
   }
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(mark(2));
   for (int l = h->lmin; l <= L; ++l) {
     Level& D = h->lev[l];
     FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), s));
@@ -411,27 +617,49 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     if (D.n_off == 0) continue;
     const R* F0 = f32 ? D.d_F32[0].as<R>() : D.d_F64[0].as<R>();
     const R* Fk = f32 ? D.d_F32[1].as<R>() : D.d_F64[1].as<R>();
-    const R* cf = f32 ? h->d_coef32.as<R>() : h->d_coef64.as<R>();
-    k_m2l<R><<<D.n, 64, 0, s>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
-                                D.d_inter_oid.as<int32_t>(), F0, Fk, cf, h->d_gidx.as<int16_t>(),
-                                h->d_mi.as<int8_t>(), D.order, D.T, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
+    const int batch = std::max(1, std::min(16, (int)(12288 / (4 * D.T * sizeof(R)))));
+    const size_t sh = std::max<size_t>((size_t)batch * 4 * D.T, (size_t)2 * D.m2l_nslot) * sizeof(R);
+    FAGBI_SPT_SWITCH(spt_of(D.m2l_nslot), k_m2l, D.n, sh, s, D.d_inter_off.as<int32_t>(),
+                     D.d_inter_src.as<int32_t>(), D.d_inter_oid.as<int32_t>(), F0, Fk, D.d_m2l_slot.as<int32_t>(),
+                     cf(D.d_m2l_c64, D.d_m2l_c32), D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, M(D, 0),
+                     M(D, 1), Lc(D, 0), Lc(D, 1));
   }
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(mark(3));
   for (int l = h->lmin; l < L; ++l) {
     Level &P = h->lev[l], &C = h->lev[l + 1];
-    k_l2l<R><<<C.n, 64, 0, s>>>(C.d_parent.as<int32_t>(), C.d_idx.as<int32_t>(), C.h, P.order, P.T, C.T,
-                                h->d_mi.as<int8_t>(), Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
+    const size_t sh = std::max<size_t>((size_t)2 * P.T, (size_t)2 * P.dn_nslot) * sizeof(R);
+    FAGBI_SPT_SWITCH(spt_of(P.dn_nslot), k_l2l, C.n, sh, s, C.d_parent.as<int32_t>(), C.d_idx.as<int32_t>(),
+                     P.d_dn_slot.as<int32_t>(), cf(P.d_dn_c64, P.d_dn_c32), P.d_dn_boff.as<int32_t>(), P.dn_nslot,
+                     P.T, C.T, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
   }
   k_l2p<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_of.as<int32_t>(),
                                                       h->d_perm.as<int32_t>(), (int)N, LF.T, eps, Lc(LF, 0),
                                                       Lc(LF, 1), y);
   FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(mark(4));
   return 0;
 }
 
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts, hipStream_t s) {
-  if (precision == FAGBI_MIXED)
-    return matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true);
-  return matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
+  if (h->profiling && !h->ev[0])
+    for (int k = 0; k < 5; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
+  int r = precision == FAGBI_MIXED
+              ? matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
+              : matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
+  if (r < 0 || !h->profiling) return r;
+  FAGBI_HIP(hipEventSynchronize(h->ev[4]));
+  float t[4];
+  for (int k = 0; k < 4; ++k) FAGBI_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
+  const int p = precision == FAGBI_MIXED ? 1 : 0;
+  fagbi_profile& P = h->prof;
+  P.matvecs[p] += 1;
+  P.ms_near[p] += t[0];
+  P.ms_up[p] += t[1];
+  P.ms_m2l[p] += t[2];
+  P.ms_down[p] += t[3];
+  P.ms_total[p] += t[0] + t[1] + t[2] + t[3];
+  return 0;
 }
 
 }  // namespace fagbi

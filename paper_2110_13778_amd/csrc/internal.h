@@ -75,6 +75,14 @@ struct Level {
   DBuf d_F64[2], d_F32[2];           // Taylor tables per offset [n_off][T], G0 / Gk
   DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
   DBuf d_M32[2], d_L32[2];
+  // slot tables (one slot per coupled pair of multi-indices) of the
+  // translations that start on this level: MtL (|a|+|b| <= p_l), and for the
+  // shifts to the children MtM (sorted by parent index a) and LtL (sorted by
+  // child index b), with one coefficient row per child octant
+  int m2l_nslot = 0, up_nslot = 0, dn_nslot = 0;
+  DBuf d_m2l_slot, d_m2l_aoff, d_m2l_c64, d_m2l_c32;
+  DBuf d_up_slot, d_up_aoff, d_up_c64, d_up_c32;
+  DBuf d_dn_slot, d_dn_boff, d_dn_c64, d_dn_c32;
 };
 
 }  // namespace fagbi
@@ -101,13 +109,17 @@ struct fagbi_handle {
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
-  fagbi::DBuf d_coef64, d_coef32, d_gidx, d_mi; // translation tables
+  fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]
   fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner
   fagbi::DBuf d_gl;                   // Gauss-Legendre nodes/weights on [0,1]
   fagbi::DBuf d_work;                 // scratch for reductions
   // Krylov workspace
   fagbi::DBuf d_V, d_Z, d_w, d_r, d_b, d_x0, d_dots, d_t1, d_t2;
   int krylov_m = 0;
+  // per-phase profiling
+  bool profiling = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);
   int upload(fagbi::DBuf& b, const void* host, size_t bytes);

@@ -208,15 +208,20 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
       ++T.n;
       a = b;
     }
-    // radius: farthest vertex of a member panel from its cube centre
+    // radius: farthest quadrature point (3-point rule: 2/3 of one corner and
+    // 1/6 of the other two) of a member panel from its cube centre; the far
+    // field only ever evaluates the rule at these points
     double rho = 0;
     for (int64_t k = 0; k < N; ++k) {
       const int32_t c = owner[k];
+      const double* cv = &out.corners[9 * k];
       for (int v = 0; v < 3; ++v) {
         double s[3];
         for (int d = 0; d < 3; ++d) {
           double ctr = out.corner[d] + ((double)T.idx[3 * c + d] + 0.5) * T.h;
-          s[d] = out.corners[9 * k + 3 * v + d] - ctr;
+          double qp = (2.0 / 3.0) * cv[3 * v + d] +
+                      (1.0 / 6.0) * (cv[3 * ((v + 1) % 3) + d] + cv[3 * ((v + 2) % 3) + d]);
+          s[d] = qp - ctr;
         }
         double dist = std::sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
         rho = std::max(rho, dist);
