@@ -114,7 +114,8 @@ typedef struct fagbi_handle fagbi_handle;
 
 /* Fill *p with the defaults: eps 1/80, kappa 0.1257, eta0 0.8, leaf 32,
    p_leaf 4 fixed order, p_max 8, quad_duffy 7, near_ratio 2, FP64, block
-   preconditioner, tol 1e-6, max_iter 200, max_outer 5, inner_tol 1e-4. */
+   preconditioner, tol 1e-6, max_iter 200, max_outer 5, inner_tol 5e-7 (one
+   inner solve normally reaches the outer tolerance). */
 int fagbi_default_params(fagbi_params* p);
 
 /* Create a handle on the current device.  *out receives the handle. */

@@ -36,7 +36,10 @@ Rules (n = Gauss-Legendre points per dimension, 7 by default):
   n^4 points per half.
 
 On flat panels I2..I5 of an identical pair vanish identically (r.n = 0); they
-are set to exactly zero.
+are set to exactly zero.  Touching and close pairs are integrated once, for
+the ordering with the lower first index, and the other ordering is filled in
+by the exact symmetries of the kernels (Sec. 2.2: every kernel depends on
+x - y): I1, I6 symmetric, I2 <-> I4 and I3 <-> I5 transposed.
 """
 import numpy as np
 
@@ -224,9 +227,17 @@ def pair_integrals(P, i, j, kappa, near_ratio=2.0, n=7, cls=None, chunk=2048):
              EDGE: (lambda a, b: edge(P, a, b, kappa, n), 1024),
              VERTEX: (lambda a, b: vertex(P, a, b, kappa, n), 256),
              CLOSE: (lambda a, b: close(P, a, b, kappa, n), 128)}
+    # touching and close pairs are integrated for the member with the lower
+    # panel index and mirrored: I1, I6 are symmetric and I2/I4, I3/I5 swap
+    # (the kernels depend on x - y only), which the cubature would otherwise
+    # satisfy only to its own error
+    mirror = (cls >= EDGE) & (i > j)
+    a = np.where(mirror, j, i)
+    b = np.where(mirror, i, j)
     for c, (fn, ch) in rules.items():
         sel = np.nonzero(cls == c)[0]
         for s in range(0, len(sel), ch):
             k = sel[s:s + ch]
-            out[k] = fn(i[k], j[k])
+            out[k] = fn(a[k], b[k])
+    out[mirror] = out[mirror][:, [0, 3, 4, 1, 2, 5]]
     return out, cls

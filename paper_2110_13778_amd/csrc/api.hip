@@ -133,7 +133,7 @@ int fagbi_default_params(fagbi_params* p) {
   p->tol = 1e-6;
   p->max_iter = 200;
   p->max_outer = 5;
-  p->inner_tol = 1e-4;
+  p->inner_tol = 5e-7;
   p->mlp_mode = FAGBI_MLP_OFF;
   p->mlp_gate_tol = 1e-3;
   return 0;
@@ -302,6 +302,19 @@ int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int
   FAGBI_TRY(h->upload(h->d_src_off, h->src_off.data(), (nl + 1) * 8));
   FAGBI_TRY(h->upload(h->d_ent_off, h->ent_off.data(), (nl + 1) * 8));
   FAGBI_TRY(h->upload(h->d_self_col, h->self_col.data(), nl * 4));
+  {
+    std::vector<int32_t> col(LF.nbr.size());
+    for (int c = 0; c < nl; ++c) {
+      int32_t s = 0;
+      for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
+        col[q] = s;
+        s += h->leaf_cnt[LF.nbr[q]];
+      }
+    }
+    FAGBI_TRY(h->upload(h->d_lnbr_off, LF.nbr_off.data(), LF.nbr_off.size() * 4));
+    FAGBI_TRY(h->upload(h->d_lnbr, LF.nbr.data(), LF.nbr.size() * 4));
+    FAGBI_TRY(h->upload(h->d_lnbr_col, col.data(), col.size() * 4));
+  }
   FAGBI_TRY(h->upload(h->d_src_tree, src_tree.data(), h->n_src * 4));
   FAGBI_TRY(h->upload(h->d_src_user, src_user.data(), h->n_src * 4));
   FAGBI_TRY(h->upload(h->d_leaf_of, leaf_of.data(), N * 4));

@@ -186,70 +186,104 @@ __device__ inline void slot_reduce(const R* red0, const R* redk, const int32_t* 
   }
 }
 
-// MtL: one block per target cluster.  slot = (g | b << 16): g the index of
-// alpha+beta, b the index of beta; slots sorted by alpha (aoff).
+// MtL: one block per target cluster.  With D_g = g! F_g/(4 pi) (per offset
+// table), Mt^b = (-1)^|b| M^b / b! and lambda^a = Lt^a / a!, the translation
+// is Lt^a = sum_{|a|+|b| <= p} D_{a+b} Mt^b: one multiply-add per slot.
+// slot = (g | b << 16): g the index of alpha+beta, b the index of beta; slots
+// sorted by alpha (aoff).  Both channels travel together (R2 = {G0, Gk}).
+template <typename R> struct Pair;
+template <> struct Pair<float> { using T = float2; };
+template <> struct Pair<double> { using T = double2; };
+
 template <typename R, int SPT>
 __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_off, const int32_t* __restrict__ inter_src,
-                                            const int32_t* __restrict__ inter_oid, const R* __restrict__ F0,
-                                            const R* __restrict__ Fk, const int32_t* __restrict__ slot,
-                                            const R* __restrict__ coef, const int32_t* __restrict__ aoff, int nslot,
-                                            int T, int batch, const R* __restrict__ M0, const R* __restrict__ Mk,
-                                            R* L0, R* Lk) {
-  extern __shared__ char smem_raw[];
-  R* sm = reinterpret_cast<R*>(smem_raw);
-  const int c = blockIdx.x;
+                                            const int32_t* __restrict__ inter_oid,
+                                            const typename Pair<R>::T* __restrict__ Dt,
+                                            const int32_t* __restrict__ slot, const R* __restrict__ mscale,
+                                            const R* __restrict__ lscale, const int32_t* __restrict__ aoff,
+                                            int nslot, int T, int batch, int cpb, int ncl,
+                                            const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
+  // cpb targets per block when a translation has few slots: group g of
+  // nslot threads (SPT == 1) owns target blockIdx.x * cpb + g
+  using R2 = typename Pair<R>::T;
+  extern __shared__ __align__(16) char smem_raw[];
   const int tid = threadIdx.x;
+  const int gsz = SPT == 1 ? nslot : TB;
+  const int g = SPT == 1 ? tid / nslot : 0;
+  const int lt = SPT == 1 ? tid - g * nslot : tid;   // thread within the group
+  const int c = blockIdx.x * cpb + g;
+  const bool active = g < cpb && c < ncl;
+  R2* sm = reinterpret_cast<R2*>(smem_raw) + (size_t)(active ? g : 0) * batch * 2 * T;
   int sg[SPT], sb[SPT];
-  R cf[SPT], a0[SPT], ak[SPT];
+  R a0[SPT], ak[SPT];
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
-    const int k = tid + j * TB;
-    const int v = k < nslot ? slot[k] : 0;
+    const int k = lt + j * TB;
+    const int v = (active && k < nslot) ? slot[k] : 0;
     sg[j] = v & 0xffff;
-    sb[j] = v >> 16;
-    cf[j] = k < nslot ? coef[k] : (R)0;
+    sb[j] = T + (v >> 16);
     a0[j] = 0;
     ak[j] = 0;
   }
-  const int q0 = inter_off[c], q1 = inter_off[c + 1];
-  const int W = 4 * T;   // row stride of one staged source: F0, Fk, M0, Mk
-  for (int qb = q0; qb < q1; qb += batch) {
-    const int nb = min(batch, q1 - qb);
+  const int q0 = active ? inter_off[c] : 0, q1 = active ? inter_off[c + 1] : 0;
+  // the block iterates over the longest list among its targets
+  int maxlen = 0;
+  for (int gg = 0; gg < cpb; ++gg) {
+    const int cc = blockIdx.x * cpb + gg;
+    if (cc < ncl) maxlen = max(maxlen, inter_off[cc + 1] - inter_off[cc]);
+  }
+  const int W = 2 * T;   // one staged source: D (T pairs) then Mt (T pairs)
+  for (int b0 = 0; b0 < maxlen; b0 += batch) {
+    const int qb = q0 + b0;
+    const int nb = active ? max(0, min(batch, q1 - qb)) : 0;
     __syncthreads();
-    for (int e = tid; e < nb * T; e += TB) {
+    for (int e = lt; e < nb * T; e += gsz) {
       const int s = e / T, t = e - s * T;
       const int q = qb + s;
-      const int64_t fo = (int64_t)inter_oid[q] * T + t;
       const int64_t mo = (int64_t)inter_src[q] * T + t;
-      R* row = sm + s * W;
-      row[t] = F0[fo];
-      row[T + t] = Fk[fo];
-      row[2 * T + t] = M0[mo];
-      row[3 * T + t] = Mk[mo];
+      const R f = mscale[t];
+      sm[s * W + t] = Dt[(int64_t)inter_oid[q] * T + t];
+      R2 m;
+      m.x = M0[mo] * f;
+      m.y = Mk[mo] * f;
+      sm[s * W + T + t] = m;
     }
     __syncthreads();
     for (int s = 0; s < nb; ++s) {
-      const R* row = sm + s * W;
+      const R2* row = sm + s * W;
 #pragma unroll
       for (int j = 0; j < SPT; ++j) {
-        a0[j] += cf[j] * row[sg[j]] * row[2 * T + sb[j]];
-        ak[j] += cf[j] * row[T + sg[j]] * row[3 * T + sb[j]];
+        const R2 d = row[sg[j]];
+        const R2 m = row[sb[j]];
+        a0[j] += d.x * m.x;
+        ak[j] += d.y * m.y;
       }
     }
   }
   __syncthreads();
-  R* red0 = sm;
-  R* redk = sm + nslot;
+  R* red0 = reinterpret_cast<R*>(smem_raw) + (size_t)(active ? g : 0) * 2 * nslot;
+  R* redk = red0 + nslot;
+  if (active) {
 #pragma unroll
-  for (int j = 0; j < SPT; ++j) {
-    const int k = tid + j * TB;
-    if (k < nslot) {
-      red0[k] = a0[j];
-      redk[k] = ak[j];
+    for (int j = 0; j < SPT; ++j) {
+      const int k = lt + j * TB;
+      if (k < nslot) {
+        red0[k] = a0[j];
+        redk[k] = ak[j];
+      }
     }
   }
   __syncthreads();
-  slot_reduce<R>(red0, redk, aoff, T, L0 + (int64_t)c * T, Lk + (int64_t)c * T, true);
+  if (!active) return;
+  for (int t = lt; t < T; t += gsz) {
+    R s0 = 0, sk = 0;
+    for (int k = aoff[t]; k < aoff[t + 1]; ++k) {
+      s0 += red0[k];
+      sk += redk[k];
+    }
+    L0[(int64_t)c * T + t] += s0 * lscale[t];
+    Lk[(int64_t)c * T + t] += sk * lscale[t];
+  }
 }
 
 // MtM: one block per parent; slot = (a | b << 16), a parent index, b child
@@ -260,7 +294,7 @@ __global__ void __launch_bounds__(TB) k_m2m(const int32_t* __restrict__ child_st
                                             const R* __restrict__ coef, const int32_t* __restrict__ aoff, int nslot,
                                             int Tp, int Tc, const R* __restrict__ C0, const R* __restrict__ Ck,
                                             R* P0, R* Pk) {
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   R* sm = reinterpret_cast<R*>(smem_raw);
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -313,7 +347,7 @@ __global__ void __launch_bounds__(TB) k_l2l(const int32_t* __restrict__ parent, 
                                             const int32_t* __restrict__ slot, const R* __restrict__ coef,
                                             const int32_t* __restrict__ boff, int nslot, int Tp, int Tc,
                                             const R* __restrict__ P0, const R* __restrict__ Pk, R* C0, R* Ck) {
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   R* sm = reinterpret_cast<R*>(smem_raw);
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -369,36 +403,51 @@ __global__ void k_l2p(const R* __restrict__ ms, const R* __restrict__ md, const 
   y[N + p] -= (double)y2;
 }
 
-// near-field block SpMV: one wavefront per target panel (tree order)
+// near-field block SpMV: one wavefront per leaf, lanes over the leaf's source
+// panels; the source index and x are loaded once per group of up to 8 target
+// rows; fixed-order FP64 reductions
 template <typename E>
-__global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const int32_t* __restrict__ leaf_of,
-                                              const int32_t* __restrict__ leaf_start,
+__global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const int32_t* __restrict__ leaf_start,
+                                              const int32_t* __restrict__ leaf_cnt,
                                               const int64_t* __restrict__ src_off,
                                               const int64_t* __restrict__ ent_off,
                                               const int32_t* __restrict__ src_user,
-                                              const int32_t* __restrict__ perm, int64_t N,
+                                              const int32_t* __restrict__ perm, int64_t N, int nl,
                                               const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  constexpr int RG = 8;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (i >= N) return;
-  const int c = leaf_of[i];
+  if (c >= nl) return;
+  const int nc = leaf_cnt[c], i0 = leaf_start[c];
   const int64_t so = src_off[c];
   const int S = (int)(src_off[c + 1] - so);
-  const E* row = ent + ent_off[c] + (i - leaf_start[c]) * (int64_t)S;
-  double a1 = 0, a2 = 0;
-  for (int k = lane; k < S; k += 64) {
-    const int j = src_user[so + k];
-    const double xj = x[j], xn = x[N + j];
-    const E e = row[k];
-    a1 += (double)e.x * xj + (double)e.y * xn;
-    a2 += (double)e.z * xj + (double)e.w * xn;
-  }
-  a1 = wave_sum(a1);
-  a2 = wave_sum(a2);
-  if (lane == 0) {
-    const int p = perm[i];
-    y[p] = a1;
-    y[N + p] = a2;
+  const E* base = ent + ent_off[c];
+  for (int r0 = 0; r0 < nc; r0 += RG) {
+    const int nr = min(RG, nc - r0);
+    double a1[RG], a2[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) a1[r] = a2[r] = 0.0;
+    for (int k = lane; k < S; k += 64) {
+      const int j = src_user[so + k];
+      const double xj = x[j], xn = x[N + j];
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+        if (r < nr) {
+          const E e = base[(int64_t)(r0 + r) * S + k];
+          a1[r] += (double)e.x * xj + (double)e.y * xn;
+          a2[r] += (double)e.z * xj + (double)e.w * xn;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+      if (r < nr) {
+        const double s1 = wave_sum(a1[r]), s2 = wave_sum(a2[r]);
+        if (lane == 0) {
+          const int p = perm[i0 + r0 + r];
+          y[p] = s1;
+          y[N + p] = s2;
+        }
+      }
   }
 }
 
@@ -426,29 +475,30 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
   const int lo = std::min(h->lmin, h->L);
   for (int l = lo; l <= h->L; ++l) {
     Level& D = h->lev[l];
-    // MtL slots: (alpha, beta), |alpha| + |beta| <= p, grouped by alpha
+    // MtL slots: (alpha, beta), |alpha| + |beta| <= p, grouped by alpha;
+    // scale tables (-1)^|b|/b! for the moments and 1/a! for the locals
     if (l >= h->lmin) {
       std::vector<int32_t> slot, aoff(1, 0);
-      std::vector<double> cf;
+      std::vector<double> msc(D.T), lsc(D.T);
       for (int ta = 0; ta < D.T; ++ta) {
         const MI A = mi_of(ta);
         const int da = A.a[0] + A.a[1] + A.a[2];
+        const double af = fact(A.a[0]) * fact(A.a[1]) * fact(A.a[2]);
+        msc[ta] = ((da & 1) ? -1.0 : 1.0) / af;
+        lsc[ta] = 1.0 / af;
         for (int tb = 0; tb < nterms(D.order - da); ++tb) {
           const MI B = mi_of(tb);
-          const int g = midx(A.a[0] + B.a[0], A.a[1] + B.a[1], A.a[2] + B.a[2]);
-          slot.push_back(g | (tb << 16));
-          const double num = fact(A.a[0] + B.a[0]) * fact(A.a[1] + B.a[1]) * fact(A.a[2] + B.a[2]);
-          const double den = fact(A.a[0]) * fact(A.a[1]) * fact(A.a[2]) * fact(B.a[0]) * fact(B.a[1]) * fact(B.a[2]);
-          const double sg = ((B.a[0] + B.a[1] + B.a[2]) & 1) ? -1.0 : 1.0;
-          cf.push_back(sg * num / den / FOUR_PI);
+          slot.push_back(midx(A.a[0] + B.a[0], A.a[1] + B.a[1], A.a[2] + B.a[2]) | (tb << 16));
         }
         aoff.push_back((int32_t)slot.size());
       }
       D.m2l_nslot = (int)slot.size();
       FAGBI_TRY(h->upload(D.d_m2l_slot, slot.data(), slot.size() * 4));
       FAGBI_TRY(h->upload(D.d_m2l_aoff, aoff.data(), aoff.size() * 4));
-      FAGBI_TRY(upload_conv<double>(h, D.d_m2l_c64, cf));
-      FAGBI_TRY(upload_conv<float>(h, D.d_m2l_c32, cf));
+      std::vector<double> sc(msc);
+      sc.insert(sc.end(), lsc.begin(), lsc.end());
+      FAGBI_TRY(upload_conv<double>(h, D.d_m2l_c64, sc));
+      FAGBI_TRY(upload_conv<float>(h, D.d_m2l_c32, sc));
     }
     // shifts between level l (parent, order p_l) and l+1 (child, p_{l+1})
     if (l < h->L) {
@@ -508,18 +558,23 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         FAGBI_TRY(upload_conv<float>(h, D.d_dn_c32, cf));
       }
     }
-    // Taylor tables per offset for G0 and Gk
+    // derivative tables per offset, D_g = g! F_g / (4 pi), channels
+    // interleaved {G0, Gk}
     if (l >= h->lmin && D.n_off > 0) {
-      std::vector<double> f0((size_t)D.n_off * D.T), fk((size_t)D.n_off * D.T);
+      std::vector<double> f0(D.T), fk(D.T), dt((size_t)2 * D.n_off * D.T);
       for (int o = 0; o < D.n_off; ++o) {
         const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h, D.off_xyz[3 * o + 2] * D.h};
-        taylor_host(x0, 0.0, D.order, f0.data() + (size_t)o * D.T);
-        taylor_host(x0, h->prm.kappa, D.order, fk.data() + (size_t)o * D.T);
+        taylor_host(x0, 0.0, D.order, f0.data());
+        taylor_host(x0, h->prm.kappa, D.order, fk.data());
+        for (int g = 0; g < D.T; ++g) {
+          const MI G = mi_of(g);
+          const double gf = fact(G.a[0]) * fact(G.a[1]) * fact(G.a[2]) / FOUR_PI;
+          dt[2 * ((size_t)o * D.T + g)] = gf * f0[g];
+          dt[2 * ((size_t)o * D.T + g) + 1] = gf * fk[g];
+        }
       }
-      FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], f0));
-      FAGBI_TRY(upload_conv<double>(h, D.d_F64[1], fk));
-      FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], f0));
-      FAGBI_TRY(upload_conv<float>(h, D.d_F32[1], fk));
+      FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], dt));
+      FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], dt));
     }
     for (int ch = 0; ch < 2; ++ch) {
       FAGBI_TRY(h->alloc(D.d_M64[ch], (size_t)D.n * D.T * 8));
@@ -573,9 +628,9 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   };
   FAGBI_TRY(mark(0));
   if (parts & FAGBI_PART_NEAR) {
-    k_spmv<E><<<(unsigned)((N + 3) / 4), 256, 0, s>>>(
-        ent.as<E>(), h->d_leaf_of.as<int32_t>(), h->d_leaf_start.as<int32_t>(), h->d_src_off.as<int64_t>(),
-        h->d_ent_off.as<int64_t>(), h->d_src_user.as<int32_t>(), h->d_perm.as<int32_t>(), N, x, y);
+    k_spmv<E><<<(unsigned)((nl + 3) / 4), 256, 0, s>>>(
+        ent.as<E>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
+        h->d_ent_off.as<int64_t>(), h->d_src_user.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl, x, y);
   } else {
     FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   }
@@ -615,14 +670,19 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), s));
     FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), s));
     if (D.n_off == 0) continue;
-    const R* F0 = f32 ? D.d_F32[0].as<R>() : D.d_F64[0].as<R>();
-    const R* Fk = f32 ? D.d_F32[1].as<R>() : D.d_F64[1].as<R>();
-    const int batch = std::max(1, std::min(16, (int)(12288 / (4 * D.T * sizeof(R)))));
-    const size_t sh = std::max<size_t>((size_t)batch * 4 * D.T, (size_t)2 * D.m2l_nslot) * sizeof(R);
-    FAGBI_SPT_SWITCH(spt_of(D.m2l_nslot), k_m2l, D.n, sh, s, D.d_inter_off.as<int32_t>(),
-                     D.d_inter_src.as<int32_t>(), D.d_inter_oid.as<int32_t>(), F0, Fk, D.d_m2l_slot.as<int32_t>(),
-                     cf(D.d_m2l_c64, D.d_m2l_c32), D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, M(D, 0),
-                     M(D, 1), Lc(D, 0), Lc(D, 1));
+    using R2 = typename Pair<R>::T;
+    const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
+    const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
+    const int spt = spt_of(D.m2l_nslot);
+    const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
+    const int batch = std::max(1, std::min(16, (int)(16384 / (cpb * 2 * D.T * sizeof(R2)))));
+    const size_t sh = (size_t)cpb * std::max<size_t>((size_t)batch * 2 * D.T * sizeof(R2),
+                                                     (size_t)2 * D.m2l_nslot * sizeof(R));
+    const unsigned grid = (unsigned)((D.n + cpb - 1) / cpb);
+    FAGBI_SPT_SWITCH(spt, k_m2l, grid, sh, s, D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
+                     D.d_inter_oid.as<int32_t>(), Dt, D.d_m2l_slot.as<int32_t>(), sc, sc + D.T,
+                     D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, cpb, D.n, M(D, 0), M(D, 1), Lc(D, 0),
+                     Lc(D, 1));
   }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(3));

@@ -107,6 +107,7 @@ struct fagbi_handle {
   // ---- device buffers ----
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
+  fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
   fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]

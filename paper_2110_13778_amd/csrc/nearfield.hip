@@ -49,6 +49,11 @@ struct NearArgs {
   const int64_t* src_off;
   const int64_t* ent_off;
   const int32_t* src_tree;
+  const int32_t* perm;       // tree position -> caller index
+  const int32_t* leaf_of;
+  const int32_t* lnbr_off;   // leaf neighbour lists and the column where
+  const int32_t* lnbr;       // each neighbour's panels start in the leaf's
+  const int32_t* lnbr_col;   // source list
   double kappa, eps, near_ratio;
 };
 
@@ -126,6 +131,9 @@ __global__ void __launch_bounds__(256) k_near_classify(NearArgs a, unsigned long
       i = i0 + il;
       j = a.src_tree[so + k];
       cls = classify(a, i, j);
+      // touching and close pairs are integrated once per unordered pair (for
+      // the member whose target has the lower caller index) and mirrored
+      if (cls >= C_EDGE && a.perm[i] > a.perm[j]) cls = -1;
       if (PASS == 1 && cls == C_REGULAR) {
         double I[6];
         regular_pair(a, i, j, I);
@@ -286,6 +294,19 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
       v.w += 0.5 * (1.0 + 1.0 / a.eps) * a.pa[i];
     }
     ent[item.ent] = v;
+    if (CLS != C_IDENT) {
+      // mirrored entry (target j, source i): I1, I6 symmetric, I2 <-> I4,
+      // I3 <-> I5 (the kernels depend on x - y only)
+      const int ci = a.leaf_of[i], cj = a.leaf_of[j];
+      int col = -1;
+      for (int q = a.lnbr_off[cj]; q < a.lnbr_off[cj + 1]; ++q)
+        if (a.lnbr[q] == ci) col = a.lnbr_col[q] + (i - a.leaf_start[ci]);
+      if (col >= 0) {
+        const int S = (int)(a.src_off[cj + 1] - a.src_off[cj]);
+        const double It[6] = {acc[0], acc[3], acc[4], acc[1], acc[2], acc[5]};
+        ent[a.ent_off[cj] + (int64_t)(j - a.leaf_start[cj]) * S + col] = combine(It, a.eps);
+      }
+    }
   }
 }
 
@@ -308,6 +329,11 @@ static NearArgs near_args(fagbi_handle* h) {
   a.src_off = h->d_src_off.as<int64_t>();
   a.ent_off = h->d_ent_off.as<int64_t>();
   a.src_tree = h->d_src_tree.as<int32_t>();
+  a.perm = h->d_perm.as<int32_t>();
+  a.leaf_of = h->d_leaf_of.as<int32_t>();
+  a.lnbr_off = h->d_lnbr_off.as<int32_t>();
+  a.lnbr = h->d_lnbr.as<int32_t>();
+  a.lnbr_col = h->d_lnbr_col.as<int32_t>();
   a.kappa = h->prm.kappa;
   a.eps = h->prm.eps_out / h->prm.eps_in;
   a.near_ratio = h->prm.near_ratio;

@@ -9,8 +9,9 @@
 //    centroids; empty cubes are dropped;
 //  * cube index of a centroid on level l: floor((c - corner)/h_l) clamped to
 //    [0, 2^l - 1] (computed once on level 20 and shifted, which is exact);
-//  * cluster centre = cube centre, one radius per level (the farthest vertex
-//    of a member panel from its cube centre), so the separation ratio
+//  * cluster centre = cube centre, one radius per level (the farthest
+//    3-point-rule quadrature point of a member panel from its cube centre:
+//    the far field only ever evaluates that rule), so the separation ratio
 //    2 rho_l / |x_c - x_c'| depends on the index offset alone and every level
 //    has a fixed stencil of interaction offsets;
 //  * c' in N(c) iff c' is a child of a neighbour of c's parent and the ratio
@@ -20,11 +21,28 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <unordered_map>
+#include <thread>
 
 #include "../../include/fagbi.h"
 
 namespace fagbi {
+
+static int host_threads(int64_t work) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int n = (int)std::min<unsigned>(hc ? hc : 1, 16);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(n, work / 4096 + 1));
+}
+
+// fn(thread, begin, end) over [0, n) split into nth contiguous chunks
+template <class F>
+static void parallel_chunks(int64_t n, int nth, F fn) {
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t) {
+    const int64_t lo = n * t / nth, hi = n * (t + 1) / nth;
+    th.emplace_back([=, &fn] { fn(t, lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
 
 static uint64_t spread3(uint64_t v) {
   uint64_t out = 0;
@@ -58,8 +76,9 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
       return FAGBI_E_ARG;
     }
   // ---- closed, consistently oriented 2-manifold check -------------------
+  // every undirected edge must occur exactly twice, once in each direction
   {
-    std::vector<uint64_t> und(3 * nt), dir(3 * nt);
+    std::vector<uint64_t> und(3 * nt);
     for (int64_t t = 0; t < nt; ++t)
       for (int e = 0; e < 3; ++e) {
         uint64_t a = (uint64_t)tris[3 * t + e], b = (uint64_t)tris[3 * t + (e + 1) % 3];
@@ -68,25 +87,20 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
           err = buf;
           return FAGBI_E_MESH;
         }
-        dir[3 * t + e] = a * (uint64_t)nv + b;
-        und[3 * t + e] = std::min(a, b) * (uint64_t)nv + std::max(a, b);
+        und[3 * t + e] = ((std::min(a, b) * (uint64_t)nv + std::max(a, b)) << 1) | (a < b ? 1u : 0u);
       }
     std::sort(und.begin(), und.end());
-    std::sort(dir.begin(), dir.end());
-    for (size_t k = 0; k < und.size();) {
-      size_t m = k;
-      while (m < und.size() && und[m] == und[k]) ++m;
-      if (m - k != 2) {
+    for (size_t k = 0; k < und.size(); k += 2) {
+      if (k + 1 >= und.size() || (und[k] >> 1) != (und[k + 1] >> 1) ||
+          (k + 2 < und.size() && (und[k + 2] >> 1) == (und[k] >> 1))) {
         err = "build_tree: mesh is open or non-manifold (an edge is not shared by exactly two triangles)";
         return FAGBI_E_MESH;
       }
-      k = m;
-    }
-    for (size_t k = 1; k < dir.size(); ++k)
-      if (dir[k] == dir[k - 1]) {
+      if ((und[k] & 1) == (und[k + 1] & 1)) {
         err = "build_tree: inconsistent triangle orientation";
         return FAGBI_E_MESH;
       }
+    }
   }
   // ---- per-panel geometry --------------------------------------------------
   const int64_t N = nt;
@@ -211,22 +225,29 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
     // radius: farthest quadrature point (3-point rule: 2/3 of one corner and
     // 1/6 of the other two) of a member panel from its cube centre; the far
     // field only ever evaluates the rule at these points
-    double rho = 0;
-    for (int64_t k = 0; k < N; ++k) {
-      const int32_t c = owner[k];
-      const double* cv = &out.corners[9 * k];
-      for (int v = 0; v < 3; ++v) {
-        double s[3];
-        for (int d = 0; d < 3; ++d) {
-          double ctr = out.corner[d] + ((double)T.idx[3 * c + d] + 0.5) * T.h;
-          double qp = (2.0 / 3.0) * cv[3 * v + d] +
-                      (1.0 / 6.0) * (cv[3 * ((v + 1) % 3) + d] + cv[3 * ((v + 2) % 3) + d]);
-          s[d] = qp - ctr;
+    const int nth = host_threads(N);
+    std::vector<double> part(nth, 0.0);
+    parallel_chunks(N, nth, [&](int t, int64_t lo, int64_t hi) {
+      double rho = 0;
+      for (int64_t k = lo; k < hi; ++k) {
+        const int32_t c = owner[k];
+        const double* cv = &out.corners[9 * k];
+        for (int v = 0; v < 3; ++v) {
+          double s[3];
+          for (int d = 0; d < 3; ++d) {
+            double ctr = out.corner[d] + ((double)T.idx[3 * c + d] + 0.5) * T.h;
+            double qp = (2.0 / 3.0) * cv[3 * v + d] +
+                        (1.0 / 6.0) * (cv[3 * ((v + 1) % 3) + d] + cv[3 * ((v + 2) % 3) + d]);
+            s[d] = qp - ctr;
+          }
+          double dist = std::sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+          rho = std::max(rho, dist);
         }
-        double dist = std::sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
-        rho = std::max(rho, dist);
       }
-    }
+      part[t] = rho;
+    });
+    double rho = 0;
+    for (double v : part) rho = std::max(rho, v);
     T.rho = rho;
   }
   // parents / children
@@ -246,7 +267,8 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
   }
   out.lev[L].child_start.assign(out.lev[L].n, 0);
   out.lev[L].child_end.assign(out.lev[L].n, 0);
-  // neighbour and interaction lists
+  // neighbour and interaction lists (clusters split over host threads; the
+  // per-thread pieces are concatenated in cluster order)
   {
     TreeLevel& R = out.lev[0];
     R.nbr_off = {0, 1};
@@ -254,12 +276,16 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
     R.inter_off = {0, 0};
   }
   out.lmin = L + 1;
+  int reach = 0;   // largest |offset component| among neighbours on level l-1
   for (int l = 1; l <= L; ++l) {
     TreeLevel &C = out.lev[l], &P = out.lev[l - 1];
-    C.nbr_off.assign(1, 0);
-    C.inter_off.assign(1, 0);
-    std::unordered_map<uint64_t, int32_t> offid;
-    for (int c = 0; c < C.n; ++c) {
+    const int W = 2 * reach + 1;            // bound on |offset| on this level
+    const int span = 2 * W + 1;
+    // pass 1: counts per cluster; pass 2: fill at the prefix-sum offsets
+    const int nth = host_threads(C.n);
+    std::vector<int32_t> ncnt(C.n), icnt(C.n);
+    std::vector<int> reach_t(nth, 0);
+    auto visit = [&](int64_t c, auto&& on_nbr, auto&& on_int) {
       const int p = C.parent[c];
       double xc[3];
       for (int d = 0; d < 3; ++d) xc[d] = out.corner[d] + ((double)C.idx[3 * c + d] + 0.5) * C.h;
@@ -271,32 +297,66 @@ int build_tree_host(const double* verts, int64_t nv, const int32_t* tris, int64_
             s[d] = xc[d] - (out.corner[d] + ((double)C.idx[3 * c2 + d] + 0.5) * C.h);
           double dist = std::sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
           double eta = (C.rho + C.rho) / dist;   // +inf for c2 == c
-          if (eta > eta0) {
-            C.nbr.push_back(c2);
-          } else {
-            int32_t o[3];
-            for (int d = 0; d < 3; ++d) o[d] = C.idx[3 * c + d] - C.idx[3 * c2 + d];
-            // |o| < 2^20 on levels <= 20: 21-bit fields after the shift
-            uint64_t k = ((uint64_t)(uint32_t)(o[0] + (1 << 20)) << 42) |
-                         ((uint64_t)(uint32_t)(o[1] + (1 << 20)) << 21) |
-                         (uint64_t)(uint32_t)(o[2] + (1 << 20));
-            auto it = offid.find(k);
-            int32_t id;
-            if (it == offid.end()) {
-              id = (int32_t)offid.size();
-              offid.emplace(k, id);
-              C.off_xyz.insert(C.off_xyz.end(), o, o + 3);
-            } else {
-              id = it->second;
-            }
-            C.inter_src.push_back(c2);
-            C.inter_oid.push_back(id);
-          }
+          int o[3];
+          for (int d = 0; d < 3; ++d) o[d] = C.idx[3 * c + d] - C.idx[3 * c2 + d];
+          if (eta > eta0)
+            on_nbr(c2, o);
+          else
+            on_int(c2, o);
         }
       }
-      C.nbr_off.push_back((int32_t)C.nbr.size());
-      C.inter_off.push_back((int32_t)C.inter_src.size());
+    };
+    parallel_chunks(C.n, nth, [&](int t, int64_t lo, int64_t hi) {
+      int rmax = 0;
+      for (int64_t c = lo; c < hi; ++c) {
+        int nn = 0, ni = 0;
+        visit(c, [&](int, const int* o) {
+          ++nn;
+          for (int d = 0; d < 3; ++d) rmax = std::max(rmax, std::abs(o[d]));
+        }, [&](int, const int*) { ++ni; });
+        ncnt[c] = nn;
+        icnt[c] = ni;
+      }
+      reach_t[t] = rmax;
+    });
+    C.nbr_off.assign(C.n + 1, 0);
+    C.inter_off.assign(C.n + 1, 0);
+    for (int c = 0; c < C.n; ++c) {
+      C.nbr_off[c + 1] = C.nbr_off[c] + ncnt[c];
+      C.inter_off[c + 1] = C.inter_off[c] + icnt[c];
     }
+    C.nbr.resize(C.nbr_off[C.n]);
+    C.inter_src.resize(C.inter_off[C.n]);
+    std::vector<int32_t> ikey(C.inter_off[C.n]);
+    parallel_chunks(C.n, nth, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t c = lo; c < hi; ++c) {
+        int32_t pn = C.nbr_off[c], pi = C.inter_off[c];
+        visit(c, [&](int c2, const int*) { C.nbr[pn++] = c2; },
+              [&](int c2, const int* o) {
+                C.inter_src[pi] = c2;
+                ikey[pi++] = ((o[0] + W) * span + (o[1] + W)) * span + (o[2] + W);
+              });
+      }
+    });
+    // distinct offsets, numbered in increasing key order (independent of the
+    // traversal and of the thread count)
+    std::vector<int32_t> id((size_t)span * span * span, -1);
+    for (int32_t k : ikey) id[k] = 0;
+    int32_t nid = 0;
+    for (size_t k = 0; k < id.size(); ++k)
+      if (id[k] == 0) {
+        id[k] = nid++;
+        C.off_xyz.push_back((int)(k / ((size_t)span * span)) - W);
+        C.off_xyz.push_back((int)((k / span) % span) - W);
+        C.off_xyz.push_back((int)(k % span) - W);
+      }
+    C.inter_oid.resize(ikey.size());
+    parallel_chunks((int64_t)ikey.size(), nth, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t k = lo; k < hi; ++k) C.inter_oid[k] = id[ikey[k]];
+    });
+    int newreach = 0;
+    for (int v : reach_t) newreach = std::max(newreach, v);
+    reach = newreach;
     if (!C.inter_src.empty() && out.lmin > L) out.lmin = l;
   }
   return 0;

@@ -188,11 +188,10 @@ def test_gauss_double_layer_identity(sphere320):
 
 def test_pair_symmetries(sphere320):
     P, I = sphere320
-    # exact for the symmetric rules; the edge rule treats its two panels
-    # differently, so swapping them moves the result by its quadrature error
+    # the product rules are symmetric; touching/close pairs are mirrored
     for a, b in ((0, 0), (5, 5), (3, 1), (4, 2)):
         scale = np.abs(I[..., a]).max()
-        assert np.abs(I[..., a] - I[..., b].T).max() < 1e-8 * scale
+        assert np.abs(I[..., a] - I[..., b].T).max() < 1e-14 * scale
 
 
 def test_sphere_constant_density_operators(sphere320):
