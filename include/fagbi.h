@@ -191,6 +191,61 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info);
    order; perm host i32[N]. */
 int fagbi_get_permutation(fagbi_handle* h, int32_t* perm);
 
+/* ---- learned near-field surrogate (an addition to the paper's method) ----
+   A 16 -> 128 -> 128 -> 128 -> 6 tanh network predicts, from the geometry of
+   a near-singular panel pair (edge- or vertex-adjacent, or closer than
+   near_ratio), the correction of its six integrals I1..I6 over the 3x3
+   regular rule, in units of h^3, h^2 (x4), h with h = sqrt(target area).
+   Features: target corners (3) and source corners (9) in the target frame
+   over h, kappa*h, class one-hot (3).  The blob exchanged by get/set holds
+   the parameters (W1 b1 W2 b2 W3 b3 W4 b4, W row-major [in][out]), the
+   input/output standardisation (input mean[16] sd[16], per class output
+   mean[3][6] sd[3][6]) and the
+   gate calibration (per class: 9 distance-ratio bin edges, then per class 8
+   calibrated error values). */
+enum { FAGBI_MLP_NIN = 16, FAGBI_MLP_NOUT = 6, FAGBI_MLP_NAUX = 8,
+       FAGBI_MLP_NPARAM = 35974, FAGBI_MLP_NBLOB = 36093 };
+
+/* Training data from the current mesh (after fagbi_assemble_nearfield):
+   up to max_pairs near-singular pairs (every k-th of each class), labelled by
+   the library's singular cubature.  X: device f32[max_pairs*16] features,
+   T: device f32[max_pairs*6] targets, aux: device f32[max_pairs*8]
+   {class 0/1/2 = edge/vertex/close, centroid distance / sqrt(h_i h_j),
+   the six full integrals in target units}.  *n_out = rows written.
+   Synchronises. */
+int fagbi_mlp_dataset(fagbi_handle* h, int64_t max_pairs, float* X, float* T,
+                      float* aux, int64_t* n_out, void* stream);
+
+/* Train the handle's network on n >= 100 rows (device arrays as produced by
+   fagbi_mlp_dataset; every tenth row is held out for the gate
+   calibration): Adam, cosine-decayed learning rate, minibatches of `batch`
+   rows, standardised inputs/targets, mean squared error; Xavier initial
+   weights from the counter-based generator splitmix64(seed).
+   loss_hist: host f32[epochs] mean training loss per epoch (may be NULL).
+   Synchronises. */
+int fagbi_mlp_train(fagbi_handle* h, const float* X, const float* T, const float* aux,
+                    int64_t n, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                    float* loss_hist, void* stream);
+
+/* Inference: Y (device f32[n*6]) = network(X) in target units. */
+int fagbi_mlp_forward(fagbi_handle* h, const float* X, float* Y, int64_t n, void* stream);
+
+/* Loss and gradient of the raw network (no standardisation) with host
+   parameters theta (f32[FAGBI_MLP_NPARAM]) on device X (f32[n*16]) and
+   T (f32[n*6]), 1 <= n <= 65536: loss = mean over rows and outputs of
+   (y - t)^2; grad host f32[FAGBI_MLP_NPARAM].  For checking the training
+   kernels.  Synchronises. */
+int fagbi_mlp_grad(fagbi_handle* h, const float* theta, const float* X, const float* T,
+                   int32_t n, float* loss, float* grad, void* stream);
+
+/* Copy the trained network out / in (host f32[FAGBI_MLP_NBLOB]). */
+int fagbi_mlp_get_weights(fagbi_handle* h, float* blob, int64_t n);
+int fagbi_mlp_set_weights(fagbi_handle* h, const float* blob, int64_t n);
+
+/* After an assembly with mlp_mode != OFF: pairs whose entries came from the
+   network (gated) out of the near-singular candidates. */
+int fagbi_get_mlp_stats(fagbi_handle* h, int64_t* gated_pairs, int64_t* candidate_pairs);
+
 void fagbi_destroy(fagbi_handle* h);
 const char* fagbi_last_error(void);
 

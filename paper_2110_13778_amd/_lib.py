@@ -24,7 +24,10 @@ EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
            "fagbi_precond_apply", "fagbi_rhs", "fagbi_solve",
            "fagbi_solvation_energy", "fagbi_get_tree_info",
            "fagbi_get_permutation", "fagbi_set_profiling", "fagbi_get_profile",
+           "fagbi_mlp_dataset", "fagbi_mlp_train", "fagbi_mlp_forward", "fagbi_mlp_grad",
+           "fagbi_mlp_get_weights", "fagbi_mlp_set_weights", "fagbi_get_mlp_stats",
            "fagbi_destroy", "fagbi_last_error"]
+MLP_NIN, MLP_NOUT, MLP_NAUX, MLP_NPARAM, MLP_NBLOB = 16, 6, 8, 35974, 36093
 
 
 class Params(C.Structure):
@@ -92,6 +95,13 @@ def load():
         "fagbi_get_permutation": [vp, vp],
         "fagbi_set_profiling": [vp, i32],
         "fagbi_get_profile": [vp, C.POINTER(Profile)],
+        "fagbi_mlp_dataset": [vp, i64, vp, vp, vp, C.POINTER(i64), vp],
+        "fagbi_mlp_train": [vp, vp, vp, vp, i64, i32, i32, C.c_float, C.c_uint64, vp, vp],
+        "fagbi_mlp_forward": [vp, vp, vp, i64, vp],
+        "fagbi_mlp_grad": [vp, vp, vp, vp, i32, C.POINTER(C.c_float), vp, vp],
+        "fagbi_mlp_get_weights": [vp, vp, i64],
+        "fagbi_mlp_set_weights": [vp, vp, i64],
+        "fagbi_get_mlp_stats": [vp, C.POINTER(i64), C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -126,6 +136,13 @@ def _dev(t):
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _devf(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -209,6 +226,69 @@ class Handle:
         ti = TreeInfo()
         _check(self.lib.fagbi_get_tree_info(self.h, C.byref(ti)))
         return ti
+
+    # ---- learned near-field surrogate ----
+    def mlp_dataset(self, max_pairs, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        X = torch.empty(max_pairs * MLP_NIN, dtype=torch.float32, device=dev)
+        T = torch.empty(max_pairs * MLP_NOUT, dtype=torch.float32, device=dev)
+        A = torch.empty(max_pairs * MLP_NAUX, dtype=torch.float32, device=dev)
+        n = C.c_int64()
+        _check(self.lib.fagbi_mlp_dataset(self.h, max_pairs, _devf(X), _devf(T), _devf(A),
+                                          C.byref(n), _stream(stream)))
+        n = n.value
+        return (X[:n * MLP_NIN].view(n, MLP_NIN), T[:n * MLP_NOUT].view(n, MLP_NOUT),
+                A[:n * MLP_NAUX].view(n, MLP_NAUX))
+
+    @staticmethod
+    def _rows(X, T=None, A=None):
+        n = X.numel() // MLP_NIN
+        if X.numel() != n * MLP_NIN or (T is not None and T.numel() != n * MLP_NOUT) or \
+                (A is not None and A.numel() != n * MLP_NAUX):
+            raise ValueError("expected X[n,16], T[n,6], aux[n,8]")
+        return n
+
+    def mlp_train(self, X, T, A, epochs=20, batch=4096, lr=2e-3, seed=1, stream=None):
+        hist = np.zeros(epochs, np.float32)
+        n = self._rows(X, T, A)
+        _check(self.lib.fagbi_mlp_train(self.h, _devf(X), _devf(T), _devf(A), n, epochs,
+                                        batch, lr, seed, hist.ctypes.data_as(C.c_void_p),
+                                        _stream(stream)))
+        return hist
+
+    def mlp_forward(self, X, stream=None):
+        import torch
+        n = self._rows(X)
+        Y = torch.empty(n * MLP_NOUT, dtype=torch.float32, device=X.device)
+        _check(self.lib.fagbi_mlp_forward(self.h, _devf(X), _devf(Y), n, _stream(stream)))
+        return Y.view(n, MLP_NOUT)
+
+    def mlp_grad(self, theta, X, T, stream=None):
+        th = np.ascontiguousarray(theta, np.float32)
+        g = np.zeros(MLP_NPARAM, np.float32)
+        loss = C.c_float()
+        if th.size != MLP_NPARAM:
+            raise ValueError("theta must hold %d floats" % MLP_NPARAM)
+        n = self._rows(X, T)
+        _check(self.lib.fagbi_mlp_grad(self.h, th.ctypes.data_as(C.c_void_p), _devf(X), _devf(T),
+                                       n, C.byref(loss), g.ctypes.data_as(C.c_void_p),
+                                       _stream(stream)))
+        return loss.value, g
+
+    def mlp_get_weights(self):
+        b = np.zeros(MLP_NBLOB, np.float32)
+        _check(self.lib.fagbi_mlp_get_weights(self.h, b.ctypes.data_as(C.c_void_p), MLP_NBLOB))
+        return b
+
+    def mlp_set_weights(self, blob):
+        b = np.ascontiguousarray(blob, np.float32)
+        _check(self.lib.fagbi_mlp_set_weights(self.h, b.ctypes.data_as(C.c_void_p), len(b)))
+
+    def mlp_stats(self):
+        g, c = C.c_int64(), C.c_int64()
+        _check(self.lib.fagbi_get_mlp_stats(self.h, C.byref(g), C.byref(c)))
+        return g.value, c.value
 
     def set_profiling(self, on):
         _check(self.lib.fagbi_set_profiling(self.h, 1 if on else 0))

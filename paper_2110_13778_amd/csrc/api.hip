@@ -329,7 +329,7 @@ int fagbi_assemble_nearfield(fagbi_handle* h, void* stream) {
   h->near_ready = false;
   FAGBI_TRY(fagbi::assemble_nearfield(h, s));
   FAGBI_TRY(fagbi::fmm_setup(h, s));
-  FAGBI_TRY(fagbi::precond_setup(h, s));
+  if (!h->precond_ready) FAGBI_TRY(fagbi::precond_setup(h, s));
   FAGBI_HIP(hipStreamSynchronize(s));
   h->near_ready = true;
   return 0;

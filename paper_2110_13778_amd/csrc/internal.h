@@ -117,6 +117,17 @@ struct fagbi_handle {
   // Krylov workspace
   fagbi::DBuf d_V, d_Z, d_w, d_r, d_b, d_x0, d_dots, d_t1, d_t2;
   int krylov_m = 0;
+  // near-singular worklists (identical, edge, vertex, close), kept after
+  // assembly for the surrogate's data generation
+  fagbi::DBuf d_wl[4];
+  int64_t wl_n[4] = {0, 0, 0, 0};
+  bool precond_ready = false;
+  // surrogate network: parameters, Adam moments, normalisation, calibration
+  bool mlp_ready = false;
+  int64_t mlp_gated_pairs = 0;
+  fagbi::DBuf d_mlp_theta, d_mlp_m, d_mlp_v, d_mlp_norm;
+  fagbi::DBuf d_mlp_skip[4];
+  std::vector<float> mlp_blob;        // parameters | normalisation | calibration
   // per-phase profiling
   bool profiling = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -134,6 +145,8 @@ int fmm_setup(fagbi_handle* h, hipStream_t s);
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts,
            hipStream_t s);
 int precond_setup(fagbi_handle* h, hipStream_t s);
+int run_singular(fagbi_handle* h, int cls_index, const uint8_t* skip, double* raw, hipStream_t s);
+int mlp_assembly_stage(fagbi_handle* h, hipStream_t s);
 int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s);
 int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b,
         hipStream_t s);

@@ -28,84 +28,9 @@
 // {0 <= x2 <= x1 <= 1}.  Every singular pair is integrated by one wavefront
 // (lanes over quadrature points, fixed-order reduction), so FP64 results do
 // not depend on scheduling.
-#include "internal.h"
+#include "near.h"
 
 namespace fagbi {
-
-enum { C_REGULAR = 0, C_IDENT = 1, C_EDGE = 2, C_VERTEX = 3, C_CLOSE = 4 };
-
-struct Item {
-  int32_t i, j;       // tree-order panels (target, source)
-  int64_t ent;        // entry index
-};
-
-struct NearArgs {
-  const double* pv;     // corners [N][9]
-  const double* pn;     // normals [N][3]
-  const double* pa;     // areas [N]
-  const int32_t* ptri;  // vertex ids [N][3]
-  const int32_t* leaf_start;
-  const int32_t* leaf_cnt;
-  const int64_t* src_off;
-  const int64_t* ent_off;
-  const int32_t* src_tree;
-  const int32_t* perm;       // tree position -> caller index
-  const int32_t* leaf_of;
-  const int32_t* lnbr_off;   // leaf neighbour lists and the column where
-  const int32_t* lnbr;       // each neighbour's panels start in the leaf's
-  const int32_t* lnbr_col;   // source list
-  double kappa, eps, near_ratio;
-};
-
-__device__ inline int classify(const NearArgs& a, int i, int j) {
-  if (i == j) return C_IDENT;
-  int shared = 0;
-  for (int p = 0; p < 3; ++p) {
-    const int vi = a.ptri[3 * i + p];
-    shared += (vi == a.ptri[3 * j]) + (vi == a.ptri[3 * j + 1]) + (vi == a.ptri[3 * j + 2]);
-  }
-  if (shared == 2) return C_EDGE;
-  if (shared == 1) return C_VERTEX;
-  // centroid distance, evaluated without contraction so the test is the
-  // IEEE result of the written expression
-  double s[3];
-  for (int d = 0; d < 3; ++d) {
-    const double ci = __dadd_rn(__dadd_rn(a.pv[9 * i + d], a.pv[9 * i + 3 + d]), a.pv[9 * i + 6 + d]) / 3.0;
-    const double cj = __dadd_rn(__dadd_rn(a.pv[9 * j + d], a.pv[9 * j + 3 + d]), a.pv[9 * j + 6 + d]) / 3.0;
-    s[d] = __dadd_rn(ci, -cj);
-  }
-  const double dist = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(s[0], s[0]), __dmul_rn(s[1], s[1])),
-                                     __dmul_rn(s[2], s[2])));
-  const double hm = fmax(sqrt(a.pa[i]), sqrt(a.pa[j]));
-  return dist < __dmul_rn(a.near_ratio, hm) ? C_CLOSE : C_REGULAR;
-}
-
-__device__ inline void regular_pair(const NearArgs& a, int i, int j, double* I) {
-  double qi[9], qj[9];
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) {
-      qi[3 * k + d] = (2.0 / 3.0) * a.pv[9 * i + 3 * k + d] +
-                      (1.0 / 6.0) * (a.pv[9 * i + 3 * ((k + 1) % 3) + d] + a.pv[9 * i + 3 * ((k + 2) % 3) + d]);
-      qj[3 * k + d] = (2.0 / 3.0) * a.pv[9 * j + 3 * k + d] +
-                      (1.0 / 6.0) * (a.pv[9 * j + 3 * ((k + 1) % 3) + d] + a.pv[9 * j + 3 * ((k + 2) % 3) + d]);
-    }
-  const double* ni = a.pn + 3 * i;
-  const double* nj = a.pn + 3 * j;
-  for (int m = 0; m < 6; ++m) I[m] = 0;
-  double k6[6];
-  for (int p = 0; p < 3; ++p)
-    for (int q = 0; q < 3; ++q) {
-      kernel6(qi[3 * p] - qj[3 * q], qi[3 * p + 1] - qj[3 * q + 1], qi[3 * p + 2] - qj[3 * q + 2], ni, nj,
-              a.kappa, k6);
-      for (int m = 0; m < 6; ++m) I[m] += k6[m];
-    }
-  const double w = (a.pa[i] / 3.0) * (a.pa[j] / 3.0);
-  for (int m = 0; m < 6; ++m) I[m] *= w;
-}
-
-__device__ inline double4 combine(const double* I, double eps) {
-  return make_double4(-(eps * I[2] - I[1]), -I[0], -I[5], -(I[3] - I[4] / eps));
-}
 
 // pass 0: count singular pairs per class; pass 1: regular entries + worklists
 template <int PASS>
@@ -160,12 +85,16 @@ __global__ void __launch_bounds__(256) k_near_classify(NearArgs a, unsigned long
 }
 
 // one wavefront per singular / close pair
+// skip (optional): items already filled in by the surrogate; raw (optional):
+// write the six integrals [n_items][6] instead of operator entries
 template <int CLS>
 __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* items, int64_t n_items,
-                                                       const double* gl, int n, double4* ent) {
+                                                       const double* gl, int n, double4* ent,
+                                                       const uint8_t* skip, double* raw) {
   const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (it >= n_items) return;
+  if (skip && skip[it]) return;
   const Item item = items[it];
   const int i = item.i, j = item.j;
   const double* gx = gl;
@@ -288,25 +217,10 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     if (CLS == C_IDENT) {
       acc[1] = acc[2] = acc[3] = acc[4] = 0.0;   // r.n = 0 on a flat panel
     }
-    double4 v = combine(acc, a.eps);
-    if (CLS == C_IDENT) {
-      v.x += 0.5 * (1.0 + a.eps) * a.pa[i];
-      v.w += 0.5 * (1.0 + 1.0 / a.eps) * a.pa[i];
-    }
-    ent[item.ent] = v;
-    if (CLS != C_IDENT) {
-      // mirrored entry (target j, source i): I1, I6 symmetric, I2 <-> I4,
-      // I3 <-> I5 (the kernels depend on x - y only)
-      const int ci = a.leaf_of[i], cj = a.leaf_of[j];
-      int col = -1;
-      for (int q = a.lnbr_off[cj]; q < a.lnbr_off[cj + 1]; ++q)
-        if (a.lnbr[q] == ci) col = a.lnbr_col[q] + (i - a.leaf_start[ci]);
-      if (col >= 0) {
-        const int S = (int)(a.src_off[cj + 1] - a.src_off[cj]);
-        const double It[6] = {acc[0], acc[3], acc[4], acc[1], acc[2], acc[5]};
-        ent[a.ent_off[cj] + (int64_t)(j - a.leaf_start[cj]) * S + col] = combine(It, a.eps);
-      }
-    }
+    if (raw)
+      for (int m = 0; m < 6; ++m) raw[6 * it + m] = acc[m];
+    else
+      write_pair(a, CLS, i, j, item.ent, acc, ent);
   }
 }
 
@@ -318,7 +232,7 @@ __global__ void k_to_f32(const double4* __restrict__ src, float4* __restrict__ d
   }
 }
 
-static NearArgs near_args(fagbi_handle* h) {
+NearArgs near_args(fagbi_handle* h) {
   NearArgs a;
   a.pv = h->d_pv.as<double>();
   a.pn = h->d_pn.as<double>();
@@ -340,6 +254,25 @@ static NearArgs near_args(fagbi_handle* h) {
   return a;
 }
 
+int run_singular(fagbi_handle* h, int cls_index, const uint8_t* skip, double* raw, hipStream_t s) {
+  NearArgs a = near_args(h);
+  const int64_t m = h->wl_n[cls_index];
+  if (m == 0) return 0;
+  const unsigned g = (unsigned)((m + 3) / 4);
+  const int n = h->prm.quad_duffy;
+  const double* gl = h->d_gl.as<double>();
+  double4* E = h->d_E64.as<double4>();
+  const Item* it = h->d_wl[cls_index].as<Item>();
+  switch (cls_index) {
+    case 0: k_near_singular<C_IDENT><<<g, 256, 0, s>>>(a, it, m, gl, n, E, skip, raw); break;
+    case 1: k_near_singular<C_EDGE><<<g, 256, 0, s>>>(a, it, m, gl, n, E, skip, raw); break;
+    case 2: k_near_singular<C_VERTEX><<<g, 256, 0, s>>>(a, it, m, gl, n, E, skip, raw); break;
+    default: k_near_singular<C_CLOSE><<<g, 256, 0, s>>>(a, it, m, gl, n, E, skip, raw); break;
+  }
+  FAGBI_HIP(hipGetLastError());
+  return 0;
+}
+
 int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   const int nl = h->lev[h->L].n;
   NearArgs a = near_args(h);
@@ -355,27 +288,39 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   unsigned long long c[4];
   FAGBI_HIP(hipMemcpyAsync(c, cnt.p, sizeof c, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
-  for (int k = 0; k < 4; ++k) h->singular_count[k] = (int64_t)c[k];
-  Tmp wl[4];
-  for (int k = 0; k < 4; ++k) FAGBI_TRY(wl[k].alloc((size_t)std::max<unsigned long long>(c[k], 1) * sizeof(Item)));
+  for (int k = 0; k < 4; ++k) {
+    h->singular_count[k] = (int64_t)c[k];
+    h->wl_n[k] = (int64_t)c[k];
+    FAGBI_TRY(h->alloc(h->d_wl[k], (size_t)std::max<unsigned long long>(c[k], 1) * sizeof(Item)));
+  }
   FAGBI_HIP(hipMemcpyAsync(cap.p, c, sizeof c, hipMemcpyHostToDevice, s));
   FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(unsigned long long), s));
-  k_near_classify<1><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), cap.as<unsigned long long>(), wl[0].as<Item>(),
-                                        wl[1].as<Item>(), wl[2].as<Item>(), wl[3].as<Item>(),
-                                        h->d_E64.as<double4>());
+  k_near_classify<1><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), cap.as<unsigned long long>(),
+                                        h->d_wl[0].as<Item>(), h->d_wl[1].as<Item>(), h->d_wl[2].as<Item>(),
+                                        h->d_wl[3].as<Item>(), h->d_E64.as<double4>());
   FAGBI_HIP(hipGetLastError());
-  const int n = h->prm.quad_duffy;
-  const double* gl = h->d_gl.as<double>();
-  double4* E = h->d_E64.as<double4>();
-  auto grid = [](unsigned long long m) { return (unsigned)((m + 3) / 4); };
-  if (c[0]) k_near_singular<C_IDENT><<<grid(c[0]), 256, 0, s>>>(a, wl[0].as<Item>(), c[0], gl, n, E);
-  if (c[1]) k_near_singular<C_EDGE><<<grid(c[1]), 256, 0, s>>>(a, wl[1].as<Item>(), c[1], gl, n, E);
-  if (c[2]) k_near_singular<C_VERTEX><<<grid(c[2]), 256, 0, s>>>(a, wl[2].as<Item>(), c[2], gl, n, E);
-  if (c[3]) k_near_singular<C_CLOSE><<<grid(c[3]), 256, 0, s>>>(a, wl[3].as<Item>(), c[3], gl, n, E);
-  FAGBI_HIP(hipGetLastError());
-  k_to_f32<<<2048, 256, 0, s>>>(E, h->d_E32.as<float4>(), h->n_ent);
+  // identical pairs: always the FP64 singular cubature
+  FAGBI_TRY(run_singular(h, 0, nullptr, nullptr, s));
+  const bool use_mlp = h->prm.mlp_mode != FAGBI_MLP_OFF && h->mlp_ready;
+  h->mlp_gated_pairs = 0;
+  if (use_mlp) {
+    // the surrogate writes its entries for every near-singular pair and flags
+    // the ones whose calibrated error passes the gate
+    FAGBI_TRY(mlp_assembly_stage(h, s));
+    if (h->prm.mlp_mode == FAGBI_MLP_PRECOND) {
+      // preconditioner from the surrogate's entries, operator from cubature
+      FAGBI_TRY(precond_setup(h, s));
+      for (int k = 1; k < 4; ++k) FAGBI_TRY(run_singular(h, k, nullptr, nullptr, s));
+    } else {
+      for (int k = 1; k < 4; ++k) FAGBI_TRY(run_singular(h, k, h->d_mlp_skip[k].as<uint8_t>(), nullptr, s));
+    }
+  } else {
+    for (int k = 1; k < 4; ++k) FAGBI_TRY(run_singular(h, k, nullptr, nullptr, s));
+  }
+  k_to_f32<<<2048, 256, 0, s>>>(h->d_E64.as<double4>(), h->d_E32.as<float4>(), h->n_ent);
   FAGBI_HIP(hipGetLastError());
   FAGBI_HIP(hipStreamSynchronize(s));
+  h->precond_ready = use_mlp && h->prm.mlp_mode == FAGBI_MLP_PRECOND;
   return 0;
 }
 
