@@ -1,8 +1,9 @@
 """Build libfagbi.so (HIP for gfx950) in the package directory.
 
 hipcc compiles each .hip file to an object (device code for gfx950 only,
-packed FP32 instructions disabled), the host-only tree builder is compiled
-with FP contraction off, and everything is linked into one shared library.
+packed FP32 instructions disabled; the tree builder additionally without FP
+contraction, so that its cube indices, radii and separation tests are the
+IEEE results of the written expressions) and links one shared library.
 """
 import os
 import subprocess
@@ -34,10 +35,8 @@ def build(verbose=False):
         src = os.path.join(CSRC, f)
         obj = os.path.join(BUILD, f + ".o")
         if f.endswith(".hip"):
-            jobs.append([HIPCC, "-c", src, "-o", obj] + HIP_FLAGS)
-        elif f.endswith(".cpp"):
-            jobs.append(["g++", "-c", src, "-o", obj, "-O2", "-std=c++17", "-fPIC",
-                         "-ffp-contract=off", "-I" + os.path.join(HERE, "..", "include")])
+            extra = ["-ffp-contract=off"] if f == "tree.hip" else []
+            jobs.append([HIPCC, "-c", src, "-o", obj] + HIP_FLAGS + extra)
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         list(ex.map(_run, jobs))
     objs = [j[4] for j in jobs]

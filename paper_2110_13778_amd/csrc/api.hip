@@ -5,7 +5,6 @@
 #include <new>
 
 #include "internal.h"
-#include "tree.h"
 
 namespace fagbi {
 
@@ -202,124 +201,7 @@ int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int
                      int64_t nt) {
   if (!h || !verts || !tris) return set_error(FAGBI_E_ARG, "null argument");
   if (nt > (int64_t)1 << 30) return set_error(FAGBI_E_ARG, "too many panels");
-  TreeOut T;
-  std::string err;
-  int r = build_tree_host(verts, nv, tris, nt, h->prm.leaf_size, h->prm.eta0, T, err);
-  if (r < 0) return set_error(r, "%s", err.c_str());
-  h->near_ready = false;
-  h->tree_ready = false;
-  // a new mesh replaces every device buffer (level buffers live inside
-  // h->lev, which is rebuilt below)
-  FAGBI_HIP(hipDeviceSynchronize());
-  h->free_all();
-  {
-    std::vector<double> gl(32, 0.0);
-    gauss_legendre01(h->prm.quad_duffy, gl.data(), gl.data() + 16);
-    FAGBI_TRY(h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double)));
-  }
-  h->N = nt;
-  h->nv = nv;
-  h->L = T.L;
-  h->lmin = T.lmin;
-  h->side = T.side;
-  for (int d = 0; d < 3; ++d) h->corner[d] = T.corner[d];
-  h->perm = T.perm;
-  const int64_t N = nt;
-  FAGBI_TRY(h->upload(h->d_perm, T.perm.data(), N * 4));
-  FAGBI_TRY(h->upload(h->d_pv, T.corners.data(), 9 * N * 8));
-  FAGBI_TRY(h->upload(h->d_pn, T.normal.data(), 3 * N * 8));
-  FAGBI_TRY(h->upload(h->d_pa, T.area.data(), N * 8));
-  FAGBI_TRY(h->upload(h->d_ptri, T.tri.data(), 3 * N * 4));
-  // levels
-  h->lev.assign(T.L + 1, Level());
-  for (int l = 0; l <= T.L; ++l) {
-    TreeLevel& S = T.lev[l];
-    Level& D = h->lev[l];
-    D.n = S.n;
-    D.h = S.h;
-    D.rho = S.rho;
-    D.order = h->prm.adaptive ? std::min(h->prm.p_leaf + T.L - l, h->prm.p_max) : h->prm.p_leaf;
-    D.T = nterms(D.order);
-    D.idx = S.idx;
-    D.parent = S.parent;
-    D.child_start = S.child_start;
-    D.child_end = S.child_end;
-    D.nbr_off = S.nbr_off;
-    D.nbr = S.nbr;
-    D.inter_off = S.inter_off;
-    D.inter_src = S.inter_src;
-    D.inter_oid = S.inter_oid;
-    D.off_xyz = S.off_xyz;
-    D.n_off = (int)(S.off_xyz.size() / 3);
-    FAGBI_TRY(h->upload(D.d_idx, D.idx.data(), D.idx.size() * 4));
-    FAGBI_TRY(h->upload(D.d_parent, D.parent.data(), D.parent.size() * 4));
-    FAGBI_TRY(h->upload(D.d_child_start, D.child_start.data(), D.child_start.size() * 4));
-    FAGBI_TRY(h->upload(D.d_child_end, D.child_end.data(), D.child_end.size() * 4));
-    FAGBI_TRY(h->upload(D.d_inter_off, D.inter_off.data(), D.inter_off.size() * 4));
-    FAGBI_TRY(h->upload(D.d_inter_src, D.inter_src.data(), D.inter_src.size() * 4));
-    FAGBI_TRY(h->upload(D.d_inter_oid, D.inter_oid.data(), D.inter_oid.size() * 4));
-  }
-  // leaf-level near-field layout: per leaf c, the source panels of every
-  // c' in N(c), and n_c x S_c entries stored row by row
-  const TreeLevel& LF = T.lev[T.L];
-  const int nl = LF.n;
-  h->leaf_start.assign(LF.start.begin(), LF.start.end());
-  h->leaf_cnt.resize(nl);
-  h->max_leaf = 0;
-  for (int c = 0; c < nl; ++c) {
-    h->leaf_cnt[c] = LF.end[c] - LF.start[c];
-    h->max_leaf = std::max(h->max_leaf, h->leaf_cnt[c]);
-  }
-  h->src_off.assign(nl + 1, 0);
-  h->ent_off.assign(nl + 1, 0);
-  h->self_col.assign(nl, -1);
-  for (int c = 0; c < nl; ++c) {
-    int64_t s = 0;
-    for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
-      if (LF.nbr[q] == c) h->self_col[c] = (int32_t)s;
-      s += h->leaf_cnt[LF.nbr[q]];
-    }
-    h->src_off[c + 1] = h->src_off[c] + s;
-    h->ent_off[c + 1] = h->ent_off[c] + s * h->leaf_cnt[c];
-  }
-  h->n_src = h->src_off[nl];
-  h->n_ent = h->ent_off[nl];
-  std::vector<int32_t> src_tree(h->n_src), src_user(h->n_src), leaf_of(N);
-  for (int c = 0; c < nl; ++c) {
-    int64_t k = h->src_off[c];
-    for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
-      const int c2 = LF.nbr[q];
-      for (int j = LF.start[c2]; j < LF.end[c2]; ++j) {
-        src_tree[k] = j;
-        src_user[k] = T.perm[j];
-        ++k;
-      }
-    }
-    for (int i = LF.start[c]; i < LF.end[c]; ++i) leaf_of[i] = c;
-  }
-  FAGBI_TRY(h->upload(h->d_leaf_start, h->leaf_start.data(), nl * 4));
-  FAGBI_TRY(h->upload(h->d_leaf_cnt, h->leaf_cnt.data(), nl * 4));
-  FAGBI_TRY(h->upload(h->d_src_off, h->src_off.data(), (nl + 1) * 8));
-  FAGBI_TRY(h->upload(h->d_ent_off, h->ent_off.data(), (nl + 1) * 8));
-  FAGBI_TRY(h->upload(h->d_self_col, h->self_col.data(), nl * 4));
-  {
-    std::vector<int32_t> col(LF.nbr.size());
-    for (int c = 0; c < nl; ++c) {
-      int32_t s = 0;
-      for (int q = LF.nbr_off[c]; q < LF.nbr_off[c + 1]; ++q) {
-        col[q] = s;
-        s += h->leaf_cnt[LF.nbr[q]];
-      }
-    }
-    FAGBI_TRY(h->upload(h->d_lnbr_off, LF.nbr_off.data(), LF.nbr_off.size() * 4));
-    FAGBI_TRY(h->upload(h->d_lnbr, LF.nbr.data(), LF.nbr.size() * 4));
-    FAGBI_TRY(h->upload(h->d_lnbr_col, col.data(), col.size() * 4));
-  }
-  FAGBI_TRY(h->upload(h->d_src_tree, src_tree.data(), h->n_src * 4));
-  FAGBI_TRY(h->upload(h->d_src_user, src_user.data(), h->n_src * 4));
-  FAGBI_TRY(h->upload(h->d_leaf_of, leaf_of.data(), N * 4));
-  h->tree_ready = true;
-  return 0;
+  return fagbi::build_tree(h, verts, nv, tris, nt);
 }
 
 int fagbi_assemble_nearfield(fagbi_handle* h, void* stream) {
@@ -389,7 +271,7 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
   int64_t pairs = 0, macs = 0;
   for (int l = 0; l <= h->L; ++l) {
     const Level& D = h->lev[l];
-    const int64_t np = (int64_t)D.inter_src.size();
+    const int64_t np = D.n_inter;
     pairs += np;
     int64_t per = 0;   // sum over alpha of T(p - |alpha|)
     for (int d = 0; d <= D.order; ++d) per += (int64_t)((d + 1) * (d + 2) / 2) * nterms(D.order - d);
@@ -421,7 +303,7 @@ int fagbi_get_profile(fagbi_handle* h, fagbi_profile* out) {
 int fagbi_get_permutation(fagbi_handle* h, int32_t* perm) {
   if (!h || !perm) return set_error(FAGBI_E_ARG, "null argument");
   if (!h->tree_ready) return set_error(FAGBI_E_STATE, "no tree");
-  memcpy(perm, h->perm.data(), h->N * 4);
+  FAGBI_HIP(hipMemcpy(perm, h->d_perm.p, h->N * 4, hipMemcpyDeviceToHost));
   return 0;
 }
 

@@ -63,14 +63,11 @@ struct Level {
   int order = 0;      // expansion order p_l
   int T = 0;          // terms of order p_l
   double h = 0, rho = 0;
-  std::vector<int32_t> idx;          // 3n cube indices
-  std::vector<int32_t> parent;       // n
-  std::vector<int32_t> child_start, child_end;  // n (children on level+1)
-  std::vector<int32_t> nbr_off, nbr;            // CSR neighbour lists
-  std::vector<int32_t> inter_off, inter_src, inter_oid;  // CSR interaction lists
+  int64_t n_inter = 0;               // interaction pairs (c, c' in I(c))
   std::vector<int32_t> off_xyz;      // 3 * n_off distinct offsets (c - c')
   int n_off = 0;
-  // device
+  // device: cube indices [n][3], parent [n] (-1 on level 0), children on
+  // level+1 [child_start, child_end), CSR interaction lists with offset ids
   DBuf d_idx, d_parent, d_child_start, d_child_end, d_inter_off, d_inter_src, d_inter_oid;
   DBuf d_F64[2], d_F32[2];           // Taylor tables per offset [n_off][T], G0 / Gk
   DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
@@ -94,17 +91,16 @@ struct fagbi_handle {
   int64_t N = 0, nv = 0;
   int L = -1, lmin = 0;
   double corner[3] = {0, 0, 0}, side = 0;
-  std::vector<int32_t> perm;          // tree position -> caller panel index
   std::vector<fagbi::Level> lev;      // 0..L
-  // leaf-level near field layout
-  std::vector<int32_t> leaf_start, leaf_cnt;
-  std::vector<int64_t> src_off, ent_off;
-  std::vector<int32_t> self_col;
+  // leaf-level near field layout (panels per leaf; device arrays below)
+  std::vector<int32_t> leaf_cnt;
   int64_t n_src = 0, n_ent = 0;
   int max_leaf = 0;
   bool tree_ready = false, near_ready = false;
   int64_t singular_count[4] = {0, 0, 0, 0};
   // ---- device buffers ----
+  // tree position -> caller panel index; per panel in tree order: corners
+  // [9], unit normal [3], area, vertex ids [3]; leaf of each panel
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
   fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
@@ -140,6 +136,7 @@ struct fagbi_handle {
 
 namespace fagbi {
 // stages implemented in the .hip files
+int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* tris, int64_t nt);
 int assemble_nearfield(fagbi_handle* h, hipStream_t s);
 int fmm_setup(fagbi_handle* h, hipStream_t s);
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts,
