@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fagbi.h"
+#include "fmath.h"
 
 namespace fagbi {
 
@@ -102,6 +103,7 @@ struct fagbi_handle {
   // tree position -> caller panel index; per panel in tree order: corners
   // [9], unit normal [3], area, vertex ids [3]; leaf of each panel
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
+  fagbi::DBuf d_pc;                   // per panel: centroid, sqrt(area)
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
   fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
@@ -173,12 +175,13 @@ __device__ inline float wave_sum(float v) {
 __device__ inline void kernel6(double rx, double ry, double rz, const double* nx,
                                const double* ny, double kappa, double* k) {
   const double r2 = rx * rx + ry * ry + rz * rz;
-  const double r = sqrt(r2);
-  const double u = kappa * r;
-  const double em1 = expm1(-u);
-  const double E = em1 + 1.0;
-  const double i4pr = 1.0 / (FOUR_PI * r);
-  const double i4pr3 = i4pr / r2;
+  const double ir = inv_sqrt(r2);
+  const double u = kappa * (r2 * ir);
+  double E, em1;
+  exp_expm1(-u, E, em1);
+  const double i4pr = ir * (1.0 / FOUR_PI);
+  const double ir2 = ir * ir;
+  const double i4pr3 = i4pr * ir2;
   const double rny = rx * ny[0] + ry * ny[1] + rz * ny[2];
   const double rnx = rx * nx[0] + ry * nx[1] + rz * nx[2];
   const double nn = nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2];
@@ -190,7 +193,7 @@ __device__ inline void kernel6(double rx, double ry, double rz, const double* nx
   k[4] = -e1u * rnx * i4pr3;
   const double c1 = em1 + u * E;
   const double c2 = 3.0 * em1 + 3.0 * u * E + u * u * E;
-  k[5] = (c1 * nn - c2 * rnx * rny / r2) * i4pr3;
+  k[5] = (c1 * nn - c2 * rnx * rny * ir2) * i4pr3;
 }
 
 }  // namespace fagbi

@@ -17,6 +17,7 @@ struct NearArgs {
   const double* pv;     // corners [N][9]
   const double* pn;     // normals [N][3]
   const double* pa;     // areas [N]
+  const double4* pc;    // centroid and sqrt(area) [N]
   const int32_t* ptri;  // vertex ids [N][3]
   const int32_t* leaf_start;
   const int32_t* leaf_cnt;
@@ -42,16 +43,10 @@ __device__ inline int classify(const NearArgs& a, int i, int j) {
   if (shared == 1) return C_VERTEX;
   // centroid distance, evaluated without contraction so the test is the
   // IEEE result of the written expression
-  double s[3];
-  for (int d = 0; d < 3; ++d) {
-    const double ci = __dadd_rn(__dadd_rn(a.pv[9 * i + d], a.pv[9 * i + 3 + d]), a.pv[9 * i + 6 + d]) / 3.0;
-    const double cj = __dadd_rn(__dadd_rn(a.pv[9 * j + d], a.pv[9 * j + 3 + d]), a.pv[9 * j + 6 + d]) / 3.0;
-    s[d] = __dadd_rn(ci, -cj);
-  }
-  const double dist = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(s[0], s[0]), __dmul_rn(s[1], s[1])),
-                                     __dmul_rn(s[2], s[2])));
-  const double hm = fmax(sqrt(a.pa[i]), sqrt(a.pa[j]));
-  return dist < __dmul_rn(a.near_ratio, hm) ? C_CLOSE : C_REGULAR;
+  const double4 pi = a.pc[i], pj = a.pc[j];
+  const double s0 = __dadd_rn(pi.x, -pj.x), s1 = __dadd_rn(pi.y, -pj.y), s2 = __dadd_rn(pi.z, -pj.z);
+  const double dist = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(s0, s0), __dmul_rn(s1, s1)), __dmul_rn(s2, s2)));
+  return dist < __dmul_rn(a.near_ratio, fmax(pi.w, pj.w)) ? C_CLOSE : C_REGULAR;
 }
 
 __device__ inline void regular_pair(const NearArgs& a, int i, int j, double* I) {

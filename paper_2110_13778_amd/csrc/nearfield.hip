@@ -29,30 +29,38 @@
 // (lanes over quadrature points, fixed-order reduction), so FP64 results do
 // not depend on scheduling.
 #include "near.h"
+#include "scan.h"
 
 namespace fagbi {
 
-// pass 0: count singular pairs per class; pass 1: regular entries + worklists
+// pass 0: count the singular / close pairs of each class per leaf (block);
+// pass 1: regular entries, and the worklists at the scanned offsets.  Slots
+// inside a block follow (iteration, wave, lane), so the worklists do not
+// depend on scheduling.  blk is [4][nl]: counts (pass 0) or the exclusive
+// scan of the counts over the flattened array (pass 1).
 template <int PASS>
-__global__ void __launch_bounds__(256) k_near_classify(NearArgs a, unsigned long long* counters,
-                                                       const unsigned long long* capacity,
-                                                       Item* w_ident, Item* w_edge, Item* w_vertex,
-                                                       Item* w_close, double4* ent) {
+__global__ void __launch_bounds__(256) k_near_classify(NearArgs a, int64_t* blk, int nl, Item* w_ident,
+                                                       Item* w_edge, Item* w_vertex, Item* w_close,
+                                                       double4* ent) {
+  __shared__ int wcnt[4][4];   // [wave][class - 1]
   const int c = blockIdx.x;
   const int nc = a.leaf_cnt[c];
   const int i0 = a.leaf_start[c];
   const int64_t so = a.src_off[c];
   const int S = (int)(a.src_off[c + 1] - so);
   const int64_t eo = a.ent_off[c];
-  const int64_t total = (int64_t)nc * S;
-  const int lane = threadIdx.x & 63;
-  for (int64_t base = 0; base < total; base += blockDim.x) {
-    const int64_t e = base + threadIdx.x;
+  const int total = nc * S;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t run[4];
+#pragma unroll
+  for (int C = 0; C < 4; ++C) run[C] = PASS ? blk[(int64_t)C * nl + c] - blk[(int64_t)C * nl] : 0;
+  for (int base = 0; base < total; base += blockDim.x) {
+    const int e = base + threadIdx.x;
     const bool valid = e < total;
     int cls = -1, i = 0, j = 0;
     if (valid) {
-      const int il = (int)(e / S);
-      const int k = (int)(e - (int64_t)il * S);
+      const int il = e / S;
+      const int k = e - il * S;
       i = i0 + il;
       j = a.src_tree[so + k];
       cls = classify(a, i, j);
@@ -65,23 +73,31 @@ __global__ void __launch_bounds__(256) k_near_classify(NearArgs a, unsigned long
         ent[eo + e] = combine(I, a.eps);
       }
     }
+    unsigned long long mask[4];
 #pragma unroll
-    for (int C = 1; C <= 4; ++C) {
-      const unsigned long long mask = __ballot(cls == C);
-      if (mask == 0) continue;
-      const int cnt = __popcll(mask);
-      const int leader = __ffsll((long long)mask) - 1;
-      unsigned long long basepos = 0;
-      if (lane == leader) basepos = atomicAdd(&counters[C - 1], (unsigned long long)cnt);
-      basepos = __shfl(basepos, leader, 64);
-      if (PASS == 1 && cls == C) {
-        const unsigned long long pos = basepos + __popcll(mask & ((1ull << lane) - 1ull));
-        Item it{i, j, eo + e};
-        Item* wl = C == C_IDENT ? w_ident : C == C_EDGE ? w_edge : C == C_VERTEX ? w_vertex : w_close;
-        if (pos < capacity[C - 1]) wl[pos] = it;
-      }
+    for (int C = 0; C < 4; ++C) {
+      mask[C] = __ballot(cls == C + 1);
+      if (lane == 0) wcnt[wave][C] = __popcll(mask[C]);
     }
+    __syncthreads();
+#pragma unroll
+    for (int C = 0; C < 4; ++C) {
+      int before = 0, all = 0;
+      for (int w = 0; w < 4; ++w) {
+        before += w < wave ? wcnt[w][C] : 0;
+        all += wcnt[w][C];
+      }
+      if (PASS == 1 && cls == C + 1) {
+        const int64_t pos = run[C] + before + __popcll(mask[C] & ((1ull << lane) - 1ull));
+        Item* wl = C == 0 ? w_ident : C == 1 ? w_edge : C == 2 ? w_vertex : w_close;
+        wl[pos] = Item{i, j, eo + e};
+      }
+      run[C] += all;
+    }
+    __syncthreads();
   }
+  if (PASS == 0 && threadIdx.x == 0)
+    for (int C = 0; C < 4; ++C) blk[(int64_t)C * nl + c] = run[C];
 }
 
 // one wavefront per singular / close pair
@@ -238,6 +254,7 @@ NearArgs near_args(fagbi_handle* h) {
   a.pn = h->d_pn.as<double>();
   a.pa = h->d_pa.as<double>();
   a.ptri = h->d_ptri.as<int32_t>();
+  a.pc = h->d_pc.as<double4>();
   a.leaf_start = h->d_leaf_start.as<int32_t>();
   a.leaf_cnt = h->d_leaf_cnt.as<int32_t>();
   a.src_off = h->d_src_off.as<int64_t>();
@@ -278,26 +295,28 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   NearArgs a = near_args(h);
   FAGBI_TRY(h->alloc(h->d_E64, (size_t)h->n_ent * sizeof(double4)));
   FAGBI_TRY(h->alloc(h->d_E32, (size_t)h->n_ent * sizeof(float4)));
-  Tmp cnt, cap;
-  FAGBI_TRY(cnt.alloc(4 * sizeof(unsigned long long)));
-  FAGBI_TRY(cap.alloc(4 * sizeof(unsigned long long)));
-  FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(unsigned long long), s));
-  k_near_classify<0><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), nullptr, nullptr, nullptr,
-                                        nullptr, nullptr, nullptr);
+  // per-leaf class counts, one scan over the flattened [class][leaf] array,
+  // then the worklists at the scanned offsets
+  Tmp cnt, off, part;
+  const int64_t m = 4 * (int64_t)nl;
+  FAGBI_TRY(cnt.alloc(m * 8));
+  FAGBI_TRY(off.alloc((m + 1) * 8));
+  FAGBI_TRY(part.alloc(scan_part_size(m) * 8));
+  k_near_classify<0><<<nl, 256, 0, s>>>(a, cnt.as<int64_t>(), nl, nullptr, nullptr, nullptr, nullptr, nullptr);
   FAGBI_HIP(hipGetLastError());
-  unsigned long long c[4];
-  FAGBI_HIP(hipMemcpyAsync(c, cnt.p, sizeof c, hipMemcpyDeviceToHost, s));
+  FAGBI_TRY((device_scan<int64_t, int64_t>(cnt.as<int64_t>(), m, off.as<int64_t>(), part.as<int64_t>(), s)));
+  int64_t bnd[5];
+  for (int k = 0; k < 5; ++k)
+    FAGBI_HIP(hipMemcpyAsync(&bnd[k], off.as<int64_t>() + (int64_t)k * nl, 8, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < 4; ++k) {
-    h->singular_count[k] = (int64_t)c[k];
-    h->wl_n[k] = (int64_t)c[k];
-    FAGBI_TRY(h->alloc(h->d_wl[k], (size_t)std::max<unsigned long long>(c[k], 1) * sizeof(Item)));
+    const int64_t c = bnd[k + 1] - bnd[k];
+    h->singular_count[k] = c;
+    h->wl_n[k] = c;
+    FAGBI_TRY(h->alloc(h->d_wl[k], (size_t)std::max<int64_t>(c, 1) * sizeof(Item)));
   }
-  FAGBI_HIP(hipMemcpyAsync(cap.p, c, sizeof c, hipMemcpyHostToDevice, s));
-  FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(unsigned long long), s));
-  k_near_classify<1><<<nl, 256, 0, s>>>(a, cnt.as<unsigned long long>(), cap.as<unsigned long long>(),
-                                        h->d_wl[0].as<Item>(), h->d_wl[1].as<Item>(), h->d_wl[2].as<Item>(),
-                                        h->d_wl[3].as<Item>(), h->d_E64.as<double4>());
+  k_near_classify<1><<<nl, 256, 0, s>>>(a, off.as<int64_t>(), nl, h->d_wl[0].as<Item>(), h->d_wl[1].as<Item>(),
+                                        h->d_wl[2].as<Item>(), h->d_wl[3].as<Item>(), h->d_E64.as<double4>());
   FAGBI_HIP(hipGetLastError());
   // identical pairs: always the FP64 singular cubature
   FAGBI_TRY(run_singular(h, 0, nullptr, nullptr, s));

@@ -9,11 +9,22 @@
 #include <cmath>
 #include <functional>
 
+#include "fmath.h"
 #include "internal.h"
 
 namespace fagbi {
 
 constexpr int RB = 256;   // reduction block
+
+// Both direct sums run one thread per panel over its three quadrature points
+// (barycentric (2/3, 1/6, 1/6) and permutations, weight A/3) with the charges
+// staged through LDS; charges carry q / (4 pi).  FP64 throughout.
+__device__ inline void quad_points(const double* __restrict__ pv, int64_t i, double* qp) {
+  const double* v = pv + 9 * i;
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d)
+      qp[3 * k + d] = (2.0 / 3.0) * v[3 * k + d] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + d] + v[3 * ((k + 2) % 3) + d]);
+}
 
 // b1 = (1/eps_in) sum_q w_q sum_k q_k G0(x_q, y_k); b2 likewise with dG0/dn_x
 __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, const double* __restrict__ pn,
@@ -23,31 +34,32 @@ __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, cons
   __shared__ double4 tile[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < N;
-  double qp[9] = {0}, n[3] = {0}, w = 0;
+  double qp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, n[3] = {0, 0, 0}, w = 0;
   if (valid) {
-    const double* v = pv + 9 * (int64_t)i;
-    for (int k = 0; k < 3; ++k)
-      for (int d = 0; d < 3; ++d)
-        qp[3 * k + d] = (2.0 / 3.0) * v[3 * k + d] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + d] + v[3 * ((k + 2) % 3) + d]);
+    quad_points(pv, i, qp);
     for (int d = 0; d < 3; ++d) n[d] = pn[3 * i + d];
     w = pa[i] / 3.0;
   }
   double s1 = 0, s2 = 0;
   for (int t0 = 0; t0 < nc; t0 += 256) {
     __syncthreads();
-    if (t0 + (int)threadIdx.x < nc) tile[threadIdx.x] = chg[t0 + threadIdx.x];
+    if (t0 + (int)threadIdx.x < nc) {
+      double4 c = chg[t0 + threadIdx.x];
+      c.w *= 1.0 / FOUR_PI;
+      tile[threadIdx.x] = c;
+    }
     __syncthreads();
     const int m = min(256, nc - t0);
     if (valid)
       for (int k = 0; k < m; ++k) {
         const double4 c = tile[k];
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
           const double rx = qp[3 * q] - c.x, ry = qp[3 * q + 1] - c.y, rz = qp[3 * q + 2] - c.z;
-          const double r2 = rx * rx + ry * ry + rz * rz;
-          const double ir = 1.0 / sqrt(r2);
-          const double g = c.w * ir / FOUR_PI;
+          const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
+          const double g = c.w * ir;
           s1 += g;
-          s2 -= g * (rx * n[0] + ry * n[1] + rz * n[2]) * ir * ir;
+          s2 -= g * (rx * n[0] + ry * n[1] + rz * n[2]) * (ir * ir);
         }
       }
   }
@@ -58,7 +70,9 @@ __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, cons
   }
 }
 
-// per-panel reaction potential contributions sum_n q_n int [K1 dphi + K2 phi]
+// per-block partial sums of sum_i w_i sum_q sum_n q_n [K1 dphi_i + K2 phi_i]
+// with K1 = (G0 - Gk)(x_n, y), K2 = d/dn_y (eps Gk - G0)(x_n, y), y on the
+// panel
 __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ pv, const double* __restrict__ pn,
                                                 const double* __restrict__ pa, const int32_t* __restrict__ perm,
                                                 int N, const double4* __restrict__ chg, int nc, double eps,
@@ -67,44 +81,44 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ pv, c
   __shared__ double red[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < N;
-  double qp[9] = {0}, n[3] = {0}, w = 0, phi = 0, dphi = 0;
+  double qp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, n[3] = {0, 0, 0}, w = 0, phi = 0, dphi = 0;
   if (valid) {
-    const double* v = pv + 9 * (int64_t)i;
-    for (int k = 0; k < 3; ++k)
-      for (int d = 0; d < 3; ++d)
-        qp[3 * k + d] = (2.0 / 3.0) * v[3 * k + d] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + d] + v[3 * ((k + 2) % 3) + d]);
+    quad_points(pv, i, qp);
     for (int d = 0; d < 3; ++d) n[d] = pn[3 * i + d];
     w = pa[i] / 3.0;
     const int p = perm[i];
     phi = x[p];
     dphi = x[N + p];
   }
-  double acc = 0;
+  double a1 = 0, a2 = 0;   // sum q K1, sum q K2
   for (int t0 = 0; t0 < nc; t0 += 256) {
     __syncthreads();
-    if (t0 + (int)threadIdx.x < nc) tile[threadIdx.x] = chg[t0 + threadIdx.x];
+    if (t0 + (int)threadIdx.x < nc) {
+      double4 c = chg[t0 + threadIdx.x];
+      c.w *= 1.0 / FOUR_PI;
+      tile[threadIdx.x] = c;
+    }
     __syncthreads();
     const int m = min(256, nc - t0);
     if (valid)
       for (int k = 0; k < m; ++k) {
         const double4 c = tile[k];
-        double pot = 0;
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
           const double rx = c.x - qp[3 * q], ry = c.y - qp[3 * q + 1], rz = c.z - qp[3 * q + 2];
           const double r2 = rx * rx + ry * ry + rz * rz;
-          const double r = sqrt(r2);
-          const double u = kappa * r;
-          const double em1 = expm1(-u);
-          const double E = em1 + 1.0;
+          const double ir = inv_sqrt(r2);
+          const double u = kappa * (r2 * ir);
+          double E, em1;
+          exp_expm1(-u, E, em1);
           const double rny = rx * n[0] + ry * n[1] + rz * n[2];
-          const double k1 = -em1 / (FOUR_PI * r);
-          const double k2 = (eps * E * (1.0 + u) - 1.0) * rny / (FOUR_PI * r * r2);
-          pot += k1 * dphi + k2 * phi;
+          const double g = c.w * ir;
+          a1 -= g * em1;
+          a2 += g * (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir);
         }
-        acc += c.w * w * pot;
       }
   }
-  red[threadIdx.x] = acc;
+  red[threadIdx.x] = valid ? w * (a1 * dphi + a2 * phi) : 0.0;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];

@@ -31,15 +31,20 @@
 #include <memory>
 
 #include "internal.h"
+#include "scan.h"
 
 namespace fagbi {
 namespace {
 
 constexpr int DEEP = 20;                 // key resolution: 2^20 cubes per axis
 constexpr unsigned long long EMPTY = ~0ull;
-constexpr int TB = 256;                  // threads per block
-constexpr int IPT = 8;                   // items per thread in scans and sorts
-constexpr int TILE = TB * IPT;
+using scan_detail::TB;
+using scan_detail::IPT;
+using scan_detail::TILE;
+using scan_detail::block_exclusive_scan;
+using scan_detail::k_scan_reduce;
+using scan_detail::k_scan_part;
+using scan_detail::k_scan_down;
 
 __host__ __device__ inline uint64_t spread3(uint64_t x) {
   x &= 0x1fffffull;
@@ -75,85 +80,6 @@ __device__ inline uint64_t edge_hash(uint64_t k) {
   k *= 0xc4ceb9fe1a85ec53ull;
   k ^= k >> 33;
   return k;
-}
-
-// ---------------------------------------------------------------------------
-// block scan helpers (256 threads = 4 waves of 64)
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ inline T block_exclusive_scan(T v, T* lds, T& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const T y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) lds[w] = x;
-  __syncthreads();
-  T off = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < TB / 64; ++i) {
-    if (i < w) off += lds[i];
-    tot += lds[i];
-  }
-  __syncthreads();
-  total = tot;
-  return off + x - v;
-}
-
-// per-tile sums of the input
-template <typename TI, typename TO>
-__global__ void __launch_bounds__(TB) k_scan_reduce(const TI* __restrict__ in, int64_t n, TO* part) {
-  __shared__ TO lds[TB / 64];
-  const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x * IPT;
-  TO s = 0;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j)
-    if (base + j < n) s += (TO)in[base + j];
-  TO tot;
-  block_exclusive_scan<TO>(s, lds, tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// exclusive scan of the tile sums in place (one block), total at part[nb]
-template <typename TO>
-__global__ void __launch_bounds__(TB) k_scan_part(TO* part, int64_t nb) {
-  __shared__ TO lds[TB / 64];
-  TO carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += TB) {
-    const int64_t i = b0 + threadIdx.x;
-    const TO v = i < nb ? part[i] : (TO)0;
-    TO tot;
-    const TO ex = block_exclusive_scan<TO>(v, lds, tot);
-    if (i < nb) part[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) part[nb] = carry;
-}
-
-// out[i] = sum of in[0..i), out[n] = total
-template <typename TI, typename TO>
-__global__ void __launch_bounds__(TB) k_scan_down(const TI* __restrict__ in, int64_t n, const TO* __restrict__ part,
-                                                  int64_t nb, TO* out) {
-  __shared__ TO lds[TB / 64];
-  const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x * IPT;
-  TO v[IPT];
-  TO s = 0;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    v[j] = base + j < n ? (TO)in[base + j] : (TO)0;
-    s += v[j];
-  }
-  TO tot;
-  TO run = part[blockIdx.x] + block_exclusive_scan<TO>(s, lds, tot);
-#pragma unroll
-  for (int j = 0; j < IPT; ++j)
-    if (base + j < n) {
-      out[base + j] = run;
-      run += v[j];
-    }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[nb];
 }
 
 // ---------------------------------------------------------------------------
@@ -405,9 +331,12 @@ __global__ void k_leaf_order(const uint64_t* __restrict__ key, const int32_t* __
   keyL[k] = kl;
 }
 
+// tree-order panel arrays; pc = (centroid, sqrt(area)) for the near-field
+// classification
 __global__ void k_permute(const int32_t* __restrict__ perm, int64_t n, const double* __restrict__ cor,
                           const double* __restrict__ nrm, const double* __restrict__ area,
-                          const int32_t* __restrict__ tri, double* pv, double* pn, double* pa, int32_t* ptri) {
+                          const int32_t* __restrict__ tri, double* pv, double* pn, double* pa, int32_t* ptri,
+                          double4* pc) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t t = perm[k];
@@ -417,6 +346,9 @@ __global__ void k_permute(const int32_t* __restrict__ perm, int64_t n, const dou
     ptri[3 * k + d] = tri[3 * t + d];
   }
   pa[k] = area[t];
+  const double* c = cor + 9 * t;
+  pc[k] = make_double4((c[0] + c[3] + c[6]) / 3.0, (c[1] + c[4] + c[7]) / 3.0, (c[2] + c[5] + c[8]) / 3.0,
+                       sqrt(area[t]));
 }
 
 // ---------------------------------------------------------------------------
@@ -648,14 +580,9 @@ struct Arena {
 // exclusive scan in[0..n) -> out[0..n], out[n] = total
 template <typename TI, typename TO>
 int scan(Arena& A, const TI* in, int64_t n, TO* out, hipStream_t s) {
-  const int64_t nb = std::max<int64_t>(1, (n + TILE - 1) / TILE);
   TO* part;
-  FAGBI_TRY(A.get(part, nb + 1));
-  k_scan_reduce<TI, TO><<<(unsigned)nb, TB, 0, s>>>(in, n, part);
-  k_scan_part<TO><<<1, TB, 0, s>>>(part, nb);
-  k_scan_down<TI, TO><<<(unsigned)nb, TB, 0, s>>>(in, n, part, nb, out);
-  FAGBI_HIP(hipGetLastError());
-  return 0;
+  FAGBI_TRY(A.get(part, scan_part_size(n)));
+  return device_scan<TI, TO>(in, n, out, part, s);
 }
 
 int scan_ii(Arena& A, const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
@@ -817,10 +744,11 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_TRY(h->alloc(h->d_pn, 3 * N * 8));
   FAGBI_TRY(h->alloc(h->d_pa, N * 8));
   FAGBI_TRY(h->alloc(h->d_ptri, 3 * N * 4));
+  FAGBI_TRY(h->alloc(h->d_pc, N * sizeof(double4)));
   int32_t* perm = h->d_perm.as<int32_t>();
   k_leaf_order<<<grid_of(N), TB, 0, s>>>(key, val, N, 3 * (DEEP - L), leaf, perm, keyL);
   k_permute<<<grid_of(N), TB, 0, s>>>(perm, N, cor, nrm, area, dt, h->d_pv.as<double>(), h->d_pn.as<double>(),
-                                      h->d_pa.as<double>(), h->d_ptri.as<int32_t>());
+                                      h->d_pa.as<double>(), h->d_ptri.as<int32_t>(), h->d_pc.as<double4>());
   // ---- levels: clusters, cube indices, radii ---------------------------------
   std::vector<int32_t*> owner(L + 1), start(L + 1), end(L + 1);
   std::vector<int32_t*> excl(L + 1), flag(L + 1);
