@@ -79,6 +79,8 @@ typedef struct fagbi_params {
   double mlp_gate_tol;         /* gated near field: max estimated rel. error */
 } fagbi_params;
 
+#define FAGBI_MAX_LEVELS 21        /* levels 0..20 (cube keys have 20 levels) */
+
 typedef struct fagbi_tree_info {
   int64_t n_panels, n_leaves;
   int32_t levels;              /* leaf level L (levels are 0..L) */
@@ -89,6 +91,12 @@ typedef struct fagbi_tree_info {
   int64_t singular_pairs[4];   /* identical, edge, vertex, close */
   int32_t order_leaf, order_root;
   double rho_leaf, h_leaf;
+  /* per level l = 0..levels (entries beyond are 0) */
+  int32_t lev_clusters[FAGBI_MAX_LEVELS];   /* clusters (non-empty cubes) */
+  int32_t lev_order[FAGBI_MAX_LEVELS];      /* expansion order p_l */
+  int32_t lev_offsets[FAGBI_MAX_LEVELS];    /* distinct interaction offsets */
+  int32_t lev_pad;
+  int64_t lev_pairs[FAGBI_MAX_LEVELS];      /* interaction pairs (c, c' in I(c)) */
 } fagbi_tree_info;
 
 typedef struct fagbi_solve_info {

@@ -46,7 +46,9 @@ class TreeInfo(C.Structure):
                 ("lmin", C.c_int32), ("near_pairs", C.c_int64), ("m2l_pairs", C.c_int64),
                 ("m2l_flops_fp", C.c_int64), ("singular_pairs", C.c_int64 * 4),
                 ("order_leaf", C.c_int32), ("order_root", C.c_int32),
-                ("rho_leaf", C.c_double), ("h_leaf", C.c_double)]
+                ("rho_leaf", C.c_double), ("h_leaf", C.c_double),
+                ("lev_clusters", C.c_int32 * 21), ("lev_order", C.c_int32 * 21),
+                ("lev_offsets", C.c_int32 * 21), ("lev_pad", C.c_int32), ("lev_pairs", C.c_int64 * 21)]
 
 
 class SolveInfo(C.Structure):

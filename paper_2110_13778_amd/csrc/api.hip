@@ -276,6 +276,12 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
     int64_t per = 0;   // sum over alpha of T(p - |alpha|)
     for (int d = 0; d <= D.order; ++d) per += (int64_t)((d + 1) * (d + 2) / 2) * nterms(D.order - d);
     macs += 2 * np * per;
+    if (l < FAGBI_MAX_LEVELS) {
+      info->lev_clusters[l] = D.n;
+      info->lev_order[l] = D.order;
+      info->lev_offsets[l] = D.n_off;
+      info->lev_pairs[l] = np;
+    }
   }
   info->m2l_pairs = pairs;
   info->m2l_flops_fp = macs;

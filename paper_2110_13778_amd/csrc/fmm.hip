@@ -31,7 +31,7 @@
 
 namespace fagbi {
 
-__host__ __device__ inline int midx(int a, int b, int c) {
+__host__ __device__ constexpr int midx(int a, int b, int c) {
   const int d = a + b + c;
   const int below = d * (d + 1) * (d + 2) / 6;
   return below + (d - a) * (d - a + 1) / 2 + (d - a - b);
@@ -147,7 +147,7 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
 // P2M: one thread per (leaf, term)
 template <typename R>
 __global__ void k_p2m(const R* __restrict__ ms, const R* __restrict__ md, const int32_t* __restrict__ leaf_start,
-                      const int32_t* __restrict__ leaf_cnt, const int32_t* __restrict__ perm, int64_t N, int nl,
+                      const int32_t* __restrict__ leaf_cnt, int64_t N, int nl,
                       int T, double eps, const double* __restrict__ x, R* M0, R* Mk) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)nl * T) return;
@@ -155,8 +155,7 @@ __global__ void k_p2m(const R* __restrict__ ms, const R* __restrict__ md, const 
   const int i0 = leaf_start[c], n = leaf_cnt[c];
   R a0 = 0, ak = 0;
   for (int i = i0; i < i0 + n; ++i) {
-    const int p = perm[i];
-    const R phi = (R)x[p], dphi = (R)x[N + p];
+    const R phi = (R)x[2 * i], dphi = (R)x[2 * i + 1];   // x in tree order, interleaved
     const R s = ms[(int64_t)i * T + t], d = md[(int64_t)i * T + t];
     a0 += s * dphi - d * phi;
     ak += -s * dphi + (R)eps * d * phi;
@@ -286,6 +285,95 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
   }
 }
 
+// MtL for low orders with the whole expansion in registers: S consecutive
+// lanes share one target cluster and take every S-th entry of its
+// interaction list; per entry the offset's derivative table (T pairs) and the
+// source moments are loaded and all (alpha, beta) with |alpha| + |beta| <= P
+// are applied with compile-time indices; the S partial sums are combined by
+// lane shuffles.  The locals are written, not accumulated.
+template <int P>
+struct TermTable {
+  static constexpr int T = (P + 1) * (P + 2) * (P + 3) / 6;
+  int e[T][3];       // exponents of term t
+  int deg[T];
+  double msc[T];     // (-1)^|b| / b!
+  double lsc[T];     // 1 / a!
+  constexpr TermTable() : e(), deg(), msc(), lsc() {
+    for (int d = 0; d <= P; ++d)
+      for (int a = d; a >= 0; --a)
+        for (int b = d - a; b >= 0; --b) {
+          const int c = d - a - b;
+          const int t = midx(a, b, c);
+          e[t][0] = a;
+          e[t][1] = b;
+          e[t][2] = c;
+          deg[t] = d;
+          double f = 1;
+          for (int k = 2; k <= a; ++k) f *= k;
+          for (int k = 2; k <= b; ++k) f *= k;
+          for (int k = 2; k <= c; ++k) f *= k;
+          lsc[t] = 1.0 / f;
+          msc[t] = ((d & 1) ? -1.0 : 1.0) / f;
+        }
+  }
+};
+
+template <typename R, int P>
+__global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ inter_off,
+                                                 const int32_t* __restrict__ inter_src,
+                                                 const int32_t* __restrict__ inter_oid,
+                                                 const typename Pair<R>::T* __restrict__ Dt, int ncl, int S,
+                                                 const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
+  using R2 = typename Pair<R>::T;
+  constexpr TermTable<P> tt{};
+  constexpr int T = TermTable<P>::T;
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous (Morton) range of targets so that their sources share its L2
+  const int nbx = (int)((gridDim.x + 7) / 8);
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * nbx + (blockIdx.x >> 3);
+  const int64_t gt = blk * blockDim.x + threadIdx.x;
+  const int c = (int)(gt / S), part = (int)(gt - (int64_t)c * S);
+  R l0[T], lk[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0;
+  if (c < ncl) {
+    const int q1 = inter_off[c + 1];
+    for (int q = inter_off[c] + part; q < q1; q += S) {
+      const int64_t src = inter_src[q];
+      const R2* dp = Dt + (int64_t)inter_oid[q] * T;
+      R2 d[T];
+#pragma unroll
+      for (int g = 0; g < T; ++g) d[g] = dp[g];
+      const R* m0p = M0 + src * T;
+      const R* mkp = Mk + src * T;
+#pragma unroll
+      for (int tb = 0; tb < T; ++tb) {
+        const R m0 = m0p[tb] * (R)tt.msc[tb], mk = mkp[tb] * (R)tt.msc[tb];
+        // terms are ordered by degree: |alpha| <= P - |beta| is a prefix
+#pragma unroll
+        for (int ta = 0; ta < nterms(P - tt.deg[tb]); ++ta) {
+          const int g = midx(tt.e[ta][0] + tt.e[tb][0], tt.e[ta][1] + tt.e[tb][1], tt.e[ta][2] + tt.e[tb][2]);
+          l0[ta] += d[g].x * m0;
+          lk[ta] += d[g].y * mk;
+        }
+      }
+    }
+  }
+  // combine the S partial sums (S divides 64, groups are lane-aligned)
+  for (int o = S >> 1; o > 0; o >>= 1)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      l0[t] += __shfl_xor(l0[t], o, 64);
+      lk[t] += __shfl_xor(lk[t], o, 64);
+    }
+  if (c < ncl && part == 0)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      L0[(int64_t)c * T + t] = l0[t] * (R)tt.lsc[t];
+      Lk[(int64_t)c * T + t] = lk[t] * (R)tt.lsc[t];
+    }
+}
+
 // MtM: one block per parent; slot = (a | b << 16), a parent index, b child
 // index (b <= a componentwise); coefficient rows per child octant.
 template <typename R, int SPT>
@@ -411,11 +499,14 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
                                               const int32_t* __restrict__ leaf_cnt,
                                               const int64_t* __restrict__ src_off,
                                               const int64_t* __restrict__ ent_off,
-                                              const int32_t* __restrict__ src_user,
+                                              const int32_t* __restrict__ src_tree,
                                               const int32_t* __restrict__ perm, int64_t N, int nl,
-                                              const double* __restrict__ x, double* __restrict__ y) {
-  constexpr int RG = 8;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+                                              const double* __restrict__ xt, double* __restrict__ y) {
+  constexpr int RG = 4;
+  // contiguous leaf ranges per XCD (workgroups are dealt round-robin)
+  const int nbx = (int)((gridDim.x + 7) / 8);
+  const int blk = (int)(blockIdx.x & 7) * nbx + (int)(blockIdx.x >> 3);
+  const int c = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= nl) return;
   const int nc = leaf_cnt[c], i0 = leaf_start[c];
@@ -428,8 +519,8 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
 #pragma unroll
     for (int r = 0; r < RG; ++r) a1[r] = a2[r] = 0.0;
     for (int k = lane; k < S; k += 64) {
-      const int j = src_user[so + k];
-      const double xj = x[j], xn = x[N + j];
+      const double2 xv = reinterpret_cast<const double2*>(xt)[src_tree[so + k]];
+      const double xj = xv.x, xn = xv.y;
 #pragma unroll
       for (int r = 0; r < RG; ++r)
         if (r < nr) {
@@ -449,6 +540,14 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
         }
       }
   }
+}
+
+// xt = x in tree order, (phi, dphi) interleaved per panel
+__global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restrict__ perm, int64_t N, double* xt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t p = perm[i];
+  reinterpret_cast<double2*>(xt)[i] = make_double2(x[p], x[N + p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -627,10 +726,12 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     return 0;
   };
   FAGBI_TRY(mark(0));
+  double* xt = h->d_xt.as<double>();
+  k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), N, xt);
   if (parts & FAGBI_PART_NEAR) {
-    k_spmv<E><<<(unsigned)((nl + 3) / 4), 256, 0, s>>>(
+    k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, s>>>(
         ent.as<E>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
-        h->d_ent_off.as<int64_t>(), h->d_src_user.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl, x, y);
+        h->d_ent_off.as<int64_t>(), h->d_src_tree.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl, xt, y);
   } else {
     FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   }
@@ -652,8 +753,8 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   {
     const int64_t tot = (int64_t)nl * LF.T;
     k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_start.as<int32_t>(),
-                                                          h->d_leaf_cnt.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl,
-                                                          LF.T, eps, x, M(LF, 0), M(LF, 1));
+                                                          h->d_leaf_cnt.as<int32_t>(), N, nl,
+                                                          LF.T, eps, xt, M(LF, 0), M(LF, 1));
   }
   for (int l = L - 1; l >= h->lmin; --l) {
     Level &P = h->lev[l], &C = h->lev[l + 1];
@@ -667,11 +768,27 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   FAGBI_TRY(mark(2));
   for (int l = h->lmin; l <= L; ++l) {
     Level& D = h->lev[l];
+    using R2 = typename Pair<R>::T;
+    const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
+    // register-blocked kernel for the low orders (FP32 up to p = 4, FP64 p = 3)
+    const int preg = f32 ? 4 : 3;
+    if (D.n_off > 0 && D.order <= preg && D.order >= 1) {
+      int S = 1;
+      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+      const unsigned grid = (unsigned)((((int64_t)D.n * S + 255) / 256 + 7) / 8 * 8);
+      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                    *id = D.d_inter_oid.as<int32_t>();
+      switch (D.order) {
+        case 1: k_m2l_reg<R, 1><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        case 2: k_m2l_reg<R, 2><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        case 3: k_m2l_reg<R, 3><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        default: k_m2l_reg<R, 4><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+      }
+      continue;
+    }
     FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), s));
     FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), s));
     if (D.n_off == 0) continue;
-    using R2 = typename Pair<R>::T;
-    const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
     const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
     const int spt = spt_of(D.m2l_nslot);
     const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;

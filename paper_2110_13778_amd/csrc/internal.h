@@ -17,7 +17,7 @@ constexpr int TMAX = (PMAX + 1) * (PMAX + 2) * (PMAX + 3) / 6;   // 286 terms
 constexpr double FOUR_PI = 12.566370614359172953850573533118;
 constexpr double UNIT_KCAL = 4.0 * 3.14159265358979323846264338327950288 * 332.0716;
 
-__host__ __device__ inline int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int nterms(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
 int set_error(int code, const char* fmt, ...);
 
@@ -104,7 +104,8 @@ struct fagbi_handle {
   // [9], unit normal [3], area, vertex ids [3]; leaf of each panel
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
   fagbi::DBuf d_pc;                   // per panel: centroid, sqrt(area)
-  fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_src_user, d_self_col;
+  fagbi::DBuf d_xt;                   // matvec input in tree order [2N]
+  fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_self_col;
   fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]

@@ -450,25 +450,98 @@ static int ensure_net(fagbi_handle* h) {
   return 0;
 }
 
-// standardised inputs -> standardised outputs for n rows (chunked)
-static int infer_std(fagbi_handle* h, const float* Xraw, int64_t n, float* out, hipStream_t s) {
-  const int CH = 65536;
-  Work w;
-  FAGBI_TRY(w.alloc(CH));
-  Tmp xb, idx;
-  FAGBI_TRY(xb.alloc((size_t)CH * NIN * 4));
-  FAGBI_TRY(idx.alloc((size_t)CH * 8));
-  std::vector<int64_t> id(CH);
-  for (int64_t r0 = 0; r0 < n; r0 += CH) {
-    const int B = (int)std::min<int64_t>(CH, n - r0);
-    for (int b = 0; b < B; ++b) id[b] = r0 + b;
-    FAGBI_HIP(hipMemcpyAsync(idx.p, id.data(), B * 8, hipMemcpyHostToDevice, s));
-    k_gather_std<<<(B + 255) / 256, 256, 0, s>>>(Xraw, nullptr, idx.as<int64_t>(), B, h->d_mlp_norm.as<float>(),
-                                                 xb.as<float>(), nullptr);
-    Net net{h->d_mlp_theta.as<float>(), B, w.h1.as<float>(), w.h2.as<float>(), w.h3.as<float>(), out + r0 * NOUT};
-    forward(net, xb.as<float>(), s);
-    FAGBI_HIP(hipStreamSynchronize(s));   // idx is reused by the next chunk
+// ---------------------------------------------------------------------------
+// fused inference on the matrix cores: one block of 4 waves per 64 rows,
+// each wave owns 16 rows; every layer is a sequence of
+// v_mfma_f32_16x16x4f32 over K, with the layer's weights staged in LDS and
+// each wave's activations kept in its own LDS rows between layers.
+// Lane layouts of the 16x16x4 FP32 instruction: A[i][k] from lane i + 16k,
+// B[k][j] from lane j + 16k, D[i][j] in lane j + 16(i/4), element i % 4.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int IR = 64;               // rows per block
+constexpr int AST = NH + 4;          // activation row stride (A reads: 2-way banks)
+constexpr int WST = NH + 16;         // weight row stride (B reads: 2-way banks)
+
+__device__ inline void mlp_layer(const float* act, const float* Ws, const float* bias, int K, int ntile, int lane,
+                                 f32x4* acc) {
+  for (int t = 0; t < ntile; ++t) {
+    const float b = bias[t * 16 + (lane & 15)];
+    acc[t] = f32x4{b, b, b, b};
   }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const float av = act[(lane & 15) * AST + k0 + (lane >> 4)];
+    const float* wr = Ws + (k0 + (lane >> 4)) * WST + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wr[t * 16], acc[t], 0, 0, 0);
+  }
+}
+
+// out[r] = network(standardised X[r]) (standardised, or in target units when
+// destd is set: times the class's output sd plus its mean)
+__global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, int64_t n,
+                                                   const float* __restrict__ th, const float* __restrict__ norm,
+                                                   int destd, float* out) {
+  extern __shared__ __align__(16) float smem[];
+  float* Ws = smem;                       // [NH][WST]
+  float* bs = Ws + NH * WST;              // [NH] bias of the current layer (padded)
+  float* act_all = bs + NH;               // [4][16][AST]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* act = act_all + wave * 16 * AST;
+  const int64_t r0 = (int64_t)blockIdx.x * IR;
+  // standardised inputs of this block's rows
+  for (int e = threadIdx.x; e < IR * NIN; e += 256) {
+    const int r = e / NIN, k = e - r * NIN;
+    const int64_t g = r0 + r;
+    act_all[(r >> 4) * 16 * AST + (r & 15) * AST + k] = g < n ? (X[g * NIN + k] - norm[k]) / norm[NIN + k] : 0.f;
+  }
+  f32x4 acc[8];
+  const int offW[4] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4};
+  const int offB[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
+  for (int l = 0; l < 4; ++l) {
+    const int K = l == 0 ? NIN : NH;
+    const int N = l == 3 ? NOUT : NH;
+    const int ncol = l == 3 ? 16 : NH;    // output padded to one 16-column tile
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * ncol; e += 256) {
+      const int k = e / ncol, j = e - k * ncol;
+      Ws[k * WST + j] = j < N ? th[offW[l] + k * N + j] : 0.f;
+    }
+    for (int j = threadIdx.x; j < ncol; j += 256) bs[j] = j < N ? th[offB[l] + j] : 0.f;
+    __syncthreads();
+    const int ntile = ncol / 16;
+    mlp_layer(act, Ws, bs, K, ntile, lane, acc);
+    if (l < 3) {
+      for (int t = 0; t < ntile; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) act[(4 * (lane >> 4) + q) * AST + t * 16 + (lane & 15)] = tanhf(acc[t][q]);
+    }
+  }
+  const int j = lane & 15;
+  if (j < NOUT)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t g = r0 + wave * 16 + 4 * (lane >> 4) + q;
+      if (g < n) {
+        float y = acc[0][q];
+        if (destd) {
+          const int c = row_class(X + g * NIN);
+          y = y * norm[OUT_SD + c * NOUT + j] + norm[OUT_MU + c * NOUT + j];
+        }
+        out[g * NOUT + j] = y;
+      }
+    }
+}
+
+constexpr size_t INFER_LDS = (size_t)(NH * WST + NH + 4 * 16 * AST) * sizeof(float);
+
+static int infer(fagbi_handle* h, const float* Xraw, int64_t n, int destd, float* out, hipStream_t s) {
+  if (n <= 0) return 0;
+  FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_infer),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)INFER_LDS));
+  k_mlp_infer<<<(unsigned)((n + IR - 1) / IR), 256, INFER_LDS, s>>>(Xraw, n, h->d_mlp_theta.as<float>(),
+                                                                     h->d_mlp_norm.as<float>(), destd, out);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }
@@ -482,34 +555,36 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s) {
   FAGBI_TRY(cnt.alloc(8));
   FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
   const int all = h->prm.mlp_mode == FAGBI_MLP_PRECOND ? 1 : 0;
-  const int CH = 262144;
+  // one set of chunk buffers for all classes; the chunks run back to back in
+  // stream order
+  const int64_t CH = 1 << 20;
+  int64_t cm = 1;
+  for (int k = 1; k < 4; ++k) cm = std::max(cm, std::min<int64_t>(h->wl_n[k], CH));
+  Tmp X, I3, hh, dr, tn;
+  FAGBI_TRY(X.alloc((size_t)cm * NIN * 4));
+  FAGBI_TRY(I3.alloc((size_t)cm * 6 * 8));
+  FAGBI_TRY(hh.alloc((size_t)cm * 8));
+  FAGBI_TRY(dr.alloc((size_t)cm * 4));
+  FAGBI_TRY(tn.alloc((size_t)cm * NOUT * 4));
   for (int k = 1; k < 4; ++k) {
     const int64_t m = h->wl_n[k];
     FAGBI_TRY(h->alloc(h->d_mlp_skip[k], (size_t)std::max<int64_t>(m, 1)));
-    if (m == 0) continue;
-    Tmp X, I3, hh, dr, tn;
-    const int64_t cm = std::min<int64_t>(m, CH);
-    FAGBI_TRY(X.alloc((size_t)cm * NIN * 4));
-    FAGBI_TRY(I3.alloc((size_t)cm * 6 * 8));
-    FAGBI_TRY(hh.alloc((size_t)cm * 8));
-    FAGBI_TRY(dr.alloc((size_t)cm * 4));
-    FAGBI_TRY(tn.alloc((size_t)cm * NOUT * 4));
     for (int64_t r0 = 0; r0 < m; r0 += CH) {
       const int64_t c = std::min<int64_t>(CH, m - r0);
       const Item* it = h->d_wl[k].as<Item>() + r0;
       const unsigned g = (unsigned)((c + 255) / 256);
       k_mlp_prepare<<<g, 256, 0, s>>>(a, k + 1, it, c, X.as<float>(), I3.as<double>(), hh.as<double>(),
                                       dr.as<float>());
-      FAGBI_TRY(infer_std(h, X.as<float>(), c, tn.as<float>(), s));
+      FAGBI_TRY(infer(h, X.as<float>(), c, 0, tn.as<float>(), s));
       k_mlp_apply<<<g, 256, 0, s>>>(a, k + 1, k, it, c, tn.as<float>(), norm, I3.as<double>(), hh.as<double>(),
                                     dr.as<float>(), cal, h->prm.mlp_gate_tol, all, h->d_E64.as<double4>(),
                                     h->d_mlp_skip[k].as<uint8_t>() + r0, cnt.as<unsigned long long>());
       FAGBI_HIP(hipGetLastError());
-      FAGBI_HIP(hipStreamSynchronize(s));
     }
   }
   unsigned long long ng = 0;
-  FAGBI_HIP(hipMemcpy(&ng, cnt.p, 8, hipMemcpyDeviceToHost));
+  FAGBI_HIP(hipMemcpyAsync(&ng, cnt.p, 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));   // also before the chunk buffers are freed
   h->mlp_gated_pairs = (int64_t)ng;
   return 0;
 }
@@ -583,6 +658,7 @@ int fagbi_mlp_train(fagbi_handle* h, const float* X, const float* T, const float
   float* norm = h->d_mlp_norm.as<float>();
   k_colstats<<<NIN, 256, 0, s>>>(X, n, NIN, norm, norm + NIN);
   std::vector<float> xall(n * NIN), tall(n * NOUT), aall(n * NAUX);
+  FAGBI_HIP(hipStreamSynchronize(s));
   FAGBI_HIP(hipMemcpy(xall.data(), X, xall.size() * 4, hipMemcpyDeviceToHost));
   FAGBI_HIP(hipMemcpy(tall.data(), T, tall.size() * 4, hipMemcpyDeviceToHost));
   FAGBI_HIP(hipMemcpy(aall.data(), aux, aall.size() * 4, hipMemcpyDeviceToHost));
@@ -670,6 +746,7 @@ int fagbi_mlp_train(fagbi_handle* h, const float* X, const float* T, const float
   FAGBI_TRY(pv.alloc((size_t)nval * NOUT * 4));
   FAGBI_TRY(xv.alloc((size_t)nval * NIN * 4));
   h->mlp_blob.assign(NBLOB, 0.f);
+  FAGBI_HIP(hipStreamSynchronize(s));
   FAGBI_HIP(hipMemcpy(h->mlp_blob.data(), h->d_mlp_theta.p, NPAR * 4, hipMemcpyDeviceToHost));
   FAGBI_HIP(hipMemcpy(h->mlp_blob.data() + NPAR, norm, NNORM * 4, hipMemcpyDeviceToHost));
   std::vector<float> xvh(nval * NIN), tt(nval * NOUT), ax(nval * NAUX), tp(nval * NOUT);
@@ -679,7 +756,8 @@ int fagbi_mlp_train(fagbi_handle* h, const float* X, const float* T, const float
     memcpy(&ax[k * NAUX], &aall[vrows[k] * NAUX], NAUX * 4);
   }
   FAGBI_HIP(hipMemcpy(xv.p, xvh.data(), xvh.size() * 4, hipMemcpyHostToDevice));
-  FAGBI_TRY(infer_std(h, xv.as<float>(), nval, pv.as<float>(), s));
+  FAGBI_TRY(infer(h, xv.as<float>(), nval, 0, pv.as<float>(), s));
+  FAGBI_HIP(hipStreamSynchronize(s));
   FAGBI_HIP(hipMemcpy(tp.data(), pv.p, tp.size() * 4, hipMemcpyDeviceToHost));
   const float* nm = h->mlp_blob.data() + NPAR;
   double rms[NOUT] = {};
@@ -725,20 +803,7 @@ int fagbi_mlp_forward(fagbi_handle* h, const float* X, float* Y, int64_t n, void
   if (!h || !X || !Y || n < 1) return set_error(FAGBI_E_ARG, "bad argument");
   FAGBI_TRY(ensure_net(h));
   hipStream_t s = (hipStream_t)stream;
-  FAGBI_TRY(infer_std(h, X, n, Y, s));
-  // back to target units
-  std::vector<float> nm(NNORM);
-  memcpy(nm.data(), h->mlp_blob.data() + NPAR, NNORM * 4);
-  std::vector<float> y(n * NOUT);
-  FAGBI_HIP(hipMemcpy(y.data(), Y, y.size() * 4, hipMemcpyDeviceToHost));
-  std::vector<float> x(n * NIN);
-  FAGBI_HIP(hipMemcpy(x.data(), X, x.size() * 4, hipMemcpyDeviceToHost));
-  for (int64_t r = 0; r < n; ++r) {
-    const int c = row_class(&x[r * NIN]);
-    for (int m = 0; m < NOUT; ++m)
-      y[r * NOUT + m] = y[r * NOUT + m] * nm[OUT_SD + c * NOUT + m] + nm[OUT_MU + c * NOUT + m];
-  }
-  FAGBI_HIP(hipMemcpy(Y, y.data(), y.size() * 4, hipMemcpyHostToDevice));
+  FAGBI_TRY(infer(h, X, n, 1, Y, s));
   return 0;
 }
 

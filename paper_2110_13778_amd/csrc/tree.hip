@@ -540,18 +540,14 @@ __global__ void __launch_bounds__(64) k_leaf_sources(const int32_t* __restrict__
                                                      const int32_t* __restrict__ end,
                                                      const int64_t* __restrict__ src_off,
                                                      const int32_t* __restrict__ col,
-                                                     const int32_t* __restrict__ perm, int32_t* src_tree,
-                                                     int32_t* src_user, int32_t* leaf_of) {
+                                                     int32_t* src_tree, int32_t* leaf_of) {
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   for (int q = nbr_off[c]; q < nbr_off[c + 1]; ++q) {
     const int c2 = nbr[q];
     const int j0 = start[c2], n2 = end[c2] - j0;
     const int64_t b = src_off[c] + col[q];
-    for (int j = lane; j < n2; j += 64) {
-      src_tree[b + j] = j0 + j;
-      src_user[b + j] = perm[j0 + j];
-    }
+    for (int j = lane; j < n2; j += 64) src_tree[b + j] = j0 + j;
   }
   for (int i = start[c] + lane; i < end[c]; i += 64) leaf_of[i] = c;
 }
@@ -745,6 +741,7 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_TRY(h->alloc(h->d_pa, N * 8));
   FAGBI_TRY(h->alloc(h->d_ptri, 3 * N * 4));
   FAGBI_TRY(h->alloc(h->d_pc, N * sizeof(double4)));
+  FAGBI_TRY(h->alloc(h->d_xt, 2 * N * sizeof(double)));
   int32_t* perm = h->d_perm.as<int32_t>();
   k_leaf_order<<<grid_of(N), TB, 0, s>>>(key, val, N, 3 * (DEEP - L), leaf, perm, keyL);
   k_permute<<<grid_of(N), TB, 0, s>>>(perm, N, cor, nrm, area, dt, h->d_pv.as<double>(), h->d_pn.as<double>(),
@@ -899,11 +896,9 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_HIP(hipMemcpy(&h->n_src, h->d_src_off.as<int64_t>() + nl, 8, hipMemcpyDeviceToHost));
   FAGBI_HIP(hipMemcpy(&h->n_ent, h->d_ent_off.as<int64_t>() + nl, 8, hipMemcpyDeviceToHost));
   FAGBI_TRY(h->alloc(h->d_src_tree, (size_t)std::max<int64_t>(1, h->n_src) * 4));
-  FAGBI_TRY(h->alloc(h->d_src_user, (size_t)std::max<int64_t>(1, h->n_src) * 4));
   FAGBI_TRY(h->alloc(h->d_leaf_of, (size_t)N * 4));
-  k_leaf_sources<<<nl, 64, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L], h->d_src_off.as<int64_t>(), col, perm,
-                                   h->d_src_tree.as<int32_t>(), h->d_src_user.as<int32_t>(),
-                                   h->d_leaf_of.as<int32_t>());
+  k_leaf_sources<<<nl, 64, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L], h->d_src_off.as<int64_t>(), col,
+                                   h->d_src_tree.as<int32_t>(), h->d_leaf_of.as<int32_t>());
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(to_host(h->leaf_cnt, h->d_leaf_cnt.as<int32_t>(), nl));
   h->max_leaf = 0;

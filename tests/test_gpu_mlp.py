@@ -28,6 +28,32 @@ def test_gradient_matches_reference_network():
         h.close()
 
 
+def test_forward_matches_reference_network():
+    """fused inference kernel (matrix cores) against the FP64 reference
+    network, with input standardisation and per-class output scaling; 1000
+    rows leave a ragged last tile"""
+    rng = np.random.default_rng(12)
+    theta = (rng.standard_normal(omlp.n_params()) * 0.15).astype(np.float32)
+    mu_in, sd_in = rng.standard_normal(16) * 0.3, 0.5 + rng.random(16)
+    mu_in[13:], sd_in[13:] = 0.0, 1.0
+    mu_out, sd_out = rng.standard_normal((3, 6)), 0.5 + rng.random((3, 6))
+    ncal = 3 * 9 + 3 * 8
+    blob = np.concatenate([theta, mu_in, sd_in, mu_out.ravel(), sd_out.ravel(), np.zeros(ncal)]).astype(np.float32)
+    assert blob.size == 36093
+    n = 1000
+    X = rng.standard_normal((n, 16)).astype(np.float32)
+    cls = rng.integers(0, 3, n)
+    X[:, 13:] = 0.0
+    X[np.arange(n), 13 + cls] = 1.0
+    h = F.Handle()
+    h.mlp_set_weights(blob)
+    Y = h.mlp_forward(torch.tensor(X, device=DEV)).cpu().numpy()
+    h.close()
+    xs = (X.astype(np.float64) - mu_in) / sd_in
+    ref = omlp.forward(theta.astype(np.float64), xs)[-1] * sd_out[cls] + mu_out[cls]
+    assert np.abs(Y - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 @pytest.fixture(scope="module")
 def trained():
     x, r, q = packed_atoms_ball(n=150, seed=7)
