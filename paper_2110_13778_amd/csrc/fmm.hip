@@ -113,6 +113,7 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
                                 const double* __restrict__ pa, const int32_t* __restrict__ leaf_of,
                                 const int32_t* __restrict__ lidx, double cx, double cy, double cz,
                                 double hL, int N, int T, const int8_t* __restrict__ mi, R* ms, R* md) {
+  // layout [N][T]: moment t of panel i at i * T + t
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)N * T) return;
   const int i = (int)(g / T), t = (int)(g - (int64_t)i * T);
@@ -144,7 +145,7 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
   md[g] = (R)dsum;
 }
 
-// P2M: one thread per (leaf, term)
+// P2M: one thread per (leaf, term); panel moments [N][T]
 template <typename R>
 __global__ void k_p2m(const R* __restrict__ ms, const R* __restrict__ md, const int32_t* __restrict__ leaf_start,
                       const int32_t* __restrict__ leaf_cnt, int64_t N, int nl,
@@ -374,6 +375,207 @@ __global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ int
     }
 }
 
+__host__ __device__ constexpr int binom_c(int n, int k) {
+  int r = 1;
+  for (int q = 1; q <= k; ++q) r = r * (n - k + q) / q;
+  return r;
+}
+
+// the (a, b) pairs of a shift between orders PP (a) and PC (b): a >= b
+// componentwise, with the index of a - b and C(a, b)
+__host__ __device__ constexpr int count_shift_pairs(int PP, int PC) {
+  int n = 0;
+  for (int da = 0; da <= PP; ++da)
+    for (int a0 = da; a0 >= 0; --a0)
+      for (int a1 = da - a0; a1 >= 0; --a1)
+        for (int db = 0; db <= PC; ++db)
+          for (int b0 = db; b0 >= 0; --b0)
+            for (int b1 = db - b0; b1 >= 0; --b1)
+              if (b0 <= a0 && b1 <= a1 && db - b0 - b1 <= da - a0 - a1) ++n;
+  return n;
+}
+
+template <int PP, int PC>
+struct ShiftPairs {
+  static constexpr int N = count_shift_pairs(PP, PC);
+  int ta[N], tb[N], g[N];
+  double coef[N];
+  constexpr ShiftPairs() : ta(), tb(), g(), coef() {
+    int n = 0;
+    for (int da = 0; da <= PP; ++da)
+      for (int a0 = da; a0 >= 0; --a0)
+        for (int a1 = da - a0; a1 >= 0; --a1) {
+          const int a2 = da - a0 - a1;
+          for (int db = 0; db <= PC; ++db)
+            for (int b0 = db; b0 >= 0; --b0)
+              for (int b1 = db - b0; b1 >= 0; --b1) {
+                const int b2 = db - b0 - b1;
+                if (!(b0 <= a0 && b1 <= a1 && b2 <= a2)) continue;
+                ta[n] = midx(a0, a1, a2);
+                tb[n] = midx(b0, b1, b2);
+                g[n] = midx(a0 - b0, a1 - b1, a2 - b2);
+                coef[n] = (double)(binom_c(a0, b0) * binom_c(a1, b1) * binom_c(a2, b2));
+                ++n;
+              }
+        }
+  }
+};
+
+// monomials (x_child - x_parent)^g for |g| <= P, with the offset
+// ((idx & 1) - 1/2) h_child per axis
+template <typename R, int P>
+__device__ inline void shift_monomials(const int32_t* __restrict__ cidx, int c, R hc, R* mono) {
+  R d[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) d[ax] = ((R)(cidx[3 * c + ax] & 1) - (R)0.5) * hc;
+  // by degree: each monomial of degree k is a degree k-1 one times one axis
+  mono[0] = 1;
+#pragma unroll
+  for (int k = 1; k <= P; ++k)
+#pragma unroll
+    for (int a = k; a >= 0; --a)
+#pragma unroll
+      for (int b = k - a; b >= 0; --b) {
+        const int c2 = k - a - b;
+        mono[midx(a, b, c2)] = a > 0 ? mono[midx(a - 1, b, c2)] * d[0]
+                             : b > 0 ? mono[midx(a, b - 1, c2)] * d[1] : mono[midx(a, b, c2 - 1)] * d[2];
+      }
+}
+
+// LtL with registers, one thread per child: child^b += sum_{a >= b, |a| <= PP}
+// C(a, b) d^(a - b) parent^a for |b| <= PC
+template <typename R, int PP, int PC>
+__global__ void __launch_bounds__(256) k_l2l_reg(const int32_t* __restrict__ parent, const int32_t* __restrict__ cidx,
+                                                 int n, R hc, const R* __restrict__ P0, const R* __restrict__ Pk,
+                                                 R* C0, R* Ck) {
+  constexpr ShiftPairs<PP, PC> sp{};
+  constexpr int TP = nterms(PP), TC = nterms(PC);
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int64_t par = parent[c];
+  R mono[TP], p0[TP], pk[TP], s0[TC], sk[TC];
+  shift_monomials<R, PP>(cidx, c, hc, mono);
+#pragma unroll
+  for (int t = 0; t < TP; ++t) {
+    p0[t] = P0[par * TP + t];
+    pk[t] = Pk[par * TP + t];
+  }
+#pragma unroll
+  for (int t = 0; t < TC; ++t) s0[t] = sk[t] = 0;
+#pragma unroll
+  for (int k = 0; k < ShiftPairs<PP, PC>::N; ++k) {
+    const R w = (R)sp.coef[k] * mono[sp.g[k]];
+    s0[sp.tb[k]] += w * p0[sp.ta[k]];
+    sk[sp.tb[k]] += w * pk[sp.ta[k]];
+  }
+#pragma unroll
+  for (int t = 0; t < TC; ++t) {
+    C0[(int64_t)c * TC + t] += s0[t];
+    Ck[(int64_t)c * TC + t] += sk[t];
+  }
+}
+
+// MtM with registers, one thread per parent: parent^a = sum_children
+// sum_{b <= a, |b| <= PC} C(a, b) d^(a - b) child^b for |a| <= PP
+template <typename R, int PP, int PC>
+__global__ void __launch_bounds__(256) k_m2m_reg(const int32_t* __restrict__ child_start,
+                                                 const int32_t* __restrict__ child_end,
+                                                 const int32_t* __restrict__ cidx, int n, R hc,
+                                                 const R* __restrict__ C0, const R* __restrict__ Ck, R* P0, R* Pk) {
+  constexpr ShiftPairs<PP, PC> sp{};
+  constexpr int TP = nterms(PP), TC = nterms(PC);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  R a0[TP], ak[TP];
+#pragma unroll
+  for (int t = 0; t < TP; ++t) a0[t] = ak[t] = 0;
+  for (int ch = child_start[p]; ch < child_end[p]; ++ch) {
+    R mono[TP], c0[TC], ck[TC];
+    shift_monomials<R, PP>(cidx, ch, hc, mono);
+#pragma unroll
+    for (int t = 0; t < TC; ++t) {
+      c0[t] = C0[(int64_t)ch * TC + t];
+      ck[t] = Ck[(int64_t)ch * TC + t];
+    }
+#pragma unroll
+    for (int k = 0; k < ShiftPairs<PP, PC>::N; ++k) {
+      const R w = (R)sp.coef[k] * mono[sp.g[k]];
+      a0[sp.ta[k]] += w * c0[sp.tb[k]];
+      ak[sp.ta[k]] += w * ck[sp.tb[k]];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TP; ++t) {
+    P0[(int64_t)p * TP + t] = a0[t];
+    Pk[(int64_t)p * TP + t] = ak[t];
+  }
+}
+
+// the same with the level's whole derivative table staged in LDS (when it
+// fits): one persistent block per CU, each block a contiguous range of
+// targets (XCD-contiguous as above), so only the source moments come from
+// the caches
+template <typename R, int P>
+__global__ void __launch_bounds__(1024) k_m2l_lds(const int32_t* __restrict__ inter_off,
+                                                  const int32_t* __restrict__ inter_src,
+                                                  const int32_t* __restrict__ inter_oid,
+                                                  const typename Pair<R>::T* __restrict__ Dt, int n_off, int ncl,
+                                                  int S, const R* __restrict__ M0, const R* __restrict__ Mk, R* L0,
+                                                  R* Lk) {
+  using R2 = typename Pair<R>::T;
+  constexpr TermTable<P> tt{};
+  constexpr int T = TermTable<P>::T;
+  extern __shared__ __align__(16) char smem_raw[];
+  R2* dsm = reinterpret_cast<R2*>(smem_raw);
+  for (int e = threadIdx.x; e < n_off * T; e += blockDim.x) dsm[e] = Dt[e];
+  __syncthreads();
+  const int nbx = (int)((gridDim.x + 7) / 8);
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * nbx + (blockIdx.x >> 3);
+  const int64_t ntile = ((int64_t)ncl * S + blockDim.x - 1) / blockDim.x;
+  const int64_t per = (ntile + (int64_t)nbx * 8 - 1) / ((int64_t)nbx * 8);
+  for (int64_t it = 0; it < per; ++it) {
+    const int64_t gt = (blk * per + it) * blockDim.x + threadIdx.x;
+    const int c = (int)(gt / S), part = (int)(gt - (int64_t)c * S);
+    R l0[T], lk[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0;
+    if (c < ncl) {
+      const int q1 = inter_off[c + 1];
+      for (int q = inter_off[c] + part; q < q1; q += S) {
+        const int64_t src = inter_src[q];
+        const R2* dp = dsm + inter_oid[q] * T;
+        R2 d[T];
+#pragma unroll
+        for (int g = 0; g < T; ++g) d[g] = dp[g];
+        const R* m0p = M0 + src * T;
+        const R* mkp = Mk + src * T;
+#pragma unroll
+        for (int tb = 0; tb < T; ++tb) {
+          const R m0 = m0p[tb] * (R)tt.msc[tb], mk = mkp[tb] * (R)tt.msc[tb];
+#pragma unroll
+          for (int ta = 0; ta < nterms(P - tt.deg[tb]); ++ta) {
+            const int g = midx(tt.e[ta][0] + tt.e[tb][0], tt.e[ta][1] + tt.e[tb][1], tt.e[ta][2] + tt.e[tb][2]);
+            l0[ta] += d[g].x * m0;
+            lk[ta] += d[g].y * mk;
+          }
+        }
+      }
+    }
+    for (int o = S >> 1; o > 0; o >>= 1)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        l0[t] += __shfl_xor(l0[t], o, 64);
+        lk[t] += __shfl_xor(lk[t], o, 64);
+      }
+    if (c < ncl && part == 0)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        L0[(int64_t)c * T + t] = l0[t] * (R)tt.lsc[t];
+        Lk[(int64_t)c * T + t] = lk[t] * (R)tt.lsc[t];
+      }
+  }
+}
+
 // MtM: one block per parent; slot = (a | b << 16), a parent index, b child
 // index (b <= a componentwise); coefficient rows per child octant.
 template <typename R, int SPT>
@@ -483,6 +685,29 @@ __global__ void k_l2p(const R* __restrict__ ms, const R* __restrict__ md, const 
   R y1 = 0, y2 = 0;
   for (int t = 0; t < T; ++t) {
     const R l0 = L0[(int64_t)c * T + t], lk = Lk[(int64_t)c * T + t];
+    y1 += (l0 + lk) * ms[(int64_t)i * T + t];
+    y2 += (l0 + lk * ie) * md[(int64_t)i * T + t];
+  }
+  const int p = perm[i];
+  y[p] -= (double)y1;
+  y[N + p] -= (double)y2;
+}
+
+// LtP for low leaf orders: whole rows in registers
+template <typename R, int P>
+__global__ void __launch_bounds__(256) k_l2p_reg(const R* __restrict__ ms, const R* __restrict__ md,
+                                                 const int32_t* __restrict__ leaf_of, const int32_t* __restrict__ perm,
+                                                 int N, double eps, const R* __restrict__ L0, const R* __restrict__ Lk,
+                                                 double* y) {
+  constexpr int T = nterms(P);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t c = leaf_of[i];
+  const R ie = (R)(1.0 / eps);
+  R y1 = 0, y2 = 0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const R l0 = L0[c * T + t], lk = Lk[c * T + t];
     y1 += (l0 + lk) * ms[(int64_t)i * T + t];
     y2 += (l0 + lk * ie) * md[(int64_t)i * T + t];
   }
@@ -753,11 +978,22 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   {
     const int64_t tot = (int64_t)nl * LF.T;
     k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_start.as<int32_t>(),
-                                                          h->d_leaf_cnt.as<int32_t>(), N, nl,
-                                                          LF.T, eps, xt, M(LF, 0), M(LF, 1));
+                                                          h->d_leaf_cnt.as<int32_t>(), N, nl, LF.T, eps, xt,
+                                                          M(LF, 0), M(LF, 1));
   }
   for (int l = L - 1; l >= h->lmin; --l) {
     Level &P = h->lev[l], &C = h->lev[l + 1];
+    const unsigned gp = (unsigned)((P.n + 255) / 256);
+    if (f32 && P.order == 4 && C.order == 3) {
+      k_m2m_reg<R, 4, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
+                                           C.d_idx.as<int32_t>(), P.n, (R)C.h, M(C, 0), M(C, 1), M(P, 0), M(P, 1));
+      continue;
+    }
+    if (P.order == 3 && C.order == 3) {
+      k_m2m_reg<R, 3, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
+                                           C.d_idx.as<int32_t>(), P.n, (R)C.h, M(C, 0), M(C, 1), M(P, 0), M(P, 1));
+      continue;
+    }
     const size_t sh = std::max<size_t>((size_t)16 * C.T, (size_t)2 * P.up_nslot) * sizeof(R);
     FAGBI_SPT_SWITCH(spt_of(P.up_nslot), k_m2m, P.n, sh, s, P.d_child_start.as<int32_t>(),
                      P.d_child_end.as<int32_t>(), C.d_idx.as<int32_t>(), P.d_up_slot.as<int32_t>(),
@@ -772,6 +1008,18 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
     // register-blocked kernel for the low orders (FP32 up to p = 4, FP64 p = 3)
     const int preg = f32 ? 4 : 3;
+    const size_t dbytes = (size_t)D.n_off * D.T * sizeof(R2);
+    if constexpr (sizeof(R) == 4)
+    if (D.n_off > 0 && D.order == 3 && dbytes <= (size_t)144 * 1024) {
+      int S = 1;
+      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+      k_m2l_lds<R, 3><<<256, 1024, dbytes, s>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
+                                                D.d_inter_oid.as<int32_t>(), Dt, D.n_off, D.n, S, M(D, 0), M(D, 1),
+                                                Lc(D, 0), Lc(D, 1));
+      continue;
+    }
     if (D.n_off > 0 && D.order <= preg && D.order >= 1) {
       int S = 1;
       while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
@@ -805,14 +1053,38 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   FAGBI_TRY(mark(3));
   for (int l = h->lmin; l < L; ++l) {
     Level &P = h->lev[l], &C = h->lev[l + 1];
+    const unsigned gc = (unsigned)((C.n + 255) / 256);
+    const int32_t *par = C.d_parent.as<int32_t>(), *cix = C.d_idx.as<int32_t>();
+    if (P.order == 4 && C.order == 3) {
+      k_l2l_reg<R, 4, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
+      continue;
+    }
+    if (P.order == 3 && C.order == 3) {
+      k_l2l_reg<R, 3, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
+      continue;
+    }
+    if (f32 && P.order == 5 && C.order == 4) {
+      k_l2l_reg<R, 5, 4><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
+      continue;
+    }
     const size_t sh = std::max<size_t>((size_t)2 * P.T, (size_t)2 * P.dn_nslot) * sizeof(R);
     FAGBI_SPT_SWITCH(spt_of(P.dn_nslot), k_l2l, C.n, sh, s, C.d_parent.as<int32_t>(), C.d_idx.as<int32_t>(),
                      P.d_dn_slot.as<int32_t>(), cf(P.d_dn_c64, P.d_dn_c32), P.d_dn_boff.as<int32_t>(), P.dn_nslot,
                      P.T, C.T, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
   }
-  k_l2p<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_of.as<int32_t>(),
-                                                      h->d_perm.as<int32_t>(), (int)N, LF.T, eps, Lc(LF, 0),
-                                                      Lc(LF, 1), y);
+  {
+    const unsigned g = (unsigned)((N + 255) / 256);
+    const R *a = ms.as<R>(), *b = md.as<R>();
+    const int32_t *lo = h->d_leaf_of.as<int32_t>(), *pm = h->d_perm.as<int32_t>();
+    switch (LF.order) {
+      case 2: k_l2p_reg<R, 2><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), y); break;
+      case 3: k_l2p_reg<R, 3><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), y); break;
+      case 4: k_l2p_reg<R, 4><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), y); break;
+      default:
+        k_l2p<R><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, LF.T, eps, Lc(LF, 0), Lc(LF, 1), y);
+        break;
+    }
+  }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(4));
   return 0;
