@@ -511,30 +511,33 @@ __global__ void __launch_bounds__(256) k_m2m_reg(const int32_t* __restrict__ chi
   }
 }
 
-// the same with the level's whole derivative table staged in LDS (when it
-// fits): one persistent block per CU, each block a contiguous range of
-// targets (XCD-contiguous as above), so only the source moments come from
-// the caches
-template <typename R, int P>
-__global__ void __launch_bounds__(1024) k_m2l_lds(const int32_t* __restrict__ inter_off,
-                                                  const int32_t* __restrict__ inter_src,
-                                                  const int32_t* __restrict__ inter_oid,
-                                                  const typename Pair<R>::T* __restrict__ Dt, int n_off, int ncl,
-                                                  int S, const R* __restrict__ M0, const R* __restrict__ Mk, R* L0,
-                                                  R* Lk) {
+// the same with the level's derivative table staged in LDS: only one of each
+// pair of opposite offsets is stored (D_g(-o) = (-1)^|g| D_g(o), the kernels
+// being even), omap[oid] = row | flip << 30.  One persistent block per CU,
+// each block a contiguous range of targets (XCD-contiguous as above), so only
+// the source moments come from the caches.
+template <typename R, int P, int NT>
+__global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inter_off,
+                                                const int32_t* __restrict__ inter_src,
+                                                const int32_t* __restrict__ inter_oid,
+                                                const typename Pair<R>::T* __restrict__ Dh, int n_half,
+                                                const int32_t* __restrict__ omap, int n_off, int ncl, int S,
+                                                const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
   using R2 = typename Pair<R>::T;
   constexpr TermTable<P> tt{};
   constexpr int T = TermTable<P>::T;
   extern __shared__ __align__(16) char smem_raw[];
   R2* dsm = reinterpret_cast<R2*>(smem_raw);
-  for (int e = threadIdx.x; e < n_off * T; e += blockDim.x) dsm[e] = Dt[e];
+  int32_t* smap = reinterpret_cast<int32_t*>(dsm + n_half * T);
+  for (int e = threadIdx.x; e < n_half * T; e += NT) dsm[e] = Dh[e];
+  for (int e = threadIdx.x; e < n_off; e += NT) smap[e] = omap[e];
   __syncthreads();
   const int nbx = (int)((gridDim.x + 7) / 8);
   const int64_t blk = (int64_t)(blockIdx.x & 7) * nbx + (blockIdx.x >> 3);
-  const int64_t ntile = ((int64_t)ncl * S + blockDim.x - 1) / blockDim.x;
+  const int64_t ntile = ((int64_t)ncl * S + NT - 1) / NT;
   const int64_t per = (ntile + (int64_t)nbx * 8 - 1) / ((int64_t)nbx * 8);
   for (int64_t it = 0; it < per; ++it) {
-    const int64_t gt = (blk * per + it) * blockDim.x + threadIdx.x;
+    const int64_t gt = (blk * per + it) * NT + threadIdx.x;
     const int c = (int)(gt / S), part = (int)(gt - (int64_t)c * S);
     R l0[T], lk[T];
 #pragma unroll
@@ -543,10 +546,18 @@ __global__ void __launch_bounds__(1024) k_m2l_lds(const int32_t* __restrict__ in
       const int q1 = inter_off[c + 1];
       for (int q = inter_off[c] + part; q < q1; q += S) {
         const int64_t src = inter_src[q];
-        const R2* dp = dsm + inter_oid[q] * T;
+        const int mo = smap[inter_oid[q]];
+        const R2* dp = dsm + (mo & 0x3fffffff) * T;
+        const R sg = (mo >> 30) ? (R)-1 : (R)1;
         R2 d[T];
 #pragma unroll
-        for (int g = 0; g < T; ++g) d[g] = dp[g];
+        for (int g = 0; g < T; ++g) {
+          d[g] = dp[g];
+          if (tt.deg[g] & 1) {
+            d[g].x *= sg;
+            d[g].y *= sg;
+          }
+        }
         const R* m0p = M0 + src * T;
         const R* mkp = Mk + src * T;
 #pragma unroll
@@ -899,6 +910,37 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
       }
       FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], dt));
       FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], dt));
+      // one of each pair of opposite offsets (first non-zero component > 0)
+      // for the LDS-staged kernels, and the map oid -> row | flip << 30
+      std::vector<int32_t> omap(D.n_off, -1), rows;
+      auto key = [&](int o, int sgn) {
+        return ((int64_t)(sgn * D.off_xyz[3 * o]) + 1024) * 4194304 + ((int64_t)(sgn * D.off_xyz[3 * o + 1]) + 1024) * 2048 +
+               (sgn * D.off_xyz[3 * o + 2] + 1024);
+      };
+      std::vector<std::pair<int64_t, int>> byk(D.n_off);
+      for (int o = 0; o < D.n_off; ++o) byk[o] = {key(o, 1), o};
+      std::sort(byk.begin(), byk.end());
+      bool ok = true;
+      for (int o = 0; o < D.n_off && ok; ++o) {
+        const int x = D.off_xyz[3 * o], y = D.off_xyz[3 * o + 1], z = D.off_xyz[3 * o + 2];
+        const bool canon = x > 0 || (x == 0 && (y > 0 || (y == 0 && z > 0)));
+        if (!canon) continue;
+        omap[o] = (int32_t)rows.size();
+        rows.push_back(o);
+        auto it = std::lower_bound(byk.begin(), byk.end(), std::make_pair(key(o, -1), -1));
+        if (it == byk.end() || it->first != key(o, -1)) ok = false;
+        else omap[it->second] = omap[o] | (1 << 30);
+      }
+      for (int o = 0; o < D.n_off && ok; ++o) ok = omap[o] >= 0;
+      D.n_half = 0;
+      if (ok) {
+        std::vector<double> dh((size_t)2 * rows.size() * D.T);
+        for (size_t k = 0; k < rows.size(); ++k)
+          for (int g = 0; g < 2 * D.T; ++g) dh[2 * k * D.T + g] = dt[(size_t)2 * rows[k] * D.T + g];
+        FAGBI_TRY(upload_conv<float>(h, D.d_F32[1], dh));
+        FAGBI_TRY(h->upload(D.d_oid_map, omap.data(), omap.size() * 4));
+        D.n_half = (int)rows.size();
+      }
     }
     for (int ch = 0; ch < 2; ++ch) {
       FAGBI_TRY(h->alloc(D.d_M64[ch], (size_t)D.n * D.T * 8));
@@ -1008,16 +1050,26 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
     // register-blocked kernel for the low orders (FP32 up to p = 4, FP64 p = 3)
     const int preg = f32 ? 4 : 3;
-    const size_t dbytes = (size_t)D.n_off * D.T * sizeof(R2);
+    const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
     if constexpr (sizeof(R) == 4)
-    if (D.n_off > 0 && D.order == 3 && dbytes <= (size_t)144 * 1024) {
+    if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
       int S = 1;
       while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-      k_m2l_lds<R, 3><<<256, 1024, dbytes, s>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
-                                                D.d_inter_oid.as<int32_t>(), Dt, D.n_off, D.n, S, M(D, 0), M(D, 1),
-                                                Lc(D, 0), Lc(D, 1));
+      const R2* Dh = (const R2*)D.d_F32[1].p;
+      const int32_t* om = D.d_oid_map.as<int32_t>();
+      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                    *id = D.d_inter_oid.as<int32_t>();
+      if (D.order == 3) {
+        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 1024>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+        k_m2l_lds<R, 3, 1024><<<256, 1024, dbytes, s>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                        M(D, 1), Lc(D, 0), Lc(D, 1));
+      } else {
+        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+        k_m2l_lds<R, 4, 768><<<256, 768, dbytes, s>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                      M(D, 1), Lc(D, 0), Lc(D, 1));
+      }
       continue;
     }
     if (D.n_off > 0 && D.order <= preg && D.order >= 1) {

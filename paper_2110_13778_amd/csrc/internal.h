@@ -70,7 +70,11 @@ struct Level {
   // device: cube indices [n][3], parent [n] (-1 on level 0), children on
   // level+1 [child_start, child_end), CSR interaction lists with offset ids
   DBuf d_idx, d_parent, d_child_start, d_child_end, d_inter_off, d_inter_src, d_inter_oid;
-  DBuf d_F64[2], d_F32[2];           // Taylor tables per offset [n_off][T], G0 / Gk
+  // derivative tables per offset [n_off][T] as {G0, Gk} pairs (index 0); FP32
+  // table of one offset of each opposite pair [n_half][T] (index 1) with the
+  // map oid -> row | flip << 30
+  DBuf d_F64[2], d_F32[2], d_oid_map;
+  int n_half = 0;
   DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
   DBuf d_M32[2], d_L32[2];
   // slot tables (one slot per coupled pair of multi-indices) of the
