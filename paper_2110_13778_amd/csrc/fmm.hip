@@ -25,6 +25,7 @@
 // and each output coefficient is a fixed-order sum over its slots
 // (deterministic in FP64).
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 
 #include "internal.h"
@@ -789,11 +790,44 @@ __global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restric
 // ---------------------------------------------------------------------------
 // setup: slot tables, Taylor tables per (level, offset), moments
 // ---------------------------------------------------------------------------
-template <typename R>
-static int upload_conv(fagbi_handle* h, DBuf& b, const std::vector<double>& v) {
-  std::vector<R> t(v.begin(), v.end());
-  return h->upload(b, t.data(), t.size() * sizeof(R));
-}
+// All tables and expansion arrays of the far field live in one device
+// allocation: the host side is packed into one staging buffer and copied
+// with one transfer; the DBufs are views into the pool (not owned).
+struct Staging {
+  struct Item {
+    DBuf* b;
+    size_t off, bytes;
+  };
+  std::vector<char> host;
+  std::vector<Item> items;
+  size_t dev_bytes = 0;   // device-only regions, after the host data
+  static size_t up(size_t n) { return (n + 255) & ~(size_t)255; }
+  void add(DBuf& b, const void* data, size_t bytes) {
+    const size_t off = up(host.size());
+    host.resize(off + bytes);
+    if (bytes) memcpy(host.data() + off, data, bytes);
+    items.push_back({&b, off, bytes});
+  }
+  template <typename R> void add_conv(DBuf& b, const std::vector<double>& v) {
+    std::vector<R> t(v.begin(), v.end());
+    add(b, t.data(), t.size() * sizeof(R));
+  }
+  void reserve(DBuf& b, size_t bytes) {
+    items.push_back({&b, ~(size_t)0 - dev_bytes, bytes});   // resolved in commit
+    dev_bytes += up(bytes);
+  }
+  int commit(fagbi_handle* h, DBuf& pool) {
+    const size_t hb = up(host.size());
+    FAGBI_TRY(h->alloc(pool, hb + dev_bytes));
+    if (!host.empty()) FAGBI_HIP(hipMemcpy(pool.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    for (const Item& it : items) {
+      const size_t off = it.off <= host.size() ? it.off : hb + (~(size_t)0 - it.off);
+      it.b->p = static_cast<char*>(pool.p) + off;
+      it.b->bytes = it.bytes;
+    }
+    return 0;
+  }
+};
 
 static int spt_of(int nslot) {
   const int s = (nslot + TB - 1) / TB;
@@ -801,12 +835,13 @@ static int spt_of(int nslot) {
 }
 
 int fmm_setup(fagbi_handle* h, hipStream_t s) {
+  Staging st;
   std::vector<int8_t> mi(3 * TMAX);
   for (int t = 0; t < TMAX; ++t) {
     const MI m = mi_of(t);
     for (int d = 0; d < 3; ++d) mi[3 * t + d] = (int8_t)m.a[d];
   }
-  FAGBI_TRY(h->upload(h->d_mi, mi.data(), mi.size()));
+  st.add(h->d_mi, mi.data(), mi.size());
   const int lo = std::min(h->lmin, h->L);
   for (int l = lo; l <= h->L; ++l) {
     Level& D = h->lev[l];
@@ -828,12 +863,12 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         aoff.push_back((int32_t)slot.size());
       }
       D.m2l_nslot = (int)slot.size();
-      FAGBI_TRY(h->upload(D.d_m2l_slot, slot.data(), slot.size() * 4));
-      FAGBI_TRY(h->upload(D.d_m2l_aoff, aoff.data(), aoff.size() * 4));
+      st.add(D.d_m2l_slot, slot.data(), slot.size() * 4);
+      st.add(D.d_m2l_aoff, aoff.data(), aoff.size() * 4);
       std::vector<double> sc(msc);
       sc.insert(sc.end(), lsc.begin(), lsc.end());
-      FAGBI_TRY(upload_conv<double>(h, D.d_m2l_c64, sc));
-      FAGBI_TRY(upload_conv<float>(h, D.d_m2l_c32, sc));
+      st.add_conv<double>(D.d_m2l_c64, sc);
+      st.add_conv<float>(D.d_m2l_c32, sc);
     }
     // shifts between level l (parent, order p_l) and l+1 (child, p_{l+1})
     if (l < h->L) {
@@ -868,10 +903,10 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         for (int oct = 0; oct < 8; ++oct)
           for (size_t k = 0; k < pairs.size(); ++k) cf[oct * pairs.size() + k] = coef(pairs[k], oct);
         D.up_nslot = (int)pairs.size();
-        FAGBI_TRY(h->upload(D.d_up_slot, slot.data(), slot.size() * 4));
-        FAGBI_TRY(h->upload(D.d_up_aoff, aoff.data(), aoff.size() * 4));
-        FAGBI_TRY(upload_conv<double>(h, D.d_up_c64, cf));
-        FAGBI_TRY(upload_conv<float>(h, D.d_up_c32, cf));
+        st.add(D.d_up_slot, slot.data(), slot.size() * 4);
+        st.add(D.d_up_aoff, aoff.data(), aoff.size() * 4);
+        st.add_conv<double>(D.d_up_c64, cf);
+        st.add_conv<float>(D.d_up_c32, cf);
       }
       // LtL: grouped by child index b
       {
@@ -887,10 +922,10 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         for (int oct = 0; oct < 8; ++oct)
           for (size_t k = 0; k < byb.size(); ++k) cf[oct * byb.size() + k] = coef(byb[k], oct);
         D.dn_nslot = (int)byb.size();
-        FAGBI_TRY(h->upload(D.d_dn_slot, slot.data(), slot.size() * 4));
-        FAGBI_TRY(h->upload(D.d_dn_boff, boff.data(), boff.size() * 4));
-        FAGBI_TRY(upload_conv<double>(h, D.d_dn_c64, cf));
-        FAGBI_TRY(upload_conv<float>(h, D.d_dn_c32, cf));
+        st.add(D.d_dn_slot, slot.data(), slot.size() * 4);
+        st.add(D.d_dn_boff, boff.data(), boff.size() * 4);
+        st.add_conv<double>(D.d_dn_c64, cf);
+        st.add_conv<float>(D.d_dn_c32, cf);
       }
     }
     // derivative tables per offset, D_g = g! F_g / (4 pi), channels
@@ -908,8 +943,8 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
           dt[2 * ((size_t)o * D.T + g) + 1] = gf * fk[g];
         }
       }
-      FAGBI_TRY(upload_conv<double>(h, D.d_F64[0], dt));
-      FAGBI_TRY(upload_conv<float>(h, D.d_F32[0], dt));
+      st.add_conv<double>(D.d_F64[0], dt);
+      st.add_conv<float>(D.d_F32[0], dt);
       // one of each pair of opposite offsets (first non-zero component > 0)
       // for the LDS-staged kernels, and the map oid -> row | flip << 30
       std::vector<int32_t> omap(D.n_off, -1), rows;
@@ -937,26 +972,27 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         std::vector<double> dh((size_t)2 * rows.size() * D.T);
         for (size_t k = 0; k < rows.size(); ++k)
           for (int g = 0; g < 2 * D.T; ++g) dh[2 * k * D.T + g] = dt[(size_t)2 * rows[k] * D.T + g];
-        FAGBI_TRY(upload_conv<float>(h, D.d_F32[1], dh));
-        FAGBI_TRY(h->upload(D.d_oid_map, omap.data(), omap.size() * 4));
+        st.add_conv<float>(D.d_F32[1], dh);
+        st.add(D.d_oid_map, omap.data(), omap.size() * 4);
         D.n_half = (int)rows.size();
       }
     }
     for (int ch = 0; ch < 2; ++ch) {
-      FAGBI_TRY(h->alloc(D.d_M64[ch], (size_t)D.n * D.T * 8));
-      FAGBI_TRY(h->alloc(D.d_L64[ch], (size_t)D.n * D.T * 8));
-      FAGBI_TRY(h->alloc(D.d_M32[ch], (size_t)D.n * D.T * 4));
-      FAGBI_TRY(h->alloc(D.d_L32[ch], (size_t)D.n * D.T * 4));
+      st.reserve(D.d_M64[ch], (size_t)D.n * D.T * 8);
+      st.reserve(D.d_L64[ch], (size_t)D.n * D.T * 8);
+      st.reserve(D.d_M32[ch], (size_t)D.n * D.T * 4);
+      st.reserve(D.d_L32[ch], (size_t)D.n * D.T * 4);
     }
   }
   // panel moments about the leaf centres
   const Level& LF = h->lev[h->L];
   const int T = LF.T;
   const int64_t NT = h->N * T;
-  FAGBI_TRY(h->alloc(h->d_ms64, NT * 8));
-  FAGBI_TRY(h->alloc(h->d_md64, NT * 8));
-  FAGBI_TRY(h->alloc(h->d_ms32, NT * 4));
-  FAGBI_TRY(h->alloc(h->d_md32, NT * 4));
+  st.reserve(h->d_ms64, NT * 8);
+  st.reserve(h->d_md64, NT * 8);
+  st.reserve(h->d_ms32, NT * 4);
+  st.reserve(h->d_md32, NT * 4);
+  FAGBI_TRY(st.commit(h, h->d_fmm_pool));
   const unsigned grid = (unsigned)((NT + 255) / 256);
   k_panel_moments<double><<<grid, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                                                 h->d_leaf_of.as<int32_t>(), LF.d_idx.as<int32_t>(), h->corner[0],

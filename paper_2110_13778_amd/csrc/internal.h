@@ -109,6 +109,7 @@ struct fagbi_handle {
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
   fagbi::DBuf d_pc;                   // per panel: centroid, sqrt(area)
   fagbi::DBuf d_xt;                   // matvec input in tree order [2N]
+  fagbi::DBuf d_fmm_pool;             // one allocation behind all far-field tables and expansions
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_self_col;
   fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
