@@ -146,7 +146,11 @@ def main():
         E = h.solvation_energy(x, w["xq"], w["q"])
         t4 = time.perf_counter()
         gated = h.mlp_stats() if prec == F.MIXED else (0, 0)
-        return h, x, dict(code=code, mlp_gated=gated[0], mlp_candidates=gated[1], tree_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
+        pr = h.profile()
+        setup = {k: pr[k] for k in ("ms_tree", "ms_classify", "ms_surrogate", "ms_singular", "ms_fmm_setup",
+                                    "ms_precond")}
+        return h, x, dict(code=code, mlp_gated=gated[0], mlp_candidates=gated[1], setup_stages_ms=setup,
+                          t_rhs_ms=info.t_rhs_ms, t_iterations_ms=info.t_solve_ms, tree_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
                           solve_ms=1e3 * (t3 - t2), energy_ms=1e3 * (t4 - t3),
                           total_ms=1e3 * (t4 - t0), iters=info.inner_iterations,
                           outer=info.outer_iterations, mv64=info.matvecs_fp64,

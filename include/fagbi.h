@@ -116,6 +116,14 @@ typedef struct fagbi_profile {
   double ms_up[2];             /* P2M + MtM */
   double ms_m2l[2];            /* MtL, all levels */
   double ms_down[2];           /* LtL + LtP */
+  /* setup stages of the last build/assembly (host wall clock around
+     stream-synchronised stages, recorded while profiling is on) */
+  double ms_tree;              /* fagbi_build_tree */
+  double ms_classify;          /* near-field pair classes, regular pairs */
+  double ms_surrogate;         /* network features, inference, gated entries */
+  double ms_singular;          /* singular / close cubature */
+  double ms_fmm_setup;         /* far-field tables, panel moments */
+  double ms_precond;           /* block-diagonal factors */
 } fagbi_profile;
 
 typedef struct fagbi_handle fagbi_handle;

@@ -61,7 +61,9 @@ class SolveInfo(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("matvecs", C.c_int64 * 2), ("ms_total", C.c_double * 2),
                 ("ms_near", C.c_double * 2), ("ms_up", C.c_double * 2),
-                ("ms_m2l", C.c_double * 2), ("ms_down", C.c_double * 2)]
+                ("ms_m2l", C.c_double * 2), ("ms_down", C.c_double * 2),
+                ("ms_tree", C.c_double), ("ms_classify", C.c_double), ("ms_surrogate", C.c_double),
+                ("ms_singular", C.c_double), ("ms_fmm_setup", C.c_double), ("ms_precond", C.c_double)]
 
 
 class FagbiError(RuntimeError):
@@ -298,7 +300,8 @@ class Handle:
     def profile(self):
         p = Profile()
         _check(self.lib.fagbi_get_profile(self.h, C.byref(p)))
-        return {k: list(getattr(p, k)) for k, _ in Profile._fields_}
+        return {k: (list(getattr(p, k)) if hasattr(getattr(p, k), "__len__") else getattr(p, k))
+                for k, _ in Profile._fields_}
 
     def permutation(self):
         p = np.zeros(self.n, np.int32)

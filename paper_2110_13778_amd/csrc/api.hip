@@ -201,6 +201,7 @@ int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int
                      int64_t nt) {
   if (!h || !verts || !tris) return set_error(FAGBI_E_ARG, "null argument");
   if (nt > (int64_t)1 << 30) return set_error(FAGBI_E_ARG, "too many panels");
+  StageTimer tm(h, 0, &h->prof.ms_tree);
   return fagbi::build_tree(h, verts, nv, tris, nt);
 }
 
@@ -210,8 +211,14 @@ int fagbi_assemble_nearfield(fagbi_handle* h, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   h->near_ready = false;
   FAGBI_TRY(fagbi::assemble_nearfield(h, s));
-  FAGBI_TRY(fagbi::fmm_setup(h, s));
-  if (!h->precond_ready) FAGBI_TRY(fagbi::precond_setup(h, s));
+  {
+    StageTimer tm(h, s, &h->prof.ms_fmm_setup);
+    FAGBI_TRY(fagbi::fmm_setup(h, s));
+  }
+  if (!h->precond_ready) {
+    StageTimer tm(h, s, &h->prof.ms_precond);
+    FAGBI_TRY(fagbi::precond_setup(h, s));
+  }
   FAGBI_HIP(hipStreamSynchronize(s));
   h->near_ready = true;
   return 0;

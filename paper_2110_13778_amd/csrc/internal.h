@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -143,6 +144,28 @@ struct fagbi_handle {
 };
 
 namespace fagbi {
+// wall clock of one setup stage into *out while profiling is on (the stream
+// is synchronised at both ends, so only then)
+struct StageTimer {
+  fagbi_handle* h;
+  hipStream_t s;
+  double* out;
+  std::chrono::steady_clock::time_point t0;
+  StageTimer(fagbi_handle* h_, hipStream_t s_, double* out_) : h(h_), s(s_), out(out_) {
+    if (h->profiling) {
+      (void)hipStreamSynchronize(s);
+      t0 = std::chrono::steady_clock::now();
+    }
+  }
+  void stop() {
+    if (!h->profiling || !out) return;
+    (void)hipStreamSynchronize(s);
+    *out = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    out = nullptr;
+  }
+  ~StageTimer() { stop(); }
+};
+
 // stages implemented in the .hip files
 int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* tris, int64_t nt);
 int assemble_nearfield(fagbi_handle* h, hipStream_t s);

@@ -295,6 +295,7 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   NearArgs a = near_args(h);
   FAGBI_TRY(h->alloc(h->d_E64, (size_t)h->n_ent * sizeof(double4)));
   FAGBI_TRY(h->alloc(h->d_E32, (size_t)h->n_ent * sizeof(float4)));
+  StageTimer t_cls(h, s, &h->prof.ms_classify);
   // per-leaf class counts, one scan over the flattened [class][leaf] array,
   // then the worklists at the scanned offsets
   Tmp cnt, off, part;
@@ -318,6 +319,9 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   k_near_classify<1><<<nl, 256, 0, s>>>(a, off.as<int64_t>(), nl, h->d_wl[0].as<Item>(), h->d_wl[1].as<Item>(),
                                         h->d_wl[2].as<Item>(), h->d_wl[3].as<Item>(), h->d_E64.as<double4>());
   FAGBI_HIP(hipGetLastError());
+  t_cls.stop();
+  h->prof.ms_surrogate = 0;
+  StageTimer t_sing(h, s, &h->prof.ms_singular);
   // identical pairs: always the FP64 singular cubature
   FAGBI_TRY(run_singular(h, 0, nullptr, nullptr, s));
   const bool use_mlp = h->prm.mlp_mode != FAGBI_MLP_OFF && h->mlp_ready;
@@ -325,7 +329,10 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   if (use_mlp) {
     // the surrogate writes its entries for every near-singular pair and flags
     // the ones whose calibrated error passes the gate
-    FAGBI_TRY(mlp_assembly_stage(h, s));
+    {
+      StageTimer t_mlp(h, s, &h->prof.ms_surrogate);
+      FAGBI_TRY(mlp_assembly_stage(h, s));
+    }
     if (h->prm.mlp_mode == FAGBI_MLP_PRECOND) {
       // preconditioner from the surrogate's entries, operator from cubature
       FAGBI_TRY(precond_setup(h, s));
@@ -339,6 +346,10 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   k_to_f32<<<2048, 256, 0, s>>>(h->d_E64.as<double4>(), h->d_E32.as<float4>(), h->n_ent);
   FAGBI_HIP(hipGetLastError());
   FAGBI_HIP(hipStreamSynchronize(s));
+  if (h->profiling) {
+    t_sing.stop();   // singular stage without the surrogate's share
+    h->prof.ms_singular -= h->prof.ms_surrogate;
+  }
   h->precond_ready = use_mlp && h->prm.mlp_mode == FAGBI_MLP_PRECOND;
   return 0;
 }
