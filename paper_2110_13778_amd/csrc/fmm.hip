@@ -26,6 +26,7 @@
 // (deterministic in FP64).
 #include <algorithm>
 #include <cstring>
+#include <thread>
 #include <cmath>
 
 #include "internal.h"
@@ -882,12 +883,18 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
           const MI A = mi_of(ta), B = mi_of(tb);
           if (B.a[0] <= A.a[0] && B.a[1] <= A.a[1] && B.a[2] <= A.a[2]) pairs.push_back({ta, tb});
         }
+      // child centre - parent centre = (bit - 1/2) h_child per axis: powers of
+      // h_child/2 with the sign of odd powers taken from the octant bit
+      double hp[PMAX + 1];
+      hp[0] = 1.0;
+      for (int k = 1; k <= PMAX; ++k) hp[k] = hp[k - 1] * (0.5 * C.h);
       auto coef = [&](const P2& q, int oct) {
         const MI A = mi_of(q.a), B = mi_of(q.b);
         double v = 1.0;
         for (int ax = 0; ax < 3; ++ax) {
-          const double d = (((oct >> (2 - ax)) & 1) - 0.5) * C.h;   // child centre - parent centre
-          v *= binom(A.a[ax], B.a[ax]) * std::pow(d, A.a[ax] - B.a[ax]);
+          const int k = A.a[ax] - B.a[ax];
+          const bool neg = !((oct >> (2 - ax)) & 1) && (k & 1);
+          v *= binom(A.a[ax], B.a[ax]) * (neg ? -hp[k] : hp[k]);
         }
         return v;
       };
@@ -931,18 +938,30 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
     // derivative tables per offset, D_g = g! F_g / (4 pi), channels
     // interleaved {G0, Gk}
     if (l >= h->lmin && D.n_off > 0) {
-      std::vector<double> f0(D.T), fk(D.T), dt((size_t)2 * D.n_off * D.T);
-      for (int o = 0; o < D.n_off; ++o) {
-        const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h, D.off_xyz[3 * o + 2] * D.h};
-        taylor_host(x0, 0.0, D.order, f0.data());
-        taylor_host(x0, h->prm.kappa, D.order, fk.data());
-        for (int g = 0; g < D.T; ++g) {
-          const MI G = mi_of(g);
-          const double gf = fact(G.a[0]) * fact(G.a[1]) * fact(G.a[2]) / FOUR_PI;
-          dt[2 * ((size_t)o * D.T + g)] = gf * f0[g];
-          dt[2 * ((size_t)o * D.T + g) + 1] = gf * fk[g];
-        }
+      std::vector<double> dt((size_t)2 * D.n_off * D.T), gf(D.T);
+      for (int g = 0; g < D.T; ++g) {
+        const MI G = mi_of(g);
+        gf[g] = fact(G.a[0]) * fact(G.a[1]) * fact(G.a[2]) / FOUR_PI;
       }
+      // offsets split over host threads (independent recurrences)
+      const int nth = (int)std::max(1u, std::min(16u, std::min(std::thread::hardware_concurrency(),
+                                                                (unsigned)(D.n_off / 32 + 1))));
+      std::vector<std::thread> pool;
+      for (int t = 0; t < nth; ++t)
+        pool.emplace_back([&, t] {
+          std::vector<double> f0(D.T), fk(D.T);
+          for (int o = (int)((int64_t)D.n_off * t / nth); o < (int)((int64_t)D.n_off * (t + 1) / nth); ++o) {
+            const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h,
+                                  D.off_xyz[3 * o + 2] * D.h};
+            taylor_host(x0, 0.0, D.order, f0.data());
+            taylor_host(x0, h->prm.kappa, D.order, fk.data());
+            for (int g = 0; g < D.T; ++g) {
+              dt[2 * ((size_t)o * D.T + g)] = gf[g] * f0[g];
+              dt[2 * ((size_t)o * D.T + g) + 1] = gf[g] * fk[g];
+            }
+          }
+        });
+      for (auto& th : pool) th.join();
       st.add_conv<double>(D.d_F64[0], dt);
       st.add_conv<float>(D.d_F32[0], dt);
       // one of each pair of opposite offsets (first non-zero component > 0)
@@ -1028,9 +1047,10 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     if (prof) FAGBI_HIP(hipEventRecord(h->ev[k], s));
     return 0;
   };
-  FAGBI_TRY(mark(0));
+  FAGBI_TRY(mark(5));
   double* xt = h->d_xt.as<double>();
   k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), N, xt);
+  FAGBI_TRY(mark(0));
   if (parts & FAGBI_PART_NEAR) {
     k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, s>>>(
         ent.as<E>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
@@ -1180,14 +1200,15 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
 
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts, hipStream_t s) {
   if (h->profiling && !h->ev[0])
-    for (int k = 0; k < 5; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
+    for (int k = 0; k < 6; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
   int r = precision == FAGBI_MIXED
               ? matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
               : matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
   if (r < 0 || !h->profiling) return r;
   FAGBI_HIP(hipEventSynchronize(h->ev[4]));
-  float t[4];
+  float t[4], tot;
   for (int k = 0; k < 4; ++k) FAGBI_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
+  FAGBI_HIP(hipEventElapsedTime(&tot, h->ev[5], h->ev[4]));
   const int p = precision == FAGBI_MIXED ? 1 : 0;
   fagbi_profile& P = h->prof;
   P.matvecs[p] += 1;
@@ -1195,7 +1216,7 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
   P.ms_up[p] += t[1];
   P.ms_m2l[p] += t[2];
   P.ms_down[p] += t[3];
-  P.ms_total[p] += t[0] + t[1] + t[2] + t[3];
+  P.ms_total[p] += tot;
   return 0;
 }
 

@@ -135,7 +135,9 @@ struct fagbi_handle {
   std::vector<float> mlp_blob;        // parameters | normalisation | calibration
   // per-phase profiling
   bool profiling = false;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // matvec phase events: 5 start, 0 after the reorder of x, 1 near field,
+  // 2 upward pass, 3 MtL, 4 downward pass
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);
