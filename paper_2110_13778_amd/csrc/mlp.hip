@@ -453,28 +453,35 @@ static int ensure_net(fagbi_handle* h) {
 // ---------------------------------------------------------------------------
 // fused inference on the matrix cores: one block of 4 waves per 64 rows,
 // each wave owns 16 rows; every layer is a sequence of
-// v_mfma_f32_16x16x4f32 over K, with the layer's weights staged in LDS and
-// each wave's activations kept in its own LDS rows between layers.
+// v_mfma_f32_16x16x4f32 over K with the weights read straight from the
+// (L2-resident, 140 KB) parameter vector and each wave's activations kept in
+// its own LDS rows between layers, so several blocks share a CU.
 // Lane layouts of the 16x16x4 FP32 instruction: A[i][k] from lane i + 16k,
 // B[k][j] from lane j + 16k, D[i][j] in lane j + 16(i/4), element i % 4.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int IR = 64;               // rows per block
 constexpr int AST = NH + 4;          // activation row stride (A reads: 2-way banks)
-constexpr int WST = NH + 16;         // weight row stride (B reads: 2-way banks)
 
-__device__ inline void mlp_layer(const float* act, const float* Ws, const float* bias, int K, int ntile, int lane,
-                                 f32x4* acc) {
+// acc[t] = bias + act[16 x K] * W[K x N] for column tiles t < ntile (W
+// row-major [K][N]; columns >= N read as 0)
+__device__ inline void mlp_layer(const float* act, const float* __restrict__ W, const float* __restrict__ bias,
+                                 int K, int N, int ntile, int lane, f32x4* acc) {
+  const int j = lane & 15, kq = lane >> 4;
   for (int t = 0; t < ntile; ++t) {
-    const float b = bias[t * 16 + (lane & 15)];
+    const int col = t * 16 + j;
+    const float b = col < N ? bias[col] : 0.f;
     acc[t] = f32x4{b, b, b, b};
   }
   for (int k0 = 0; k0 < K; k0 += 4) {
-    const float av = act[(lane & 15) * AST + k0 + (lane >> 4)];
-    const float* wr = Ws + (k0 + (lane >> 4)) * WST + (lane & 15);
+    const float av = act[j * AST + k0 + kq];
+    const float* wr = W + (int64_t)(k0 + kq) * N + j;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
-      if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wr[t * 16], acc[t], 0, 0, 0);
+      if (t < ntile) {
+        const float bv = (t * 16 + j) < N ? wr[t * 16] : 0.f;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
   }
 }
 
@@ -483,46 +490,37 @@ __device__ inline void mlp_layer(const float* act, const float* Ws, const float*
 __global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, int64_t n,
                                                    const float* __restrict__ th, const float* __restrict__ norm,
                                                    int destd, float* out) {
-  extern __shared__ __align__(16) float smem[];
-  float* Ws = smem;                       // [NH][WST]
-  float* bs = Ws + NH * WST;              // [NH] bias of the current layer (padded)
-  float* act_all = bs + NH;               // [4][16][AST]
+  __shared__ float act_all[4 * 16 * AST];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* act = act_all + wave * 16 * AST;
-  const int64_t r0 = (int64_t)blockIdx.x * IR;
-  // standardised inputs of this block's rows
-  for (int e = threadIdx.x; e < IR * NIN; e += 256) {
+  const int64_t r0 = (int64_t)blockIdx.x * IR + wave * 16;
+  // standardised inputs of this wave's rows
+  for (int e = lane; e < 16 * NIN; e += 64) {
     const int r = e / NIN, k = e - r * NIN;
     const int64_t g = r0 + r;
-    act_all[(r >> 4) * 16 * AST + (r & 15) * AST + k] = g < n ? (X[g * NIN + k] - norm[k]) / norm[NIN + k] : 0.f;
+    act[r * AST + k] = g < n ? (X[g * NIN + k] - norm[k]) / norm[NIN + k] : 0.f;
   }
+  __syncthreads();
   f32x4 acc[8];
-  const int offW[4] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4};
-  const int offB[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
-  for (int l = 0; l < 4; ++l) {
-    const int K = l == 0 ? NIN : NH;
-    const int N = l == 3 ? NOUT : NH;
-    const int ncol = l == 3 ? 16 : NH;    // output padded to one 16-column tile
-    __syncthreads();
-    for (int e = threadIdx.x; e < K * ncol; e += 256) {
-      const int k = e / ncol, j = e - k * ncol;
-      Ws[k * WST + j] = j < N ? th[offW[l] + k * N + j] : 0.f;
-    }
-    for (int j = threadIdx.x; j < ncol; j += 256) bs[j] = j < N ? th[offB[l] + j] : 0.f;
-    __syncthreads();
-    const int ntile = ncol / 16;
-    mlp_layer(act, Ws, bs, K, ntile, lane, acc);
-    if (l < 3) {
-      for (int t = 0; t < ntile; ++t)
+  mlp_layer(act, th + OFF_W1, th + OFF_B1, NIN, NH, 8, lane, acc);
+  for (int l = 0; l < 3; ++l) {
+    // every read of act by this layer is issued before the overwrite below
+    // (program order within the wave); the barrier orders the writes before
+    // the next layer's reads
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) act[(4 * (lane >> 4) + q) * AST + t * 16 + (lane & 15)] = tanhf(acc[t][q]);
-    }
+      for (int q = 0; q < 4; ++q) act[(4 * (lane >> 4) + q) * AST + t * 16 + (lane & 15)] = tanhf(acc[t][q]);
+    __syncthreads();
+    if (l < 2)
+      mlp_layer(act, th + (l == 0 ? OFF_W2 : OFF_W3), th + (l == 0 ? OFF_B2 : OFF_B3), NH, NH, 8, lane, acc);
+    else
+      mlp_layer(act, th + OFF_W4, th + OFF_B4, NH, NOUT, 1, lane, acc);
   }
   const int j = lane & 15;
   if (j < NOUT)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t g = r0 + wave * 16 + 4 * (lane >> 4) + q;
+      const int64_t g = r0 + 4 * (lane >> 4) + q;
       if (g < n) {
         float y = acc[0][q];
         if (destd) {
@@ -534,14 +532,10 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, 
     }
 }
 
-constexpr size_t INFER_LDS = (size_t)(NH * WST + NH + 4 * 16 * AST) * sizeof(float);
-
 static int infer(fagbi_handle* h, const float* Xraw, int64_t n, int destd, float* out, hipStream_t s) {
   if (n <= 0) return 0;
-  FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_infer),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)INFER_LDS));
-  k_mlp_infer<<<(unsigned)((n + IR - 1) / IR), 256, INFER_LDS, s>>>(Xraw, n, h->d_mlp_theta.as<float>(),
-                                                                     h->d_mlp_norm.as<float>(), destd, out);
+  k_mlp_infer<<<(unsigned)((n + IR - 1) / IR), 256, 0, s>>>(Xraw, n, h->d_mlp_theta.as<float>(),
+                                                             h->d_mlp_norm.as<float>(), destd, out);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }
