@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="ellipsoid500k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=12)
+    ap.add_argument("--mlp-epochs", type=int, default=120,
+                    help="training epochs of the near-field surrogate (before the timed steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -131,7 +133,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     log("workload %s: %d panels, %d charges" % (args.workload, N, len(w["q"])))
-    blob, mlp_info = train_surrogate(F, torch)
+    blob, mlp_info = train_surrogate(F, torch, epochs=args.mlp_epochs)
     log("surrogate trained on %d pairs in %.1f s" % (mlp_info["pairs"], mlp_info["train_s"]))
 
     def run(prec, profile):

@@ -534,12 +534,15 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
   for (int e = threadIdx.x; e < n_half * T; e += NT) dsm[e] = Dh[e];
   for (int e = threadIdx.x; e < n_off; e += NT) smap[e] = omap[e];
   __syncthreads();
+  // XCD x (= block id mod 8) owns a contiguous range of tiles; its blocks
+  // sweep that range together (tile it * nbx + local block), so the sources
+  // in use at any time stay within the XCD's L2
   const int nbx = (int)((gridDim.x + 7) / 8);
-  const int64_t blk = (int64_t)(blockIdx.x & 7) * nbx + (blockIdx.x >> 3);
+  const int64_t xcd = blockIdx.x & 7, bl = blockIdx.x >> 3;
   const int64_t ntile = ((int64_t)ncl * S + NT - 1) / NT;
   const int64_t per = (ntile + (int64_t)nbx * 8 - 1) / ((int64_t)nbx * 8);
   for (int64_t it = 0; it < per; ++it) {
-    const int64_t gt = (blk * per + it) * NT + threadIdx.x;
+    const int64_t gt = ((xcd * per + it) * nbx + bl) * NT + threadIdx.x;
     const int c = (int)(gt / S), part = (int)(gt - (int64_t)c * S);
     R l0[T], lk[T];
 #pragma unroll
