@@ -161,24 +161,34 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
       av[d] = ci[3 * ri + d] - Q;
       bv[d] = cj[3 * rj + d] - Q;
     }
-    for (int p = lane; p < 4 * n3; p += 64) {
-      const int piece = p / n3, rem = p - piece * n3;
-      const int ia = rem / n2, ib = (rem / n) % n, ic = rem % n;
-      const double xi = gx[ia], w1 = gx[ib], w2 = gx[ic];
-      double w = gw[ia] * gw[ib] * gw[ic] * (1.0 - xi) * xi * xi;
-      double z1, x2, y2;
+    // lanes over (piece, xi, w1); the innermost variable w2 enters the
+    // separation linearly, r = R0 + w2 R1
+    for (int it = lane; it < 4 * n2; it += 64) {
+      const int piece = it / n2, rem = it - piece * n2;
+      const int ia = rem / n, ib = rem - ia * n;
+      const double xi = gx[ia], w1 = gx[ib];
+      double wb = gw[ia] * gw[ib] * (1.0 - xi) * xi * xi;
+      // (z1, x2, y2) = (z1_0, x2_0, y2_0) + w2 (z1_1, x2_1, y2_1)
+      double z0, z1c, x0, x1, y0, y1;
       if (piece == 0) {
-        z1 = xi * w1; x2 = xi * (1 - w1); y2 = xi * w2;
+        z0 = xi * w1; z1c = 0; x0 = xi * (1 - w1); x1 = 0; y0 = 0; y1 = xi;
       } else if (piece == 1) {
-        z1 = xi * w1 * (1 - w2); x2 = xi * w1 * w2; y2 = xi; w *= w1;
+        z0 = xi * w1; z1c = -xi * w1; x0 = 0; x1 = xi * w1; y0 = xi; y1 = 0; wb *= w1;
       } else if (piece == 2) {
-        z1 = -xi * w1 * (1 - w2); x2 = xi; y2 = xi * w1 * w2; w *= w1;
+        z0 = -xi * w1; z1c = xi * w1; x0 = xi; x1 = 0; y0 = 0; y1 = xi * w1; wb *= w1;
       } else {
-        z1 = -xi * w1; x2 = xi * w2; y2 = xi * (1 - w1);
+        z0 = -xi * w1; z1c = 0; x0 = 0; x1 = xi; y0 = xi * (1 - w1); y1 = 0;
       }
-      kernel6(-z1 * e[0] + x2 * av[0] - y2 * bv[0], -z1 * e[1] + x2 * av[1] - y2 * bv[1],
-              -z1 * e[2] + x2 * av[2] - y2 * bv[2], ni, nj, a.kappa, k6);
-      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      double R0[3], R1[3];
+      for (int d = 0; d < 3; ++d) {
+        R0[d] = -z0 * e[d] + x0 * av[d] - y0 * bv[d];
+        R1[d] = -z1c * e[d] + x1 * av[d] - y1 * bv[d];
+      }
+      for (int ic = 0; ic < n; ++ic) {
+        const double w2 = gx[ic], w = wb * gw[ic];
+        kernel6(R0[0] + w2 * R1[0], R0[1] + w2 * R1[1], R0[2] + w2 * R1[2], ni, nj, a.kappa, k6);
+        for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      }
     }
   } else if (CLS == C_VERTEX) {
     int si = 0, sj = 0;
@@ -196,32 +206,43 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
       B0[d] = cj[3 * vj + d] - S[d];
       B1[d] = cj[3 * wj + d] - cj[3 * vj + d];
     }
-    for (int p = lane; p < 2 * n4; p += 64) {
-      const int piece = p / n4, rem = p - piece * n4;
-      const int ia = rem / n3, ib = (rem / n2) % n, ic = (rem / n) % n, id = rem % n;
-      const double xi = gx[ia], eta = gx[ib], t1 = gx[ic], t2 = gx[id];
-      const double w = gw[ia] * gw[ib] * gw[ic] * gw[id] * xi * xi * xi * eta;
+    // lanes over (piece, xi, eta, t1); the innermost t2 enters linearly
+    for (int it = lane; it < 2 * n3; it += 64) {
+      const int piece = it / n3, rem = it - piece * n3;
+      const int ia = rem / n2, ib = (rem / n) % n, ic = rem % n;
+      const double xi = gx[ia], eta = gx[ib], t1 = gx[ic];
+      const double wb = gw[ia] * gw[ib] * gw[ic] * xi * xi * xi * eta;
       const double sa = piece == 0 ? xi : xi * eta;
       const double sb = piece == 0 ? xi * eta : xi;
-      double r[3];
-      for (int d = 0; d < 3; ++d) r[d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
-      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
-      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      double R0[3], R1[3];
+      for (int d = 0; d < 3; ++d) {
+        R0[d] = sa * (A0[d] + t1 * A1[d]) - sb * B0[d];
+        R1[d] = -sb * B1[d];
+      }
+      for (int id = 0; id < n; ++id) {
+        const double t2 = gx[id], w = wb * gw[id];
+        kernel6(R0[0] + t2 * R1[0], R0[1] + t2 * R1[1], R0[2] + t2 * R1[2], ni, nj, a.kappa, k6);
+        for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      }
     }
   } else {  // CLOSE
     const double tai = 2.0 * a.pa[i], taj = 2.0 * a.pa[j];
-    for (int p = lane; p < n4; p += 64) {
-      const int ia = p / n3, ib = (p / n2) % n, ic = (p / n) % n, id = p % n;
-      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic], t2 = gx[id];
-      const double w = tai * s1 * gw[ia] * gw[ib] * taj * s2 * gw[ic] * gw[id];
-      double r[3];
+    // lanes over (s1, t1, s2); the innermost t2 enters linearly
+    for (int it = lane; it < n3; it += 64) {
+      const int ia = it / n2, ib = (it / n) % n, ic = it % n;
+      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic];
+      const double wb = tai * s1 * gw[ia] * gw[ib] * taj * s2 * gw[ic];
+      double R0[3], R1[3];
       for (int d = 0; d < 3; ++d) {
         const double x = ci[d] + s1 * (ci[3 + d] - ci[d]) + s1 * t1 * (ci[6 + d] - ci[3 + d]);
-        const double y = cj[d] + s2 * (cj[3 + d] - cj[d]) + s2 * t2 * (cj[6 + d] - cj[3 + d]);
-        r[d] = x - y;
+        R0[d] = x - (cj[d] + s2 * (cj[3 + d] - cj[d]));
+        R1[d] = -s2 * (cj[6 + d] - cj[3 + d]);
       }
-      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
-      for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      for (int id = 0; id < n; ++id) {
+        const double t2 = gx[id], w = wb * gw[id];
+        kernel6(R0[0] + t2 * R1[0], R0[1] + t2 * R1[1], R0[2] + t2 * R1[2], ni, nj, a.kappa, k6);
+        for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
+      }
     }
   }
   for (int m = 0; m < 6; ++m) acc[m] = wave_sum(acc[m]);
