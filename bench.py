@@ -53,7 +53,7 @@ def parse():
 
 PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7,
               near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=5e-7)
-MLP_GATE = 0.07         # stated per-pair error tolerance of the gated near field
+MLP_GATE = 0.05         # stated per-pair error tolerance of the gated near field
 
 
 def train_surrogate(F, torch, pairs_per_mesh=1000000, epochs=120):
