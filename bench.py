@@ -52,7 +52,8 @@ def parse():
 
 
 PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7,
-              near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=5e-7)
+              near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=5e-7,
+              precond=3)   # block-diagonal preconditioner over consecutive leaves, <= 32 panels
 MLP_GATE = 0.05         # stated per-pair error tolerance of the gated near field
 
 

@@ -48,7 +48,7 @@ enum {
 };
 
 enum { FAGBI_FP64 = 0, FAGBI_MIXED = 1 };
-enum { FAGBI_PRECOND_NONE = 0, FAGBI_PRECOND_DIAG = 1, FAGBI_PRECOND_BLOCK = 2 };
+enum { FAGBI_PRECOND_NONE = 0, FAGBI_PRECOND_DIAG = 1, FAGBI_PRECOND_BLOCK = 2, FAGBI_PRECOND_GROUP = 3 };
 enum { FAGBI_MLP_OFF = 0, FAGBI_MLP_PRECOND = 1, FAGBI_MLP_GATED = 2 };
 /* parts of the operator for fagbi_matvec_parts */
 enum { FAGBI_PART_NEAR = 1, FAGBI_PART_FAR = 2, FAGBI_PART_ALL = 3 };

@@ -53,19 +53,40 @@ def energy(P, x, xq, q, eps, kappa):
     return 0.5 * UNIT_KCAL * total
 
 
-def block_preconditioner(P, tree, eps, kappa, near_ratio=2.0, n=7):
-    """Returns a function z -> M^{-1} z (per-leaf dense LU via numpy.solve)."""
+def block_preconditioner(P, tree, eps, kappa, near_ratio=2.0, n=7, group_max=0):
+    """Returns a function z -> M^{-1} z (dense solves per block), Sec. 2.6.
+
+    Blocks: one per leaf (group_max = 0), or groups of consecutive leaves in
+    tree order holding at most group_max panels.  A block [phi_g; dphi_g]
+    holds the operator entries of every pair of its panels whose leaves are
+    neighbours (the pairs the near field stores); other pairs are far field
+    and left out."""
     from .pairs import pair_integrals
     from .kernels import combine
     N = P.n
     leaf = tree.levels[tree.L]
-    blocks = []
+    groups, cur, cnt = [], [], 0
     for c in range(leaf.n):
-        ids = tree.perm[leaf.start[c]:leaf.end[c]]
+        nc = leaf.end[c] - leaf.start[c]
+        if cur and (group_max == 0 or cnt + nc > group_max):
+            groups.append(cur)
+            cur, cnt = [], 0
+        cur.append(c)
+        cnt += nc
+    groups.append(cur)
+    blocks = []
+    for g in groups:
+        ids = tree.perm[leaf.start[g[0]]:leaf.end[g[-1]]]
+        lf = np.concatenate([np.full(leaf.end[c] - leaf.start[c], c) for c in g])
         m = len(ids)
-        a, b = np.meshgrid(ids, ids, indexing="ij")
-        I, _ = pair_integrals(P, a.ravel(), b.ravel(), kappa, near_ratio, n)
-        B = combine(I, eps).reshape(m, m, 4)
+        ra, rb = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+        ra, rb = ra.ravel(), rb.ravel()
+        near = np.array([lf[b] in set(leaf.nbr[lf[a]].tolist()) for a, b in zip(ra, rb)], bool)
+        B = np.zeros((m * m, 4))
+        if near.any():
+            I, _ = pair_integrals(P, ids[ra[near]], ids[rb[near]], kappa, near_ratio, n)
+            B[near] = combine(I, eps)
+        B = B.reshape(m, m, 4)
         M = np.zeros((2 * m, 2 * m))
         M[:m, :m] = B[..., 0] + np.diag(0.5 * (1 + eps) * P.area[ids])
         M[:m, m:] = B[..., 1]

@@ -15,7 +15,7 @@ LIBPATH = os.path.join(HERE, "libfagbi.so")
 OK, E_ARG, E_MESH, E_STATE, E_OOM, E_HIP, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 W_NOT_CONVERGED = 1
 FP64, MIXED = 0, 1
-PRECOND_NONE, PRECOND_DIAG, PRECOND_BLOCK = 0, 1, 2
+PRECOND_NONE, PRECOND_DIAG, PRECOND_BLOCK, PRECOND_GROUP = 0, 1, 2, 3
 MLP_OFF, MLP_PRECOND, MLP_GATED = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 

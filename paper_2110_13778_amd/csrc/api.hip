@@ -152,7 +152,7 @@ static int check_params(const fagbi_params* p) {
   if (!(p->near_ratio >= 0)) return set_error(FAGBI_E_ARG, "near_ratio must be >= 0");
   if (p->precision != FAGBI_FP64 && p->precision != FAGBI_MIXED)
     return set_error(FAGBI_E_ARG, "precision must be FAGBI_FP64 or FAGBI_MIXED");
-  if (p->precond < 0 || p->precond > 2) return set_error(FAGBI_E_ARG, "bad precond");
+  if (p->precond < 0 || p->precond > 3) return set_error(FAGBI_E_ARG, "bad precond");
   if (!(p->tol > 0) || p->max_iter < 1 || p->max_iter > 2000 || p->max_outer < 1 ||
       !(p->inner_tol > 0))
     return set_error(FAGBI_E_ARG, "bad solver tolerances/iteration limits");

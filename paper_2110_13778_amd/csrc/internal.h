@@ -117,6 +117,8 @@ struct fagbi_handle {
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
   fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]
   fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner
+  fagbi::DBuf d_grp_leaf, d_grp_panel;         // its blocks: leaf and panel ranges
+  int n_groups = 0;
   fagbi::DBuf d_gl;                   // Gauss-Legendre nodes/weights on [0,1]
   fagbi::DBuf d_work;                 // scratch for reductions
   // Krylov workspace

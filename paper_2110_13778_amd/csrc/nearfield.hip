@@ -381,25 +381,45 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
 // Gauss-Jordan elimination with partial pivoting (one wavefront per leaf,
 // matrix in LDS).  The inverse is stored transposed for coalesced apply.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__ ent,
+// Blocks of the preconditioner: groups of consecutive leaves (one leaf per
+// group for FAGBI_PRECOND_BLOCK; consecutive leaves up to 32 panels for
+// FAGBI_PRECOND_GROUP).  Group g covers leaves [gl[g], gl[g+1]) and panels
+// [gp[g], gp[g+1]); its block is ordered [phi of the group's panels; dphi of
+// them] and holds every stored near-field entry between them (pairs of
+// leaves that are not neighbours have none: they are far field).
+__global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__ ent, const int32_t* gl,
+                                                     const int32_t* gp, const int32_t* leaf_start,
                                                      const int32_t* leaf_cnt, const int64_t* src_off,
-                                                     const int64_t* ent_off, const int32_t* self_col,
+                                                     const int64_t* ent_off, const int32_t* lnbr_off,
+                                                     const int32_t* lnbr, const int32_t* lnbr_col,
                                                      const int64_t* inv_off, double* inv, int* bad) {
   __shared__ double A[64][65];
   __shared__ int swp[64];
-  const int c = blockIdx.x;
-  const int nc = leaf_cnt[c];
-  const int m = 2 * nc;
-  const int S = (int)(src_off[c + 1] - src_off[c]);
-  const int64_t eo = ent_off[c];
-  const int sc = self_col[c];
+  const int g = blockIdx.x;
+  const int l0 = gl[g], l1 = gl[g + 1];
+  const int p0 = gp[g];
+  const int ng = gp[g + 1] - p0;
+  const int m = 2 * ng;
   const int r = threadIdx.x;
-  if (r < m) {
-    const int il = r < nc ? r : r - nc;
-    for (int col = 0; col < m; ++col) {
-      const int jl = col < nc ? col : col - nc;
-      const double4 e = ent[eo + (int64_t)il * S + sc + jl];
-      A[r][col] = r < nc ? (col < nc ? e.x : e.y) : (col < nc ? e.z : e.w);
+  for (int j = 0; j < m; ++j)
+    if (r < m) A[r][j] = 0.0;
+  __syncthreads();
+  for (int c1 = l0; c1 < l1; ++c1) {
+    const int n1 = leaf_cnt[c1], o1 = leaf_start[c1] - p0;
+    const int S = (int)(src_off[c1 + 1] - src_off[c1]);
+    const int64_t eo = ent_off[c1];
+    for (int q = lnbr_off[c1]; q < lnbr_off[c1 + 1]; ++q) {
+      const int c2 = lnbr[q];
+      if (c2 < l0 || c2 >= l1) continue;
+      const int n2 = leaf_cnt[c2], o2 = leaf_start[c2] - p0, col = lnbr_col[q];
+      for (int e = r; e < n1 * n2; e += 64) {
+        const int il = e / n2, jl = e - il * n2;
+        const double4 v = ent[eo + (int64_t)il * S + col + jl];
+        A[o1 + il][o2 + jl] = v.x;
+        A[o1 + il][ng + o2 + jl] = v.y;
+        A[ng + o1 + il][o2 + jl] = v.z;
+        A[ng + o1 + il][ng + o2 + jl] = v.w;
+      }
     }
   }
   __syncthreads();
@@ -445,30 +465,30 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
     __syncthreads();
   }
   if (r < m) {
-    double* out = inv + inv_off[c];
+    double* out = inv + inv_off[g];
     for (int b = 0; b < m; ++b) out[(int64_t)b * m + r] = A[r][b];
   }
 }
 
+// y = M^-1 z, one wavefront per group (inverse stored transposed)
 __global__ void __launch_bounds__(64) k_block_apply(const double* __restrict__ inv,
-                                                    const int64_t* inv_off, const int32_t* leaf_start,
-                                                    const int32_t* leaf_cnt, const int32_t* perm,
-                                                    int64_t N, const double* z, double* y) {
+                                                    const int64_t* inv_off, const int32_t* gp,
+                                                    const int32_t* perm, int64_t N, const double* z, double* y) {
   __shared__ double zb[64];
-  const int c = blockIdx.x;
-  const int nc = leaf_cnt[c];
-  const int m = 2 * nc;
-  const int i0 = leaf_start[c];
+  const int g = blockIdx.x;
+  const int p0 = gp[g];
+  const int ng = gp[g + 1] - p0;
+  const int m = 2 * ng;
   const int r = threadIdx.x;
   int64_t row = 0;
   if (r < m) {
-    const int p = perm[i0 + (r < nc ? r : r - nc)];
-    row = r < nc ? (int64_t)p : N + p;
+    const int p = perm[p0 + (r < ng ? r : r - ng)];
+    row = r < ng ? (int64_t)p : N + p;
     zb[r] = z[row];
   }
   __syncthreads();
   if (r < m) {
-    const double* T = inv + inv_off[c];
+    const double* T = inv + inv_off[g];
     double acc = 0;
     for (int b = 0; b < m; ++b) acc += T[(int64_t)b * m + r] * zb[b];
     y[row] = acc;
@@ -503,17 +523,40 @@ int precond_setup(fagbi_handle* h, hipStream_t s) {
                                    h->d_ent_off.as<int64_t>(), h->d_self_col.as<int32_t>(),
                                    h->d_perm.as<int32_t>(), h->N, h->d_diag.as<double>());
   FAGBI_HIP(hipGetLastError());
-  std::vector<int64_t> off(nl + 1, 0);
-  for (int c = 0; c < nl; ++c) off[c + 1] = off[c] + 4LL * h->leaf_cnt[c] * h->leaf_cnt[c];
+  // groups of consecutive leaves: one leaf each, or (GROUP) as many as fit in
+  // 32 panels
+  const int gmax = h->prm.precond == FAGBI_PRECOND_GROUP ? 32 : 0;
+  std::vector<int32_t> gl(1, 0), gp(1, 0);
+  int panels = 0, cur = 0;
+  for (int c = 0; c < nl; ++c) {
+    const int n = h->leaf_cnt[c];
+    if (c > gl.back() && (gmax == 0 || cur + n > gmax)) {
+      gl.push_back(c);
+      gp.push_back(panels);
+      cur = 0;
+    }
+    cur += n;
+    panels += n;
+  }
+  gl.push_back(nl);
+  gp.push_back(panels);
+  const int ng = (int)gl.size() - 1;
+  h->n_groups = ng;
+  std::vector<int64_t> off(ng + 1, 0);
+  for (int g = 0; g < ng; ++g) off[g + 1] = off[g] + 4LL * (gp[g + 1] - gp[g]) * (gp[g + 1] - gp[g]);
+  FAGBI_TRY(h->upload(h->d_grp_leaf, gl.data(), gl.size() * 4));
+  FAGBI_TRY(h->upload(h->d_grp_panel, gp.data(), gp.size() * 4));
   FAGBI_TRY(h->upload(h->d_lu_off, off.data(), off.size() * 8));
-  FAGBI_TRY(h->alloc(h->d_lu, (size_t)off[nl] * sizeof(double)));
+  FAGBI_TRY(h->alloc(h->d_lu, (size_t)off[ng] * sizeof(double)));
   Tmp bad;
   FAGBI_TRY(bad.alloc(sizeof(int)));
   FAGBI_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-  k_block_invert<<<nl, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_leaf_cnt.as<int32_t>(),
+  k_block_invert<<<ng, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_grp_leaf.as<int32_t>(), h->d_grp_panel.as<int32_t>(),
+                                   h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
                                    h->d_src_off.as<int64_t>(), h->d_ent_off.as<int64_t>(),
-                                   h->d_self_col.as<int32_t>(), h->d_lu_off.as<int64_t>(),
-                                   h->d_lu.as<double>(), bad.as<int>());
+                                   h->d_lnbr_off.as<int32_t>(), h->d_lnbr.as<int32_t>(),
+                                   h->d_lnbr_col.as<int32_t>(), h->d_lu_off.as<int64_t>(), h->d_lu.as<double>(),
+                                   bad.as<int>());
   FAGBI_HIP(hipGetLastError());
   int hb = 0;
   FAGBI_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -532,10 +575,8 @@ int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s) {
     FAGBI_HIP(hipGetLastError());
     return 0;
   }
-  const int nl = h->lev[h->L].n;
-  k_block_apply<<<nl, 64, 0, s>>>(h->d_lu.as<double>(), h->d_lu_off.as<int64_t>(),
-                                  h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
-                                  h->d_perm.as<int32_t>(), h->N, z, y);
+  k_block_apply<<<h->n_groups, 64, 0, s>>>(h->d_lu.as<double>(), h->d_lu_off.as<int64_t>(),
+                                          h->d_grp_panel.as<int32_t>(), h->d_perm.as<int32_t>(), h->N, z, y);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }

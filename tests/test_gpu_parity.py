@@ -94,6 +94,23 @@ def test_fmm_matches_oracle_fmm(sphere1280, cfg):
     h.close()
 
 
+@pytest.mark.parametrize("leaf", [8, 4])
+def test_grouped_preconditioner_matches_oracle(sphere1280, leaf):
+    """blocks over consecutive leaves up to 32 panels (small leaves, so the
+    groups mix neighbouring and non-neighbouring leaves)"""
+    v, t, P = sphere1280
+    h = F.Handle(leaf_size=leaf, precond=F.PRECOND_GROUP).build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, leaf, 0.8)
+    Minv = osolve.block_preconditioner(P, tr, EPS, KAP, group_max=32)
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal(2 * P.n)
+    y = torch.empty(2 * P.n, dtype=torch.float64, device=DEV)
+    h.precond_apply(dev(z), y)
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), Minv(z)) < 1e-11
+    h.close()
+
+
 def test_precond_and_rhs_and_energy(sphere1280):
     v, t, P = sphere1280
     h = F.Handle().build_tree(v, t).assemble_nearfield()
