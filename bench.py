@@ -76,9 +76,30 @@ def train_surrogate(F, torch, pairs_per_mesh=1000000, epochs=120):
                        lr=3e-3, seed=5)
     t2 = time.perf_counter()
     blob = h.mlp_get_weights()
+    # per-pair error on the held-out rows (every tenth) against the cubature:
+    # max over the six outputs of |pred - true| / (|full integral| + 0.1 rms)
+    val = torch.arange(9, X.shape[0], 10, device=X.device)
+    Y = h.mlp_forward(X[val].contiguous()).cpu().numpy()
+    t = T[val].cpu().numpy()
+    full = A[val, 2:].cpu().numpy()
+    cls = A[val, 0].cpu().numpy()
     h.close()
+    rms = np.sqrt((full ** 2).mean(0))
+    err = (np.abs(Y - t) / (np.abs(full) + 0.1 * rms)).max(1)
+    err0 = (np.abs(t) / (np.abs(full) + 0.1 * rms)).max(1)
+    edges = [0.0, 0.003, 0.01, 0.03, 0.1, 0.3, 1.0, np.inf]
+    hist_err = {}
+    for c, name in enumerate(("edge", "vertex", "close")):
+        e, e0 = err[cls == c], err0[cls == c]
+        hist_err[name] = {"pairs": int(e.size),
+                          "p50": float(np.percentile(e, 50)), "p90": float(np.percentile(e, 90)),
+                          "p99": float(np.percentile(e, 99)),
+                          "p50_without_network": float(np.percentile(e0, 50)),
+                          "histogram": {"edges": [float(x) for x in edges[:-1]] + ["inf"],
+                                        "counts": np.histogram(e, bins=edges)[0].tolist()}}
     return blob, {"pairs": int(X.shape[0]), "epochs": epochs, "data_s": t1 - t0, "train_s": t2 - t1,
-                  "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+                  "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                  "heldout_error_vs_cubature": hist_err}
 
 
 def log(msg):

@@ -112,7 +112,8 @@ typedef struct fagbi_solve_info {
 typedef struct fagbi_profile {
   int64_t matvecs[2];
   double ms_total[2];          /* whole matvec (incl. the reorder of x into tree order) */
-  double ms_near[2];           /* near-field block SpMV kernel (incl. identity terms) */
+  double ms_near[2];           /* near-field block SpMV kernel (incl. identity terms; it runs on a
+                                  second stream beside the far field, so the phases overlap) */
   double ms_up[2];             /* P2M + MtM */
   double ms_m2l[2];            /* MtL, all levels */
   double ms_down[2];           /* LtL + LtP */

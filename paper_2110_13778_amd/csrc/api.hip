@@ -193,6 +193,9 @@ void fagbi_destroy(fagbi_handle* h) {
   h->free_all();
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->s_near) (void)hipStreamDestroy(h->s_near);
   (void)hipSetDevice(cur);
   delete h;
 }

@@ -82,13 +82,19 @@ static void taylor_host(const double x0[3], double kappa, int p, double* F) {
       }
 }
 
+__host__ __device__ constexpr int binom_c(int n, int k) {
+  int r = 1;
+  for (int q = 1; q <= k; ++q) r = r * (n - k + q) / q;
+  return r;
+}
+
 static double fact(int n) {
   double f = 1;
   for (int k = 2; k <= n; ++k) f *= k;
   return f;
 }
 
-static double binom(int n, int k) { return fact(n) / (fact(k) * fact(n - k)); }
+static double binom(int n, int k) { return (double)binom_c(n, k); }
 
 struct MI {
   int a[3];
@@ -377,11 +383,6 @@ __global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ int
     }
 }
 
-__host__ __device__ constexpr int binom_c(int n, int k) {
-  int r = 1;
-  for (int q = 1; q <= k; ++q) r = r * (n - k + q) / q;
-  return r;
-}
 
 // the (a, b) pairs of a shift between orders PP (a) and PC (b): a >= b
 // componentwise, with the index of a - b and C(a, b)
@@ -1046,24 +1047,41 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   const int64_t N = h->N;
   const int nl = h->lev[h->L].n;
   const bool prof = h->profiling;
-  auto mark = [&](int k) -> int {
-    if (prof) FAGBI_HIP(hipEventRecord(h->ev[k], s));
+  auto mark_on = [&](int k, hipStream_t st) -> int {
+    if (prof) FAGBI_HIP(hipEventRecord(h->ev[k], st));
     return 0;
   };
+  auto mark = [&](int k) { return mark_on(k, s); };
   FAGBI_TRY(mark(5));
   double* xt = h->d_xt.as<double>();
   k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), N, xt);
-  FAGBI_TRY(mark(0));
-  if (parts & FAGBI_PART_NEAR) {
-    k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, s>>>(
+  const bool near = parts & FAGBI_PART_NEAR;
+  const bool far = (parts & FAGBI_PART_FAR) && h->lmin <= h->L;
+  // the near-field SpMV (HBM bound) runs on a second stream beside the far
+  // field (cache bound); the far field joins it before LtP adds into y
+  hipStream_t sn = s;
+  if (near && far) {
+    if (!h->s_near) {
+      FAGBI_HIP(hipStreamCreateWithFlags(&h->s_near, hipStreamNonBlocking));
+      FAGBI_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      FAGBI_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    FAGBI_HIP(hipEventRecord(h->ev_fork, s));
+    FAGBI_HIP(hipStreamWaitEvent(h->s_near, h->ev_fork, 0));
+    sn = h->s_near;
+  }
+  FAGBI_TRY(mark_on(0, sn));
+  if (near) {
+    k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, sn>>>(
         ent.as<E>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
         h->d_ent_off.as<int64_t>(), h->d_src_tree.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl, xt, y);
   } else {
     FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   }
   FAGBI_HIP(hipGetLastError());
-  FAGBI_TRY(mark(1));
-  const bool far = (parts & FAGBI_PART_FAR) && h->lmin <= h->L;
+  FAGBI_TRY(mark_on(1, sn));
+  if (sn != s) FAGBI_HIP(hipEventRecord(h->ev_join, sn));
+  FAGBI_TRY(mark(6));
   if (!far) {
     FAGBI_TRY(mark(2));
     FAGBI_TRY(mark(3));
@@ -1183,6 +1201,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
                      P.d_dn_slot.as<int32_t>(), cf(P.d_dn_c64, P.d_dn_c32), P.d_dn_boff.as<int32_t>(), P.dn_nslot,
                      P.T, C.T, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
   }
+  if (sn != s) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
   {
     const unsigned g = (unsigned)((N + 255) / 256);
     const R *a = ms.as<R>(), *b = md.as<R>();
@@ -1203,14 +1222,18 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
 
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts, hipStream_t s) {
   if (h->profiling && !h->ev[0])
-    for (int k = 0; k < 6; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
+    for (int k = 0; k < 7; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
   int r = precision == FAGBI_MIXED
               ? matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
               : matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
   if (r < 0 || !h->profiling) return r;
   FAGBI_HIP(hipEventSynchronize(h->ev[4]));
   float t[4], tot;
-  for (int k = 0; k < 4; ++k) FAGBI_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
+  FAGBI_HIP(hipEventSynchronize(h->ev[1]));
+  FAGBI_HIP(hipEventElapsedTime(&t[0], h->ev[0], h->ev[1]));
+  FAGBI_HIP(hipEventElapsedTime(&t[1], h->ev[6], h->ev[2]));
+  FAGBI_HIP(hipEventElapsedTime(&t[2], h->ev[2], h->ev[3]));
+  FAGBI_HIP(hipEventElapsedTime(&t[3], h->ev[3], h->ev[4]));
   FAGBI_HIP(hipEventElapsedTime(&tot, h->ev[5], h->ev[4]));
   const int p = precision == FAGBI_MIXED ? 1 : 0;
   fagbi_profile& P = h->prof;

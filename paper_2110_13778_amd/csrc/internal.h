@@ -116,7 +116,8 @@ struct fagbi_handle {
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
   fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]
-  fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner
+  fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner (block inverses, FP64)
+  fagbi::DBuf d_lu32;                          // FP32 copy for the mixed path's inner solves
   fagbi::DBuf d_grp_leaf, d_grp_panel;         // its blocks: leaf and panel ranges
   int n_groups = 0;
   fagbi::DBuf d_gl;                   // Gauss-Legendre nodes/weights on [0,1]
@@ -137,9 +138,12 @@ struct fagbi_handle {
   std::vector<float> mlp_blob;        // parameters | normalisation | calibration
   // per-phase profiling
   bool profiling = false;
-  // matvec phase events: 5 start, 0 after the reorder of x, 1 near field,
-  // 2 upward pass, 3 MtL, 4 downward pass
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // matvec phase events: 5 start; 0, 1 around the near-field SpMV (on its
+  // own stream when the far field runs beside it); 6 start of the far field,
+  // 2 upward pass, 3 MtL, 4 downward pass (after joining the near field)
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t s_near = nullptr;                 // default priority
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);
@@ -179,7 +183,7 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
 int precond_setup(fagbi_handle* h, hipStream_t s);
 int run_singular(fagbi_handle* h, int cls_index, const uint8_t* skip, double* raw, hipStream_t s);
 int mlp_assembly_stage(fagbi_handle* h, hipStream_t s);
-int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s);
+int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s, bool f32 = false);
 int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b,
         hipStream_t s);
 int energy(fagbi_handle* h, const double* x, const double* xq, const double* q,

@@ -470,8 +470,10 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
   }
 }
 
-// y = M^-1 z, one wavefront per group (inverse stored transposed)
-__global__ void __launch_bounds__(64) k_block_apply(const double* __restrict__ inv,
+// y = M^-1 z, one wavefront per group (inverse stored transposed; FP64, or an
+// FP32 copy for the inner solves of the mixed-precision path)
+template <typename T>
+__global__ void __launch_bounds__(64) k_block_apply(const T* __restrict__ inv,
                                                     const int64_t* inv_off, const int32_t* gp,
                                                     const int32_t* perm, int64_t N, const double* z, double* y) {
   __shared__ double zb[64];
@@ -488,9 +490,9 @@ __global__ void __launch_bounds__(64) k_block_apply(const double* __restrict__ i
   }
   __syncthreads();
   if (r < m) {
-    const double* T = inv + inv_off[g];
+    const T* Ti = inv + inv_off[g];
     double acc = 0;
-    for (int b = 0; b < m; ++b) acc += T[(int64_t)b * m + r] * zb[b];
+    for (int b = 0; b < m; ++b) acc += (double)Ti[(int64_t)b * m + r] * zb[b];
     y[row] = acc;
   }
 }
@@ -513,6 +515,11 @@ __global__ void k_diag_apply(const double* diag, const double* z, double* y, int
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
     y[e] = z[e] / diag[e];
+}
+
+__global__ void k_to_f32_1(const double* __restrict__ a, float* b, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = (float)a[e];
 }
 
 int precond_setup(fagbi_handle* h, hipStream_t s) {
@@ -558,6 +565,9 @@ int precond_setup(fagbi_handle* h, hipStream_t s) {
                                    h->d_lnbr_col.as<int32_t>(), h->d_lu_off.as<int64_t>(), h->d_lu.as<double>(),
                                    bad.as<int>());
   FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(h->alloc(h->d_lu32, (size_t)off[ng] * sizeof(float)));
+  k_to_f32_1<<<1024, 256, 0, s>>>(h->d_lu.as<double>(), h->d_lu32.as<float>(), off[ng]);
+  FAGBI_HIP(hipGetLastError());
   int hb = 0;
   FAGBI_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
@@ -565,7 +575,7 @@ int precond_setup(fagbi_handle* h, hipStream_t s) {
   return 0;
 }
 
-int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s) {
+int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s, bool f32) {
   if (h->prm.precond == FAGBI_PRECOND_NONE) {
     if (z != y) FAGBI_HIP(hipMemcpyAsync(y, z, 2 * h->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     return 0;
@@ -575,8 +585,14 @@ int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s) {
     FAGBI_HIP(hipGetLastError());
     return 0;
   }
-  k_block_apply<<<h->n_groups, 64, 0, s>>>(h->d_lu.as<double>(), h->d_lu_off.as<int64_t>(),
-                                          h->d_grp_panel.as<int32_t>(), h->d_perm.as<int32_t>(), h->N, z, y);
+  if (f32)
+    k_block_apply<float><<<h->n_groups, 64, 0, s>>>(h->d_lu32.as<float>(), h->d_lu_off.as<int64_t>(),
+                                                    h->d_grp_panel.as<int32_t>(), h->d_perm.as<int32_t>(), h->N, z,
+                                                    y);
+  else
+    k_block_apply<double><<<h->n_groups, 64, 0, s>>>(h->d_lu.as<double>(), h->d_lu_off.as<int64_t>(),
+                                                     h->d_grp_panel.as<int32_t>(), h->d_perm.as<int32_t>(), h->N, z,
+                                                     y);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }

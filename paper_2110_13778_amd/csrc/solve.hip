@@ -394,6 +394,7 @@ int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double
     return matvec(h, in, out, FAGBI_MIXED, FAGBI_PART_ALL, s);
   };
   Op M = [&](const double* in, double* out) { return precond_apply(h, in, out, s); };
+  Op M32 = [&](const double* in, double* out) { return precond_apply(h, in, out, s, true); };
   int status = 0, it = 0;
   double rel = 0;
   if (h->prm.precision == FAGBI_FP64) {
@@ -410,7 +411,7 @@ int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double
     Op inner = [&](const double* in, double* out) {
       int iti = 0;
       double rr = 0;
-      int st = gmres(h, KI, A32, M, in, out, h->prm.inner_tol, h->prm.max_iter, true, &iti, &rr, s);
+      int st = gmres(h, KI, A32, M32, in, out, h->prm.inner_tol, h->prm.max_iter, true, &iti, &rr, s);
       total_inner += iti;
       return st < 0 ? st : 0;
     };

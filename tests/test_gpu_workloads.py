@@ -1,0 +1,53 @@
+"""The smaller benchmark configurations end to end on the GPU:
+
+* the multi-charge Kirkwood sphere (81,920 flat panels, R 20 A, 50 charges in a
+  15 A ball, adaptive orders 3..8): solvation energy within 0.1 % of the
+  Kirkwood series (degree 60), FP64 and mixed precision;
+* the 2,000-atom isosurface globule (~200k panels): mixed-precision and FP64
+  paths agree on the energy (the mixed path's error is stated, not assumed).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2110_13778_amd as F  # noqa: E402
+from oracle import kirkwood  # noqa: E402
+from synth import workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7, near_ratio=2.0, tol=1e-6,
+              max_iter=200, max_outer=5, inner_tol=5e-7)
+
+
+def solve(w, prec, **kw):
+    h = F.Handle(precision=prec, eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], **PARAMS, **kw)
+    h.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+    x = torch.zeros(2 * len(w["tris"]), dtype=torch.float64, device=DEV)
+    code, info = h.solve(w["xq"], w["q"], x)
+    E = h.solvation_energy(x, w["xq"], w["q"])
+    h.close()
+    return code, info, E
+
+
+def test_multicharge_kirkwood_sphere_within_0p1_percent():
+    w = workload("kirkwood2")
+    ref = kirkwood.energy(w["xq"], w["q"], 20.0, w["eps_in"], w["eps_out"], w["kappa"], nmax=60)
+    for prec in (F.FP64, F.MIXED):
+        code, info, E = solve(w, prec)
+        assert code == 0 and info.rel_residual <= 1e-6
+        print("kirkwood2 %s: E %.6f series %.6f rel %.2e its %d" % (
+            "fp64" if prec == F.FP64 else "mixed", E, ref, abs(E - ref) / abs(ref), info.inner_iterations))
+        assert abs(E - ref) < 1e-3 * abs(ref)
+
+
+def test_globule_mixed_against_fp64():
+    w = workload("globule200k")
+    c64, i64, E64 = solve(w, F.FP64, precond=F.PRECOND_GROUP)
+    c32, i32, E32 = solve(w, F.MIXED, precond=F.PRECOND_GROUP)
+    assert c64 == 0 and c32 == 0
+    assert i64.rel_residual <= 1e-6 and i32.rel_residual <= 1e-6
+    print("globule200k: E fp64 %.6f mixed %.6f rel %.2e its %d / %d" % (E64, E32, abs(E32 - E64) / abs(E64),
+                                                                        i64.inner_iterations, i32.inner_iterations))
+    assert abs(E32 - E64) < 1e-5 * abs(E64)
