@@ -141,8 +141,9 @@ def cpu_baseline(w, rows):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
-              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus %d is not supported "
+              "(the path shards by contiguous Morton ranges of leaves; not built here)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2110_13778_amd as F

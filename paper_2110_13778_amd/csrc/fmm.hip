@@ -1125,8 +1125,8 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     Level& D = h->lev[l];
     using R2 = typename Pair<R>::T;
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
-    // register-blocked kernel for the low orders (FP32 up to p = 4, FP64 p = 3)
-    const int preg = f32 ? 4 : 3;
+    // register-blocked kernel for the low orders (up to p = 4)
+    const int preg = 4;
     const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
     if constexpr (sizeof(R) == 4)
     if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
