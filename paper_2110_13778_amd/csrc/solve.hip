@@ -257,7 +257,7 @@ static int krylov_alloc(Krylov& K, int m, int64_t n) {
   FAGBI_TRY(K.Z.alloc((size_t)m * n * 8));
   FAGBI_TRY(K.w.alloc((size_t)n * 8));
   FAGBI_TRY(K.partial.alloc((size_t)(m + 2) * K.NB * 8));
-  FAGBI_TRY(K.hcol.alloc((size_t)(m + 2) * 8));
+  FAGBI_TRY(K.hcol.alloc((size_t)2 * (m + 2) * 8));
   return 0;
 }
 
@@ -313,16 +313,17 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
     double* zk = Z + (int64_t)k * n;
     FAGBI_TRY(P(vk, zk));
     FAGBI_TRY(A(zk, w));
-    // classical Gram-Schmidt, twice
-    multidot(K, V, k + 1, w, hc, 0, s);
-    k_combine<<<G, 256, 0, s>>>(V, n, hc, k + 1, -1.0, n, w);
-    FAGBI_HIP(hipMemcpyAsync(col.data(), hc, (k + 1) * 8, hipMemcpyDeviceToHost, s));
-    FAGBI_HIP(hipStreamSynchronize(s));
-    std::vector<double> h1(col.begin(), col.begin() + k + 1);
+    // classical Gram-Schmidt, twice; the first pass's coefficients stay on
+    // the device (hc2) until the one read-back per iteration
+    double* hc2 = hc + (m + 2);
+    multidot(K, V, k + 1, w, hc2, 0, s);
+    k_combine<<<G, 256, 0, s>>>(V, n, hc2, k + 1, -1.0, n, w);
     multidot(K, V, k + 1, w, hc, 0, s);
     k_combine<<<G, 256, 0, s>>>(V, n, hc, k + 1, -1.0, n, w);
     multidot(K, w, 1, w, hc + k + 1, 0, s);
+    std::vector<double> h1(k + 1);
     FAGBI_HIP(hipMemcpyAsync(col.data(), hc, (k + 2) * 8, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipMemcpyAsync(h1.data(), hc2, (k + 1) * 8, hipMemcpyDeviceToHost, s));
     FAGBI_HIP(hipStreamSynchronize(s));
     for (int i = 0; i <= k; ++i) col[i] += h1[i];
     const double hn = std::sqrt(col[k + 1]);
