@@ -1093,6 +1093,74 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   auto M = [&](Level& D, int ch) { return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>(); };
   auto Lc = [&](Level& D, int ch) { return f32 ? D.d_L32[ch].as<R>() : D.d_L64[ch].as<R>(); };
   auto cf = [&](const DBuf& c64, const DBuf& c32) { return f32 ? c32.as<R>() : c64.as<R>(); };
+  // MtL of one level (levels are independent of each other)
+  auto launch_m2l = [&](int l, hipStream_t st) -> int {
+    Level& D = h->lev[l];
+    using R2 = typename Pair<R>::T;
+    const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
+    // register-blocked kernel for the low orders (up to p = 4)
+    const int preg = 4;
+    const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
+    if constexpr (sizeof(R) == 4)
+    if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
+      int S = 1;
+      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+      const R2* Dh = (const R2*)D.d_F32[1].p;
+      const int32_t* om = D.d_oid_map.as<int32_t>();
+      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                    *id = D.d_inter_oid.as<int32_t>();
+      if (D.order == 3) {
+        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 1024>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+        k_m2l_lds<R, 3, 1024><<<256, 1024, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                        M(D, 1), Lc(D, 0), Lc(D, 1));
+      } else {
+        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+        k_m2l_lds<R, 4, 768><<<256, 768, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                      M(D, 1), Lc(D, 0), Lc(D, 1));
+      }
+      return 0;
+    }
+    if (D.n_off > 0 && D.order <= preg && D.order >= 1) {
+      int S = 1;
+      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+      const unsigned grid = (unsigned)((((int64_t)D.n * S + 255) / 256 + 7) / 8 * 8);
+      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                    *id = D.d_inter_oid.as<int32_t>();
+      switch (D.order) {
+        case 1: k_m2l_reg<R, 1><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        case 2: k_m2l_reg<R, 2><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        case 3: k_m2l_reg<R, 3><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        default: k_m2l_reg<R, 4><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+      }
+      return 0;
+    }
+    FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), st));
+    FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), st));
+    if (D.n_off == 0) return 0;
+    const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
+    const int spt = spt_of(D.m2l_nslot);
+    const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
+    const int batch = std::max(1, std::min(16, (int)(16384 / (cpb * 2 * D.T * sizeof(R2)))));
+    const size_t sh = (size_t)cpb * std::max<size_t>((size_t)batch * 2 * D.T * sizeof(R2),
+                                                     (size_t)2 * D.m2l_nslot * sizeof(R));
+    const unsigned grid = (unsigned)((D.n + cpb - 1) / cpb);
+    FAGBI_SPT_SWITCH(spt, k_m2l, grid, sh, st, D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
+                     D.d_inter_oid.as<int32_t>(), Dt, D.d_m2l_slot.as<int32_t>(), sc, sc + D.T,
+                     D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, cpb, D.n, M(D, 0), M(D, 1), Lc(D, 0),
+                     Lc(D, 1));
+    return 0;
+  };
+  // pipelined MtL: the two finest levels (most of the pairs) run on a second
+  // stream as soon as their moments exist, beside the rest of the upward pass
+  const bool pipe = L - 1 >= h->lmin;
+  if (pipe && !h->s_m2l) {
+    FAGBI_HIP(hipStreamCreateWithFlags(&h->s_m2l, hipStreamNonBlocking));
+    FAGBI_HIP(hipEventCreateWithFlags(&h->ev_up0, hipEventDisableTiming));
+    FAGBI_HIP(hipEventCreateWithFlags(&h->ev_up1, hipEventDisableTiming));
+    FAGBI_HIP(hipEventCreateWithFlags(&h->ev_m2l, hipEventDisableTiming));
+  }
   Level& LF = h->lev[L];
   {
     const int64_t tot = (int64_t)nl * LF.T;
@@ -1100,7 +1168,17 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
                                                           h->d_leaf_cnt.as<int32_t>(), N, nl, LF.T, eps, xt,
                                                           M(LF, 0), M(LF, 1));
   }
+  if (pipe) {
+    FAGBI_HIP(hipEventRecord(h->ev_up0, s));
+    FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up0, 0));
+    FAGBI_TRY(launch_m2l(L, h->s_m2l));
+  }
   for (int l = L - 1; l >= h->lmin; --l) {
+    if (pipe && l == L - 2) {   // level L-1 moments are complete
+      FAGBI_HIP(hipEventRecord(h->ev_up1, s));
+      FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up1, 0));
+      FAGBI_TRY(launch_m2l(L - 1, h->s_m2l));
+    }
     Level &P = h->lev[l], &C = h->lev[l + 1];
     const unsigned gp = (unsigned)((P.n + 255) / 256);
     if (f32 && P.order == 4 && C.order == 3) {
@@ -1119,64 +1197,17 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
                      cf(P.d_up_c64, P.d_up_c32), P.d_up_aoff.as<int32_t>(), P.up_nslot, P.T, C.T, M(C, 0),
                      M(C, 1), M(P, 0), M(P, 1));
   }
+  if (pipe && h->lmin == L - 1) {
+    FAGBI_HIP(hipEventRecord(h->ev_up1, s));
+    FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up1, 0));
+    FAGBI_TRY(launch_m2l(L - 1, h->s_m2l));
+  }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(2));
-  for (int l = h->lmin; l <= L; ++l) {
-    Level& D = h->lev[l];
-    using R2 = typename Pair<R>::T;
-    const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
-    // register-blocked kernel for the low orders (up to p = 4)
-    const int preg = 4;
-    const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
-    if constexpr (sizeof(R) == 4)
-    if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
-      int S = 1;
-      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      const R2* Dh = (const R2*)D.d_F32[1].p;
-      const int32_t* om = D.d_oid_map.as<int32_t>();
-      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
-                    *id = D.d_inter_oid.as<int32_t>();
-      if (D.order == 3) {
-        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 1024>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-        k_m2l_lds<R, 3, 1024><<<256, 1024, dbytes, s>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
-                                                        M(D, 1), Lc(D, 0), Lc(D, 1));
-      } else {
-        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-        k_m2l_lds<R, 4, 768><<<256, 768, dbytes, s>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
-                                                      M(D, 1), Lc(D, 0), Lc(D, 1));
-      }
-      continue;
-    }
-    if (D.n_off > 0 && D.order <= preg && D.order >= 1) {
-      int S = 1;
-      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      const unsigned grid = (unsigned)((((int64_t)D.n * S + 255) / 256 + 7) / 8 * 8);
-      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
-                    *id = D.d_inter_oid.as<int32_t>();
-      switch (D.order) {
-        case 1: k_m2l_reg<R, 1><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        case 2: k_m2l_reg<R, 2><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        case 3: k_m2l_reg<R, 3><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        default: k_m2l_reg<R, 4><<<grid, 256, 0, s>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-      }
-      continue;
-    }
-    FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), s));
-    FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), s));
-    if (D.n_off == 0) continue;
-    const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
-    const int spt = spt_of(D.m2l_nslot);
-    const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
-    const int batch = std::max(1, std::min(16, (int)(16384 / (cpb * 2 * D.T * sizeof(R2)))));
-    const size_t sh = (size_t)cpb * std::max<size_t>((size_t)batch * 2 * D.T * sizeof(R2),
-                                                     (size_t)2 * D.m2l_nslot * sizeof(R));
-    const unsigned grid = (unsigned)((D.n + cpb - 1) / cpb);
-    FAGBI_SPT_SWITCH(spt, k_m2l, grid, sh, s, D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
-                     D.d_inter_oid.as<int32_t>(), Dt, D.d_m2l_slot.as<int32_t>(), sc, sc + D.T,
-                     D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, cpb, D.n, M(D, 0), M(D, 1), Lc(D, 0),
-                     Lc(D, 1));
+  for (int l = h->lmin; l <= (pipe ? L - 2 : L); ++l) FAGBI_TRY(launch_m2l(l, s));
+  if (pipe) {
+    FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
+    FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
   }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(3));

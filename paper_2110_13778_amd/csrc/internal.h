@@ -144,6 +144,8 @@ struct fagbi_handle {
   hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t s_near = nullptr;                 // default priority
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t s_m2l = nullptr;                  // MtL of the two finest levels, default priority
+  hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr, ev_m2l = nullptr;
   fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);
