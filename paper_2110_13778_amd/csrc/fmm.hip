@@ -1205,13 +1205,12 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(2));
   for (int l = h->lmin; l <= (pipe ? L - 2 : L); ++l) FAGBI_TRY(launch_m2l(l, s));
-  if (pipe) {
-    FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
-    FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
-  }
+  if (pipe) FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(3));
   for (int l = h->lmin; l < L; ++l) {
+    // LtL into the two finest levels adds to their MtL results
+    if (pipe && l + 1 == std::max(L - 1, h->lmin + 1)) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
     Level &P = h->lev[l], &C = h->lev[l + 1];
     const unsigned gc = (unsigned)((C.n + 255) / 256);
     const int32_t *par = C.d_parent.as<int32_t>(), *cix = C.d_idx.as<int32_t>();
