@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of k_spmv<float4> from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (calibrated with a device copy of known size); None until measured for the
 # kernel as it stands
-TRAFFIC_SPMV = 1374398128   # FETCH 658,860 KiB x 2.0000 + WRITE 24,514 KiB x 1.0 per launch
+TRAFFIC_SPMV = None
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 

@@ -733,9 +733,31 @@ __global__ void __launch_bounds__(256) k_l2p_reg(const R* __restrict__ ms, const
   y[N + p] -= (double)y2;
 }
 
+// Sum of eight per-lane values over the wavefront, scattered: recursive
+// halving over lane bits 3, 2, 1 (each lane keeps the half of its values
+// selected by the bit and adds the other half of its partner's, the partner
+// differing in that bit), then plain sums over lane bits 0, 4, 5.  Lane 2 i
+// (i < 8) ends with the total of value i.  One eighth of the exchanges of eight
+// separate wavefront sums; the summation order is fixed.
+__device__ inline double reduce_scatter8(const double* v, int lane) {
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+  double w[4], u[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = (b3 ? v[k + 4] : v[k]) + __shfl_xor(b3 ? v[k] : v[k + 4], 15, 64);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) u[k] = (b2 ? w[k + 2] : w[k]) + __shfl_xor(b2 ? w[k] : w[k + 2], 7, 64);
+  double z = (b1 ? u[1] : u[0]) + __shfl_xor(b1 ? u[0] : u[1], 2, 64);
+  z += __shfl_xor(z, 1, 64);
+  z += __shfl_xor(z, 16, 64);
+  z += __shfl_xor(z, 32, 64);
+  return z;
+}
+
 // near-field block SpMV: one wavefront per leaf, lanes over the leaf's source
-// panels; the source index and x are loaded once per group of up to 8 target
-// rows; fixed-order FP64 reductions
+// panels, target rows in groups of four.  Every load of a step is issued
+// unconditionally (addresses clamped into the leaf's block, the clamped
+// source's contribution masked), so a lane has all of them in flight at once;
+// the eight row sums of a group are one reduce-scatter.
 template <typename E>
 __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const int32_t* __restrict__ leaf_start,
                                               const int32_t* __restrict__ leaf_cnt,
@@ -757,30 +779,29 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
   const E* base = ent + ent_off[c];
   for (int r0 = 0; r0 < nc; r0 += RG) {
     const int nr = min(RG, nc - r0);
-    double a1[RG], a2[RG];
+    double a[2 * RG];   // rows' first components, then second components
 #pragma unroll
-    for (int r = 0; r < RG; ++r) a1[r] = a2[r] = 0.0;
-    for (int k = lane; k < S; k += 64) {
-      const double2 xv = reinterpret_cast<const double2*>(xt)[src_tree[so + k]];
-      const double xj = xv.x, xn = xv.y;
+    for (int r = 0; r < 2 * RG; ++r) a[r] = 0.0;
+    for (int k0 = 0; k0 < S; k0 += 64) {
+      const int k = min(k0 + lane, S - 1);
+      const int j = src_tree[so + k];
+      E e[RG];
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
-        if (r < nr) {
-          const E e = base[(int64_t)(r0 + r) * S + k];
-          a1[r] += (double)e.x * xj + (double)e.y * xn;
-          a2[r] += (double)e.z * xj + (double)e.w * xn;
-        }
-    }
+      for (int r = 0; r < RG; ++r) e[r] = base[(int64_t)min(r0 + r, nc - 1) * S + k];
+      double2 xv = reinterpret_cast<const double2*>(xt)[j];
+      if (k0 + lane >= S) xv = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int r = 0; r < RG; ++r)
-      if (r < nr) {
-        const double s1 = wave_sum(a1[r]), s2 = wave_sum(a2[r]);
-        if (lane == 0) {
-          const int p = perm[i0 + r0 + r];
-          y[p] = s1;
-          y[N + p] = s2;
-        }
+      for (int r = 0; r < RG; ++r) {
+        a[r] += (double)e[r].x * xv.x + (double)e[r].y * xv.y;
+        a[RG + r] += (double)e[r].z * xv.x + (double)e[r].w * xv.y;
       }
+    }
+    const double z = reduce_scatter8(a, lane);
+    const int v = (lane >> 1) & 7, r = v & 3;
+    if (lane < 16 && !(lane & 1) && r < nr) {
+      const int p = perm[i0 + r0 + r];
+      y[v < RG ? p : N + p] = z;
+    }
   }
 }
 
