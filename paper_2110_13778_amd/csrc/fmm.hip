@@ -347,9 +347,20 @@ __global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ int
   for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0;
   if (c < ncl) {
     const int q1 = inter_off[c + 1];
-    for (int q = inter_off[c] + part; q < q1; q += S) {
-      const int64_t src = inter_src[q];
-      const R2* dp = Dt + (int64_t)inter_oid[q] * T;
+    int q = inter_off[c] + part;
+    // the next pair's source and offset are loaded one step ahead
+    int32_t src_n = 0, oid_n = 0;
+    if (q < q1) {
+      src_n = inter_src[q];
+      oid_n = inter_oid[q];
+    }
+    for (; q < q1; q += S) {
+      const int64_t src = src_n;
+      const R2* dp = Dt + (int64_t)oid_n * T;
+      if (q + S < q1) {
+        src_n = inter_src[q + S];
+        oid_n = inter_oid[q + S];
+      }
       R2 d[T];
 #pragma unroll
       for (int g = 0; g < T; ++g) d[g] = dp[g];
@@ -550,9 +561,20 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
     for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0;
     if (c < ncl) {
       const int q1 = inter_off[c + 1];
-      for (int q = inter_off[c] + part; q < q1; q += S) {
-        const int64_t src = inter_src[q];
-        const int mo = smap[inter_oid[q]];
+      int q = inter_off[c] + part;
+      // the next pair's source and offset are loaded one step ahead
+      int32_t src_n = 0, oid_n = 0;
+      if (q < q1) {
+        src_n = inter_src[q];
+        oid_n = inter_oid[q];
+      }
+      for (; q < q1; q += S) {
+        const int64_t src = src_n;
+        const int mo = smap[oid_n];
+        if (q + S < q1) {
+          src_n = inter_src[q + S];
+          oid_n = inter_oid[q + S];
+        }
         const R2* dp = dsm + (mo & 0x3fffffff) * T;
         const R sg = (mo >> 30) ? (R)-1 : (R)1;
         R2 d[T];
