@@ -143,8 +143,10 @@ def matvec(F, x, far=True, near=True):
     return np.concatenate([y1, y2])
 
 
-def far_field(F, phi, dphi):
-    P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
+def upward(F, phi, dphi):
+    """Steps 2 and 3: leaf moments of the two channels and the MtM upward pass.
+    Returns dicts level -> [n_l, T(p_l)] of M0 and Mk for l = l_min..L."""
+    tree, eps, pl = F.tree, F.eps, F.orders
     L, perm = tree.L, tree.perm
     levels = tree.levels
     # step 2: leaf moments (two channels)
@@ -170,6 +172,14 @@ def far_field(F, phi, dphi):
             S = shift_matrix(dvec, pl[l], pl[l + 1])
             np.add.at(M0[l], ch.parent[sel], M0[l + 1][sel] @ S.T)
             np.add.at(Mk[l], ch.parent[sel], Mk[l + 1][sel] @ S.T)
+    return M0, Mk
+
+
+def far_field(F, phi, dphi):
+    P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
+    L, perm = tree.L, tree.perm
+    levels = tree.levels
+    M0, Mk = upward(F, phi, dphi)
     # step 4: interaction phase
     lam0, lamk = {}, {}
     for l in range(tree.lmin, L + 1):
