@@ -193,6 +193,25 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
                            const double* q, int64_t nc, double* E_kcal,
                            void* stream);
 
+/* Solvation energy as above by the Cartesian treecode of Sec. 2.5: the
+   moments of x (leaf moments and the MtM upward pass of the far field, FP64,
+   orders p_l) give each charge a particle-cluster term from every cluster
+   with rho_l / R <= theta (rho_l the level's cluster radius, R the distance
+   of the charge from the cube centre); clusters failing the criterion pass
+   it to their children, from level min(l_min, L) down; leaves failing it are
+   summed directly as in fagbi_solvation_energy.  theta in [0, 1); theta = 0
+   gives the direct sum on trees whose levels have at most 2048 clusters.
+   x: device f64[2N] (caller order); xq: host f64[nc][3]; q: host f64[nc].
+   Requires fagbi_assemble_nearfield (the far-field tables); orders above 8
+   are rejected.  FAGBI_E_ARG when one charge would visit more than 2048
+   clusters of one level (theta too small for the tree).  Uses the far
+   field's moment buffers (not concurrently with a matvec of the same
+   handle).  Synchronises. */
+int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x,
+                                    const double* xq, const double* q,
+                                    int64_t nc, double theta, double* E_kcal,
+                                    void* stream);
+
 /* Turn per-phase matvec timing on (1) or off (0); turning it on resets the
    counters.  While on, every matvec waits for its last phase to finish
    (one host synchronisation per matvec). */

@@ -22,7 +22,7 @@ PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
            "fagbi_assemble_nearfield", "fagbi_matvec", "fagbi_matvec_parts",
            "fagbi_precond_apply", "fagbi_rhs", "fagbi_solve",
-           "fagbi_solvation_energy", "fagbi_get_tree_info",
+           "fagbi_solvation_energy", "fagbi_solvation_energy_treecode", "fagbi_get_tree_info",
            "fagbi_get_permutation", "fagbi_set_profiling", "fagbi_get_profile",
            "fagbi_mlp_dataset", "fagbi_mlp_train", "fagbi_mlp_forward", "fagbi_mlp_grad",
            "fagbi_mlp_get_weights", "fagbi_mlp_set_weights", "fagbi_get_mlp_stats",
@@ -95,6 +95,7 @@ def load():
         "fagbi_rhs": [vp, vp, vp, i64, vp, vp],
         "fagbi_solve": [vp, vp, vp, i64, vp, C.POINTER(SolveInfo), vp],
         "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
+        "fagbi_solvation_energy_treecode": [vp, vp, vp, vp, i64, C.c_double, dp, vp],
         "fagbi_get_tree_info": [vp, C.POINTER(TreeInfo)],
         "fagbi_get_permutation": [vp, vp],
         "fagbi_set_profiling": [vp, i32],
@@ -224,6 +225,14 @@ class Handle:
         e = C.c_double()
         _check(self.lib.fagbi_solvation_energy(self.h, _dev(x), xqp, qp, len(q_), C.byref(e),
                                                _stream(stream)))
+        return e.value
+
+    def solvation_energy_treecode(self, x, xq, q, theta, stream=None):
+        xq_, xqp = _host(xq, np.float64)
+        q_, qp = _host(q, np.float64)
+        e = C.c_double()
+        _check(self.lib.fagbi_solvation_energy_treecode(self.h, _dev(x), xqp, qp, len(q_), float(theta),
+                                                        C.byref(e), _stream(stream)))
         return e.value
 
     def tree_info(self):

@@ -272,6 +272,14 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq, c
   return fagbi::energy(h, x, xq, q, nc, E_kcal, (hipStream_t)stream);
 }
 
+int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q,
+                                    int64_t nc, double theta, double* E_kcal, void* stream) {
+  if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
+  if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode energy before assemble_nearfield");
+  return fagbi::energy_treecode(h, x, xq, q, nc, theta, E_kcal, (hipStream_t)stream);
+}
+
 int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
   if (!h || !info) return set_error(FAGBI_E_ARG, "null argument");
   if (!h->tree_ready) return set_error(FAGBI_E_STATE, "no tree");

@@ -1084,6 +1084,49 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
     default: KER<R, 16><<<GRID, TB, SH, STREAM>>>(__VA_ARGS__); break;      \
   }
 
+template <typename R>
+static R* moments_of(Level& D, int ch, bool f32) {
+  return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>();
+}
+
+// step 2: leaf moments of the two channels from x in tree order
+template <typename R>
+static int launch_p2m(fagbi_handle* h, const R* ms, const R* md, const double* xt, bool f32, hipStream_t s) {
+  Level& LF = h->lev[h->L];
+  const int nl = LF.n;
+  const double eps = h->prm.eps_out / h->prm.eps_in;
+  const int64_t tot = (int64_t)nl * LF.T;
+  k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms, md, h->d_leaf_start.as<int32_t>(),
+                                                        h->d_leaf_cnt.as<int32_t>(), h->N, nl, LF.T, eps, xt,
+                                                        moments_of<R>(LF, 0, f32), moments_of<R>(LF, 1, f32));
+  return 0;
+}
+
+// step 3 for one level: moments of level l from those of level l + 1
+template <typename R>
+static int launch_m2m(fagbi_handle* h, int l, bool f32, hipStream_t s) {
+  Level &P = h->lev[l], &C = h->lev[l + 1];
+  R *c0 = moments_of<R>(C, 0, f32), *ck = moments_of<R>(C, 1, f32);
+  R *p0 = moments_of<R>(P, 0, f32), *pk = moments_of<R>(P, 1, f32);
+  const unsigned gp = (unsigned)((P.n + 255) / 256);
+  if (f32 && P.order == 4 && C.order == 3) {
+    k_m2m_reg<R, 4, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
+                                         C.d_idx.as<int32_t>(), P.n, (R)C.h, c0, ck, p0, pk);
+    return 0;
+  }
+  if (P.order == 3 && C.order == 3) {
+    k_m2m_reg<R, 3, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
+                                         C.d_idx.as<int32_t>(), P.n, (R)C.h, c0, ck, p0, pk);
+    return 0;
+  }
+  const size_t sh = std::max<size_t>((size_t)16 * C.T, (size_t)2 * P.up_nslot) * sizeof(R);
+  const R* coef = f32 ? P.d_up_c32.as<R>() : P.d_up_c64.as<R>();
+  FAGBI_SPT_SWITCH(spt_of(P.up_nslot), k_m2m, P.n, sh, s, P.d_child_start.as<int32_t>(),
+                   P.d_child_end.as<int32_t>(), C.d_idx.as<int32_t>(), P.d_up_slot.as<int32_t>(), coef,
+                   P.d_up_aoff.as<int32_t>(), P.up_nslot, P.T, C.T, c0, ck, p0, pk);
+  return 0;
+}
+
 template <typename R, typename E>
 static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipStream_t s,
                     const DBuf& ent, const DBuf& ms, const DBuf& md, bool f32) {
@@ -1205,12 +1248,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_HIP(hipEventCreateWithFlags(&h->ev_m2l, hipEventDisableTiming));
   }
   Level& LF = h->lev[L];
-  {
-    const int64_t tot = (int64_t)nl * LF.T;
-    k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms.as<R>(), md.as<R>(), h->d_leaf_start.as<int32_t>(),
-                                                          h->d_leaf_cnt.as<int32_t>(), N, nl, LF.T, eps, xt,
-                                                          M(LF, 0), M(LF, 1));
-  }
+  FAGBI_TRY(launch_p2m<R>(h, ms.as<R>(), md.as<R>(), xt, f32, s));
   if (pipe) {
     FAGBI_HIP(hipEventRecord(h->ev_up0, s));
     FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up0, 0));
@@ -1222,23 +1260,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
       FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up1, 0));
       FAGBI_TRY(launch_m2l(L - 1, h->s_m2l));
     }
-    Level &P = h->lev[l], &C = h->lev[l + 1];
-    const unsigned gp = (unsigned)((P.n + 255) / 256);
-    if (f32 && P.order == 4 && C.order == 3) {
-      k_m2m_reg<R, 4, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
-                                           C.d_idx.as<int32_t>(), P.n, (R)C.h, M(C, 0), M(C, 1), M(P, 0), M(P, 1));
-      continue;
-    }
-    if (P.order == 3 && C.order == 3) {
-      k_m2m_reg<R, 3, 3><<<gp, 256, 0, s>>>(P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(),
-                                           C.d_idx.as<int32_t>(), P.n, (R)C.h, M(C, 0), M(C, 1), M(P, 0), M(P, 1));
-      continue;
-    }
-    const size_t sh = std::max<size_t>((size_t)16 * C.T, (size_t)2 * P.up_nslot) * sizeof(R);
-    FAGBI_SPT_SWITCH(spt_of(P.up_nslot), k_m2m, P.n, sh, s, P.d_child_start.as<int32_t>(),
-                     P.d_child_end.as<int32_t>(), C.d_idx.as<int32_t>(), P.d_up_slot.as<int32_t>(),
-                     cf(P.d_up_c64, P.d_up_c32), P.d_up_aoff.as<int32_t>(), P.up_nslot, P.T, C.T, M(C, 0),
-                     M(C, 1), M(P, 0), M(P, 1));
+    FAGBI_TRY(launch_m2m<R>(h, l, f32, s));
   }
   if (pipe && h->lmin == L - 1) {
     FAGBI_HIP(hipEventRecord(h->ev_up1, s));
@@ -1316,6 +1338,230 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
   P.ms_m2l[p] += t[2];
   P.ms_down[p] += t[3];
   P.ms_total[p] += tot;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Cartesian treecode for the solvation energy (Sec. 2.5): every charge visits
+// the clusters level by level from l0 = min(l_min, L).  A cluster with
+// rho_l / R <= theta adds its particle-cluster term, the MtL row alpha = 0 at
+// the charge from the FMM moments of the same x:
+//   V += sum_|b|<=p_l (-1)^|b| [F_b(x_n - x_c; 0) M0_b + F_b(x_n - x_c; kappa) Mk_b] / 4 pi,
+// a cluster that fails passes its children on, and a leaf that fails is
+// summed directly with the 3-point rule.  One wavefront per charge; the
+// frontier of a level lives in LDS, children are appended in a fixed order (a
+// wavefront prefix sum), so the sum order is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int TC_CAP = 2048;          // frontier capacity (clusters of one level, one charge)
+constexpr int TC_T = nterms(8);       // coefficient storage for orders up to 8
+
+struct TcLevels {
+  const int32_t* idx[FAGBI_MAX_LEVELS];
+  const int32_t* cs[FAGBI_MAX_LEVELS];
+  const int32_t* ce[FAGBI_MAX_LEVELS];
+  const double* m0[FAGBI_MAX_LEVELS];
+  const double* mk[FAGBI_MAX_LEVELS];
+  double h[FAGBI_MAX_LEVELS], rho2[FAGBI_MAX_LEVELS];
+  int n[FAGBI_MAX_LEVELS], order[FAGBI_MAX_LEVELS], T[FAGBI_MAX_LEVELS];
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Taylor coefficients F_k (Coulomb), F_k and H_k (screened) of one offset d by
+// the recurrence of the MtL tables, degree by degree with the lanes over the
+// terms of a degree, contracted with the cluster's moments on the fly.
+// Returns this lane's part of the particle-cluster term (times 4 pi).
+__device__ double tc_far(double dx, double dy, double dz, double kappa, int p, const double* __restrict__ m0,
+                         const double* __restrict__ mk, double* F0, double* FK, double* HK, int lane) {
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  const double ir = inv_sqrt(r2), ir2 = ir * ir;
+  double E, em1;
+  exp_expm1(-kappa * (r2 * ir), E, em1);
+  const double x0[3] = {dx, dy, dz};
+  double v = 0;
+  if (lane == 0) {
+    F0[0] = ir;
+    FK[0] = E * ir;
+    HK[0] = E;
+    v = ir * m0[0] + E * ir * mk[0];
+  }
+  wave_sync();
+  for (int d = 1; d <= p; ++d) {
+    const int below = d * (d + 1) * (d + 2) / 6, nd = (d + 1) * (d + 2) / 2;
+    if (lane < nd) {
+      int m = 0;
+      while ((m + 1) * (m + 2) / 2 <= lane) ++m;
+      const int sidx = lane - m * (m + 1) / 2;
+      const int e[3] = {d - m, m - sidx, sidx};
+      double s1f = 0, s2f = 0, s1k = 0, s2k = 0, s1h = 0, s2h = 0;
+      for (int i = 0; i < 3; ++i) {
+        if (e[i] >= 1) {
+          const int k = midx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
+          s1f += x0[i] * F0[k];
+          s1k += x0[i] * FK[k];
+          s1h += x0[i] * HK[k];
+        }
+        if (e[i] >= 2) {
+          const int k = midx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1), e[2] - 2 * (i == 2));
+          s2f += F0[k];
+          s2k += FK[k];
+          s2h += HK[k];
+        }
+      }
+      const double id = 1.0 / d;
+      const double f0 = (-(2 * d - 1) * s1f - (d - 1) * s2f) * ir2 * id;
+      const double fk = (-kappa * (s1h + s2h) - (2 * d - 1) * s1k - (d - 1) * s2k) * ir2 * id;
+      const double hk = -kappa * (s1k + s2k) * id;
+      const int t = below + lane;
+      F0[t] = f0;
+      FK[t] = fk;
+      HK[t] = hk;
+      const double c = f0 * m0[t] + fk * mk[t];
+      v += (d & 1) ? -c : c;
+    }
+    wave_sync();
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, double th2, double kappa, double eps,
+                                                 const double3 corner, const double4* __restrict__ chg, int nc,
+                                                 const double* __restrict__ pv, const double* __restrict__ pn,
+                                                 const double* __restrict__ pa, const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ leaf_start,
+                                                 const int32_t* __restrict__ leaf_cnt, int64_t N,
+                                                 const double* __restrict__ x, double* qv, int* overflow) {
+  __shared__ int32_t fr[2][TC_CAP];
+  __shared__ double F0[TC_T], FK[TC_T], HK[TC_T];
+  const int n = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (n >= nc) return;
+  const double4 xq = chg[n];
+  int32_t *cur = fr[0], *nxt = fr[1];
+  int cnt = lv.n[l0];
+  double v = 0;
+  for (int l = l0; l <= L && cnt > 0; ++l) {
+    const bool first = l == l0;
+    const double h = lv.h[l], rho2 = lv.rho2[l];
+    int nn = 0;
+    for (int base = 0; base < cnt; base += 64) {
+      const int i = base + lane;
+      const bool act = i < cnt;
+      const int c = act ? (first ? i : cur[i]) : 0;
+      double dx = 0, dy = 0, dz = 0;
+      bool acc = false;
+      if (act) {
+        // cube centre corner + (idx + 1/2) h and the criterion, in the oracle's rounding
+        const int32_t* ix = lv.idx[l] + 3 * (int64_t)c;
+        dx = __dsub_rn(xq.x, __dadd_rn(corner.x, __dmul_rn((double)ix[0] + 0.5, h)));
+        dy = __dsub_rn(xq.y, __dadd_rn(corner.y, __dmul_rn((double)ix[1] + 0.5, h)));
+        dz = __dsub_rn(xq.z, __dadd_rn(corner.z, __dmul_rn((double)ix[2] + 0.5, h)));
+        const double R2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        acc = rho2 <= __dmul_rn(th2, R2);
+      }
+      // particle-cluster terms, one accepted cluster at a time across the wave
+      uint64_t am = __ballot(acc);
+      while (am) {
+        const int src = __builtin_ctzll(am);
+        am &= am - 1;
+        const int cc = __shfl(c, src, 64);
+        v += tc_far(__shfl(dx, src, 64), __shfl(dy, src, 64), __shfl(dz, src, 64), kappa, lv.order[l],
+                    lv.m0[l] + (int64_t)cc * lv.T[l], lv.mk[l] + (int64_t)cc * lv.T[l], F0, FK, HK, lane);
+      }
+      if (l < L) {
+        // children of the clusters that failed, appended in lane order
+        const int k = (act && !acc) ? lv.ce[l][c] - lv.cs[l][c] : 0;
+        int inc = k;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int t = __shfl_up(inc, o, 64);
+          if (lane >= o) inc += t;
+        }
+        const int tot = __shfl(inc, 63, 64);
+        if (nn + tot > TC_CAP) {
+          if (lane == 0) atomicOr(overflow, 1);
+          return;
+        }
+        const int at = nn + inc - k, c0 = k ? lv.cs[l][c] : 0;
+        for (int j = 0; j < k; ++j) nxt[at + j] = c0 + j;
+        nn += tot;
+      } else if (act && !acc) {
+        // direct sum over the leaf's panels (tree order)
+        const int i0 = leaf_start[c], i1 = i0 + leaf_cnt[c];
+        for (int ii = i0; ii < i1; ++ii) {
+          double qp[9];
+          quad_points(pv, ii, qp);
+          const double nx = pn[3 * (int64_t)ii], ny = pn[3 * (int64_t)ii + 1], nz = pn[3 * (int64_t)ii + 2];
+          const int p = perm[ii];
+          const double ph = x[p], dph = x[N + p], w = pa[ii] / 3.0;
+          double a = 0;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const double rx = xq.x - qp[3 * q], ry = xq.y - qp[3 * q + 1], rz = xq.z - qp[3 * q + 2];
+            const double rr2 = rx * rx + ry * ry + rz * rz;
+            const double ir = inv_sqrt(rr2);
+            const double u = kappa * (rr2 * ir);
+            double E, em1;
+            exp_expm1(-u, E, em1);
+            const double rny = rx * nx + ry * ny + rz * nz;
+            a += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
+          }
+          v += w * a;
+        }
+      }
+    }
+    wave_sync();
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    cnt = nn;
+  }
+  v = wave_sum(v);
+  if (lane == 0) qv[n] = xq.w * v * (1.0 / FOUR_PI);
+}
+
+int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta, double* qv,
+                        hipStream_t s) {
+  const int L = h->L, l0 = std::min(h->lmin, h->L);
+  // moments of x: leaf moments and the upward pass, FP64
+  double* xt = h->d_xt.as<double>();
+  k_to_tree<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), h->N, xt);
+  FAGBI_TRY(launch_p2m<double>(h, h->d_ms64.as<double>(), h->d_md64.as<double>(), xt, false, s));
+  for (int l = L - 1; l >= l0; --l) FAGBI_TRY(launch_m2m<double>(h, l, false, s));
+  TcLevels lv{};
+  for (int l = l0; l <= L; ++l) {
+    Level& D = h->lev[l];
+    if (D.order > 8) return set_error(FAGBI_E_ARG, "treecode: expansion order above 8");
+    lv.idx[l] = D.d_idx.as<int32_t>();
+    lv.cs[l] = D.d_child_start.as<int32_t>();
+    lv.ce[l] = D.d_child_end.as<int32_t>();
+    lv.m0[l] = D.d_M64[0].as<double>();
+    lv.mk[l] = D.d_M64[1].as<double>();
+    lv.h[l] = D.h;
+    lv.rho2[l] = D.rho * D.rho;
+    lv.n[l] = D.n;
+    lv.order[l] = D.order;
+    lv.T[l] = D.T;
+  }
+  Tmp flag;
+  FAGBI_TRY(flag.alloc(4));
+  FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+  const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
+  const double eps = h->prm.eps_out / h->prm.eps_in;
+  k_treecode<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
+                                         reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
+                                         h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
+                                         h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv,
+                                         flag.as<int>());
+  FAGBI_HIP(hipGetLastError());
+  int of = 0;
+  FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
+                                        "(theta too small for this tree)");
   return 0;
 }
 

@@ -190,6 +190,10 @@ int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* 
         hipStream_t s);
 int energy(fagbi_handle* h, const double* x, const double* xq, const double* q,
            int64_t nc, double* E, hipStream_t s);
+int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc,
+                    double theta, double* E, hipStream_t s);
+int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta,
+                        double* qv, hipStream_t s);
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
           fagbi_solve_info* info, hipStream_t s);
 void gauss_legendre01(int n, double* x, double* w);
@@ -199,6 +203,15 @@ void gauss_legendre01(int n, double* x, double* w);
 // device helpers
 // ---------------------------------------------------------------------------
 namespace fagbi {
+
+// the three quadrature points of panel i (barycentric (2/3, 1/6, 1/6) and
+// permutations, weight A/3 each) from its corners pv[9 i ..]
+__device__ inline void quad_points(const double* __restrict__ pv, int64_t i, double* qp) {
+  const double* v = pv + 9 * i;
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d)
+      qp[3 * k + d] = (2.0 / 3.0) * v[3 * k + d] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + d] + v[3 * ((k + 2) % 3) + d]);
+}
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

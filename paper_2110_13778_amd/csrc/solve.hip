@@ -17,14 +17,8 @@ namespace fagbi {
 constexpr int RB = 256;   // reduction block
 
 // Both direct sums run one thread per panel over its three quadrature points
-// (barycentric (2/3, 1/6, 1/6) and permutations, weight A/3) with the charges
-// staged through LDS; charges carry q / (4 pi).  FP64 throughout.
-__device__ inline void quad_points(const double* __restrict__ pv, int64_t i, double* qp) {
-  const double* v = pv + 9 * i;
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d)
-      qp[3 * k + d] = (2.0 / 3.0) * v[3 * k + d] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + d] + v[3 * ((k + 2) % 3) + d]);
-}
+// (quad_points) with the charges staged through LDS; charges carry q / (4 pi).
+// FP64 throughout.
 
 // b1 = (1/eps_in) sum_q w_q sum_k q_k G0(x_q, y_k); b2 likewise with dG0/dn_x
 __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, const double* __restrict__ pn,
@@ -230,6 +224,26 @@ int energy(fagbi_handle* h, const double* x, const double* xq, const double* q, 
                               h->d_perm.as<int32_t>(), (int)h->N, chg.as<double4>(), (int)nc,
                               h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part.as<double>());
   k_sum<<<1, RB, 0, s>>>(part.as<double>(), nb, out.as<double>());
+  FAGBI_HIP(hipGetLastError());
+  double tot = 0;
+  FAGBI_HIP(hipMemcpyAsync(&tot, out.p, 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  *E = 0.5 * UNIT_KCAL * tot;
+  if (!std::isfinite(*E)) return set_error(FAGBI_E_NUMERIC, "non-finite energy");
+  return 0;
+}
+
+// E by the Cartesian treecode: per-charge terms q_n V_n on the GPU, then the
+// fixed-order sum
+int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc, double theta,
+                    double* E, hipStream_t s) {
+  if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
+  Tmp chg, qv, out;
+  FAGBI_TRY(upload_charges(chg, xq, q, nc));
+  FAGBI_TRY(qv.alloc((size_t)nc * 8));
+  FAGBI_TRY(out.alloc(8));
+  FAGBI_TRY(treecode_potentials(h, x, chg.as<double>(), nc, theta, qv.as<double>(), s));
+  k_sum<<<1, RB, 0, s>>>(qv.as<double>(), (int)nc, out.as<double>());
   FAGBI_HIP(hipGetLastError());
   double tot = 0;
   FAGBI_HIP(hipMemcpyAsync(&tot, out.p, 8, hipMemcpyDeviceToHost, s));
