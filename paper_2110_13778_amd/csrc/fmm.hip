@@ -1352,8 +1352,10 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
 // frontier of a level lives in LDS, children are appended in a fixed order (a
 // wavefront prefix sum), so the sum order is deterministic.
 // ---------------------------------------------------------------------------
-constexpr int TC_CAP = 2048;          // frontier capacity (clusters of one level, one charge)
-constexpr int TC_T = nterms(8);       // coefficient storage for orders up to 8
+constexpr int TC_CAP = 1024;          // frontier capacity (clusters of one level, one charge)
+// coefficient storage of one wavefront: 64 / g groups of T(p) terms,
+// at most 4 T(4), 2 T(6) or T(8)
+constexpr int TC_TG = 2 * nterms(6);
 
 struct TcLevels {
   const int32_t* idx[FAGBI_MAX_LEVELS];
@@ -1372,55 +1374,75 @@ __device__ inline void wave_sync() {
 }
 
 // Taylor coefficients F_k (Coulomb), F_k and H_k (screened) of one offset d by
-// the recurrence of the MtL tables, degree by degree with the lanes over the
-// terms of a degree, contracted with the cluster's moments on the fly.
-// Returns this lane's part of the particle-cluster term (times 4 pi).
-__device__ double tc_far(double dx, double dy, double dz, double kappa, int p, const double* __restrict__ m0,
-                         const double* __restrict__ mk, double* F0, double* FK, double* HK, int lane) {
-  const double r2 = (dx * dx + dy * dy) + dz * dz;
-  const double ir = inv_sqrt(r2), ir2 = ir * ir;
-  double E, em1;
-  exp_expm1(-kappa * (r2 * ir), E, em1);
-  const double x0[3] = {dx, dy, dz};
-  double v = 0;
-  if (lane == 0) {
-    F0[0] = ir;
-    FK[0] = E * ir;
-    HK[0] = E;
-    v = ir * m0[0] + E * ir * mk[0];
+// the recurrence of the MtL tables, degree by degree with the lanes of a
+// group over the terms of a degree, contracted with the cluster's moments
+// (staged in LDS first) on the fly.  The wavefront runs 64 / g groups of g
+// lanes, each on its own accepted cluster (g >= the terms of the top degree).
+// Returns this lane's part of the particle-cluster terms (times 4 pi).
+__device__ double tc_far(bool has, double dx, double dy, double dz, double kappa, int p, int T, int g,
+                         const double* __restrict__ m0, const double* __restrict__ mk, double* F0, double* FK,
+                         double* HK, double* S0, double* SK, int gl) {
+  double v = 0, ir = 0, ir2 = 0, E = 0, em1;
+  if (has) {
+    for (int t = gl; t < T; t += g) {
+      S0[t] = m0[t];
+      SK[t] = mk[t];
+    }
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    ir = inv_sqrt(r2);
+    ir2 = ir * ir;
+    exp_expm1(-kappa * (r2 * ir), E, em1);
+    if (gl == 0) {
+      F0[0] = ir;
+      FK[0] = E * ir;
+      HK[0] = E;
+    }
   }
   wave_sync();
+  if (has && gl == 0) v = ir * S0[0] + E * ir * SK[0];
+  const double x0[3] = {dx, dy, dz};
   for (int d = 1; d <= p; ++d) {
     const int below = d * (d + 1) * (d + 2) / 6, nd = (d + 1) * (d + 2) / 2;
-    if (lane < nd) {
+    if (has && gl < nd) {
       int m = 0;
-      while ((m + 1) * (m + 2) / 2 <= lane) ++m;
-      const int sidx = lane - m * (m + 1) / 2;
+      while ((m + 1) * (m + 2) / 2 <= gl) ++m;
+      const int sidx = gl - m * (m + 1) / 2;
       const int e[3] = {d - m, m - sidx, sidx};
-      double s1f = 0, s2f = 0, s1k = 0, s2k = 0, s1h = 0, s2h = 0;
+      // every read is issued (a missing term reads entry 0 with weight 0), so
+      // none waits for another
+      double a1[3], a2[3], f1[3], k1[3], h1[3], f2[3], k2[3], h2[3];
+#pragma unroll
       for (int i = 0; i < 3; ++i) {
-        if (e[i] >= 1) {
-          const int k = midx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
-          s1f += x0[i] * F0[k];
-          s1k += x0[i] * FK[k];
-          s1h += x0[i] * HK[k];
-        }
-        if (e[i] >= 2) {
-          const int k = midx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1), e[2] - 2 * (i == 2));
-          s2f += F0[k];
-          s2k += FK[k];
-          s2h += HK[k];
-        }
+        const int j1 = e[i] >= 1 ? midx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2)) : 0;
+        const int j2 = e[i] >= 2 ? midx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1), e[2] - 2 * (i == 2)) : 0;
+        a1[i] = e[i] >= 1 ? x0[i] : 0.0;
+        a2[i] = e[i] >= 2 ? 1.0 : 0.0;
+        f1[i] = F0[j1];
+        k1[i] = FK[j1];
+        h1[i] = HK[j1];
+        f2[i] = F0[j2];
+        k2[i] = FK[j2];
+        h2[i] = HK[j2];
+      }
+      double s1f = 0, s2f = 0, s1k = 0, s2k = 0, s1h = 0, s2h = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        s1f += a1[i] * f1[i];
+        s1k += a1[i] * k1[i];
+        s1h += a1[i] * h1[i];
+        s2f += a2[i] * f2[i];
+        s2k += a2[i] * k2[i];
+        s2h += a2[i] * h2[i];
       }
       const double id = 1.0 / d;
       const double f0 = (-(2 * d - 1) * s1f - (d - 1) * s2f) * ir2 * id;
       const double fk = (-kappa * (s1h + s2h) - (2 * d - 1) * s1k - (d - 1) * s2k) * ir2 * id;
       const double hk = -kappa * (s1k + s2k) * id;
-      const int t = below + lane;
+      const int t = below + gl;
       F0[t] = f0;
       FK[t] = fk;
       HK[t] = hk;
-      const double c = f0 * m0[t] + fk * mk[t];
+      const double c = f0 * S0[t] + fk * SK[t];
       v += (d & 1) ? -c : c;
     }
     wave_sync();
@@ -1436,7 +1458,7 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
                                                  const int32_t* __restrict__ leaf_cnt, int64_t N,
                                                  const double* __restrict__ x, double* qv, int* overflow) {
   __shared__ int32_t fr[2][TC_CAP];
-  __shared__ double F0[TC_T], FK[TC_T], HK[TC_T];
+  __shared__ double F0[TC_TG], FK[TC_TG], HK[TC_TG], S0[TC_TG], SK[TC_TG];
   const int n = blockIdx.x;
   const int lane = threadIdx.x;
   if (n >= nc) return;
@@ -1447,34 +1469,47 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
   for (int l = l0; l <= L && cnt > 0; ++l) {
     const bool first = l == l0;
     const double h = lv.h[l], rho2 = lv.rho2[l];
+    const int p = lv.order[l], T = lv.T[l];
+    // lanes per cluster: at least the terms of degree p
+    const int g = p <= 4 ? 16 : p <= 6 ? 32 : 64, ng = 64 / g, gi = lane / g, gl = lane % g;
     int nn = 0;
     for (int base = 0; base < cnt; base += 64) {
       const int i = base + lane;
       const bool act = i < cnt;
       const int c = act ? (first ? i : cur[i]) : 0;
-      double dx = 0, dy = 0, dz = 0;
-      bool acc = false;
-      if (act) {
-        // cube centre corner + (idx + 1/2) h and the criterion, in the oracle's rounding
-        const int32_t* ix = lv.idx[l] + 3 * (int64_t)c;
-        dx = __dsub_rn(xq.x, __dadd_rn(corner.x, __dmul_rn((double)ix[0] + 0.5, h)));
-        dy = __dsub_rn(xq.y, __dadd_rn(corner.y, __dmul_rn((double)ix[1] + 0.5, h)));
-        dz = __dsub_rn(xq.z, __dadd_rn(corner.z, __dmul_rn((double)ix[2] + 0.5, h)));
-        const double R2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        acc = rho2 <= __dmul_rn(th2, R2);
-      }
-      // particle-cluster terms, one accepted cluster at a time across the wave
+      // cube centre corner + (idx + 1/2) h and the criterion, in the oracle's
+      // rounding (inactive lanes look at cluster 0 and are masked)
+      const int32_t* ix = lv.idx[l] + 3 * (int64_t)c;
+      const int32_t ix0 = ix[0], ix1 = ix[1], ix2 = ix[2];
+      const int c0 = l < L ? lv.cs[l][c] : 0, c1 = l < L ? lv.ce[l][c] : 0;
+      const double dx = __dsub_rn(xq.x, __dadd_rn(corner.x, __dmul_rn((double)ix0 + 0.5, h)));
+      const double dy = __dsub_rn(xq.y, __dadd_rn(corner.y, __dmul_rn((double)ix1 + 0.5, h)));
+      const double dz = __dsub_rn(xq.z, __dadd_rn(corner.z, __dmul_rn((double)ix2 + 0.5, h)));
+      const double R2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      const bool acc = act && rho2 <= __dmul_rn(th2, R2);
+      // particle-cluster terms: groups of g lanes, one accepted cluster each
       uint64_t am = __ballot(acc);
       while (am) {
-        const int src = __builtin_ctzll(am);
-        am &= am - 1;
-        const int cc = __shfl(c, src, 64);
-        v += tc_far(__shfl(dx, src, 64), __shfl(dy, src, 64), __shfl(dz, src, 64), kappa, lv.order[l],
-                    lv.m0[l] + (int64_t)cc * lv.T[l], lv.mk[l] + (int64_t)cc * lv.T[l], F0, FK, HK, lane);
+        // the group's cluster: the gi-th remaining accepted lane
+        uint64_t mm = am;
+        int src = -1;
+        for (int k = 0; k < ng && mm; ++k) {
+          const int b = __builtin_ctzll(mm);
+          mm &= mm - 1;
+          if (k == gi) src = b;
+        }
+        am = mm;
+        const bool has = src >= 0;
+        const int sl = has ? src : 0;
+        const int cc = __shfl(c, sl, 64);
+        const double ex = __shfl(dx, sl, 64), ey = __shfl(dy, sl, 64), ez = __shfl(dz, sl, 64);
+        const int64_t off = (int64_t)cc * T;
+        v += tc_far(has, ex, ey, ez, kappa, p, T, g, lv.m0[l] + off, lv.mk[l] + off, F0 + gi * T, FK + gi * T,
+                    HK + gi * T, S0 + gi * T, SK + gi * T, gl);
       }
       if (l < L) {
         // children of the clusters that failed, appended in lane order
-        const int k = (act && !acc) ? lv.ce[l][c] - lv.cs[l][c] : 0;
+        const int k = (act && !acc) ? c1 - c0 : 0;
         int inc = k;
         for (int o = 1; o < 64; o <<= 1) {
           const int t = __shfl_up(inc, o, 64);
@@ -1485,7 +1520,7 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
           if (lane == 0) atomicOr(overflow, 1);
           return;
         }
-        const int at = nn + inc - k, c0 = k ? lv.cs[l][c] : 0;
+        const int at = nn + inc - k;
         for (int j = 0; j < k; ++j) nxt[at + j] = c0 + j;
         nn += tot;
       } else if (act && !acc) {
@@ -1560,7 +1595,7 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
   int of = 0;
   FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
-  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
+  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 1024 clusters of one level for one charge "
                                         "(theta too small for this tree)");
   return 0;
 }
