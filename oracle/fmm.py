@@ -175,6 +175,21 @@ def upward(F, phi, dphi):
     return M0, Mk
 
 
+def downward(F, lam, l_from):
+    """Step 5 for one channel: lam[l + 1] += LtL(lam[l]) for l = l_from..L-1
+    (dict level -> [n_l, T(p_l)], updated in place)."""
+    tree, pl = F.tree, F.orders
+    levels = tree.levels
+    for l in range(l_from, tree.L):
+        ch = levels[l + 1]
+        octant = ch.idx & 1
+        for o in np.unique(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2]):
+            sel = np.nonzero(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2] == o)[0]
+            dvec = (np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1]) - 0.5) * ch.h
+            S = shift_matrix(dvec, pl[l], pl[l + 1])
+            lam[l + 1][sel] += lam[l][ch.parent[sel]] @ S
+
+
 def far_field(F, phi, dphi):
     P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
     L, perm = tree.L, tree.perm
@@ -202,15 +217,8 @@ def far_field(F, phi, dphi):
             np.add.at(lam0[l], tgt[sel], M0[l][src[sel]] @ T0.T)
             np.add.at(lamk[l], tgt[sel], Mk[l][src[sel]] @ Tk.T)
     # step 5: downward pass
-    for l in range(tree.lmin, L):
-        ch = levels[l + 1]
-        octant = ch.idx & 1
-        for o in np.unique(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2]):
-            sel = np.nonzero(octant[:, 0] * 4 + octant[:, 1] * 2 + octant[:, 2] == o)[0]
-            dvec = (np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1]) - 0.5) * ch.h
-            S = shift_matrix(dvec, pl[l], pl[l + 1])
-            lam0[l + 1][sel] += lam0[l][ch.parent[sel]] @ S
-            lamk[l + 1][sel] += lamk[l][ch.parent[sel]] @ S
+    downward(F, lam0, tree.lmin)
+    downward(F, lamk, tree.lmin)
     # step 6: evaluation
     l0 = lam0[L][F.owner]
     lk = lamk[L][F.owner]

@@ -25,11 +25,20 @@ Readings (one choice, used by the GPU path as well):
     coarser cluster can pass the criterion);
   * a leaf that fails the criterion is summed directly with the 3-point rule,
     with the integrand of the direct energy sum (oracle.solve.energy).
+
+The right-hand side (Sec. 2.2 source terms, b1 = (1/eps_in) int psi_i
+sum_n q_n G0(x, x_n), b2 likewise with dG0/dn_x) by the same visit run in
+reverse: a charge accepted by a cluster adds its particle-to-local expansion
+q_n F_a(x_c - x_n; 0) / 4 pi to the cluster's Coulomb local expansion (the
+MtL column beta = 0 of a point source), a leaf that fails is summed directly
+(the integrand of oracle.solve.rhs), then the far field's LtL takes the
+locals down to the leaves and LtP tests them with the single- and double-
+layer moments of each panel (step 6 of the FMM).
 """
 import numpy as np
 
 from . import taylor
-from .fmm import upward
+from .fmm import downward, upward
 from .solve import UNIT_KCAL
 
 FOUR_PI = 4.0 * np.pi
@@ -104,3 +113,51 @@ def energy(F, x, xq, q, theta):
     direct sum)."""
     V, _, _ = potentials(F, x, xq, theta)
     return 0.5 * UNIT_KCAL * float(np.dot(np.asarray(q, np.float64), V))
+
+
+def rhs(F, xq, q, theta, eps_in):
+    """b = [b1; b2] (panel order) by the reverse treecode (theta = 0: the
+    direct sum of oracle.solve.rhs)."""
+    P, tree, pl = F.P, F.tree, F.orders
+    N = P.n
+    L, levels, perm = tree.L, tree.levels, tree.perm
+    l0 = min(tree.lmin, L)
+    xq = np.atleast_2d(np.asarray(xq, np.float64))
+    q = np.asarray(q, np.float64)
+    lam = {l: np.zeros((levels[l].n, len(taylor.multi_indices(pl[l])))) for l in range(l0, L + 1)}
+    b1 = np.zeros(N)
+    b2 = np.zeros(N)
+    th2 = theta * theta
+    for n in range(len(xq)):
+        xn = xq[n]
+        front = np.arange(levels[l0].n)
+        for l in range(l0, L + 1):
+            if len(front) == 0:
+                break
+            cl = levels[l]
+            d = xn[None, :] - cl.center[front]
+            R2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+            acc = cl.rho * cl.rho <= th2 * R2
+            if acc.any():
+                a = front[acc]
+                Fc = taylor.coefficients(-d[acc], 0.0, pl[l])      # at x_c - x_n
+                for t, k in enumerate(taylor.multi_indices(pl[l])):
+                    lam[l][a, t] += q[n] * Fc[k] / FOUR_PI
+            rest = front[~acc]
+            if l < L:
+                front = np.concatenate([np.arange(cl.child_start[c], cl.child_end[c]) for c in rest]) \
+                    if len(rest) else rest
+            else:
+                for c in rest:
+                    ids = perm[cl.start[c]:cl.end[c]]
+                    r = P.qp[ids] - xn[None, None, :]                # y_q - x_n
+                    rr = np.sqrt((r * r).sum(-1))
+                    g0 = 1.0 / (FOUR_PI * rr)
+                    dg0 = -(r * P.normal[ids][:, None, :]).sum(-1) / (FOUR_PI * rr ** 3)
+                    b1[ids] += q[n] * (P.qw[ids] * g0).sum(1)
+                    b2[ids] += q[n] * (P.qw[ids] * dg0).sum(1)
+    downward(F, lam, l0)
+    f = lam[L][F.owner]                                             # tree order
+    b1[perm] += (f * F.ms).sum(1)
+    b2[perm] += (f * F.md).sum(1)
+    return np.concatenate([b1, b2]) / eps_in

@@ -82,3 +82,25 @@ def test_adaptive_orders_energy(sphere):
     Ed = osolve.energy(P, x, xq, q, EPS, KAP)
     E = otc.energy(F, x, xq, q, 0.3)
     assert abs(E - Ed) < 3e-3 * abs(Ed)
+
+
+def test_rhs_theta_zero_is_the_direct_sum(sphere):
+    P, tr, x, xq, q, Vd = sphere
+    F = setup(P, tr, 3, 1)
+    b = otc.rhs(F, xq, q, 0.0, 2.0)
+    bd = osolve.rhs(P, xq, q, 2.0)
+    assert np.abs(b - bd).max() <= 1e-13 * np.abs(bd).max()
+
+
+def test_rhs_converges_with_order_and_theta(sphere):
+    P, tr, x, xq, q, Vd = sphere
+    bd = osolve.rhs(P, xq, q, 1.0)
+    errs = []
+    for p in (1, 3, 5, 7):
+        b = otc.rhs(setup(P, tr, p), xq, q, 0.4, 1.0)
+        errs.append(np.linalg.norm(b - bd) / np.linalg.norm(bd))
+    assert all(e2 < 0.5 * e1 for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-4, errs
+    F = setup(P, tr, 5)
+    et = [np.linalg.norm(otc.rhs(F, xq, q, th, 1.0) - bd) / np.linalg.norm(bd) for th in (0.7, 0.5, 0.3)]
+    assert et[0] > et[1] > et[2], et
