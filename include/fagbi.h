@@ -77,6 +77,9 @@ typedef struct fagbi_params {
   double inner_tol;            /* inner relative tolerance in FAGBI_MIXED */
   int32_t mlp_mode;            /* FAGBI_MLP_* (needs fagbi_mlp_set_weights) */
   double mlp_gate_tol;         /* gated near field: max estimated rel. error */
+  /* right-hand side of fagbi_solve: 0 = direct sum (fagbi_rhs), in (0, 1) =
+     reverse treecode with this acceptance parameter (fagbi_rhs_treecode) */
+  double rhs_theta;
 } fagbi_params;
 
 #define FAGBI_MAX_LEVELS 21        /* levels 0..20 (cube keys have 20 levels) */
@@ -192,6 +195,22 @@ int fagbi_solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
 int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
                            const double* q, int64_t nc, double* E_kcal,
                            void* stream);
+
+/* Right-hand side as fagbi_rhs by the Cartesian treecode of Sec. 2.5 run in
+   reverse: every charge visits the clusters as in
+   fagbi_solvation_energy_treecode; an accepted cluster receives the charge's
+   particle-to-local Taylor expansion (order p_l, Coulomb kernel), a leaf that
+   fails receives the direct 3-point sums; the far field's LtL then takes the
+   local expansions to the leaves and LtP tests them with each panel's single-
+   and double-layer moments.  theta in [0, 1) (theta = 0: the direct sum on
+   trees whose levels have at most 1024 clusters).  xq: host f64[nc][3]; q:
+   host f64[nc]; b: device f64[2N] (caller order), overwritten.  Requires
+   fagbi_assemble_nearfield.  The expansions are accumulated with device
+   atomics: results agree between runs to rounding, not bit for bit.  Uses
+   the far field's local-expansion buffers (not concurrently with a matvec of
+   the same handle).  FAGBI_E_ARG as for the treecode energy.  Synchronises. */
+int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q,
+                       int64_t nc, double theta, double* b, void* stream);
 
 /* Solvation energy as above by the Cartesian treecode of Sec. 2.5: the
    moments of x (leaf moments and the MtM upward pass of the far field, FP64,

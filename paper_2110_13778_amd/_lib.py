@@ -21,7 +21,7 @@ PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 
 EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
            "fagbi_assemble_nearfield", "fagbi_matvec", "fagbi_matvec_parts",
-           "fagbi_precond_apply", "fagbi_rhs", "fagbi_solve",
+           "fagbi_precond_apply", "fagbi_rhs", "fagbi_rhs_treecode", "fagbi_solve",
            "fagbi_solvation_energy", "fagbi_solvation_energy_treecode", "fagbi_get_tree_info",
            "fagbi_get_permutation", "fagbi_set_profiling", "fagbi_get_profile",
            "fagbi_mlp_dataset", "fagbi_mlp_train", "fagbi_mlp_forward", "fagbi_mlp_grad",
@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("quad_duffy", C.c_int32), ("near_ratio", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_outer", C.c_int32), ("inner_tol", C.c_double),
-                ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double)]
+                ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double), ("rhs_theta", C.c_double)]
 
 
 class TreeInfo(C.Structure):
@@ -93,6 +93,7 @@ def load():
         "fagbi_matvec_parts": [vp, vp, vp, i32, i32, vp],
         "fagbi_precond_apply": [vp, vp, vp, vp],
         "fagbi_rhs": [vp, vp, vp, i64, vp, vp],
+        "fagbi_rhs_treecode": [vp, vp, vp, i64, C.c_double, vp, vp],
         "fagbi_solve": [vp, vp, vp, i64, vp, C.POINTER(SolveInfo), vp],
         "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
         "fagbi_solvation_energy_treecode": [vp, vp, vp, vp, i64, C.c_double, dp, vp],
@@ -209,6 +210,12 @@ class Handle:
         xq_, xqp = _host(xq, np.float64)
         q_, qp = _host(q, np.float64)
         _check(self.lib.fagbi_rhs(self.h, xqp, qp, len(q_), _dev(b), _stream(stream)))
+        return b
+
+    def rhs_treecode(self, xq, q, theta, b, stream=None):
+        xq_, xqp = _host(xq, np.float64)
+        q_, qp = _host(q, np.float64)
+        _check(self.lib.fagbi_rhs_treecode(self.h, xqp, qp, len(q_), float(theta), _dev(b), _stream(stream)))
         return b
 
     def solve(self, xq, q, x, stream=None):

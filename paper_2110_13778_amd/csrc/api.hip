@@ -157,6 +157,7 @@ static int check_params(const fagbi_params* p) {
       !(p->inner_tol > 0))
     return set_error(FAGBI_E_ARG, "bad solver tolerances/iteration limits");
   if (p->mlp_mode < 0 || p->mlp_mode > 2) return set_error(FAGBI_E_ARG, "bad mlp_mode");
+  if (!(p->rhs_theta >= 0 && p->rhs_theta < 1)) return set_error(FAGBI_E_ARG, "rhs_theta must be in [0, 1)");
   return 0;
 }
 
@@ -270,6 +271,14 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq, c
   if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!h->tree_ready) return set_error(FAGBI_E_STATE, "energy before build_tree");
   return fagbi::energy(h, x, xq, q, nc, E_kcal, (hipStream_t)stream);
+}
+
+int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
+                       void* stream) {
+  if (!h || !xq || !q || !b || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
+  if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode right-hand side before assemble_nearfield");
+  return fagbi::rhs_treecode(h, xq, q, nc, theta, b, (hipStream_t)stream);
 }
 
 int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q,

@@ -1127,6 +1127,38 @@ static int launch_m2m(fagbi_handle* h, int l, bool f32, hipStream_t s) {
   return 0;
 }
 
+template <typename R>
+static R* locals_of(Level& D, int ch, bool f32) {
+  return f32 ? D.d_L32[ch].as<R>() : D.d_L64[ch].as<R>();
+}
+
+// step 5 for one level: locals of level l + 1 += LtL of those of level l
+template <typename R>
+static int launch_l2l(fagbi_handle* h, int l, bool f32, hipStream_t s) {
+  Level &P = h->lev[l], &C = h->lev[l + 1];
+  const unsigned gc = (unsigned)((C.n + 255) / 256);
+  const int32_t *par = C.d_parent.as<int32_t>(), *cix = C.d_idx.as<int32_t>();
+  R *p0 = locals_of<R>(P, 0, f32), *pk = locals_of<R>(P, 1, f32);
+  R *c0 = locals_of<R>(C, 0, f32), *ck = locals_of<R>(C, 1, f32);
+  if (P.order == 4 && C.order == 3) {
+    k_l2l_reg<R, 4, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, p0, pk, c0, ck);
+    return 0;
+  }
+  if (P.order == 3 && C.order == 3) {
+    k_l2l_reg<R, 3, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, p0, pk, c0, ck);
+    return 0;
+  }
+  if (f32 && P.order == 5 && C.order == 4) {
+    k_l2l_reg<R, 5, 4><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, p0, pk, c0, ck);
+    return 0;
+  }
+  const size_t sh = std::max<size_t>((size_t)2 * P.T, (size_t)2 * P.dn_nslot) * sizeof(R);
+  const R* coef = f32 ? P.d_dn_c32.as<R>() : P.d_dn_c64.as<R>();
+  FAGBI_SPT_SWITCH(spt_of(P.dn_nslot), k_l2l, C.n, sh, s, par, cix, P.d_dn_slot.as<int32_t>(), coef,
+                   P.d_dn_boff.as<int32_t>(), P.dn_nslot, P.T, C.T, p0, pk, c0, ck);
+  return 0;
+}
+
 template <typename R, typename E>
 static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipStream_t s,
                     const DBuf& ent, const DBuf& ms, const DBuf& md, bool f32) {
@@ -1178,7 +1210,6 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   const int L = h->L;
   auto M = [&](Level& D, int ch) { return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>(); };
   auto Lc = [&](Level& D, int ch) { return f32 ? D.d_L32[ch].as<R>() : D.d_L64[ch].as<R>(); };
-  auto cf = [&](const DBuf& c64, const DBuf& c32) { return f32 ? c32.as<R>() : c64.as<R>(); };
   // MtL of one level (levels are independent of each other)
   auto launch_m2l = [&](int l, hipStream_t st) -> int {
     Level& D = h->lev[l];
@@ -1276,25 +1307,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   for (int l = h->lmin; l < L; ++l) {
     // LtL into the two finest levels adds to their MtL results
     if (pipe && l + 1 == std::max(L - 1, h->lmin + 1)) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
-    Level &P = h->lev[l], &C = h->lev[l + 1];
-    const unsigned gc = (unsigned)((C.n + 255) / 256);
-    const int32_t *par = C.d_parent.as<int32_t>(), *cix = C.d_idx.as<int32_t>();
-    if (P.order == 4 && C.order == 3) {
-      k_l2l_reg<R, 4, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
-      continue;
-    }
-    if (P.order == 3 && C.order == 3) {
-      k_l2l_reg<R, 3, 3><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
-      continue;
-    }
-    if (f32 && P.order == 5 && C.order == 4) {
-      k_l2l_reg<R, 5, 4><<<gc, 256, 0, s>>>(par, cix, C.n, (R)C.h, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
-      continue;
-    }
-    const size_t sh = std::max<size_t>((size_t)2 * P.T, (size_t)2 * P.dn_nslot) * sizeof(R);
-    FAGBI_SPT_SWITCH(spt_of(P.dn_nslot), k_l2l, C.n, sh, s, C.d_parent.as<int32_t>(), C.d_idx.as<int32_t>(),
-                     P.d_dn_slot.as<int32_t>(), cf(P.d_dn_c64, P.d_dn_c32), P.d_dn_boff.as<int32_t>(), P.dn_nslot,
-                     P.T, C.T, Lc(P, 0), Lc(P, 1), Lc(C, 0), Lc(C, 1));
+    FAGBI_TRY(launch_l2l<R>(h, l, f32, s));
   }
   if (sn != s) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
   {
@@ -1363,6 +1376,7 @@ struct TcLevels {
   const int32_t* ce[FAGBI_MAX_LEVELS];
   const double* m0[FAGBI_MAX_LEVELS];
   const double* mk[FAGBI_MAX_LEVELS];
+  double* lam[FAGBI_MAX_LEVELS];       // Coulomb locals (right-hand side mode)
   double h[FAGBI_MAX_LEVELS], rho2[FAGBI_MAX_LEVELS];
   int n[FAGBI_MAX_LEVELS], order[FAGBI_MAX_LEVELS], T[FAGBI_MAX_LEVELS];
 };
@@ -1379,15 +1393,20 @@ __device__ inline void wave_sync() {
 // (staged in LDS first) on the fly.  The wavefront runs 64 / g groups of g
 // lanes, each on its own accepted cluster (g >= the terms of the top degree).
 // Returns this lane's part of the particle-cluster terms (times 4 pi).
+// In the right-hand side mode (RHS) the coefficients at x_c - x_n = -d,
+// (-1)^|a| F_a(d), times qs are added to the cluster's Coulomb locals lam
+// instead (kappa = 0, no moments).
+template <bool RHS>
 __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa, int p, int T, int g,
-                         const double* __restrict__ m0, const double* __restrict__ mk, double* F0, double* FK,
-                         double* HK, double* S0, double* SK, int gl) {
+                         const double* __restrict__ m0, const double* __restrict__ mk, double* lam, double qs,
+                         double* F0, double* FK, double* HK, double* S0, double* SK, int gl) {
   double v = 0, ir = 0, ir2 = 0, E = 0, em1;
   if (has) {
-    for (int t = gl; t < T; t += g) {
-      S0[t] = m0[t];
-      SK[t] = mk[t];
-    }
+    if (!RHS)
+      for (int t = gl; t < T; t += g) {
+        S0[t] = m0[t];
+        SK[t] = mk[t];
+      }
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     ir = inv_sqrt(r2);
     ir2 = ir * ir;
@@ -1399,7 +1418,10 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
     }
   }
   wave_sync();
-  if (has && gl == 0) v = ir * S0[0] + E * ir * SK[0];
+  if (has && gl == 0) {
+    if (RHS) unsafeAtomicAdd(lam, qs * ir);
+    else v = ir * S0[0] + E * ir * SK[0];
+  }
   const double x0[3] = {dx, dy, dz};
   for (int d = 1; d <= p; ++d) {
     const int below = d * (d + 1) * (d + 2) / 6, nd = (d + 1) * (d + 2) / 2;
@@ -1442,21 +1464,27 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
       F0[t] = f0;
       FK[t] = fk;
       HK[t] = hk;
-      const double c = f0 * S0[t] + fk * SK[t];
-      v += (d & 1) ? -c : c;
+      if (RHS) {
+        unsafeAtomicAdd(lam + t, (d & 1) ? -qs * f0 : qs * f0);
+      } else {
+        const double c = f0 * S0[t] + fk * SK[t];
+        v += (d & 1) ? -c : c;
+      }
     }
     wave_sync();
   }
   return v;
 }
 
+template <bool RHS>
 __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, double th2, double kappa, double eps,
                                                  const double3 corner, const double4* __restrict__ chg, int nc,
                                                  const double* __restrict__ pv, const double* __restrict__ pn,
                                                  const double* __restrict__ pa, const int32_t* __restrict__ perm,
                                                  const int32_t* __restrict__ leaf_start,
                                                  const int32_t* __restrict__ leaf_cnt, int64_t N,
-                                                 const double* __restrict__ x, double* qv, int* overflow) {
+                                                 const double* __restrict__ x, double* qv, double* b,
+                                                 int* overflow) {
   __shared__ int32_t fr[2][TC_CAP];
   __shared__ double F0[TC_TG], FK[TC_TG], HK[TC_TG], S0[TC_TG], SK[TC_TG];
   const int n = blockIdx.x;
@@ -1504,8 +1532,9 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
         const int cc = __shfl(c, sl, 64);
         const double ex = __shfl(dx, sl, 64), ey = __shfl(dy, sl, 64), ez = __shfl(dz, sl, 64);
         const int64_t off = (int64_t)cc * T;
-        v += tc_far(has, ex, ey, ez, kappa, p, T, g, lv.m0[l] + off, lv.mk[l] + off, F0 + gi * T, FK + gi * T,
-                    HK + gi * T, S0 + gi * T, SK + gi * T, gl);
+        v += tc_far<RHS>(has, ex, ey, ez, kappa, p, T, g, RHS ? nullptr : lv.m0[l] + off,
+                         RHS ? nullptr : lv.mk[l] + off, RHS ? lv.lam[l] + off : nullptr, xq.w, F0 + gi * T,
+                         FK + gi * T, HK + gi * T, S0 + gi * T, SK + gi * T, gl);
       }
       if (l < L) {
         // children of the clusters that failed, appended in lane order
@@ -1531,20 +1560,35 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
           quad_points(pv, ii, qp);
           const double nx = pn[3 * (int64_t)ii], ny = pn[3 * (int64_t)ii + 1], nz = pn[3 * (int64_t)ii + 2];
           const int p = perm[ii];
-          const double ph = x[p], dph = x[N + p], w = pa[ii] / 3.0;
-          double a = 0;
+          const double w = pa[ii] / 3.0;
+          if (RHS) {
+            // b1 += qs sum_q w / r, b2 += -qs sum_q w (y_q - x_n) . n / r^3
+            double a1 = 0, a2 = 0;
 #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const double rx = xq.x - qp[3 * q], ry = xq.y - qp[3 * q + 1], rz = xq.z - qp[3 * q + 2];
-            const double rr2 = rx * rx + ry * ry + rz * rz;
-            const double ir = inv_sqrt(rr2);
-            const double u = kappa * (rr2 * ir);
-            double E, em1;
-            exp_expm1(-u, E, em1);
-            const double rny = rx * nx + ry * ny + rz * nz;
-            a += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
+            for (int q = 0; q < 3; ++q) {
+              const double rx = qp[3 * q] - xq.x, ry = qp[3 * q + 1] - xq.y, rz = qp[3 * q + 2] - xq.z;
+              const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
+              a1 += ir;
+              a2 -= (rx * nx + ry * ny + rz * nz) * (ir * ir * ir);
+            }
+            unsafeAtomicAdd(b + p, xq.w * w * a1);
+            unsafeAtomicAdd(b + N + p, xq.w * w * a2);
+          } else {
+            const double ph = x[p], dph = x[N + p];
+            double a = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const double rx = xq.x - qp[3 * q], ry = xq.y - qp[3 * q + 1], rz = xq.z - qp[3 * q + 2];
+              const double rr2 = rx * rx + ry * ry + rz * rz;
+              const double ir = inv_sqrt(rr2);
+              const double u = kappa * (rr2 * ir);
+              double E, em1;
+              exp_expm1(-u, E, em1);
+              const double rny = rx * nx + ry * ny + rz * nz;
+              a += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
+            }
+            v += w * a;
           }
-          v += w * a;
         }
       }
     }
@@ -1554,8 +1598,49 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
     nxt = t;
     cnt = nn;
   }
+  if (RHS) return;
   v = wave_sum(v);
   if (lane == 0) qv[n] = xq.w * v * (1.0 / FOUR_PI);
+}
+
+// right-hand side, step 6 of the far field: b += locals tested with the
+// panel's single- and double-layer moments (tree order -> caller order)
+__global__ void __launch_bounds__(256) k_l2p_rhs(const double* __restrict__ ms, const double* __restrict__ md,
+                                                 const int32_t* __restrict__ leaf_of,
+                                                 const int32_t* __restrict__ perm, int64_t N, int T,
+                                                 const double* __restrict__ lam, double* b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t c = leaf_of[i];
+  double s1 = 0, s2 = 0;
+  for (int t = 0; t < T; ++t) {
+    const double l = lam[c * T + t];
+    s1 += l * ms[i * T + t];
+    s2 += l * md[i * T + t];
+  }
+  const int p = perm[i];
+  b[p] += s1;
+  b[N + p] += s2;
+}
+
+static int tc_levels(fagbi_handle* h, int l0, TcLevels& lv) {
+  lv = TcLevels{};
+  for (int l = l0; l <= h->L; ++l) {
+    Level& D = h->lev[l];
+    if (D.order > 8) return set_error(FAGBI_E_ARG, "treecode: expansion order above 8");
+    lv.idx[l] = D.d_idx.as<int32_t>();
+    lv.cs[l] = D.d_child_start.as<int32_t>();
+    lv.ce[l] = D.d_child_end.as<int32_t>();
+    lv.m0[l] = D.d_M64[0].as<double>();
+    lv.mk[l] = D.d_M64[1].as<double>();
+    lv.lam[l] = D.d_L64[0].as<double>();
+    lv.h[l] = D.h;
+    lv.rho2[l] = D.rho * D.rho;
+    lv.n[l] = D.n;
+    lv.order[l] = D.order;
+    lv.T[l] = D.T;
+  }
+  return 0;
 }
 
 int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta, double* qv,
@@ -1566,31 +1651,55 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
   k_to_tree<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), h->N, xt);
   FAGBI_TRY(launch_p2m<double>(h, h->d_ms64.as<double>(), h->d_md64.as<double>(), xt, false, s));
   for (int l = L - 1; l >= l0; --l) FAGBI_TRY(launch_m2m<double>(h, l, false, s));
-  TcLevels lv{};
-  for (int l = l0; l <= L; ++l) {
-    Level& D = h->lev[l];
-    if (D.order > 8) return set_error(FAGBI_E_ARG, "treecode: expansion order above 8");
-    lv.idx[l] = D.d_idx.as<int32_t>();
-    lv.cs[l] = D.d_child_start.as<int32_t>();
-    lv.ce[l] = D.d_child_end.as<int32_t>();
-    lv.m0[l] = D.d_M64[0].as<double>();
-    lv.mk[l] = D.d_M64[1].as<double>();
-    lv.h[l] = D.h;
-    lv.rho2[l] = D.rho * D.rho;
-    lv.n[l] = D.n;
-    lv.order[l] = D.order;
-    lv.T[l] = D.T;
-  }
+  TcLevels lv;
+  FAGBI_TRY(tc_levels(h, l0, lv));
   Tmp flag;
   FAGBI_TRY(flag.alloc(4));
   FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
   const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
   const double eps = h->prm.eps_out / h->prm.eps_in;
-  k_treecode<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
-                                         reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
-                                         h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
-                                         h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv,
-                                         flag.as<int>());
+  k_treecode<false><<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
+                                                reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
+                                                h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
+                                                h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv,
+                                                nullptr, flag.as<int>());
+  FAGBI_HIP(hipGetLastError());
+  int of = 0;
+  FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 1024 clusters of one level for one charge "
+                                        "(theta too small for this tree)");
+  return 0;
+}
+
+// b (caller order, f64[2N]) by the reverse treecode; chg holds x, y, z and
+// q / (4 pi eps_in) per charge.  The locals are accumulated with atomics, so
+// the summation order (not the value beyond rounding) varies between runs.
+int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, double* b, hipStream_t s) {
+  const int L = h->L, l0 = std::min(h->lmin, h->L);
+  TcLevels lv;
+  FAGBI_TRY(tc_levels(h, l0, lv));
+  FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
+  for (int l = l0; l <= L; ++l) {
+    Level& D = h->lev[l];
+    for (int ch = 0; ch < 2; ++ch)
+      FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
+  }
+  Tmp flag;
+  FAGBI_TRY(flag.alloc(4));
+  FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+  const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
+  k_treecode<true><<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, 0.0, 1.0, corner,
+                                               reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
+                                               h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
+                                               h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N,
+                                               nullptr, nullptr, b, flag.as<int>());
+  FAGBI_HIP(hipGetLastError());
+  for (int l = l0; l < L; ++l) FAGBI_TRY(launch_l2l<double>(h, l, false, s));
+  Level& LF = h->lev[L];
+  k_l2p_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_ms64.as<double>(), h->d_md64.as<double>(),
+                                                          h->d_leaf_of.as<int32_t>(), h->d_perm.as<int32_t>(), h->N,
+                                                          LF.T, LF.d_L64[0].as<double>(), b);
   FAGBI_HIP(hipGetLastError());
   int of = 0;
   FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));

@@ -194,6 +194,9 @@ int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const do
                     double theta, double* E, hipStream_t s);
 int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta,
                         double* qv, hipStream_t s);
+int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
+                 hipStream_t s);
+int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, double* b, hipStream_t s);
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
           fagbi_solve_info* info, hipStream_t s);
 void gauss_legendre01(int n, double* x, double* w);

@@ -233,6 +233,17 @@ int energy(fagbi_handle* h, const double* x, const double* xq, const double* q, 
   return 0;
 }
 
+// b by the reverse treecode (the charges carry q / (4 pi eps_in))
+int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
+                 hipStream_t s) {
+  if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
+  std::vector<double> qs(nc);
+  for (int64_t k = 0; k < nc; ++k) qs[k] = q[k] / (FOUR_PI * h->prm.eps_in);
+  Tmp chg;
+  FAGBI_TRY(upload_charges(chg, xq, qs.data(), nc));
+  return treecode_rhs(h, chg.as<double>(), nc, theta, b, s);
+}
+
 // E by the Cartesian treecode: per-charge terms q_n V_n on the GPU, then the
 // fixed-order sum
 int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc, double theta,
@@ -388,7 +399,10 @@ int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double
   auto t0 = std::chrono::steady_clock::now();
   Tmp b, r;
   FAGBI_TRY(b.alloc(n * 8));
-  FAGBI_TRY(rhs(h, xq, q, nc, b.as<double>(), s));
+  if (h->prm.rhs_theta > 0)
+    FAGBI_TRY(rhs_treecode(h, xq, q, nc, h->prm.rhs_theta, b.as<double>(), s));
+  else
+    FAGBI_TRY(rhs(h, xq, q, nc, b.as<double>(), s));
   FAGBI_HIP(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
   // is the initial guess zero?

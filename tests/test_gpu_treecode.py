@@ -92,3 +92,69 @@ def test_full_size_sampled_charges_and_capacity():
     # the handle is still usable
     assert np.isfinite(h.solvation_energy_treecode(xd, xq[:2], q[:2], 0.5))
     h.close()
+
+
+@pytest.mark.parametrize("p_leaf,adaptive", [(3, 1), (8, 0)])
+def test_rhs_small_sphere_matches_oracle(p_leaf, adaptive):
+    """right-hand side by the reverse treecode against the oracle's (the
+    atomics change the summation order only: 1e-11 of max |b|)"""
+    v, t = icosphere(3, 10.0)
+    P = panels(v, t)
+    prm = dict(leaf_size=8, eta0=0.8, p_leaf=p_leaf, adaptive=adaptive, p_max=8)
+    h = F.Handle(eps_in=2.0, eps_out=EPS_OUT, kappa=KAP, **prm)
+    h.build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, 8, 0.8)
+    Fo = ofmm.setup(P, tr, EPS_OUT / 2.0, KAP, p_leaf=p_leaf, adaptive=adaptive, p_max=8, with_near=False)
+    rng = np.random.default_rng(10 + p_leaf)
+    xq = rng.uniform(-5.0, 5.0, (70, 3))
+    q = rng.standard_normal(70)
+    b = torch.empty(2 * P.n, dtype=torch.float64, device=DEV)
+    for theta in (0.0, 0.3, 0.5):
+        h.rhs_treecode(xq, q, theta, b)
+        bo = otc.rhs(Fo, xq, q, theta, 2.0)
+        err = np.abs(b.cpu().numpy() - bo).max() / np.abs(bo).max()
+        print("theta %.1f  max rel %.2e" % (theta, err))
+        assert err <= 1e-11, theta
+    bd = torch.empty_like(b)
+    h.rhs(xq, q, bd)
+    h.rhs_treecode(xq, q, 0.0, b)
+    assert (b - bd).abs().max().item() <= 1e-12 * bd.abs().max().item()
+    h.close()
+
+
+def test_rhs_full_size_sampled_charges_and_solve():
+    w = workload("ellipsoid500k")
+    P = panels(w["verts"], w["tris"])
+    prm = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8)
+    h = F.Handle(eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], **prm)
+    h.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+    tr = otree.build(P, 32, 0.8)
+    eps = w["eps_out"] / w["eps_in"]
+    Fo = ofmm.setup(P, tr, eps, w["kappa"], p_leaf=3, adaptive=1, p_max=8, with_near=False)
+    rng = np.random.default_rng(9)
+    sel = rng.choice(len(w["q"]), 16, replace=False)
+    b = torch.empty(2 * P.n, dtype=torch.float64, device=DEV)
+    h.rhs_treecode(w["xq"][sel], w["q"][sel], 0.5, b)
+    bo = otc.rhs(Fo, w["xq"][sel], w["q"][sel], 0.5, w["eps_in"])
+    assert np.abs(b.cpu().numpy() - bo).max() <= 1e-11 * np.abs(bo).max()
+    # whole RHS of all charges against the direct sum (the treecode's own error)
+    bd = torch.empty_like(b)
+    h.rhs(w["xq"], w["q"], bd)
+    h.rhs_treecode(w["xq"], w["q"], 0.5, b)
+    err = ((b - bd).norm() / bd.norm()).item()
+    print("treecode RHS against the direct sum: %.2e" % err)
+    assert err < 1e-3
+    h.close()
+    # a solve with the treecode right-hand side
+    E = {}
+    for th in (0.0, 0.5):
+        hs = F.Handle(precision=F.FP64, eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], tol=1e-6,
+                      rhs_theta=th, quad_duffy=7, near_ratio=2.0, **prm)
+        hs.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+        x = torch.zeros(2 * P.n, dtype=torch.float64, device=DEV)
+        code, info = hs.solve(w["xq"], w["q"], x)
+        assert code == 0
+        E[th] = hs.solvation_energy(x, w["xq"], w["q"])
+        hs.close()
+    print("energy with the treecode RHS against the direct RHS: %.2e" % (abs(E[0.5] - E[0.0]) / abs(E[0.0])))
+    assert abs(E[0.5] - E[0.0]) < 1e-4 * abs(E[0.0])
