@@ -55,7 +55,8 @@ def parse():
 
 PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7,
               near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=5e-7,
-              precond=3)   # block-diagonal preconditioner over consecutive leaves, <= 32 panels
+              precond=3,   # block-diagonal preconditioner over consecutive leaves, <= 32 panels
+              rhs_theta=0.5)   # right-hand side by the reverse treecode
 MLP_GATE = 0.05         # stated per-pair error tolerance of the gated near field
 
 
@@ -161,10 +162,11 @@ def main():
     blob, mlp_info = train_surrogate(F, torch, epochs=args.mlp_epochs)
     log("surrogate trained on %d pairs in %.1f s" % (mlp_info["pairs"], mlp_info["train_s"]))
 
-    def run(prec, profile):
+    def run(prec, profile, direct=False):
         mlp = dict(mlp_mode=F.MLP_GATED, mlp_gate_tol=MLP_GATE) if prec == F.MIXED else {}
+        prm = dict(PARAMS, rhs_theta=0.0) if direct else PARAMS
         h = F.Handle(precision=prec, eps_in=w["eps_in"], eps_out=w["eps_out"],
-                     kappa=w["kappa"], **PARAMS, **mlp)
+                     kappa=w["kappa"], **prm, **mlp)
         if prec == F.MIXED:
             h.mlp_set_weights(blob)
         h.set_profiling(profile)
@@ -176,7 +178,10 @@ def main():
         x = torch.zeros(2 * N, dtype=torch.float64, device=dev)
         code, info = h.solve(w["xq"], w["q"], x)
         t3 = time.perf_counter()
-        E = h.solvation_energy_treecode(x, w["xq"], w["q"], ENERGY_THETA)
+        if direct:
+            E = h.solvation_energy(x, w["xq"], w["q"])
+        else:
+            E = h.solvation_energy_treecode(x, w["xq"], w["q"], ENERGY_THETA)
         t4 = time.perf_counter()
         gated = h.mlp_stats() if prec == F.MIXED else (0, 0)
         pr = h.profile()
@@ -227,12 +232,17 @@ def main():
     h64, x64, st64 = run(F.FP64, True)
     p64 = h64.profile()
     mv64_ms = p64["ms_total"][0] / max(p64["matvecs"][0], 1)
-    # the direct energy sum of the FP64 solution (the treecode's reference)
+    # the direct energy sum of the FP64 solution (the treecode energy's reference)
     torch.cuda.synchronize()
     t = time.perf_counter()
     E64_direct = h64.solvation_energy(x64, w["xq"], w["q"])
     direct_ms = 1e3 * (time.perf_counter() - t)
     h64.close()
+    # reference: FP64 with the direct right-hand side and the direct energy sum
+    href, _, stref = run(F.FP64, False, direct=True)
+    href.close()
+    E_ref = stref["E"]
+    log("fp64 reference (direct sums) %.0f ms" % stref["total_ms"])
     log("fp64 path %.0f ms (%d iterations)" % (st64["total_ms"], st64["iters"]))
     # dominant single kernel of the mixed matvec: the near-field block SpMV
     # (its launch is exactly the "near" interval of the profile events; it
@@ -267,10 +277,15 @@ def main():
         "solve_breakdown_mixed": steps[-1], "solve_breakdown_fp64": st64,
         "energy_kcal": {"mixed": E_mixed, "fp64": st64["E"],
                         "rel_diff": abs(E_mixed - st64["E"]) / abs(st64["E"]),
-                        "method": "Cartesian treecode, theta %.2f, FMM moments (orders p_l)" % ENERGY_THETA,
-                        "fp64_direct_sum": E64_direct, "direct_sum_ms": direct_ms,
-                        "treecode_vs_direct_fp64": abs(st64["E"] - E64_direct) / abs(E64_direct),
-                        "mixed_vs_direct_fp64": abs(E_mixed - E64_direct) / abs(E64_direct)},
+                        "method": "right-hand side and energy by the Cartesian treecode, theta %.2f / %.2f, "
+                                  "FMM moments and locals (orders p_l)" % (PARAMS["rhs_theta"], ENERGY_THETA),
+                        "fp64_energy_direct_sum": E64_direct, "energy_direct_sum_ms": direct_ms,
+                        "treecode_energy_vs_direct_fp64": abs(st64["E"] - E64_direct) / abs(E64_direct),
+                        "fp64_reference_direct_rhs_and_energy": E_ref,
+                        "reference_time_to_solve_ms": stref["total_ms"],
+                        "reference_rhs_ms": stref["t_rhs_ms"],
+                        "mixed_vs_reference": abs(E_mixed - E_ref) / abs(E_ref),
+                        "fp64_vs_reference": abs(st64["E"] - E_ref) / abs(E_ref)},
         "mlp": dict(mlp_info, gate_tol=MLP_GATE,
                     gated_pairs=steps[-1]["mlp_gated"], candidate_pairs=steps[-1]["mlp_candidates"],
                     note="mixed path = FP32 operator with the gated surrogate near field inside FP64 "

@@ -203,7 +203,7 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
    fails receives the direct 3-point sums; the far field's LtL then takes the
    local expansions to the leaves and LtP tests them with each panel's single-
    and double-layer moments.  theta in [0, 1) (theta = 0: the direct sum on
-   trees whose levels have at most 1024 clusters).  xq: host f64[nc][3]; q:
+   trees whose levels have at most 2048 clusters).  xq: host f64[nc][3]; q:
    host f64[nc]; b: device f64[2N] (caller order), overwritten.  Requires
    fagbi_assemble_nearfield.  The expansions are accumulated with device
    atomics: results agree between runs to rounding, not bit for bit.  Uses
@@ -219,10 +219,10 @@ int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q,
    of the charge from the cube centre); clusters failing the criterion pass
    it to their children, from level min(l_min, L) down; leaves failing it are
    summed directly as in fagbi_solvation_energy.  theta in [0, 1); theta = 0
-   gives the direct sum on trees whose levels have at most 1024 clusters.
+   gives the direct sum on trees whose levels have at most 2048 clusters.
    x: device f64[2N] (caller order); xq: host f64[nc][3]; q: host f64[nc].
    Requires fagbi_assemble_nearfield (the far-field tables); orders above 8
-   are rejected.  FAGBI_E_ARG when one charge would visit more than 1024
+   are rejected.  FAGBI_E_ARG when one charge would visit more than 2048
    clusters of one level (theta too small for the tree).  Uses the far
    field's moment buffers (not concurrently with a matvec of the same
    handle).  Synchronises. */

@@ -1365,7 +1365,9 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
 // frontier of a level lives in LDS, children are appended in a fixed order (a
 // wavefront prefix sum), so the sum order is deterministic.
 // ---------------------------------------------------------------------------
-constexpr int TC_CAP = 1024;          // frontier capacity (clusters of one level, one charge)
+// frontier capacity (clusters of one level, one charge): a small one first
+// (more wavefronts per CU), the large one when a charge overflows it
+constexpr int TC_CAP_SMALL = 512, TC_CAP = 2048;
 // coefficient storage of one wavefront: 64 / g groups of T(p) terms,
 // at most 4 T(4), 2 T(6) or T(8)
 constexpr int TC_TG = 2 * nterms(6);
@@ -1476,7 +1478,7 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
   return v;
 }
 
-template <bool RHS>
+template <bool RHS, int CAP>
 __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, double th2, double kappa, double eps,
                                                  const double3 corner, const double4* __restrict__ chg, int nc,
                                                  const double* __restrict__ pv, const double* __restrict__ pn,
@@ -1485,7 +1487,7 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
                                                  const int32_t* __restrict__ leaf_cnt, int64_t N,
                                                  const double* __restrict__ x, double* qv, double* b,
                                                  int* overflow) {
-  __shared__ int32_t fr[2][TC_CAP];
+  __shared__ int32_t fr[2][CAP];
   __shared__ double F0[TC_TG], FK[TC_TG], HK[TC_TG], S0[TC_TG], SK[TC_TG];
   const int n = blockIdx.x;
   const int lane = threadIdx.x;
@@ -1545,7 +1547,7 @@ __global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, dou
           if (lane >= o) inc += t;
         }
         const int tot = __shfl(inc, 63, 64);
-        if (nn + tot > TC_CAP) {
+        if (nn + tot > CAP) {
           if (lane == 0) atomicOr(overflow, 1);
           return;
         }
@@ -1655,21 +1657,24 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
   FAGBI_TRY(tc_levels(h, l0, lv));
   Tmp flag;
   FAGBI_TRY(flag.alloc(4));
-  FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
   const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
   const double eps = h->prm.eps_out / h->prm.eps_in;
-  k_treecode<false><<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
-                                                reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
-                                                h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
-                                                h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv,
-                                                nullptr, flag.as<int>());
-  FAGBI_HIP(hipGetLastError());
-  int of = 0;
-  FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
-  FAGBI_HIP(hipStreamSynchronize(s));
-  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 1024 clusters of one level for one charge "
-                                        "(theta too small for this tree)");
-  return 0;
+  for (int big = 0; big < 2; ++big) {
+    FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    auto ker = big ? k_treecode<false, TC_CAP> : k_treecode<false, TC_CAP_SMALL>;
+    ker<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
+                                    reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
+                                    h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
+                                    h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv, nullptr,
+                                    flag.as<int>());
+    FAGBI_HIP(hipGetLastError());
+    int of = 0;
+    FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipStreamSynchronize(s));
+    if (!of) return 0;
+  }
+  return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
+                                "(theta too small for this tree)");
 }
 
 // b (caller order, f64[2N]) by the reverse treecode; chg holds x, y, z and
@@ -1679,33 +1684,37 @@ int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, d
   const int L = h->L, l0 = std::min(h->lmin, h->L);
   TcLevels lv;
   FAGBI_TRY(tc_levels(h, l0, lv));
-  FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
-  for (int l = l0; l <= L; ++l) {
-    Level& D = h->lev[l];
-    for (int ch = 0; ch < 2; ++ch)
-      FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
-  }
   Tmp flag;
   FAGBI_TRY(flag.alloc(4));
-  FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
   const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
-  k_treecode<true><<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, 0.0, 1.0, corner,
-                                               reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
-                                               h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
-                                               h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N,
-                                               nullptr, nullptr, b, flag.as<int>());
-  FAGBI_HIP(hipGetLastError());
+  int of = 1;
+  for (int big = 0; big < 2 && of; ++big) {
+    FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
+    for (int l = l0; l <= L; ++l) {
+      Level& D = h->lev[l];
+      for (int ch = 0; ch < 2; ++ch)
+        FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
+    }
+    FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    auto ker = big ? k_treecode<true, TC_CAP> : k_treecode<true, TC_CAP_SMALL>;
+    ker<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, 0.0, 1.0, corner,
+                                    reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
+                                    h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
+                                    h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, nullptr,
+                                    nullptr, b, flag.as<int>());
+    FAGBI_HIP(hipGetLastError());
+    FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipStreamSynchronize(s));
+  }
+  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
+                                        "(theta too small for this tree)");
   for (int l = l0; l < L; ++l) FAGBI_TRY(launch_l2l<double>(h, l, false, s));
   Level& LF = h->lev[L];
   k_l2p_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_ms64.as<double>(), h->d_md64.as<double>(),
                                                           h->d_leaf_of.as<int32_t>(), h->d_perm.as<int32_t>(), h->N,
                                                           LF.T, LF.d_L64[0].as<double>(), b);
   FAGBI_HIP(hipGetLastError());
-  int of = 0;
-  FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
-  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 1024 clusters of one level for one charge "
-                                        "(theta too small for this tree)");
   return 0;
 }
 
