@@ -32,8 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # (calibrated with a device copy of known size); None until measured for the
 # kernel as it stands
 TRAFFIC_SPMV = 1339025613   # FETCH 643,529.1 KiB x 2.0000 + WRITE 20,584.0 KiB x 1.0 per launch
-# acceptance parameter of the treecode energy (rho_l / R <= theta)
+# acceptance parameter of the treecode energy (rho_l / R <= theta) and its
+# order cap (terms |b| <= min(p_l, 6))
 ENERGY_THETA = 0.5
+ENERGY_PMAX = 6
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
@@ -56,7 +58,7 @@ def parse():
 PARAMS = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7,
               near_ratio=2.0, tol=1e-6, max_iter=200, max_outer=5, inner_tol=5e-7,
               precond=3,   # block-diagonal preconditioner over consecutive leaves, <= 32 panels
-              rhs_theta=0.5)   # right-hand side by the reverse treecode
+              rhs_theta=0.5, rhs_pmax=6)   # right-hand side by the reverse treecode
 MLP_GATE = 0.05         # stated per-pair error tolerance of the gated near field
 
 
@@ -181,7 +183,7 @@ def main():
         if direct:
             E = h.solvation_energy(x, w["xq"], w["q"])
         else:
-            E = h.solvation_energy_treecode(x, w["xq"], w["q"], ENERGY_THETA)
+            E = h.solvation_energy_treecode(x, w["xq"], w["q"], ENERGY_THETA, p_max=ENERGY_PMAX)
         t4 = time.perf_counter()
         gated = h.mlp_stats() if prec == F.MIXED else (0, 0)
         pr = h.profile()
@@ -278,7 +280,8 @@ def main():
         "energy_kcal": {"mixed": E_mixed, "fp64": st64["E"],
                         "rel_diff": abs(E_mixed - st64["E"]) / abs(st64["E"]),
                         "method": "right-hand side and energy by the Cartesian treecode, theta %.2f / %.2f, "
-                                  "FMM moments and locals (orders p_l)" % (PARAMS["rhs_theta"], ENERGY_THETA),
+                                  "FMM moments and locals, orders min(p_l, %d)" % (PARAMS["rhs_theta"], ENERGY_THETA,
+                                                                                   ENERGY_PMAX),
                         "fp64_energy_direct_sum": E64_direct, "energy_direct_sum_ms": direct_ms,
                         "treecode_energy_vs_direct_fp64": abs(st64["E"] - E64_direct) / abs(E64_direct),
                         "fp64_reference_direct_rhs_and_energy": E_ref,

@@ -80,6 +80,7 @@ typedef struct fagbi_params {
   /* right-hand side of fagbi_solve: 0 = direct sum (fagbi_rhs), in (0, 1) =
      reverse treecode with this acceptance parameter (fagbi_rhs_treecode) */
   double rhs_theta;
+  int32_t rhs_pmax;            /* its order cap: terms |a| <= min(p_l, rhs_pmax) */
 } fagbi_params;
 
 #define FAGBI_MAX_LEVELS 21        /* levels 0..20 (cube keys have 20 levels) */
@@ -199,37 +200,41 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
 /* Right-hand side as fagbi_rhs by the Cartesian treecode of Sec. 2.5 run in
    reverse: every charge visits the clusters as in
    fagbi_solvation_energy_treecode; an accepted cluster receives the charge's
-   particle-to-local Taylor expansion (order p_l, Coulomb kernel), a leaf that
+   particle-to-local Taylor expansion (order min(p_l, p_max), Coulomb kernel;
+   p_max >= 8 evaluates the full orders), a leaf that
    fails receives the direct 3-point sums; the far field's LtL then takes the
    local expansions to the leaves and LtP tests them with each panel's single-
-   and double-layer moments.  theta in [0, 1) (theta = 0: the direct sum on
-   trees whose levels have at most 2048 clusters).  xq: host f64[nc][3]; q:
+   and double-layer moments.  theta in [0, 1) (theta = 0: the direct sum).  xq: host f64[nc][3]; q:
    host f64[nc]; b: device f64[2N] (caller order), overwritten.  Requires
    fagbi_assemble_nearfield.  The expansions are accumulated with device
    atomics: results agree between runs to rounding, not bit for bit.  Uses
    the far field's local-expansion buffers (not concurrently with a matvec of
    the same handle).  FAGBI_E_ARG as for the treecode energy.  Synchronises. */
 int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q,
-                       int64_t nc, double theta, double* b, void* stream);
+                       int64_t nc, double theta, int32_t p_max, double* b,
+                       void* stream);
 
 /* Solvation energy as above by the Cartesian treecode of Sec. 2.5: the
    moments of x (leaf moments and the MtM upward pass of the far field, FP64,
-   orders p_l) give each charge a particle-cluster term from every cluster
+   orders p_l) give each charge a particle-cluster term of order
+   min(p_l, p_max) (p_max >= 8: the full orders) from every cluster
    with rho_l / R <= theta (rho_l the level's cluster radius, R the distance
    of the charge from the cube centre); clusters failing the criterion pass
    it to their children, from level min(l_min, L) down; leaves failing it are
-   summed directly as in fagbi_solvation_energy.  theta in [0, 1); theta = 0
-   gives the direct sum on trees whose levels have at most 2048 clusters.
+   summed directly as in fagbi_solvation_energy.  All charges advance level
+   by level together (one list of (charge, cluster) pairs per level).
+   theta in [0, 1); theta = 0 gives the direct sum.
    x: device f64[2N] (caller order); xq: host f64[nc][3]; q: host f64[nc].
    Requires fagbi_assemble_nearfield (the far-field tables); orders above 8
-   are rejected.  FAGBI_E_ARG when one charge would visit more than 2048
-   clusters of one level (theta too small for the tree).  Uses the far
-   field's moment buffers (not concurrently with a matvec of the same
-   handle).  Synchronises. */
+   are rejected.  FAGBI_E_ARG when a level would hold more than 2^26
+   (charge, cluster) pairs (theta too small for the tree and the charges).
+   Contributions are accumulated with device atomics: results agree between
+   runs to rounding, not bit for bit.  Uses the far field's moment buffers
+   (not concurrently with a matvec of the same handle).  Synchronises. */
 int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x,
                                     const double* xq, const double* q,
-                                    int64_t nc, double theta, double* E_kcal,
-                                    void* stream);
+                                    int64_t nc, double theta, int32_t p_max,
+                                    double* E_kcal, void* stream);
 
 /* Turn per-phase matvec timing on (1) or off (0); turning it on resets the
    counters.  While on, every matvec waits for its last phase to finish

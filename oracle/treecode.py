@@ -24,7 +24,9 @@ Readings (one choice, used by the GPU path as well):
     coarsest level that carries moments (for charges inside the molecule no
     coarser cluster can pass the criterion);
   * a leaf that fails the criterion is summed directly with the 3-point rule,
-    with the integrand of the direct energy sum (oracle.solve.energy).
+    with the integrand of the direct energy sum (oracle.solve.energy);
+  * an optional order cap p_max evaluates the terms |b| <= min(p_l, p_max)
+    only (the leading terms of the level's moments).
 
 The right-hand side (Sec. 2.2 source terms, b1 = (1/eps_in) int psi_i
 sum_n q_n G0(x, x_n), b2 likewise with dG0/dn_x) by the same visit run in
@@ -69,7 +71,7 @@ def _far(d, m0, mk, kappa, p):
     return v / FOUR_PI
 
 
-def potentials(F, x, xq, theta, moments=None):
+def potentials(F, x, xq, theta, moments=None, p_max=None):
     """V_n for every charge by the treecode, and the number of particle-cluster
     terms and of directly summed leaves (per charge)."""
     P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
@@ -95,7 +97,9 @@ def potentials(F, x, xq, theta, moments=None):
             acc = cl.rho * cl.rho <= th2 * R2
             if acc.any():
                 a = front[acc]
-                V[n] += _far(d[acc], M0[l][a], Mk[l][a], kappa, pl[l]).sum()
+                p = pl[l] if p_max is None else min(pl[l], p_max)
+                T = len(taylor.multi_indices(p))
+                V[n] += _far(d[acc], M0[l][a][:, :T], Mk[l][a][:, :T], kappa, p).sum()
                 n_far[n] += len(a)
             rest = front[~acc]
             if l < L:
@@ -108,14 +112,14 @@ def potentials(F, x, xq, theta, moments=None):
     return V, n_far, n_leaf
 
 
-def energy(F, x, xq, q, theta):
+def energy(F, x, xq, q, theta, p_max=None):
     """E_sol in kcal/mol by the treecode (theta = 0 accepts no cluster: the
     direct sum)."""
-    V, _, _ = potentials(F, x, xq, theta)
+    V, _, _ = potentials(F, x, xq, theta, p_max=p_max)
     return 0.5 * UNIT_KCAL * float(np.dot(np.asarray(q, np.float64), V))
 
 
-def rhs(F, xq, q, theta, eps_in):
+def rhs(F, xq, q, theta, eps_in, p_max=None):
     """b = [b1; b2] (panel order) by the reverse treecode (theta = 0: the
     direct sum of oracle.solve.rhs)."""
     P, tree, pl = F.P, F.tree, F.orders
@@ -140,8 +144,9 @@ def rhs(F, xq, q, theta, eps_in):
             acc = cl.rho * cl.rho <= th2 * R2
             if acc.any():
                 a = front[acc]
-                Fc = taylor.coefficients(-d[acc], 0.0, pl[l])      # at x_c - x_n
-                for t, k in enumerate(taylor.multi_indices(pl[l])):
+                p = pl[l] if p_max is None else min(pl[l], p_max)
+                Fc = taylor.coefficients(-d[acc], 0.0, p)           # at x_c - x_n
+                for t, k in enumerate(taylor.multi_indices(p)):
                     lam[l][a, t] += q[n] * Fc[k] / FOUR_PI
             rest = front[~acc]
             if l < L:

@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("quad_duffy", C.c_int32), ("near_ratio", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_outer", C.c_int32), ("inner_tol", C.c_double),
-                ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double), ("rhs_theta", C.c_double)]
+                ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double), ("rhs_theta", C.c_double),
+                ("rhs_pmax", C.c_int32)]
 
 
 class TreeInfo(C.Structure):
@@ -93,10 +94,10 @@ def load():
         "fagbi_matvec_parts": [vp, vp, vp, i32, i32, vp],
         "fagbi_precond_apply": [vp, vp, vp, vp],
         "fagbi_rhs": [vp, vp, vp, i64, vp, vp],
-        "fagbi_rhs_treecode": [vp, vp, vp, i64, C.c_double, vp, vp],
+        "fagbi_rhs_treecode": [vp, vp, vp, i64, C.c_double, i32, vp, vp],
         "fagbi_solve": [vp, vp, vp, i64, vp, C.POINTER(SolveInfo), vp],
         "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
-        "fagbi_solvation_energy_treecode": [vp, vp, vp, vp, i64, C.c_double, dp, vp],
+        "fagbi_solvation_energy_treecode": [vp, vp, vp, vp, i64, C.c_double, i32, dp, vp],
         "fagbi_get_tree_info": [vp, C.POINTER(TreeInfo)],
         "fagbi_get_permutation": [vp, vp],
         "fagbi_set_profiling": [vp, i32],
@@ -212,10 +213,11 @@ class Handle:
         _check(self.lib.fagbi_rhs(self.h, xqp, qp, len(q_), _dev(b), _stream(stream)))
         return b
 
-    def rhs_treecode(self, xq, q, theta, b, stream=None):
+    def rhs_treecode(self, xq, q, theta, b, p_max=8, stream=None):
         xq_, xqp = _host(xq, np.float64)
         q_, qp = _host(q, np.float64)
-        _check(self.lib.fagbi_rhs_treecode(self.h, xqp, qp, len(q_), float(theta), _dev(b), _stream(stream)))
+        _check(self.lib.fagbi_rhs_treecode(self.h, xqp, qp, len(q_), float(theta), int(p_max), _dev(b),
+                                           _stream(stream)))
         return b
 
     def solve(self, xq, q, x, stream=None):
@@ -234,12 +236,12 @@ class Handle:
                                                _stream(stream)))
         return e.value
 
-    def solvation_energy_treecode(self, x, xq, q, theta, stream=None):
+    def solvation_energy_treecode(self, x, xq, q, theta, p_max=8, stream=None):
         xq_, xqp = _host(xq, np.float64)
         q_, qp = _host(q, np.float64)
         e = C.c_double()
         _check(self.lib.fagbi_solvation_energy_treecode(self.h, _dev(x), xqp, qp, len(q_), float(theta),
-                                                        C.byref(e), _stream(stream)))
+                                                        int(p_max), C.byref(e), _stream(stream)))
         return e.value
 
     def tree_info(self):

@@ -135,6 +135,7 @@ int fagbi_default_params(fagbi_params* p) {
   p->inner_tol = 5e-7;
   p->mlp_mode = FAGBI_MLP_OFF;
   p->mlp_gate_tol = 1e-3;
+  p->rhs_pmax = 8;
   return 0;
 }
 
@@ -158,6 +159,7 @@ static int check_params(const fagbi_params* p) {
     return set_error(FAGBI_E_ARG, "bad solver tolerances/iteration limits");
   if (p->mlp_mode < 0 || p->mlp_mode > 2) return set_error(FAGBI_E_ARG, "bad mlp_mode");
   if (!(p->rhs_theta >= 0 && p->rhs_theta < 1)) return set_error(FAGBI_E_ARG, "rhs_theta must be in [0, 1)");
+  if (p->rhs_pmax < 0) return set_error(FAGBI_E_ARG, "rhs_pmax must be >= 0");
   return 0;
 }
 
@@ -192,6 +194,7 @@ void fagbi_destroy(fagbi_handle* h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   h->free_all();
+  for (auto& t : h->tc_ws) t.release();
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -273,20 +276,22 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq, c
   return fagbi::energy(h, x, xq, q, nc, E_kcal, (hipStream_t)stream);
 }
 
-int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
-                       void* stream) {
+int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta,
+                       int32_t p_max, double* b, void* stream) {
   if (!h || !xq || !q || !b || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
+  if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode right-hand side before assemble_nearfield");
-  return fagbi::rhs_treecode(h, xq, q, nc, theta, b, (hipStream_t)stream);
+  return fagbi::rhs_treecode(h, xq, q, nc, theta, p_max, b, (hipStream_t)stream);
 }
 
 int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q,
-                                    int64_t nc, double theta, double* E_kcal, void* stream) {
+                                    int64_t nc, double theta, int32_t p_max, double* E_kcal, void* stream) {
   if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
+  if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode energy before assemble_nearfield");
-  return fagbi::energy_treecode(h, x, xq, q, nc, theta, E_kcal, (hipStream_t)stream);
+  return fagbi::energy_treecode(h, x, xq, q, nc, theta, p_max, E_kcal, (hipStream_t)stream);
 }
 
 int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {

@@ -30,6 +30,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "scan.h"
 
 namespace fagbi {
 
@@ -1361,13 +1362,15 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
 // the charge from the FMM moments of the same x:
 //   V += sum_|b|<=p_l (-1)^|b| [F_b(x_n - x_c; 0) M0_b + F_b(x_n - x_c; kappa) Mk_b] / 4 pi,
 // a cluster that fails passes its children on, and a leaf that fails is
-// summed directly with the 3-point rule.  One wavefront per charge; the
-// frontier of a level lives in LDS, children are appended in a fixed order (a
-// wavefront prefix sum), so the sum order is deterministic.
+// summed directly with the 3-point rule.  All charges advance together: the
+// frontier of a level is a list of (charge, cluster) pairs; one thread per
+// pair takes the decision (and sums a failing leaf), the accepted pairs are
+// compacted and evaluated by lane groups, the children of the others are
+// appended in pair order by a scan.  Contributions meet in device atomics,
+// so the summation order (not the value beyond rounding) varies between runs.
 // ---------------------------------------------------------------------------
-// frontier capacity (clusters of one level, one charge): a small one first
-// (more wavefronts per CU), the large one when a charge overflows it
-constexpr int TC_CAP_SMALL = 512, TC_CAP = 2048;
+// pairs of one level, at most
+constexpr int64_t TC_MAX_PAIRS = (int64_t)1 << 26;
 // coefficient storage of one wavefront: 64 / g groups of T(p) terms,
 // at most 4 T(4), 2 T(6) or T(8)
 constexpr int TC_TG = 2 * nterms(6);
@@ -1380,7 +1383,9 @@ struct TcLevels {
   const double* mk[FAGBI_MAX_LEVELS];
   double* lam[FAGBI_MAX_LEVELS];       // Coulomb locals (right-hand side mode)
   double h[FAGBI_MAX_LEVELS], rho2[FAGBI_MAX_LEVELS];
-  int n[FAGBI_MAX_LEVELS], order[FAGBI_MAX_LEVELS], T[FAGBI_MAX_LEVELS];
+  // clusters, expansion order p_l, terms T(p_l) (row length of moments and
+  // locals), and the order the treecode evaluates, min(p_l, p_max)
+  int n[FAGBI_MAX_LEVELS], order[FAGBI_MAX_LEVELS], T[FAGBI_MAX_LEVELS], pt[FAGBI_MAX_LEVELS];
 };
 
 __device__ inline void wave_sync() {
@@ -1434,6 +1439,7 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
       const int e[3] = {d - m, m - sidx, sidx};
       // every read is issued (a missing term reads entry 0 with weight 0), so
       // none waits for another
+      // (the right-hand side needs the Coulomb coefficients only)
       double a1[3], a2[3], f1[3], k1[3], h1[3], f2[3], k2[3], h2[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -1442,30 +1448,36 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
         a1[i] = e[i] >= 1 ? x0[i] : 0.0;
         a2[i] = e[i] >= 2 ? 1.0 : 0.0;
         f1[i] = F0[j1];
-        k1[i] = FK[j1];
-        h1[i] = HK[j1];
         f2[i] = F0[j2];
-        k2[i] = FK[j2];
-        h2[i] = HK[j2];
+        if (!RHS) {
+          k1[i] = FK[j1];
+          h1[i] = HK[j1];
+          k2[i] = FK[j2];
+          h2[i] = HK[j2];
+        }
       }
       double s1f = 0, s2f = 0, s1k = 0, s2k = 0, s1h = 0, s2h = 0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         s1f += a1[i] * f1[i];
-        s1k += a1[i] * k1[i];
-        s1h += a1[i] * h1[i];
         s2f += a2[i] * f2[i];
-        s2k += a2[i] * k2[i];
-        s2h += a2[i] * h2[i];
+        if (!RHS) {
+          s1k += a1[i] * k1[i];
+          s1h += a1[i] * h1[i];
+          s2k += a2[i] * k2[i];
+          s2h += a2[i] * h2[i];
+        }
       }
       const double id = 1.0 / d;
       const double f0 = (-(2 * d - 1) * s1f - (d - 1) * s2f) * ir2 * id;
-      const double fk = (-kappa * (s1h + s2h) - (2 * d - 1) * s1k - (d - 1) * s2k) * ir2 * id;
-      const double hk = -kappa * (s1k + s2k) * id;
       const int t = below + gl;
       F0[t] = f0;
-      FK[t] = fk;
-      HK[t] = hk;
+      double fk = 0;
+      if (!RHS) {
+        fk = (-kappa * (s1h + s2h) - (2 * d - 1) * s1k - (d - 1) * s2k) * ir2 * id;
+        FK[t] = fk;
+        HK[t] = -kappa * (s1k + s2k) * id;
+      }
       if (RHS) {
         unsafeAtomicAdd(lam + t, (d & 1) ? -qs * f0 : qs * f0);
       } else {
@@ -1478,131 +1490,147 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
   return v;
 }
 
-template <bool RHS, int CAP>
-__global__ void __launch_bounds__(64) k_treecode(TcLevels lv, int l0, int L, double th2, double kappa, double eps,
-                                                 const double3 corner, const double4* __restrict__ chg, int nc,
-                                                 const double* __restrict__ pv, const double* __restrict__ pn,
-                                                 const double* __restrict__ pa, const int32_t* __restrict__ perm,
-                                                 const int32_t* __restrict__ leaf_start,
-                                                 const int32_t* __restrict__ leaf_cnt, int64_t N,
-                                                 const double* __restrict__ x, double* qv, double* b,
-                                                 int* overflow) {
-  __shared__ int32_t fr[2][CAP];
-  __shared__ double F0[TC_TG], FK[TC_TG], HK[TC_TG], S0[TC_TG], SK[TC_TG];
-  const int n = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (n >= nc) return;
+// cube centre corner + (idx + 1/2) h of cluster c and d = x - centre, in the
+// oracle's rounding
+__device__ inline void tc_offset(const TcLevels& lv, int l, int c, double3 corner, double4 xq, double& dx,
+                                 double& dy, double& dz) {
+  const int32_t* ix = lv.idx[l] + 3 * (int64_t)c;
+  const double h = lv.h[l];
+  dx = __dsub_rn(xq.x, __dadd_rn(corner.x, __dmul_rn((double)ix[0] + 0.5, h)));
+  dy = __dsub_rn(xq.y, __dadd_rn(corner.y, __dmul_rn((double)ix[1] + 0.5, h)));
+  dz = __dsub_rn(xq.z, __dadd_rn(corner.z, __dmul_rn((double)ix[2] + 0.5, h)));
+}
+
+// the first frontier: every (charge, cluster of level l0) pair
+__global__ void k_tc_init(int64_t M, int n0, int32_t* pn, int32_t* pc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  pn[i] = (int32_t)(i / n0);
+  pc[i] = (int32_t)(i % n0);
+}
+
+// one thread per (charge, cluster) pair of level l: acc[i] = 1 when the
+// criterion holds, nch[i] = children to visit; a leaf that fails is summed
+// directly here (energy: into V[n] times 4 pi / q; right-hand side: into b)
+template <bool RHS>
+__global__ void __launch_bounds__(256) k_tc_classify(TcLevels lv, int l, int L, double th2, double kappa, double eps,
+                                                     double3 corner, const double4* __restrict__ chg, int64_t M,
+                                                     const int32_t* __restrict__ pn, const int32_t* __restrict__ pc,
+                                                     const double* __restrict__ pv, const double* __restrict__ pnrm,
+                                                     const double* __restrict__ pa, const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ leaf_start,
+                                                     const int32_t* __restrict__ leaf_cnt, int64_t N,
+                                                     const double* __restrict__ x, double* V, double* b, int32_t* acc,
+                                                     int32_t* nch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int n = pn[i], c = pc[i];
   const double4 xq = chg[n];
-  int32_t *cur = fr[0], *nxt = fr[1];
-  int cnt = lv.n[l0];
+  double dx, dy, dz;
+  tc_offset(lv, l, c, corner, xq, dx, dy, dz);
+  const double R2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  const bool a = lv.rho2[l] <= __dmul_rn(th2, R2);
+  acc[i] = a;
+  nch[i] = (!a && l < L) ? lv.ce[l][c] - lv.cs[l][c] : 0;
+  if (a || l < L) return;
+  // direct sum over the leaf's panels (tree order)
+  const int i0 = leaf_start[c], i1 = i0 + leaf_cnt[c];
   double v = 0;
-  for (int l = l0; l <= L && cnt > 0; ++l) {
-    const bool first = l == l0;
-    const double h = lv.h[l], rho2 = lv.rho2[l];
-    const int p = lv.order[l], T = lv.T[l];
-    // lanes per cluster: at least the terms of degree p
-    const int g = p <= 4 ? 16 : p <= 6 ? 32 : 64, ng = 64 / g, gi = lane / g, gl = lane % g;
-    int nn = 0;
-    for (int base = 0; base < cnt; base += 64) {
-      const int i = base + lane;
-      const bool act = i < cnt;
-      const int c = act ? (first ? i : cur[i]) : 0;
-      // cube centre corner + (idx + 1/2) h and the criterion, in the oracle's
-      // rounding (inactive lanes look at cluster 0 and are masked)
-      const int32_t* ix = lv.idx[l] + 3 * (int64_t)c;
-      const int32_t ix0 = ix[0], ix1 = ix[1], ix2 = ix[2];
-      const int c0 = l < L ? lv.cs[l][c] : 0, c1 = l < L ? lv.ce[l][c] : 0;
-      const double dx = __dsub_rn(xq.x, __dadd_rn(corner.x, __dmul_rn((double)ix0 + 0.5, h)));
-      const double dy = __dsub_rn(xq.y, __dadd_rn(corner.y, __dmul_rn((double)ix1 + 0.5, h)));
-      const double dz = __dsub_rn(xq.z, __dadd_rn(corner.z, __dmul_rn((double)ix2 + 0.5, h)));
-      const double R2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-      const bool acc = act && rho2 <= __dmul_rn(th2, R2);
-      // particle-cluster terms: groups of g lanes, one accepted cluster each
-      uint64_t am = __ballot(acc);
-      while (am) {
-        // the group's cluster: the gi-th remaining accepted lane
-        uint64_t mm = am;
-        int src = -1;
-        for (int k = 0; k < ng && mm; ++k) {
-          const int b = __builtin_ctzll(mm);
-          mm &= mm - 1;
-          if (k == gi) src = b;
-        }
-        am = mm;
-        const bool has = src >= 0;
-        const int sl = has ? src : 0;
-        const int cc = __shfl(c, sl, 64);
-        const double ex = __shfl(dx, sl, 64), ey = __shfl(dy, sl, 64), ez = __shfl(dz, sl, 64);
-        const int64_t off = (int64_t)cc * T;
-        v += tc_far<RHS>(has, ex, ey, ez, kappa, p, T, g, RHS ? nullptr : lv.m0[l] + off,
+  for (int ii = i0; ii < i1; ++ii) {
+    double qp[9];
+    quad_points(pv, ii, qp);
+    const double nx = pnrm[3 * (int64_t)ii], ny = pnrm[3 * (int64_t)ii + 1], nz = pnrm[3 * (int64_t)ii + 2];
+    const int p = perm[ii];
+    const double w = pa[ii] / 3.0;
+    if (RHS) {
+      // b1 += qs sum_q w / r, b2 += -qs sum_q w (y_q - x_n) . n / r^3
+      double a1 = 0, a2 = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double rx = qp[3 * q] - xq.x, ry = qp[3 * q + 1] - xq.y, rz = qp[3 * q + 2] - xq.z;
+        const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
+        a1 += ir;
+        a2 -= (rx * nx + ry * ny + rz * nz) * (ir * ir * ir);
+      }
+      unsafeAtomicAdd(b + p, xq.w * w * a1);
+      unsafeAtomicAdd(b + N + p, xq.w * w * a2);
+    } else {
+      const double ph = x[p], dph = x[N + p];
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double rx = xq.x - qp[3 * q], ry = xq.y - qp[3 * q + 1], rz = xq.z - qp[3 * q + 2];
+        const double rr2 = rx * rx + ry * ry + rz * rz;
+        const double ir = inv_sqrt(rr2);
+        const double u = kappa * (rr2 * ir);
+        double E, em1;
+        exp_expm1(-u, E, em1);
+        const double rny = rx * nx + ry * ny + rz * nz;
+        s += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
+      }
+      v += w * s;
+    }
+  }
+  if (!RHS) unsafeAtomicAdd(V + n, v);
+}
+
+// pair list of the accepted pairs (in pair order)
+__global__ void k_tc_compact(int64_t M, const int32_t* __restrict__ acc, const int64_t* __restrict__ off,
+                             int64_t* list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M && acc[i]) list[off[i]] = i;
+}
+
+// particle-cluster terms of the accepted pairs: 64 / g groups of g lanes per
+// wavefront, one pair each
+template <bool RHS>
+__global__ void __launch_bounds__(64) k_tc_far(TcLevels lv, int l, double kappa, double3 corner,
+                                               const double4* __restrict__ chg, const int64_t* __restrict__ list,
+                                               int64_t nacc, const int32_t* __restrict__ pn,
+                                               const int32_t* __restrict__ pc, double* V) {
+  __shared__ double F0[TC_TG], FK[TC_TG], HK[TC_TG], S0[TC_TG], SK[TC_TG];
+  const int lane = threadIdx.x;
+  const int p = lv.pt[l], T = nterms(p);
+  const int g = p <= 4 ? 16 : p <= 6 ? 32 : 64, ng = 64 / g, gi = lane / g, gl = lane % g;
+  const int64_t k = (int64_t)blockIdx.x * ng + gi;
+  const bool has = k < nacc;
+  int n = 0, c = 0;
+  double dx = 0, dy = 0, dz = 0;
+  double4 xq = make_double4(0, 0, 0, 0);
+  if (has) {
+    const int64_t i = list[k];
+    n = pn[i];
+    c = pc[i];
+    xq = chg[n];
+    tc_offset(lv, l, c, corner, xq, dx, dy, dz);
+  }
+  const int64_t off = (int64_t)c * lv.T[l];
+  double v = tc_far<RHS>(has, dx, dy, dz, kappa, p, T, g, RHS ? nullptr : lv.m0[l] + off,
                          RHS ? nullptr : lv.mk[l] + off, RHS ? lv.lam[l] + off : nullptr, xq.w, F0 + gi * T,
                          FK + gi * T, HK + gi * T, S0 + gi * T, SK + gi * T, gl);
-      }
-      if (l < L) {
-        // children of the clusters that failed, appended in lane order
-        const int k = (act && !acc) ? c1 - c0 : 0;
-        int inc = k;
-        for (int o = 1; o < 64; o <<= 1) {
-          const int t = __shfl_up(inc, o, 64);
-          if (lane >= o) inc += t;
-        }
-        const int tot = __shfl(inc, 63, 64);
-        if (nn + tot > CAP) {
-          if (lane == 0) atomicOr(overflow, 1);
-          return;
-        }
-        const int at = nn + inc - k;
-        for (int j = 0; j < k; ++j) nxt[at + j] = c0 + j;
-        nn += tot;
-      } else if (act && !acc) {
-        // direct sum over the leaf's panels (tree order)
-        const int i0 = leaf_start[c], i1 = i0 + leaf_cnt[c];
-        for (int ii = i0; ii < i1; ++ii) {
-          double qp[9];
-          quad_points(pv, ii, qp);
-          const double nx = pn[3 * (int64_t)ii], ny = pn[3 * (int64_t)ii + 1], nz = pn[3 * (int64_t)ii + 2];
-          const int p = perm[ii];
-          const double w = pa[ii] / 3.0;
-          if (RHS) {
-            // b1 += qs sum_q w / r, b2 += -qs sum_q w (y_q - x_n) . n / r^3
-            double a1 = 0, a2 = 0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              const double rx = qp[3 * q] - xq.x, ry = qp[3 * q + 1] - xq.y, rz = qp[3 * q + 2] - xq.z;
-              const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
-              a1 += ir;
-              a2 -= (rx * nx + ry * ny + rz * nz) * (ir * ir * ir);
-            }
-            unsafeAtomicAdd(b + p, xq.w * w * a1);
-            unsafeAtomicAdd(b + N + p, xq.w * w * a2);
-          } else {
-            const double ph = x[p], dph = x[N + p];
-            double a = 0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              const double rx = xq.x - qp[3 * q], ry = xq.y - qp[3 * q + 1], rz = xq.z - qp[3 * q + 2];
-              const double rr2 = rx * rx + ry * ry + rz * rz;
-              const double ir = inv_sqrt(rr2);
-              const double u = kappa * (rr2 * ir);
-              double E, em1;
-              exp_expm1(-u, E, em1);
-              const double rny = rx * nx + ry * ny + rz * nz;
-              a += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
-            }
-            v += w * a;
-          }
-        }
-      }
-    }
-    wave_sync();
-    int32_t* t = cur;
-    cur = nxt;
-    nxt = t;
-    cnt = nn;
-  }
   if (RHS) return;
-  v = wave_sum(v);
-  if (lane == 0) qv[n] = xq.w * v * (1.0 / FOUR_PI);
+  for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (has && gl == 0) unsafeAtomicAdd(V + n, v);
+}
+
+// children of the pairs that failed, appended in pair order
+__global__ void k_tc_expand(TcLevels lv, int l, int64_t M, const int32_t* __restrict__ pn,
+                            const int32_t* __restrict__ pc, const int32_t* __restrict__ nch,
+                            const int64_t* __restrict__ off, int32_t* npn, int32_t* npc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M || !nch[i]) return;
+  const int n = pn[i], c0 = lv.cs[l][pc[i]];
+  const int64_t o = off[i];
+  for (int j = 0; j < nch[i]; ++j) {
+    npn[o + j] = n;
+    npc[o + j] = c0 + j;
+  }
+}
+
+// q_n V_n / 4 pi
+__global__ void k_tc_qv(const double4* __restrict__ chg, const double* __restrict__ V, int64_t nc, double* qv) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < nc) qv[n] = chg[n].w * V[n] * (1.0 / FOUR_PI);
 }
 
 // right-hand side, step 6 of the far field: b += locals tested with the
@@ -1625,7 +1653,7 @@ __global__ void __launch_bounds__(256) k_l2p_rhs(const double* __restrict__ ms, 
   b[N + p] += s2;
 }
 
-static int tc_levels(fagbi_handle* h, int l0, TcLevels& lv) {
+static int tc_levels(fagbi_handle* h, int l0, int p_max, TcLevels& lv) {
   lv = TcLevels{};
   for (int l = l0; l <= h->L; ++l) {
     Level& D = h->lev[l];
@@ -1641,12 +1669,83 @@ static int tc_levels(fagbi_handle* h, int l0, TcLevels& lv) {
     lv.n[l] = D.n;
     lv.order[l] = D.order;
     lv.T[l] = D.T;
+    lv.pt[l] = std::min(D.order, p_max);
   }
   return 0;
 }
 
-int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta, double* qv,
-                        hipStream_t s) {
+// the level-by-level visit shared by the energy (RHS = false: V[n] += the
+// charge's potential times 4 pi) and the right-hand side (RHS = true: b and
+// the Coulomb locals)
+// a work list of at least `bytes` (reallocated only while it holds nothing live)
+static int tc_grow(fagbi::Tmp& t, size_t bytes) {
+  if (t.bytes >= bytes) return 0;
+  FAGBI_HIP(hipDeviceSynchronize());   // no kernel still reads the old list
+  t.release();
+  return t.alloc(bytes + bytes / 2);
+}
+
+template <bool RHS>
+static int tc_visit(fagbi_handle* h, const TcLevels& lv, int l0, const double* chg, int64_t nc, double theta,
+                    const double* x, double* V, double* b, hipStream_t s) {
+  const int L = h->L;
+  const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
+  const double eps = h->prm.eps_out / h->prm.eps_in, kappa = RHS ? 0.0 : h->prm.kappa;
+  const double4* q4 = reinterpret_cast<const double4*>(chg);
+  Tmp* W = h->tc_ws;   // pn[2], pc[2], acc, nch, aoff, koff, part, list
+  int64_t M = nc * (int64_t)lv.n[l0];
+  if (M > TC_MAX_PAIRS) return set_error(FAGBI_E_ARG, "treecode: too many (charge, cluster) pairs on one level");
+  int cur = 0;
+  FAGBI_TRY(tc_grow(W[0], (size_t)M * 4));
+  FAGBI_TRY(tc_grow(W[2], (size_t)M * 4));
+  k_tc_init<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(M, lv.n[l0], W[0].as<int32_t>(), W[2].as<int32_t>());
+  for (int l = l0; l <= L && M > 0; ++l) {
+    FAGBI_TRY(tc_grow(W[4], (size_t)M * 4));
+    FAGBI_TRY(tc_grow(W[5], (size_t)M * 4));
+    FAGBI_TRY(tc_grow(W[6], (size_t)(M + 1) * 8));
+    FAGBI_TRY(tc_grow(W[7], (size_t)(M + 1) * 8));
+    FAGBI_TRY(tc_grow(W[8], (size_t)scan_part_size(M) * 8));
+    int32_t *pn = W[cur].as<int32_t>(), *pc = W[2 + cur].as<int32_t>();
+    int32_t *acc = W[4].as<int32_t>(), *nch = W[5].as<int32_t>();
+    int64_t *aoff = W[6].as<int64_t>(), *koff = W[7].as<int64_t>(), *part = W[8].as<int64_t>();
+    const unsigned gm = (unsigned)((M + 255) / 256);
+    k_tc_classify<RHS><<<gm, 256, 0, s>>>(lv, l, L, theta * theta, kappa, eps, corner, q4, M, pn, pc,
+                                          h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
+                                          h->d_perm.as<int32_t>(), h->d_leaf_start.as<int32_t>(),
+                                          h->d_leaf_cnt.as<int32_t>(), h->N, x, V, b, acc, nch);
+    FAGBI_TRY((device_scan<int32_t, int64_t>(acc, M, aoff, part, s)));
+    FAGBI_TRY((device_scan<int32_t, int64_t>(nch, M, koff, part, s)));
+    int64_t tot[2];
+    FAGBI_HIP(hipMemcpyAsync(&tot[0], aoff + M, 8, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipMemcpyAsync(&tot[1], koff + M, 8, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipStreamSynchronize(s));
+    const int64_t nacc = tot[0], Mn = tot[1];
+    if (nacc > 0) {
+      FAGBI_TRY(tc_grow(W[9], (size_t)nacc * 8));
+      int64_t* list = W[9].as<int64_t>();
+      k_tc_compact<<<gm, 256, 0, s>>>(M, acc, aoff, list);
+      const int p = lv.pt[l], ng = p <= 4 ? 4 : p <= 6 ? 2 : 1;
+      k_tc_far<RHS><<<(unsigned)((nacc + ng - 1) / ng), 64, 0, s>>>(lv, l, kappa, corner, q4, list, nacc, pn, pc,
+                                                                    V);
+    }
+    if (Mn > TC_MAX_PAIRS)
+      return set_error(FAGBI_E_ARG, "treecode: too many (charge, cluster) pairs on one level (theta too small)");
+    if (Mn > 0) {
+      // the other pair buffers hold nothing live now
+      FAGBI_TRY(tc_grow(W[1 - cur], (size_t)Mn * 4));
+      FAGBI_TRY(tc_grow(W[3 - cur], (size_t)Mn * 4));
+      k_tc_expand<<<gm, 256, 0, s>>>(lv, l, M, pn, pc, nch, koff, W[1 - cur].as<int32_t>(),
+                                     W[3 - cur].as<int32_t>());
+    }
+    FAGBI_HIP(hipGetLastError());
+    cur = 1 - cur;
+    M = Mn;
+  }
+  return 0;
+}
+
+int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta, int p_max,
+                        double* qv, hipStream_t s) {
   const int L = h->L, l0 = std::min(h->lmin, h->L);
   // moments of x: leaf moments and the upward pass, FP64
   double* xt = h->d_xt.as<double>();
@@ -1654,60 +1753,31 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
   FAGBI_TRY(launch_p2m<double>(h, h->d_ms64.as<double>(), h->d_md64.as<double>(), xt, false, s));
   for (int l = L - 1; l >= l0; --l) FAGBI_TRY(launch_m2m<double>(h, l, false, s));
   TcLevels lv;
-  FAGBI_TRY(tc_levels(h, l0, lv));
-  Tmp flag;
-  FAGBI_TRY(flag.alloc(4));
-  const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
-  const double eps = h->prm.eps_out / h->prm.eps_in;
-  for (int big = 0; big < 2; ++big) {
-    FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
-    auto ker = big ? k_treecode<false, TC_CAP> : k_treecode<false, TC_CAP_SMALL>;
-    ker<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, h->prm.kappa, eps, corner,
-                                    reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
-                                    h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
-                                    h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, x, qv, nullptr,
-                                    flag.as<int>());
-    FAGBI_HIP(hipGetLastError());
-    int of = 0;
-    FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
-    FAGBI_HIP(hipStreamSynchronize(s));
-    if (!of) return 0;
-  }
-  return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
-                                "(theta too small for this tree)");
+  FAGBI_TRY(tc_levels(h, l0, p_max, lv));
+  Tmp V;
+  FAGBI_TRY(V.alloc((size_t)nc * 8));
+  FAGBI_HIP(hipMemsetAsync(V.p, 0, (size_t)nc * 8, s));
+  FAGBI_TRY(tc_visit<false>(h, lv, l0, chg, nc, theta, x, V.as<double>(), nullptr, s));
+  k_tc_qv<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(reinterpret_cast<const double4*>(chg), V.as<double>(), nc,
+                                                        qv);
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_HIP(hipStreamSynchronize(s));
+  return 0;
 }
 
 // b (caller order, f64[2N]) by the reverse treecode; chg holds x, y, z and
-// q / (4 pi eps_in) per charge.  The locals are accumulated with atomics, so
-// the summation order (not the value beyond rounding) varies between runs.
-int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, double* b, hipStream_t s) {
+// q / (4 pi eps_in) per charge
+int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, int p_max, double* b, hipStream_t s) {
   const int L = h->L, l0 = std::min(h->lmin, h->L);
   TcLevels lv;
-  FAGBI_TRY(tc_levels(h, l0, lv));
-  Tmp flag;
-  FAGBI_TRY(flag.alloc(4));
-  const double3 corner = make_double3(h->corner[0], h->corner[1], h->corner[2]);
-  int of = 1;
-  for (int big = 0; big < 2 && of; ++big) {
-    FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
-    for (int l = l0; l <= L; ++l) {
-      Level& D = h->lev[l];
-      for (int ch = 0; ch < 2; ++ch)
-        FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
-    }
-    FAGBI_HIP(hipMemsetAsync(flag.p, 0, 4, s));
-    auto ker = big ? k_treecode<true, TC_CAP> : k_treecode<true, TC_CAP_SMALL>;
-    ker<<<(unsigned)nc, 64, 0, s>>>(lv, l0, L, theta * theta, 0.0, 1.0, corner,
-                                    reinterpret_cast<const double4*>(chg), (int)nc, h->d_pv.as<double>(),
-                                    h->d_pn.as<double>(), h->d_pa.as<double>(), h->d_perm.as<int32_t>(),
-                                    h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->N, nullptr,
-                                    nullptr, b, flag.as<int>());
-    FAGBI_HIP(hipGetLastError());
-    FAGBI_HIP(hipMemcpyAsync(&of, flag.p, 4, hipMemcpyDeviceToHost, s));
-    FAGBI_HIP(hipStreamSynchronize(s));
+  FAGBI_TRY(tc_levels(h, l0, p_max, lv));
+  FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
+  for (int l = l0; l <= L; ++l) {
+    Level& D = h->lev[l];
+    for (int ch = 0; ch < 2; ++ch)
+      FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
   }
-  if (of) return set_error(FAGBI_E_ARG, "treecode: more than 2048 clusters of one level for one charge "
-                                        "(theta too small for this tree)");
+  FAGBI_TRY(tc_visit<true>(h, lv, l0, chg, nc, theta, nullptr, nullptr, b, s));
   for (int l = l0; l < L; ++l) FAGBI_TRY(launch_l2l<double>(h, l, false, s));
   Level& LF = h->lev[L];
   k_l2p_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_ms64.as<double>(), h->d_md64.as<double>(),

@@ -110,6 +110,10 @@ struct fagbi_handle {
   fagbi::DBuf d_perm, d_pv, d_pn, d_pa, d_ptri, d_leaf_of;
   fagbi::DBuf d_pc;                   // per panel: centroid, sqrt(area)
   fagbi::DBuf d_xt;                   // matvec input in tree order [2N]
+  // treecode work lists, grown as needed and kept: (charge, cluster) pairs
+  // of a level [2 x 2], decisions, child counts, their scans, scan scratch,
+  // accepted pair list
+  fagbi::Tmp tc_ws[10];
   fagbi::DBuf d_fmm_pool;             // one allocation behind all far-field tables and expansions
   fagbi::DBuf d_leaf_start, d_leaf_cnt, d_src_off, d_ent_off, d_src_tree, d_self_col;
   fagbi::DBuf d_lnbr_off, d_lnbr, d_lnbr_col;  // leaf neighbour lists, column of each block
@@ -191,12 +195,13 @@ int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* 
 int energy(fagbi_handle* h, const double* x, const double* xq, const double* q,
            int64_t nc, double* E, hipStream_t s);
 int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc,
-                    double theta, double* E, hipStream_t s);
+                    double theta, int p_max, double* E, hipStream_t s);
 int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta,
-                        double* qv, hipStream_t s);
-int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
+                        int p_max, double* qv, hipStream_t s);
+int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, int p_max,
+                 double* b, hipStream_t s);
+int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, int p_max, double* b,
                  hipStream_t s);
-int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, double* b, hipStream_t s);
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
           fagbi_solve_info* info, hipStream_t s);
 void gauss_legendre01(int n, double* x, double* w);

@@ -234,26 +234,26 @@ int energy(fagbi_handle* h, const double* x, const double* xq, const double* q, 
 }
 
 // b by the reverse treecode (the charges carry q / (4 pi eps_in))
-int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, double* b,
-                 hipStream_t s) {
+int rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta, int p_max,
+                 double* b, hipStream_t s) {
   if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
   std::vector<double> qs(nc);
   for (int64_t k = 0; k < nc; ++k) qs[k] = q[k] / (FOUR_PI * h->prm.eps_in);
   Tmp chg;
   FAGBI_TRY(upload_charges(chg, xq, qs.data(), nc));
-  return treecode_rhs(h, chg.as<double>(), nc, theta, b, s);
+  return treecode_rhs(h, chg.as<double>(), nc, theta, p_max, b, s);
 }
 
 // E by the Cartesian treecode: per-charge terms q_n V_n on the GPU, then the
 // fixed-order sum
 int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc, double theta,
-                    double* E, hipStream_t s) {
+                    int p_max, double* E, hipStream_t s) {
   if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
   Tmp chg, qv, out;
   FAGBI_TRY(upload_charges(chg, xq, q, nc));
   FAGBI_TRY(qv.alloc((size_t)nc * 8));
   FAGBI_TRY(out.alloc(8));
-  FAGBI_TRY(treecode_potentials(h, x, chg.as<double>(), nc, theta, qv.as<double>(), s));
+  FAGBI_TRY(treecode_potentials(h, x, chg.as<double>(), nc, theta, p_max, qv.as<double>(), s));
   k_sum<<<1, RB, 0, s>>>(qv.as<double>(), (int)nc, out.as<double>());
   FAGBI_HIP(hipGetLastError());
   double tot = 0;
@@ -400,7 +400,7 @@ int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double
   Tmp b, r;
   FAGBI_TRY(b.alloc(n * 8));
   if (h->prm.rhs_theta > 0)
-    FAGBI_TRY(rhs_treecode(h, xq, q, nc, h->prm.rhs_theta, b.as<double>(), s));
+    FAGBI_TRY(rhs_treecode(h, xq, q, nc, h->prm.rhs_theta, h->prm.rhs_pmax, b.as<double>(), s));
   else
     FAGBI_TRY(rhs(h, xq, q, nc, b.as<double>(), s));
   FAGBI_HIP(hipStreamSynchronize(s));

@@ -67,7 +67,7 @@ def test_single_leaf_mesh():
     h.close()
 
 
-def test_full_size_sampled_charges_and_capacity():
+def test_full_size_sampled_charges_and_pair_limit():
     w = workload("ellipsoid500k")
     P = panels(w["verts"], w["tris"])
     prm = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8)
@@ -85,9 +85,14 @@ def test_full_size_sampled_charges_and_capacity():
         E = h.solvation_energy_treecode(xd, xq, q, theta)
         Eo = otc.energy(Fo, x, xq, q, theta)
         assert abs(E - Eo) <= 1e-11 * abs(Eo), theta
-    # theta = 0 would need every cluster of a level in one frontier: refused
+    # theta = 0 visits every leaf: the direct sum, also on the big tree
+    E0 = h.solvation_energy_treecode(xd, xq[:2], q[:2], 0.0)
+    Ed = h.solvation_energy(xd, xq[:2], q[:2])
+    assert abs(E0 - Ed) <= 1e-12 * abs(Ed)
+    # with every charge it would need more than 2^26 (charge, cluster) pairs on
+    # one level: refused on the host, before any allocation
     with pytest.raises(F.FagbiError) as e:
-        h.solvation_energy_treecode(xd, xq[:2], q[:2], 0.0)
+        h.solvation_energy_treecode(xd, w["xq"], w["q"], 0.0)
     assert e.value.code == -1
     # the handle is still usable
     assert np.isfinite(h.solvation_energy_treecode(xd, xq[:2], q[:2], 0.5))
@@ -158,3 +163,27 @@ def test_rhs_full_size_sampled_charges_and_solve():
         hs.close()
     print("energy with the treecode RHS against the direct RHS: %.2e" % (abs(E[0.5] - E[0.0]) / abs(E[0.0])))
     assert abs(E[0.5] - E[0.0]) < 1e-4 * abs(E[0.0])
+
+
+def test_order_cap_matches_oracle():
+    v, t = icosphere(3, 10.0)
+    P = panels(v, t)
+    prm = dict(leaf_size=8, eta0=0.8, p_leaf=3, adaptive=1, p_max=8)
+    h = F.Handle(eps_in=2.0, eps_out=EPS_OUT, kappa=KAP, **prm)
+    h.build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, 8, 0.8)
+    Fo = ofmm.setup(P, tr, EPS_OUT / 2.0, KAP, p_leaf=3, adaptive=1, p_max=8, with_near=False)
+    rng = np.random.default_rng(12)
+    x = smooth_x(P, 10.0)
+    xq = rng.uniform(-5.0, 5.0, (40, 3))
+    q = rng.standard_normal(40)
+    xd = torch.tensor(x, device=DEV)
+    b = torch.empty(2 * P.n, dtype=torch.float64, device=DEV)
+    for cap in (3, 5):
+        E = h.solvation_energy_treecode(xd, xq, q, 0.4, p_max=cap)
+        Eo = otc.energy(Fo, x, xq, q, 0.4, p_max=cap)
+        assert abs(E - Eo) <= 1e-11 * abs(Eo), cap
+        h.rhs_treecode(xq, q, 0.4, b, p_max=cap)
+        bo = otc.rhs(Fo, xq, q, 0.4, 2.0, p_max=cap)
+        assert np.abs(b.cpu().numpy() - bo).max() <= 1e-11 * np.abs(bo).max(), cap
+    h.close()

@@ -104,3 +104,19 @@ def test_rhs_converges_with_order_and_theta(sphere):
     F = setup(P, tr, 5)
     et = [np.linalg.norm(otc.rhs(F, xq, q, th, 1.0) - bd) / np.linalg.norm(bd) for th in (0.7, 0.5, 0.3)]
     assert et[0] > et[1] > et[2], et
+
+
+def test_order_cap(sphere):
+    """a cap at or above every level's order is no cap; a cap p evaluates the
+    same terms as moments of order p on every level above it"""
+    P, tr, x, xq, q, Vd = sphere
+    F = setup(P, tr, 3, 1)
+    assert otc.energy(F, x, xq, q, 0.4, p_max=8) == otc.energy(F, x, xq, q, 0.4)
+    Fc = setup(P, tr, 4, 0)   # fixed order 4 on every level
+    E4 = otc.energy(Fc, x, xq, q, 0.4)
+    Fa = setup(P, tr, 4, 1)   # orders 4.. upwards, capped at 4
+    assert abs(otc.energy(Fa, x, xq, q, 0.4, p_max=4) - E4) <= 1e-12 * abs(E4)
+    # capped locals are polynomials of degree 4: LtL shifts them exactly, so
+    # the right-hand side equals the fixed-order one too
+    b4 = otc.rhs(Fc, xq, q, 0.4, 1.0)
+    assert np.abs(otc.rhs(Fa, xq, q, 0.4, 1.0, p_max=4) - b4).max() <= 1e-12 * np.abs(b4).max()
