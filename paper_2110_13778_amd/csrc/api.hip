@@ -2,7 +2,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -59,15 +64,108 @@ void gauss_legendre01(int n, double* x, double* w) {
 
 using namespace fagbi;
 
-int Tmp::alloc(size_t n) {
-  release();
+namespace fagbi {
+namespace {
+
+// size class: multiples of 2 MiB from 2 MiB on, powers of two (>= 256 B) below
+size_t size_class(size_t n) {
+  constexpr size_t big = (size_t)2 << 20;
+  if (n >= big) return (n + big - 1) / big * big;
+  size_t c = 256;
+  while (c < n) c <<= 1;
+  return c;
+}
+
+struct DevCache {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;   // (device, class) -> blocks
+  std::unordered_map<void*, std::pair<int, size_t>> live;             // block -> (device, class)
+  size_t cached = 0;
+  // caller holds mu; returns every cached block of this device to HIP
+  void trim(int dev) {
+    for (auto it = free_blocks.begin(); it != free_blocks.end();) {
+      if (it->first.first != dev) {
+        ++it;
+        continue;
+      }
+      for (void* b : it->second) {
+        (void)hipFree(b);
+        cached -= it->first.second;
+      }
+      it = free_blocks.erase(it);
+    }
+  }
+};
+
+// never destroyed: blocks still cached at exit go back with the process
+DevCache& cache() {
+  static DevCache* c = new DevCache();
+  return *c;
+}
+
+constexpr size_t kCacheCap = (size_t)64 << 30;   // cached bytes kept, at most
+
+}  // namespace
+
+int dev_alloc(void** p, size_t n) {
+  *p = nullptr;
   if (n == 0) return 0;
-  hipError_t e = hipMalloc(&p, n);
+  int dev = 0;
+  FAGBI_HIP(hipGetDevice(&dev));
+  const size_t c = size_class(n);
+  DevCache& C = cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  auto it = C.free_blocks.find({dev, c});
+  if (it != C.free_blocks.end() && !it->second.empty()) {
+    FAGBI_HIP(hipDeviceSynchronize());   // every earlier use of the block has finished
+    *p = it->second.back();
+    it->second.pop_back();
+    C.cached -= c;
+    C.live[*p] = {dev, c};
+    return 0;
+  }
+  hipError_t e = hipMalloc(p, c);
   if (e != hipSuccess) {
-    p = nullptr;
+    (void)hipGetLastError();
+    FAGBI_HIP(hipDeviceSynchronize());
+    C.trim(dev);
+    e = hipMalloc(p, c);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
     (void)hipGetLastError();
     return set_error(FAGBI_E_OOM, "device allocation of %zu bytes failed: %s", n, hipGetErrorString(e));
   }
+  C.live[*p] = {dev, c};
+  return 0;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  DevCache& C = cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  auto it = C.live.find(p);
+  if (it == C.live.end()) return;
+  const auto key = it->second;
+  C.live.erase(it);
+  C.free_blocks[key].push_back(p);
+  C.cached += key.second;
+  if (C.cached > kCacheCap) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(key.first);
+    (void)hipDeviceSynchronize();
+    C.trim(key.first);
+    (void)hipSetDevice(cur);
+  }
+}
+
+}  // namespace fagbi
+
+int Tmp::alloc(size_t n) {
+  release();
+  if (n == 0) return 0;
+  FAGBI_TRY(dev_alloc(&p, n));
   bytes = n;
   return 0;
 }
@@ -76,7 +174,7 @@ int Tmp::alloc(size_t n) {
 // the handle (or of one of its levels), registered once for free_all()
 int fagbi_handle::alloc(DBuf& b, size_t bytes) {
   if (b.p) {
-    (void)hipFree(b.p);
+    dev_free(b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -84,13 +182,7 @@ int fagbi_handle::alloc(DBuf& b, size_t bytes) {
   for (DBuf* o : owned) known |= (o == &b);
   if (!known) owned.push_back(&b);
   if (bytes == 0) return 0;
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    (void)hipGetLastError();
-    return set_error(FAGBI_E_OOM, "device allocation of %zu bytes failed: %s", bytes,
-                     hipGetErrorString(e));
-  }
+  FAGBI_TRY(dev_alloc(&b.p, bytes));
   b.bytes = bytes;
   return 0;
 }
@@ -103,7 +195,7 @@ int fagbi_handle::upload(DBuf& b, const void* host, size_t bytes) {
 
 void fagbi_handle::free_all() {
   for (DBuf* b : owned) {
-    if (b->p) (void)hipFree(b->p);
+    if (b->p) dev_free(b->p);
     b->p = nullptr;
     b->bytes = 0;
   }

@@ -43,6 +43,13 @@ struct DBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// device memory through a process-wide cache: freed blocks are kept per
+// device and size class and handed out again (after a device
+// synchronisation, so no kernel still uses them); the cache returns its
+// blocks to HIP when it holds more than a cap or an allocation fails
+int dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+
 // scratch device memory owned by a scope (freed on destruction)
 struct Tmp {
   void* p = nullptr;
@@ -52,7 +59,7 @@ struct Tmp {
   Tmp& operator=(const Tmp&) = delete;
   ~Tmp() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     bytes = 0;
   }
