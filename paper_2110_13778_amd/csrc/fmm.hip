@@ -26,7 +26,6 @@
 // (deterministic in FP64).
 #include <algorithm>
 #include <cstring>
-#include <thread>
 #include <cmath>
 
 #include "internal.h"
@@ -842,6 +841,66 @@ __global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restric
 // All tables and expansion arrays of the far field live in one device
 // allocation: the host side is packed into one staging buffer and copied
 // with one transfer; the DBufs are views into the pool (not owned).
+// Taylor coefficients of one offset by the recurrence above (one thread per
+// offset and channel: kappa = 0 for G0), written as D_g = g! F_g / (4 pi)
+// into the interleaved {G0, Gk} tables, FP64 and FP32
+__global__ void __launch_bounds__(64) k_taylor_table(int n_off, const int32_t* __restrict__ off, double h,
+                                                     double kappa, int p, int T, double* dt, float* dt32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * n_off) return;
+  const int o = i >> 1, ch = i & 1;
+  const double ka = ch ? kappa : 0.0;
+  const double x0[3] = {off[3 * o] * h, off[3 * o + 1] * h, off[3 * o + 2] * h};
+  double F[TMAX], H[TMAX];
+  const double r2 = x0[0] * x0[0] + x0[1] * x0[1] + x0[2] * x0[2];
+  const double r0 = sqrt(r2);
+  F[0] = exp(-ka * r0) / r0;
+  H[0] = exp(-ka * r0);
+  for (int d = 1; d <= p; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) {
+        const int c = d - a - b;
+        const int k[3] = {a, b, c};
+        double s1f = 0, s2f = 0, s1h = 0, s2h = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+          if (k[ax] >= 1) {
+            const int id = midx(a - (ax == 0), b - (ax == 1), c - (ax == 2));
+            s1f += x0[ax] * F[id];
+            s1h += x0[ax] * H[id];
+          }
+          if (k[ax] >= 2) {
+            const int id = midx(a - 2 * (ax == 0), b - 2 * (ax == 1), c - 2 * (ax == 2));
+            s2f += F[id];
+            s2h += H[id];
+          }
+        }
+        const int id = midx(a, b, c);
+        F[id] = (-ka * (s1h + s2h) - (2 * d - 1) * s1f - (d - 1) * s2f) / (d * r2);
+        H[id] = -ka * (s1f + s2f) / d;
+      }
+  for (int d = 0; d <= p; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) {
+        const int c = d - a - b, g = midx(a, b, c);
+        double f = 1.0 / FOUR_PI;
+        for (int q = 2; q <= a; ++q) f *= q;
+        for (int q = 2; q <= b; ++q) f *= q;
+        for (int q = 2; q <= c; ++q) f *= q;
+        const double v = f * F[g];
+        dt[2 * ((int64_t)o * T + g) + ch] = v;
+        dt32[2 * ((int64_t)o * T + g) + ch] = (float)v;
+      }
+}
+
+// the FP32 table rows of one offset of each opposite pair
+__global__ void k_half_rows(const int32_t* __restrict__ rows, int n_half, int T, const float* __restrict__ full,
+                            float* half) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_half * 2 * T) return;
+  const int64_t k = i / (2 * T), r = i - k * 2 * T;
+  half[i] = full[(int64_t)rows[k] * 2 * T + r];
+}
+
 struct Staging {
   struct Item {
     DBuf* b;
@@ -984,34 +1043,11 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
       }
     }
     // derivative tables per offset, D_g = g! F_g / (4 pi), channels
-    // interleaved {G0, Gk}
+    // interleaved {G0, Gk}: computed on the device after the upload
     if (l >= h->lmin && D.n_off > 0) {
-      std::vector<double> dt((size_t)2 * D.n_off * D.T), gf(D.T);
-      for (int g = 0; g < D.T; ++g) {
-        const MI G = mi_of(g);
-        gf[g] = fact(G.a[0]) * fact(G.a[1]) * fact(G.a[2]) / FOUR_PI;
-      }
-      // offsets split over host threads (independent recurrences)
-      const int nth = (int)std::max(1u, std::min(16u, std::min(std::thread::hardware_concurrency(),
-                                                                (unsigned)(D.n_off / 32 + 1))));
-      std::vector<std::thread> pool;
-      for (int t = 0; t < nth; ++t)
-        pool.emplace_back([&, t] {
-          std::vector<double> f0(D.T), fk(D.T);
-          for (int o = (int)((int64_t)D.n_off * t / nth); o < (int)((int64_t)D.n_off * (t + 1) / nth); ++o) {
-            const double x0[3] = {D.off_xyz[3 * o] * D.h, D.off_xyz[3 * o + 1] * D.h,
-                                  D.off_xyz[3 * o + 2] * D.h};
-            taylor_host(x0, 0.0, D.order, f0.data());
-            taylor_host(x0, h->prm.kappa, D.order, fk.data());
-            for (int g = 0; g < D.T; ++g) {
-              dt[2 * ((size_t)o * D.T + g)] = gf[g] * f0[g];
-              dt[2 * ((size_t)o * D.T + g) + 1] = gf[g] * fk[g];
-            }
-          }
-        });
-      for (auto& th : pool) th.join();
-      st.add_conv<double>(D.d_F64[0], dt);
-      st.add_conv<float>(D.d_F32[0], dt);
+      st.add(D.d_off, D.off_xyz.data(), D.off_xyz.size() * 4);
+      st.reserve(D.d_F64[0], (size_t)2 * D.n_off * D.T * 8);
+      st.reserve(D.d_F32[0], (size_t)2 * D.n_off * D.T * 4);
       // one of each pair of opposite offsets (first non-zero component > 0)
       // for the LDS-staged kernels, and the map oid -> row | flip << 30
       std::vector<int32_t> omap(D.n_off, -1), rows;
@@ -1036,10 +1072,8 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
       for (int o = 0; o < D.n_off && ok; ++o) ok = omap[o] >= 0;
       D.n_half = 0;
       if (ok) {
-        std::vector<double> dh((size_t)2 * rows.size() * D.T);
-        for (size_t k = 0; k < rows.size(); ++k)
-          for (int g = 0; g < 2 * D.T; ++g) dh[2 * k * D.T + g] = dt[(size_t)2 * rows[k] * D.T + g];
-        st.add_conv<float>(D.d_F32[1], dh);
+        st.add(D.d_rows, rows.data(), rows.size() * 4);
+        st.reserve(D.d_F32[1], (size_t)2 * rows.size() * D.T * 4);
         st.add(D.d_oid_map, omap.data(), omap.size() * 4);
         D.n_half = (int)rows.size();
       }
@@ -1060,6 +1094,19 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
   st.reserve(h->d_ms32, NT * 4);
   st.reserve(h->d_md32, NT * 4);
   FAGBI_TRY(st.commit(h, h->d_fmm_pool));
+  for (int l = std::max(lo, h->lmin); l <= h->L; ++l) {
+    Level& D = h->lev[l];
+    if (D.n_off == 0) continue;
+    k_taylor_table<<<(unsigned)((2 * D.n_off + 63) / 64), 64, 0, s>>>(
+        D.n_off, D.d_off.as<int32_t>(), D.h, h->prm.kappa, D.order, D.T, D.d_F64[0].as<double>(),
+        D.d_F32[0].as<float>());
+    if (D.n_half > 0) {
+      const int64_t m = (int64_t)D.n_half * 2 * D.T;
+      k_half_rows<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
+                                                             D.d_F32[0].as<float>(), D.d_F32[1].as<float>());
+    }
+  }
+  FAGBI_HIP(hipGetLastError());
   const unsigned grid = (unsigned)((NT + 255) / 256);
   k_panel_moments<double><<<grid, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                                                 h->d_leaf_of.as<int32_t>(), LF.d_idx.as<int32_t>(), h->corner[0],

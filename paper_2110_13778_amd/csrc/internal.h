@@ -82,6 +82,7 @@ struct Level {
   // table of one offset of each opposite pair [n_half][T] (index 1) with the
   // map oid -> row | flip << 30
   DBuf d_F64[2], d_F32[2], d_oid_map;
+  DBuf d_off, d_rows;   // offsets [n_off][3] and the half table's rows, for the table kernels
   int n_half = 0;
   DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
   DBuf d_M32[2], d_L32[2];
