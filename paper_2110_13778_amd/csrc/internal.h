@@ -240,6 +240,44 @@ __device__ inline float wave_sum(float v) {
 
 // the six pair integrands at separation r = x - y with normals nx (target),
 // ny (source): G0-Gk, dG0/dny, dGk/dny, dG0/dnx, dGk/dnx, d2(Gk-G0)/dnx dny
+// the six kernels from r^2, r.n_x, r.n_y and n_x.n_y (the innermost loops of
+// the cubature, where r = R0 + t R1, form these as polynomials in t)
+__device__ inline void kernel6s(double r2, double rnx, double rny, double nn, double kappa, double* k) {
+  const double ir = inv_sqrt(r2);
+  const double u = kappa * (r2 * ir);
+  double E, em1;
+  exp_expm1(-u, E, em1);
+  const double i4pr = ir * (1.0 / FOUR_PI);
+  const double ir2 = ir * ir;
+  const double i4pr3 = i4pr * ir2;
+  const double e1u = E * (1.0 + u);
+  k[0] = -em1 * i4pr;
+  k[1] = rny * i4pr3;
+  k[2] = e1u * rny * i4pr3;
+  k[3] = -rnx * i4pr3;
+  k[4] = -e1u * rnx * i4pr3;
+  const double c1 = em1 + u * E;
+  const double c2 = 3.0 * em1 + 3.0 * u * E + u * u * E;
+  k[5] = (c1 * nn - c2 * rnx * rny * ir2) * i4pr3;
+}
+
+// r = R0 + t R1 on the innermost cubature axis: r^2 = a + t (b + t c),
+// r.n_x = p0 + t p1, r.n_y = q0 + t q1
+struct LinSep {
+  double a, b, c, p0, p1, q0, q1;
+};
+__device__ inline LinSep lin_sep(const double* R0, const double* R1, const double* nx, const double* ny) {
+  LinSep L;
+  L.a = R0[0] * R0[0] + R0[1] * R0[1] + R0[2] * R0[2];
+  L.b = 2.0 * (R0[0] * R1[0] + R0[1] * R1[1] + R0[2] * R1[2]);
+  L.c = R1[0] * R1[0] + R1[1] * R1[1] + R1[2] * R1[2];
+  L.p0 = R0[0] * nx[0] + R0[1] * nx[1] + R0[2] * nx[2];
+  L.p1 = R1[0] * nx[0] + R1[1] * nx[1] + R1[2] * nx[2];
+  L.q0 = R0[0] * ny[0] + R0[1] * ny[1] + R0[2] * ny[2];
+  L.q1 = R1[0] * ny[0] + R1[1] * ny[1] + R1[2] * ny[2];
+  return L;
+}
+
 __device__ inline void kernel6(double rx, double ry, double rz, const double* nx,
                                const double* ny, double kappa, double* k) {
   const double r2 = rx * rx + ry * ry + rz * rz;

@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
   double acc[6] = {0, 0, 0, 0, 0, 0};
   double k6[6];
   const int n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  const double nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
   if (CLS == C_IDENT) {
     double e1[3], e2[3];
     for (int d = 0; d < 3; ++d) {
@@ -184,9 +185,10 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
         R0[d] = -z0 * e[d] + x0 * av[d] - y0 * bv[d];
         R1[d] = -z1c * e[d] + x1 * av[d] - y1 * bv[d];
       }
+      const LinSep L = lin_sep(R0, R1, ni, nj);
       for (int ic = 0; ic < n; ++ic) {
         const double w2 = gx[ic], w = wb * gw[ic];
-        kernel6(R0[0] + w2 * R1[0], R0[1] + w2 * R1[1], R0[2] + w2 * R1[2], ni, nj, a.kappa, k6);
+        kernel6s(fma(w2, fma(w2, L.c, L.b), L.a), fma(w2, L.p1, L.p0), fma(w2, L.q1, L.q0), nn, a.kappa, k6);
         for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
       }
     }
@@ -219,9 +221,10 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
         R0[d] = sa * (A0[d] + t1 * A1[d]) - sb * B0[d];
         R1[d] = -sb * B1[d];
       }
+      const LinSep L = lin_sep(R0, R1, ni, nj);
       for (int id = 0; id < n; ++id) {
         const double t2 = gx[id], w = wb * gw[id];
-        kernel6(R0[0] + t2 * R1[0], R0[1] + t2 * R1[1], R0[2] + t2 * R1[2], ni, nj, a.kappa, k6);
+        kernel6s(fma(t2, fma(t2, L.c, L.b), L.a), fma(t2, L.p1, L.p0), fma(t2, L.q1, L.q0), nn, a.kappa, k6);
         for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
       }
     }
@@ -238,9 +241,10 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
         R0[d] = x - (cj[d] + s2 * (cj[3 + d] - cj[d]));
         R1[d] = -s2 * (cj[6 + d] - cj[3 + d]);
       }
+      const LinSep L = lin_sep(R0, R1, ni, nj);
       for (int id = 0; id < n; ++id) {
         const double t2 = gx[id], w = wb * gw[id];
-        kernel6(R0[0] + t2 * R1[0], R0[1] + t2 * R1[1], R0[2] + t2 * R1[2], ni, nj, a.kappa, k6);
+        kernel6s(fma(t2, fma(t2, L.c, L.b), L.a), fma(t2, L.p1, L.p0), fma(t2, L.q1, L.q0), nn, a.kappa, k6);
         for (int m = 0; m < 6; ++m) acc[m] += w * k6[m];
       }
     }
