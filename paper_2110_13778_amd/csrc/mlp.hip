@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "near.h"
+#include "scan.h"
 
 namespace fagbi {
 
@@ -331,7 +332,34 @@ __global__ void k_colstats(const float* __restrict__ D, int64_t rows, int cols, 
 // surrogate entries: I = I3x3 + h^k (t * sd + mu); gate on the calibrated
 // error of (class, distance bin); write entries of gated pairs (or of all
 // pairs when all != 0) and flag gated pairs for the cubature to skip
+// gate of a pair: its class's calibrated error estimate in the bin of its
+// distance ratio is within tol
+__device__ inline bool mlp_gated(const float* __restrict__ cal, int cls_index, float dr, double tol) {
+  const int ci = cls_index - 1;
+  const float* edges = cal + ci * (NBIN + 1);
+  const float* est = cal + NCLS * (NBIN + 1) + ci * NBIN;
+  int b = 0;
+  while (b < NBIN - 1 && dr >= edges[b + 1]) ++b;
+  return est[b] <= tol;
+}
+
+// the pairs whose prediction is used (gated, or every pair with all != 0)
+__global__ void k_mlp_flag(int cls_index, int64_t n, const float* __restrict__ dr, const float* __restrict__ cal,
+                           double tol, int all, int32_t* flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) flag[t] = (all || mlp_gated(cal, cls_index, dr[t], tol)) ? 1 : 0;
+}
+
+// features of the flagged pairs, packed in pair order
+__global__ void k_mlp_pack(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                           const float* __restrict__ X, float* Xp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n || !flag[t]) return;
+  for (int f = 0; f < NIN; ++f) Xp[(int64_t)pos[t] * NIN + f] = X[t * NIN + f];
+}
+
 __global__ void k_mlp_apply(NearArgs a, int cls, int cls_index, const Item* __restrict__ items, int64_t n,
+                            const int32_t* __restrict__ pos,
                             const float* __restrict__ tn, const float* __restrict__ norm, const double* __restrict__ I3,
                             const double* __restrict__ hh, const float* __restrict__ dr, const float* __restrict__ cal,
                             double tol, int all, double4* ent, uint8_t* skip, unsigned long long* n_gated) {
@@ -339,16 +367,13 @@ __global__ void k_mlp_apply(NearArgs a, int cls, int cls_index, const Item* __re
   bool gated = false;
   if (t < n) {
     const int ci = cls_index - 1;
-    const float* edges = cal + ci * (NBIN + 1);
-    const float* est = cal + NCLS * (NBIN + 1) + ci * NBIN;
-    int b = 0;
-    while (b < NBIN - 1 && dr[t] >= edges[b + 1]) ++b;
-    gated = est[b] <= tol;
+    gated = mlp_gated(cal, cls_index, dr[t], tol);
     const Item it = items[t];
     if (gated || all) {
+      const int64_t q = pos[t];   // row of this pair among the predicted ones
       double I[6];
       for (int m = 0; m < 6; ++m)
-        I[m] = I3[t * 6 + m] + hpow(hh[t], m) * ((double)tn[t * NOUT + m] * norm[OUT_SD + ci * NOUT + m] +
+        I[m] = I3[t * 6 + m] + hpow(hh[t], m) * ((double)tn[q * NOUT + m] * norm[OUT_SD + ci * NOUT + m] +
                                                  norm[OUT_MU + ci * NOUT + m]);
       write_pair(a, cls, it.i, it.j, it.ent, I, ent);
     }
@@ -554,8 +579,12 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s) {
   const int64_t CH = 1 << 20;
   int64_t cm = 1;
   for (int k = 1; k < 4; ++k) cm = std::max(cm, std::min<int64_t>(h->wl_n[k], CH));
-  Tmp X, I3, hh, dr, tn;
+  Tmp X, Xp, I3, hh, dr, tn, flag, pos, part;
   FAGBI_TRY(X.alloc((size_t)cm * NIN * 4));
+  FAGBI_TRY(Xp.alloc((size_t)cm * NIN * 4));
+  FAGBI_TRY(flag.alloc((size_t)cm * 4));
+  FAGBI_TRY(pos.alloc((size_t)(cm + 1) * 4));
+  FAGBI_TRY(part.alloc((size_t)scan_part_size(cm) * 4));
   FAGBI_TRY(I3.alloc((size_t)cm * 6 * 8));
   FAGBI_TRY(hh.alloc((size_t)cm * 8));
   FAGBI_TRY(dr.alloc((size_t)cm * 4));
@@ -569,8 +598,18 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s) {
       const unsigned g = (unsigned)((c + 255) / 256);
       k_mlp_prepare<<<g, 256, 0, s>>>(a, k + 1, it, c, X.as<float>(), I3.as<double>(), hh.as<double>(),
                                       dr.as<float>());
-      FAGBI_TRY(infer(h, X.as<float>(), c, 0, tn.as<float>(), s));
-      k_mlp_apply<<<g, 256, 0, s>>>(a, k + 1, k, it, c, tn.as<float>(), norm, I3.as<double>(), hh.as<double>(),
+      // the network runs on the pairs whose prediction is used only
+      k_mlp_flag<<<g, 256, 0, s>>>(k, c, dr.as<float>(), cal, h->prm.mlp_gate_tol, all, flag.as<int32_t>());
+      FAGBI_TRY((device_scan<int32_t, int32_t>(flag.as<int32_t>(), c, pos.as<int32_t>(), part.as<int32_t>(), s)));
+      int32_t np = 0;
+      FAGBI_HIP(hipMemcpyAsync(&np, pos.as<int32_t>() + c, 4, hipMemcpyDeviceToHost, s));
+      FAGBI_HIP(hipStreamSynchronize(s));
+      if (np > 0) {
+        k_mlp_pack<<<g, 256, 0, s>>>(c, flag.as<int32_t>(), pos.as<int32_t>(), X.as<float>(), Xp.as<float>());
+        FAGBI_TRY(infer(h, Xp.as<float>(), np, 0, tn.as<float>(), s));
+      }
+      k_mlp_apply<<<g, 256, 0, s>>>(a, k + 1, k, it, c, pos.as<int32_t>(), tn.as<float>(), norm, I3.as<double>(),
+                                    hh.as<double>(),
                                     dr.as<float>(), cal, h->prm.mlp_gate_tol, all, h->d_E64.as<double4>(),
                                     h->d_mlp_skip[k].as<uint8_t>() + r0, cnt.as<unsigned long long>());
       FAGBI_HIP(hipGetLastError());
