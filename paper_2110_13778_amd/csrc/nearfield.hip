@@ -391,7 +391,10 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
 // [gp[g], gp[g+1]); its block is ordered [phi of the group's panels; dphi of
 // them] and holds every stored near-field entry between them (pairs of
 // leaves that are not neighbours have none: they are far field).
-__global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__ ent, const int32_t* gl,
+// Gauss-Jordan with partial pivoting in LDS; two wavefronts per block, each
+// updating one half of every row's columns (the LDS matrix limits a CU to a
+// few blocks: the second wavefront doubles the work in flight)
+__global__ void __launch_bounds__(128) k_block_invert(const double4* __restrict__ ent, const int32_t* gl,
                                                      const int32_t* gp, const int32_t* leaf_start,
                                                      const int32_t* leaf_cnt, const int64_t* src_off,
                                                      const int64_t* ent_off, const int32_t* lnbr_off,
@@ -404,8 +407,9 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
   const int p0 = gp[g];
   const int ng = gp[g + 1] - p0;
   const int m = 2 * ng;
-  const int r = threadIdx.x;
-  for (int j = 0; j < m; ++j)
+  const int r = threadIdx.x & 63, hf = threadIdx.x >> 6;
+  const int j0 = hf * 32, j1 = min(m, j0 + 32);   // this wavefront's columns
+  for (int j = j0; j < j1; ++j)
     if (r < m) A[r][j] = 0.0;
   __syncthreads();
   for (int c1 = l0; c1 < l1; ++c1) {
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
       const int c2 = lnbr[q];
       if (c2 < l0 || c2 >= l1) continue;
       const int n2 = leaf_cnt[c2], o2 = leaf_start[c2] - p0, col = lnbr_col[q];
-      for (int e = r; e < n1 * n2; e += 64) {
+      for (int e = threadIdx.x; e < n1 * n2; e += 128) {
         const int il = e / n2, jl = e - il * n2;
         const double4 v = ent[eo + (int64_t)il * S + col + jl];
         A[o1 + il][o2 + jl] = v.x;
@@ -436,12 +440,12 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
       const int oi = __shfl_xor(vi, o, 64);
       if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
     }
-    if (r == 0) swp[k] = vi;
-    if (!(v > 0.0)) {
-      if (r == 0) atomicExch(bad, 1);
+    if (threadIdx.x == 0) swp[k] = vi;
+    if (!(v > 0.0)) {   // both wavefronts see the same column
+      if (threadIdx.x == 0) atomicExch(bad, 1);
       return;
     }
-    if (vi != k && r < m) {
+    if (hf == 0 && vi != k && r < m) {
       const double t = A[k][r];
       A[k][r] = A[vi][r];
       A[vi][r] = t;
@@ -449,19 +453,20 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
     __syncthreads();
     const double d = 1.0 / A[k][k];
     __syncthreads();
-    if (r < m) A[k][r] = (r == k ? 1.0 : A[k][r]) * d;
+    if (hf == 0 && r < m) A[k][r] = (r == k ? 1.0 : A[k][r]) * d;
     __syncthreads();
+    const double f = (r < m && r != k) ? A[r][k] : 0.0;
+    __syncthreads();   // both halves have read column k before it is overwritten
     if (r < m && r != k) {
-      const double f = A[r][k];
-      A[r][k] = 0.0;
-      for (int j = 0; j < m; ++j) A[r][j] -= f * A[k][j];
+      if (k >= j0 && k < j1) A[r][k] = 0.0;
+      for (int j = j0; j < j1; ++j) A[r][j] -= f * A[k][j];
     }
     __syncthreads();
   }
   // undo the row interchanges as column interchanges, last first
   for (int k = m - 1; k >= 0; --k) {
     const int p = swp[k];
-    if (p != k && r < m) {
+    if (hf == 0 && p != k && r < m) {
       const double t = A[r][k];
       A[r][k] = A[r][p];
       A[r][p] = t;
@@ -470,7 +475,7 @@ __global__ void __launch_bounds__(64) k_block_invert(const double4* __restrict__
   }
   if (r < m) {
     double* out = inv + inv_off[g];
-    for (int b = 0; b < m; ++b) out[(int64_t)b * m + r] = A[r][b];
+    for (int b = j0; b < j1; ++b) out[(int64_t)b * m + r] = A[r][b];
   }
 }
 
@@ -562,7 +567,7 @@ int precond_setup(fagbi_handle* h, hipStream_t s) {
   Tmp bad;
   FAGBI_TRY(bad.alloc(sizeof(int)));
   FAGBI_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-  k_block_invert<<<ng, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_grp_leaf.as<int32_t>(), h->d_grp_panel.as<int32_t>(),
+  k_block_invert<<<ng, 128, 0, s>>>(h->d_E64.as<double4>(), h->d_grp_leaf.as<int32_t>(), h->d_grp_panel.as<int32_t>(),
                                    h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
                                    h->d_src_off.as<int64_t>(), h->d_ent_off.as<int64_t>(),
                                    h->d_lnbr_off.as<int32_t>(), h->d_lnbr.as<int32_t>(),
