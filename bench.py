@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of k_spmv<float4> from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (calibrated with a device copy of known size); None until measured for the
 # kernel as it stands
-TRAFFIC_SPMV = 1339025613   # FETCH 643,529.1 KiB x 2.0000 + WRITE 20,584.0 KiB x 1.0 per launch
+TRAFFIC_SPMV = 1332068352   # FETCH 640,595.2 KiB x 2.0000 + WRITE 19,657.6 KiB x 1.0 per launch
 # acceptance parameter of the treecode energy (rho_l / R <= theta) and its
 # order cap (terms |b| <= min(p_l, 6))
 ENERGY_THETA = 0.5

@@ -804,9 +804,11 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
     double a[2 * RG];   // rows' first components, then second components
 #pragma unroll
     for (int r = 0; r < 2 * RG; ++r) a[r] = 0.0;
+    int jn = src_tree[so + min(lane, S - 1)];   // the next step's source, loaded one step ahead
     for (int k0 = 0; k0 < S; k0 += 64) {
       const int k = min(k0 + lane, S - 1);
-      const int j = src_tree[so + k];
+      const int j = jn;
+      if (k0 + 64 < S) jn = src_tree[so + min(k0 + 64 + lane, S - 1)];
       E e[RG];
 #pragma unroll
       for (int r = 0; r < RG; ++r) e[r] = base[(int64_t)min(r0 + r, nc - 1) * S + k];
