@@ -1,4 +1,5 @@
 // C ABI entry points, handle lifetime, error reporting and tree upload.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -58,6 +59,85 @@ void gauss_legendre01(int n, double* x, double* w) {
     x[n - 1 - i] = 0.5 * (z + 1.0);
     w[n - 1 - i] = 1.0 / ((1 - z * z) * dp * dp);   // (2/((1-z^2)P'^2)) / 2
   }
+}
+
+// Radial table of one touching class.  Its transform writes the separation as
+// r = xi * rho_hat with Jacobian factor g(xi) (identical: (1 - xi)^2 xi / 2,
+// edge: (1 - xi) xi^2, vertex: xi^3), so with v = kappa * |rho_hat| the
+// xi-rule of each kernel is a fixed power series in v:
+//   T0  = sum_i w_i g(x_i) em1(v x_i) / x_i      em1(u) = e^-u - 1
+//   T1  = sum_i w_i g(x_i) / x_i^2
+//   T2  = sum_i w_i g(x_i) e1u(v x_i) / x_i^2     e1u(u) = e^-u (1 + u)
+//   T5a = sum_i w_i g(x_i) c1(v x_i) / x_i^3      c1 = e1u - 1
+//   T5b = sum_i w_i g(x_i) c2(v x_i) / x_i^3      c2 = 3 c1 + u^2 e^-u
+// with Taylor coefficients (-1)^k / k!, (-1)^k (1 - k) / k!, and
+// (-1)^k (k - 1)(k - 3) / k! of em1, e1u (and c1 from k = 2) and c2, times
+// the moments G_j = sum_i w_i g(x_i) x_i^j.
+static void radial_table(int n, const double* x, const double* w, int cls, double* t) {
+  constexpr int KX = RAD_KMAX + 40;
+  std::vector<double> G(KX + 3);   // G[j + 2], j = -2 .. KX
+  for (int j = -2; j <= KX; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double xi = x[i];
+      const double g = cls == 0 ? 0.5 * (1.0 - xi) * (1.0 - xi) * xi
+                     : cls == 1 ? (1.0 - xi) * xi * xi : xi * xi * xi;
+      s += w[i] * g * std::pow(xi, j);
+    }
+    G[j + 2] = s;
+  }
+  std::vector<double> c(4 * (KX + 1), 0.0);
+  double fact = 1.0;
+  for (int k = 0; k <= KX; ++k) {
+    if (k > 0) fact *= k;
+    const double sg = (k & 1) ? -1.0 : 1.0;
+    if (k >= 1) c[4 * k] = sg / fact * G[k + 1];
+    c[4 * k + 1] = sg * (1.0 - k) / fact * G[k];
+    if (k >= 2) {
+      c[4 * k + 2] = sg * (1.0 - k) / fact * G[k - 1];
+      c[4 * k + 3] = sg * (k - 1.0) * (k - 3.0) / fact * G[k - 1];
+    }
+  }
+  for (int k = 0; k <= RAD_KMAX; ++k)
+    for (int f = 0; f < 4; ++f) t[4 * k + f] = c[4 * k + f];
+  t[RAD_T1] = G[0];
+  // truncation: the largest v at which the tail above degree K is <= 2^-56
+  // of the leading term of every series (leading degrees 1, 0, 2, 2)
+  const int lead[4] = {1, 0, 2, 2};
+  auto ratio = [&](int K, double v) {
+    double r = 0.0;
+    for (int f = 0; f < 4; ++f) {
+      double tail = 0.0;
+      for (int k = KX; k > K; --k) tail = tail * v + std::fabs(c[4 * k + f]);
+      tail *= std::pow(v, K + 1 - lead[f]);
+      r = std::max(r, tail / std::fabs(c[4 * lead[f] + f]));
+    }
+    return r;
+  };
+  for (int K = 0; K <= RAD_KMAX; ++K) {
+    double lo = 0.0, hi = 16.0;
+    if (K >= 2)
+      for (int it = 0; it < 48; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (ratio(K, mid) <= 0x1p-56) lo = mid; else hi = mid;
+      }
+    t[RAD_VK + K] = lo;
+  }
+}
+
+// the table depends on n only: built once per process and order
+void quad_table(int n, double* t) {
+  static std::mutex mu;
+  static std::map<int, std::vector<double>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  std::vector<double>& c = cache[n];
+  if (c.empty()) {
+    c.assign(QT_SIZE, 0.0);
+    gauss_legendre01(n, c.data(), c.data() + 16);
+    for (int cls = 0; cls < 3; ++cls)
+      radial_table(n, c.data(), c.data() + 16, cls, c.data() + QT_RAD + cls * RAD_STRIDE);
+  }
+  std::copy(c.begin(), c.end(), t);
 }
 
 }  // namespace fagbi
@@ -267,8 +347,8 @@ int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
     return set_error(FAGBI_E_HIP, "no HIP device");
   }
   // Gauss-Legendre nodes and weights of the singular/close rules
-  std::vector<double> gl(32, 0.0);
-  gauss_legendre01(p->quad_duffy, gl.data(), gl.data() + 16);
+  std::vector<double> gl(QT_SIZE);
+  quad_table(p->quad_duffy, gl.data());
   int r = h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double));
   if (r < 0) {
     h->free_all();

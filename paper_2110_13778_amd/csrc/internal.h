@@ -213,6 +213,23 @@ int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, i
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
           fagbi_solve_info* info, hipStream_t s);
 void gauss_legendre01(int n, double* x, double* w);
+
+// The quadrature table of the singular and close rules (device d_gl):
+// [0, 16) Gauss-Legendre nodes on [0, 1], [16, 32) weights, then one radial
+// table per touching class (identical, edge, vertex; RAD_STRIDE doubles each):
+// the xi-rule of that class's transform applied to the kernels' functions of
+// u = kappa * xi * rho as power series in v = kappa * rho,
+//   [4 k + f], k = 0..RAD_KMAX, f = T0 (em1), T2 (e^-u (1 + u)), T5a (c1), T5b (c2)
+//   [RAD_T1]   the Laplace double-layer factor (xi-rule of the Jacobian / xi^2)
+//   [RAD_VK + K] the largest v for which the terms above degree K stay below
+//              2^-56 of each series' leading term
+constexpr int RAD_KMAX = 24;
+constexpr int RAD_T1 = 4 * (RAD_KMAX + 1);
+constexpr int RAD_VK = RAD_T1 + 1;
+constexpr int RAD_STRIDE = 128;
+constexpr int QT_RAD = 32;
+constexpr int QT_SIZE = QT_RAD + 3 * RAD_STRIDE;
+void quad_table(int n, double* t);   // t: QT_SIZE doubles
 }  // namespace fagbi
 
 // ---------------------------------------------------------------------------

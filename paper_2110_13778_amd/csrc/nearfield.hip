@@ -100,6 +100,52 @@ __global__ void __launch_bounds__(256) k_near_classify(NearArgs a, int64_t* blk,
     for (int C = 0; C < 4; ++C) blk[(int64_t)C * nl + c] = run[C];
 }
 
+// The touching transforms write the separation as r = xi * R_hat (xi the
+// radial coordinate), so every kernel is a power of xi times a function of
+// u = kappa * xi * |R_hat|: the xi-rule of one ray is a power series in
+// v = kappa * |R_hat| with precomputed coefficients (the class's radial
+// table).  Up to the truncation (below 2^-56 relative, degree K) this is the
+// same tensor-product rule as evaluating the n points of the ray.
+// radial_order: the degree for a pair whose rays all have kappa |R_hat| <= vb,
+// -1 if the table does not reach vb (then the rays are summed point by point).
+// (vb is the same on every lane: one pair per wavefront; the degree is made
+// wave-uniform so that the series loop and its table reads are scalar)
+__device__ inline int radial_order(const double* tab, double vb) {
+  int K = -1;
+  for (int k = RAD_KMAX; k >= 2; --k)
+    if (vb <= tab[RAD_VK + k]) K = k;
+  return __builtin_amdgcn_readfirstlane(K);
+}
+
+// adds the xi-rule of one ray with weight W (the other coordinates' weights)
+__device__ inline void radial_ray(const double* R, const double* nx, const double* ny, double nn, double kappa,
+                                  const double* tab, int K, double W, double* acc) {
+  const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+  const double p = R[0] * nx[0] + R[1] * nx[1] + R[2] * nx[2];
+  const double q = R[0] * ny[0] + R[1] * ny[1] + R[2] * ny[2];
+  const double ir = inv_sqrt(r2);
+  const double v = kappa * (r2 * ir);
+  double t0 = 0.0, t2 = 0.0, t5a = 0.0, t5b = 0.0;
+  for (int k = K; k >= 0; --k) {
+    const double* c = tab + 4 * k;
+    t0 = fma(t0, v, c[0]);
+    t2 = fma(t2, v, c[1]);
+    t5a = fma(t5a, v, c[2]);
+    t5b = fma(t5b, v, c[3]);
+  }
+  const double wi = W * (1.0 / FOUR_PI);
+  const double w3 = wi * ir * ir * ir;
+  const double a1 = w3 * tab[RAD_T1], a2 = w3 * t2;
+  acc[0] -= wi * t0 * ir;
+  acc[1] += a1 * q;
+  acc[2] += a2 * q;
+  acc[3] -= a1 * p;
+  acc[4] -= a2 * p;
+  acc[5] += w3 * (nn * t5a - p * q * (ir * ir) * t5b);
+}
+
+__device__ inline double norm3(const double* a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
 // one wavefront per singular / close pair
 // skip (optional): items already filled in by the surrogate; raw (optional):
 // write the six integrals [n_items][6] instead of operator entries
@@ -132,6 +178,23 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     // hexagon sectors (P_s, Q_s)
     const int HP[6][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}};
     const int HQ[6][2] = {{1, 1}, {0, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, 0}};
+    const double* tab = gl + QT_RAD + (C_IDENT - 1) * RAD_STRIDE;
+    double e12[3];
+    for (int d = 0; d < 3; ++d) e12[d] = e1[d] + e2[d];
+    // z = xi ((1 - t) P_s + t Q_s): |R_hat| <= max over the hexagon's corners
+    const int K = radial_order(tab, a.kappa * fmax(fmax(norm3(e1), norm3(e2)), norm3(e12)));
+    if (K >= 0) {
+      // lanes over (sector, t); xi by the radial table
+      for (int p = lane; p < 6 * n; p += 64) {
+        const int s = p / n, ib = p - s * n;
+        const double t = gx[ib];
+        const double z1 = (1.0 - t) * HP[s][0] + t * HQ[s][0];
+        const double z2 = (1.0 - t) * HP[s][1] + t * HQ[s][1];
+        double R[3];
+        for (int d = 0; d < 3; ++d) R[d] = -(z1 * e1[d] + z2 * e2[d]);
+        radial_ray(R, ni, ni, nn, a.kappa, tab, K, gw[ib], acc);
+      }
+    } else
     for (int p = lane; p < 6 * n2; p += 64) {
       const int s = p / n2, rem = p - s * n2, ia = rem / n, ib = rem - ia * n;
       const double xi = gx[ia], t = gx[ib];
@@ -162,6 +225,28 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
       av[d] = ci[3 * ri + d] - Q;
       bv[d] = cj[3 * rj + d] - Q;
     }
+    const double* tab = gl + QT_RAD + (C_EDGE - 1) * RAD_STRIDE;
+    // (z1, x2, y2) / xi lie in [-1, 1] x [0, 1] x [0, 1]
+    const int K = radial_order(tab, a.kappa * (norm3(e) + norm3(av) + norm3(bv)));
+    if (K >= 0) {
+      // lanes over (piece, w1, w2); xi by the radial table
+      for (int it = lane; it < 4 * n2; it += 64) {
+        const int piece = it / n2, rem = it - piece * n2;
+        const int ib = rem / n, ic = rem - ib * n;
+        const double w1 = gx[ib], w2 = gx[ic];
+        // the four pieces' (z1, x2, y2) / xi as selects (a divergent if-chain
+        // over the pieces was compiled without the last piece's z1)
+        const double u1 = 1.0 - w1, v12 = w1 * (1.0 - w2), w12 = w1 * w2;
+        const bool p0 = piece == 0, p1 = piece == 1, p2 = piece == 2;
+        const double z = p0 ? w1 : p1 ? v12 : p2 ? -v12 : -w1;
+        const double x = p0 ? u1 : p1 ? w12 : p2 ? 1.0 : w2;
+        const double y = p0 ? w2 : p1 ? 1.0 : p2 ? w12 : u1;
+        const double W = gw[ib] * gw[ic] * ((p1 || p2) ? w1 : 1.0);
+        double R[3];
+        for (int d = 0; d < 3; ++d) R[d] = -z * e[d] + x * av[d] - y * bv[d];
+        radial_ray(R, ni, nj, nn, a.kappa, tab, K, W, acc);
+      }
+    } else
     // lanes over (piece, xi, w1); the innermost variable w2 enters the
     // separation linearly, r = R0 + w2 R1
     for (int it = lane; it < 4 * n2; it += 64) {
@@ -208,6 +293,27 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
       B0[d] = cj[3 * vj + d] - S[d];
       B1[d] = cj[3 * wj + d] - cj[3 * vj + d];
     }
+    const double* tab = gl + QT_RAD + (C_VERTEX - 1) * RAD_STRIDE;
+    double A01[3], B01[3];
+    for (int d = 0; d < 3; ++d) {
+      A01[d] = A0[d] + A1[d];
+      B01[d] = B0[d] + B1[d];
+    }
+    const int K = radial_order(tab, a.kappa * (fmax(norm3(A0), norm3(A01)) + fmax(norm3(B0), norm3(B01))));
+    if (K >= 0) {
+      // lanes over (piece, eta, t1, t2); xi by the radial table
+      for (int it = lane; it < 2 * n3; it += 64) {
+        const int piece = it / n3, rem = it - piece * n3;
+        const int ib = rem / n2, ic = (rem / n) % n, id = rem % n;
+        const double eta = gx[ib], t1 = gx[ic], t2 = gx[id];
+        const double W = gw[ib] * gw[ic] * gw[id] * eta;
+        const double sa = piece == 0 ? 1.0 : eta;
+        const double sb = piece == 0 ? eta : 1.0;
+        double R[3];
+        for (int d = 0; d < 3; ++d) R[d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
+        radial_ray(R, ni, nj, nn, a.kappa, tab, K, W, acc);
+      }
+    } else
     // lanes over (piece, xi, eta, t1); the innermost t2 enters linearly
     for (int it = lane; it < 2 * n3; it += 64) {
       const int piece = it / n3, rem = it - piece * n3;

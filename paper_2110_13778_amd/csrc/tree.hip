@@ -724,8 +724,8 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_HIP(hipDeviceSynchronize());
   h->free_all();
   {
-    std::vector<double> gl(32, 0.0);
-    gauss_legendre01(h->prm.quad_duffy, gl.data(), gl.data() + 16);
+    std::vector<double> gl(QT_SIZE);
+    quad_table(h->prm.quad_duffy, gl.data());
     FAGBI_TRY(h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double)));
   }
   h->N = N;
