@@ -117,31 +117,45 @@ __device__ inline int radial_order(const double* tab, double vb) {
   return __builtin_amdgcn_readfirstlane(K);
 }
 
-// adds the xi-rule of one ray with weight W (the other coordinates' weights)
-__device__ inline void radial_ray(const double* R, const double* nx, const double* ny, double nn, double kappa,
-                                  const double* tab, int K, double W, double* acc) {
-  const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-  const double p = R[0] * nx[0] + R[1] * nx[1] + R[2] * nx[2];
-  const double q = R[0] * ny[0] + R[1] * ny[1] + R[2] * ny[2];
-  const double ir = inv_sqrt(r2);
-  const double v = kappa * (r2 * ir);
-  double t0 = 0.0, t2 = 0.0, t5a = 0.0, t5b = 0.0;
+// adds the xi-rule of NR rays with weights W (the other coordinates' weights);
+// the rays share the series' coefficient reads
+template <int NR>
+__device__ inline void radial_rays(const double (&R)[NR][3], const double (&W)[NR], const double* nx,
+                                   const double* ny, double nn, double kappa, const double* tab, int K,
+                                   double* acc) {
+  double ir[NR], v[NR], p[NR], q[NR], t0[NR], t2[NR], t5a[NR], t5b[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double r2 = R[r][0] * R[r][0] + R[r][1] * R[r][1] + R[r][2] * R[r][2];
+    p[r] = R[r][0] * nx[0] + R[r][1] * nx[1] + R[r][2] * nx[2];
+    q[r] = R[r][0] * ny[0] + R[r][1] * ny[1] + R[r][2] * ny[2];
+    ir[r] = inv_sqrt(r2);
+    v[r] = kappa * (r2 * ir[r]);
+    t0[r] = t2[r] = t5a[r] = t5b[r] = 0.0;
+  }
+#pragma unroll 2
   for (int k = K; k >= 0; --k) {
     const double* c = tab + 4 * k;
-    t0 = fma(t0, v, c[0]);
-    t2 = fma(t2, v, c[1]);
-    t5a = fma(t5a, v, c[2]);
-    t5b = fma(t5b, v, c[3]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      t0[r] = fma(t0[r], v[r], c[0]);
+      t2[r] = fma(t2[r], v[r], c[1]);
+      t5a[r] = fma(t5a[r], v[r], c[2]);
+      t5b[r] = fma(t5b[r], v[r], c[3]);
+    }
   }
-  const double wi = W * (1.0 / FOUR_PI);
-  const double w3 = wi * ir * ir * ir;
-  const double a1 = w3 * tab[RAD_T1], a2 = w3 * t2;
-  acc[0] -= wi * t0 * ir;
-  acc[1] += a1 * q;
-  acc[2] += a2 * q;
-  acc[3] -= a1 * p;
-  acc[4] -= a2 * p;
-  acc[5] += w3 * (nn * t5a - p * q * (ir * ir) * t5b);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double wi = W[r] * (1.0 / FOUR_PI);
+    const double w3 = wi * ir[r] * ir[r] * ir[r];
+    const double a1 = w3 * tab[RAD_T1], a2 = w3 * t2[r];
+    acc[0] -= wi * t0[r] * ir[r];
+    acc[1] += a1 * q[r];
+    acc[2] += a2 * q[r];
+    acc[3] -= a1 * p[r];
+    acc[4] -= a2 * p[r];
+    acc[5] += w3 * (nn * t5a[r] - p[r] * q[r] * (ir[r] * ir[r]) * t5b[r]);
+  }
 }
 
 __device__ inline double norm3(const double* a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
@@ -184,15 +198,21 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     // z = xi ((1 - t) P_s + t Q_s): |R_hat| <= max over the hexagon's corners
     const int K = radial_order(tab, a.kappa * fmax(fmax(norm3(e1), norm3(e2)), norm3(e12)));
     if (K >= 0) {
-      // lanes over (sector, t); xi by the radial table
-      for (int p = lane; p < 6 * n; p += 64) {
-        const int s = p / n, ib = p - s * n;
-        const double t = gx[ib];
-        const double z1 = (1.0 - t) * HP[s][0] + t * HQ[s][0];
-        const double z2 = (1.0 - t) * HP[s][1] + t * HQ[s][1];
-        double R[3];
-        for (int d = 0; d < 3; ++d) R[d] = -(z1 * e1[d] + z2 * e2[d]);
-        radial_ray(R, ni, ni, nn, a.kappa, tab, K, gw[ib], acc);
+      // lanes over (sector, t), two rays per lane; xi by the radial table
+      const int nr = 6 * n;
+      for (int p0 = lane; p0 < nr; p0 += 128) {
+        double R[2][3], W[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int p = p0 + 64 * r < nr ? p0 + 64 * r : p0;
+          const int s = p / n, ib = p - s * n;
+          const double t = gx[ib];
+          const double z1 = (1.0 - t) * HP[s][0] + t * HQ[s][0];
+          const double z2 = (1.0 - t) * HP[s][1] + t * HQ[s][1];
+          for (int d = 0; d < 3; ++d) R[r][d] = -(z1 * e1[d] + z2 * e2[d]);
+          W[r] = p0 + 64 * r < nr ? gw[ib] : 0.0;
+        }
+        radial_rays<2>(R, W, ni, ni, nn, a.kappa, tab, K, acc);
       }
     } else
     for (int p = lane; p < 6 * n2; p += 64) {
@@ -229,22 +249,27 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     // (z1, x2, y2) / xi lie in [-1, 1] x [0, 1] x [0, 1]
     const int K = radial_order(tab, a.kappa * (norm3(e) + norm3(av) + norm3(bv)));
     if (K >= 0) {
-      // lanes over (piece, w1, w2); xi by the radial table
-      for (int it = lane; it < 4 * n2; it += 64) {
-        const int piece = it / n2, rem = it - piece * n2;
-        const int ib = rem / n, ic = rem - ib * n;
-        const double w1 = gx[ib], w2 = gx[ic];
-        // the four pieces' (z1, x2, y2) / xi as selects (a divergent if-chain
-        // over the pieces was compiled without the last piece's z1)
-        const double u1 = 1.0 - w1, v12 = w1 * (1.0 - w2), w12 = w1 * w2;
-        const bool p0 = piece == 0, p1 = piece == 1, p2 = piece == 2;
-        const double z = p0 ? w1 : p1 ? v12 : p2 ? -v12 : -w1;
-        const double x = p0 ? u1 : p1 ? w12 : p2 ? 1.0 : w2;
-        const double y = p0 ? w2 : p1 ? 1.0 : p2 ? w12 : u1;
-        const double W = gw[ib] * gw[ic] * ((p1 || p2) ? w1 : 1.0);
-        double R[3];
-        for (int d = 0; d < 3; ++d) R[d] = -z * e[d] + x * av[d] - y * bv[d];
-        radial_ray(R, ni, nj, nn, a.kappa, tab, K, W, acc);
+      // lanes over (piece, w1, w2), two rays per lane; xi by the radial table
+      const int nr = 4 * n2;
+      for (int i0 = lane; i0 < nr; i0 += 128) {
+        double R[2][3], W[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
+          const int piece = it / n2, rem = it - piece * n2;
+          const int ib = rem / n, ic = rem - ib * n;
+          const double w1 = gx[ib], w2 = gx[ic];
+          // the four pieces' (z1, x2, y2) / xi as selects (a divergent
+          // if-chain over the pieces was compiled without the last piece's z1)
+          const double u1 = 1.0 - w1, v12 = w1 * (1.0 - w2), w12 = w1 * w2;
+          const bool p0 = piece == 0, p1 = piece == 1, p2 = piece == 2;
+          const double z = p0 ? w1 : p1 ? v12 : p2 ? -v12 : -w1;
+          const double x = p0 ? u1 : p1 ? w12 : p2 ? 1.0 : w2;
+          const double y = p0 ? w2 : p1 ? 1.0 : p2 ? w12 : u1;
+          for (int d = 0; d < 3; ++d) R[r][d] = -z * e[d] + x * av[d] - y * bv[d];
+          W[r] = i0 + 64 * r < nr ? gw[ib] * gw[ic] * ((p1 || p2) ? w1 : 1.0) : 0.0;
+        }
+        radial_rays<2>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
     } else
     // lanes over (piece, xi, w1); the innermost variable w2 enters the
@@ -301,17 +326,22 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     }
     const int K = radial_order(tab, a.kappa * (fmax(norm3(A0), norm3(A01)) + fmax(norm3(B0), norm3(B01))));
     if (K >= 0) {
-      // lanes over (piece, eta, t1, t2); xi by the radial table
-      for (int it = lane; it < 2 * n3; it += 64) {
-        const int piece = it / n3, rem = it - piece * n3;
-        const int ib = rem / n2, ic = (rem / n) % n, id = rem % n;
-        const double eta = gx[ib], t1 = gx[ic], t2 = gx[id];
-        const double W = gw[ib] * gw[ic] * gw[id] * eta;
-        const double sa = piece == 0 ? 1.0 : eta;
-        const double sb = piece == 0 ? eta : 1.0;
-        double R[3];
-        for (int d = 0; d < 3; ++d) R[d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
-        radial_ray(R, ni, nj, nn, a.kappa, tab, K, W, acc);
+      // lanes over (piece, eta, t1, t2), two rays per lane; xi by the radial table
+      const int nr = 2 * n3;
+      for (int i0 = lane; i0 < nr; i0 += 128) {
+        double R[2][3], W[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
+          const int piece = it / n3, rem = it - piece * n3;
+          const int ib = rem / n2, ic = (rem / n) % n, id = rem % n;
+          const double eta = gx[ib], t1 = gx[ic], t2 = gx[id];
+          const double sa = piece == 0 ? 1.0 : eta;
+          const double sb = piece == 0 ? eta : 1.0;
+          for (int d = 0; d < 3; ++d) R[r][d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
+          W[r] = i0 + 64 * r < nr ? gw[ib] * gw[ic] * gw[id] * eta : 0.0;
+        }
+        radial_rays<2>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
     } else
     // lanes over (piece, xi, eta, t1); the innermost t2 enters linearly
