@@ -289,8 +289,10 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
       s0 += red0[k];
       sk += redk[k];
     }
-    L0[(int64_t)c * T + t] += s0 * lscale[t];
-    Lk[(int64_t)c * T + t] += sk * lscale[t];
+    // every cluster of the level is some group's target and the MtL is the
+    // first writer of the level's locals (LtL adds into them afterwards)
+    L0[(int64_t)c * T + t] = s0 * lscale[t];
+    Lk[(int64_t)c * T + t] = sk * lscale[t];
   }
 }
 
@@ -1303,9 +1305,11 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
       }
       return 0;
     }
-    FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), st));
-    FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), st));
-    if (D.n_off == 0) return 0;
+    if (D.n_off == 0) {   // no interactions: LtL adds into zero locals
+      FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), st));
+      FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), st));
+      return 0;
+    }
     const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
     const int spt = spt_of(D.m2l_nslot);
     const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
