@@ -460,34 +460,74 @@ __device__ inline void shift_monomials(const int32_t* __restrict__ cidx, int c, 
 
 // LtL with registers, one thread per child: child^b += sum_{a >= b, |a| <= PP}
 // C(a, b) d^(a - b) parent^a for |b| <= PC
+// A block's rows [r0, r0 + nr) of width W (one row per thread, contiguous in
+// global memory) pass through LDS with an odd row stride, so that the global
+// side is one coalesced span and a thread's own row has no bank conflicts.
+template <int W>
+struct RowStage {
+  static constexpr int S = W | 1;
+};
+template <typename R, int W>
+__device__ inline void stage_load(const R* __restrict__ g, int64_t r0, int nr, R* st) {
+  const R* src = g + r0 * W;
+  for (int e = threadIdx.x; e < nr * W; e += blockDim.x) {
+    const int i = e / W;
+    st[i * RowStage<W>::S + (e - i * W)] = src[e];
+  }
+}
+template <typename R, int W>
+__device__ inline void stage_store(R* g, int64_t r0, int nr, const R* st) {
+  R* dst = g + r0 * W;
+  for (int e = threadIdx.x; e < nr * W; e += blockDim.x) {
+    const int i = e / W;
+    dst[e] = st[i * RowStage<W>::S + (e - i * W)];
+  }
+}
+
 template <typename R, int PP, int PC>
 __global__ void __launch_bounds__(256) k_l2l_reg(const int32_t* __restrict__ parent, const int32_t* __restrict__ cidx,
                                                  int n, R hc, const R* __restrict__ P0, const R* __restrict__ Pk,
                                                  R* C0, R* Ck) {
   constexpr ShiftPairs<PP, PC> sp{};
   constexpr int TP = nterms(PP), TC = nterms(PC);
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int64_t par = parent[c];
-  R mono[TP], p0[TP], pk[TP], s0[TC], sk[TC];
-  shift_monomials<R, PP>(cidx, c, hc, mono);
-#pragma unroll
-  for (int t = 0; t < TP; ++t) {
-    p0[t] = P0[par * TP + t];
-    pk[t] = Pk[par * TP + t];
-  }
+  constexpr int WS = RowStage<TC>::S;
+  __shared__ R st[256 * WS];
+  const int cb = blockIdx.x * blockDim.x;   // launched with 256 threads
+  const int c = cb + threadIdx.x;
+  const int nr = min((int)blockDim.x, n - cb);
+  const bool active = c < n;
+  R s0[TC], sk[TC];
 #pragma unroll
   for (int t = 0; t < TC; ++t) s0[t] = sk[t] = 0;
+  if (active) {
+    const int64_t par = parent[c];
+    R mono[TP], p0[TP], pk[TP];
+    shift_monomials<R, PP>(cidx, c, hc, mono);
 #pragma unroll
-  for (int k = 0; k < ShiftPairs<PP, PC>::N; ++k) {
-    const R w = (R)sp.coef[k] * mono[sp.g[k]];
-    s0[sp.tb[k]] += w * p0[sp.ta[k]];
-    sk[sp.tb[k]] += w * pk[sp.ta[k]];
+    for (int t = 0; t < TP; ++t) {
+      p0[t] = P0[par * TP + t];
+      pk[t] = Pk[par * TP + t];
+    }
+#pragma unroll
+    for (int k = 0; k < ShiftPairs<PP, PC>::N; ++k) {
+      const R w = (R)sp.coef[k] * mono[sp.g[k]];
+      s0[sp.tb[k]] += w * p0[sp.ta[k]];
+      sk[sp.tb[k]] += w * pk[sp.ta[k]];
+    }
   }
+  // the children's rows (the MtL results) += the shifted parent, one channel
+  // at a time through LDS
 #pragma unroll
-  for (int t = 0; t < TC; ++t) {
-    C0[(int64_t)c * TC + t] += s0[t];
-    Ck[(int64_t)c * TC + t] += sk[t];
+  for (int chn = 0; chn < 2; ++chn) {
+    R* g = chn ? Ck : C0;
+    stage_load<R, TC>(g, cb, nr, st);
+    __syncthreads();
+    if (active)
+#pragma unroll
+      for (int t = 0; t < TC; ++t) st[threadIdx.x * WS + t] += chn ? sk[t] : s0[t];
+    __syncthreads();
+    stage_store<R, TC>(g, cb, nr, st);
+    __syncthreads();
   }
 }
 
@@ -500,12 +540,17 @@ __global__ void __launch_bounds__(256) k_m2m_reg(const int32_t* __restrict__ chi
                                                  const R* __restrict__ C0, const R* __restrict__ Ck, R* P0, R* Pk) {
   constexpr ShiftPairs<PP, PC> sp{};
   constexpr int TP = nterms(PP), TC = nterms(PC);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  constexpr int WS = RowStage<TP>::S;
+  __shared__ R st[256 * WS];
+  const int pb = blockIdx.x * blockDim.x;   // launched with 256 threads
+  const int p = pb + threadIdx.x;
+  const int nr = min((int)blockDim.x, n - pb);
+  const bool active = p < n;
   R a0[TP], ak[TP];
 #pragma unroll
   for (int t = 0; t < TP; ++t) a0[t] = ak[t] = 0;
-  for (int ch = child_start[p]; ch < child_end[p]; ++ch) {
+  const int ce = active ? child_end[p] : 0;
+  for (int ch = active ? child_start[p] : 0; ch < ce; ++ch) {
     R mono[TP], c0[TC], ck[TC];
     shift_monomials<R, PP>(cidx, ch, hc, mono);
 #pragma unroll
@@ -520,10 +565,15 @@ __global__ void __launch_bounds__(256) k_m2m_reg(const int32_t* __restrict__ chi
       ak[sp.ta[k]] += w * ck[sp.tb[k]];
     }
   }
+  // the parents' rows, one channel at a time through LDS
 #pragma unroll
-  for (int t = 0; t < TP; ++t) {
-    P0[(int64_t)p * TP + t] = a0[t];
-    Pk[(int64_t)p * TP + t] = ak[t];
+  for (int chn = 0; chn < 2; ++chn) {
+    if (active)
+#pragma unroll
+      for (int t = 0; t < TP; ++t) st[threadIdx.x * WS + t] = chn ? ak[t] : a0[t];
+    __syncthreads();
+    stage_store<R, TP>(chn ? Pk : P0, pb, nr, st);
+    __syncthreads();
   }
 }
 
