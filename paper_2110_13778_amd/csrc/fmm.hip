@@ -1330,8 +1330,9 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     Level& D = h->lev[l];
     using R2 = typename Pair<R>::T;
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
-    // register-blocked kernel for the low orders (up to p = 4)
-    const int preg = 4;
+    // register-blocked kernels for the low orders (up to p = 4, FP32 up to 5)
+    // (order 5 in registers in FP32 only: the FP64 version would spill)
+    const int preg = sizeof(R) == 4 ? 5 : 4;
     const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
     if constexpr (sizeof(R) == 4)
     if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
@@ -1367,7 +1368,11 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
         case 1: k_m2l_reg<R, 1><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
         case 2: k_m2l_reg<R, 2><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
         case 3: k_m2l_reg<R, 3><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        default: k_m2l_reg<R, 4><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        case 4: k_m2l_reg<R, 4><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+        default:
+          if constexpr (sizeof(R) == 4)
+            k_m2l_reg<R, 5><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
+          break;
       }
       return 0;
     }
