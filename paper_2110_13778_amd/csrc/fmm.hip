@@ -1425,16 +1425,31 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(2));
-  for (int l = h->lmin; l <= (pipe ? L - 2 : L); ++l) FAGBI_TRY(launch_m2l(l, s));
+  // The coarse levels' MtL (few clusters at high order: latency bound) run on
+  // the near-field stream once the SpMV is done, beside the main stream's
+  // finest remaining level; the main stream joins both before LtL.
+  const int l_hi = pipe ? L - 2 : L;
+  const bool side = sn != s && l_hi > h->lmin;
+  if (side) {
+    if (!h->ev_upd) FAGBI_HIP(hipEventCreateWithFlags(&h->ev_upd, hipEventDisableTiming));
+    FAGBI_HIP(hipEventRecord(h->ev_upd, s));
+    FAGBI_HIP(hipStreamWaitEvent(sn, h->ev_upd, 0));
+    for (int l = h->lmin; l < l_hi; ++l) FAGBI_TRY(launch_m2l(l, sn));
+    FAGBI_HIP(hipEventRecord(h->ev_join, sn));   // the SpMV and those levels
+    FAGBI_TRY(launch_m2l(l_hi, s));
+  } else {
+    for (int l = h->lmin; l <= l_hi; ++l) FAGBI_TRY(launch_m2l(l, s));
+  }
   if (pipe) FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(3));
+  if (side) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
   for (int l = h->lmin; l < L; ++l) {
     // LtL into the two finest levels adds to their MtL results
     if (pipe && l + 1 == std::max(L - 1, h->lmin + 1)) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
     FAGBI_TRY(launch_l2l<R>(h, l, f32, s));
   }
-  if (sn != s) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
+  if (sn != s && !side) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
   {
     const unsigned g = (unsigned)((N + 255) / 256);
     const R *a = ms.as<R>(), *b = md.as<R>();

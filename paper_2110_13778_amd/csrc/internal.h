@@ -158,6 +158,7 @@ struct fagbi_handle {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t s_m2l = nullptr;                  // MtL of the two finest levels, default priority
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr, ev_m2l = nullptr;
+  hipEvent_t ev_upd = nullptr;                  // upward pass complete (coarse MtL on the near stream)
   fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);
