@@ -132,10 +132,45 @@ void quad_table(int n, double* t) {
   std::lock_guard<std::mutex> lock(mu);
   std::vector<double>& c = cache[n];
   if (c.empty()) {
-    c.assign(QT_SIZE, 0.0);
+    c.assign(qt_size(n), 0.0);
+    const double *x = c.data(), *w = c.data() + 16;
     gauss_legendre01(n, c.data(), c.data() + 16);
     for (int cls = 0; cls < 3; ++cls)
-      radial_table(n, c.data(), c.data() + 16, cls, c.data() + QT_RAD + cls * RAD_STRIDE);
+      radial_table(n, x, w, cls, c.data() + QT_RAD + cls * RAD_STRIDE);
+    // vertex rays (piece, eta, t1, t2): R / xi = s_a (A0 + t1 A1) - s_b (B0 + t2 B1)
+    const int n2 = n * n, n3 = n2 * n;
+    for (int it = 0; it < 2 * n3; ++it) {
+      const int piece = it / n3, rem = it - piece * n3;
+      const int ib = rem / n2, ic = (rem / n) % n, id = rem % n;
+      const double eta = x[ib], sa = piece == 0 ? 1.0 : eta, sb = piece == 0 ? eta : 1.0;
+      double* r = c.data() + QT_RAY + 6 * it;
+      r[0] = sa;
+      r[1] = sa * x[ic];
+      r[2] = sb;
+      r[3] = sb * x[id];
+      r[4] = w[ib] * w[ic] * w[id] * eta;
+    }
+    // edge rays (piece, w1, w2): R / xi = -z1 e + x2 a - y2 b
+    for (int it = 0; it < 4 * n2; ++it) {
+      const int piece = it / n2, rem = it - piece * n2;
+      const int ib = rem / n, ic = rem - ib * n;
+      const double w1 = x[ib], w2 = x[ic];
+      double z, xx, y, W = w[ib] * w[ic];
+      if (piece == 0) {
+        z = w1; xx = 1.0 - w1; y = w2;
+      } else if (piece == 1) {
+        z = w1 * (1.0 - w2); xx = w1 * w2; y = 1.0; W *= w1;
+      } else if (piece == 2) {
+        z = -w1 * (1.0 - w2); xx = 1.0; y = w1 * w2; W *= w1;
+      } else {
+        z = -w1; xx = w2; y = 1.0 - w1;
+      }
+      double* r = c.data() + qt_edge_rays(n) + 4 * it;
+      r[0] = z;
+      r[1] = xx;
+      r[2] = y;
+      r[3] = W;
+    }
   }
   std::copy(c.begin(), c.end(), t);
 }
@@ -347,7 +382,7 @@ int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
     return set_error(FAGBI_E_HIP, "no HIP device");
   }
   // Gauss-Legendre nodes and weights of the singular/close rules
-  std::vector<double> gl(QT_SIZE);
+  std::vector<double> gl(qt_size(p->quad_duffy));
   quad_table(p->quad_duffy, gl.data());
   int r = h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double));
   if (r < 0) {

@@ -229,8 +229,13 @@ constexpr int RAD_T1 = 4 * (RAD_KMAX + 1);
 constexpr int RAD_VK = RAD_T1 + 1;
 constexpr int RAD_STRIDE = 128;
 constexpr int QT_RAD = 32;
-constexpr int QT_SIZE = QT_RAD + 3 * RAD_STRIDE;
-void quad_table(int n, double* t);   // t: QT_SIZE doubles
+// then the per-ray data of the vertex rule ([2 n^3][6]: s_a, s_a t1, s_b,
+// s_b t2, weight, 0) and of the edge rule ([4 n^2][4]: z1, x2, y2, weight),
+// the coordinates of a ray divided by its radial coordinate
+constexpr int QT_RAY = QT_RAD + 3 * RAD_STRIDE;
+__host__ __device__ inline int qt_edge_rays(int n) { return QT_RAY + 12 * n * n * n; }
+__host__ __device__ inline int qt_size(int n) { return qt_edge_rays(n) + 16 * n * n; }
+void quad_table(int n, double* t);   // t: qt_size(n) doubles
 }  // namespace fagbi
 
 // ---------------------------------------------------------------------------

@@ -158,6 +158,9 @@ __device__ inline void radial_rays(const double (&R)[NR][3], const double (&W)[N
   }
 }
 
+// rays per lane in the touching rules (they share the series' coefficient reads)
+constexpr int NRAY = 2;
+
 __device__ inline double norm3(const double* a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 
 // one wavefront per singular / close pair
@@ -198,12 +201,12 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     // z = xi ((1 - t) P_s + t Q_s): |R_hat| <= max over the hexagon's corners
     const int K = radial_order(tab, a.kappa * fmax(fmax(norm3(e1), norm3(e2)), norm3(e12)));
     if (K >= 0) {
-      // lanes over (sector, t), two rays per lane; xi by the radial table
+      // lanes over (sector, t), NRAY rays per lane; xi by the radial table
       const int nr = 6 * n;
-      for (int p0 = lane; p0 < nr; p0 += 128) {
-        double R[2][3], W[2];
+      for (int p0 = lane; p0 < nr; p0 += 64 * NRAY) {
+        double R[NRAY][3], W[NRAY];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < NRAY; ++r) {
           const int p = p0 + 64 * r < nr ? p0 + 64 * r : p0;
           const int s = p / n, ib = p - s * n;
           const double t = gx[ib];
@@ -212,7 +215,7 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
           for (int d = 0; d < 3; ++d) R[r][d] = -(z1 * e1[d] + z2 * e2[d]);
           W[r] = p0 + 64 * r < nr ? gw[ib] : 0.0;
         }
-        radial_rays<2>(R, W, ni, ni, nn, a.kappa, tab, K, acc);
+        radial_rays<NRAY>(R, W, ni, ni, nn, a.kappa, tab, K, acc);
       }
     } else
     for (int p = lane; p < 6 * n2; p += 64) {
@@ -249,27 +252,20 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     // (z1, x2, y2) / xi lie in [-1, 1] x [0, 1] x [0, 1]
     const int K = radial_order(tab, a.kappa * (norm3(e) + norm3(av) + norm3(bv)));
     if (K >= 0) {
-      // lanes over (piece, w1, w2), two rays per lane; xi by the radial table
+      // lanes over (piece, w1, w2), NRAY rays per lane; xi by the radial table
       const int nr = 4 * n2;
-      for (int i0 = lane; i0 < nr; i0 += 128) {
-        double R[2][3], W[2];
+      for (int i0 = lane; i0 < nr; i0 += 64 * NRAY) {
+        double R[NRAY][3], W[NRAY];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < NRAY; ++r) {
+          // the ray's (z1, x2, y2) / xi and weight from the table (consecutive
+          // lanes, consecutive rays)
           const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
-          const int piece = it / n2, rem = it - piece * n2;
-          const int ib = rem / n, ic = rem - ib * n;
-          const double w1 = gx[ib], w2 = gx[ic];
-          // the four pieces' (z1, x2, y2) / xi as selects (a divergent
-          // if-chain over the pieces was compiled without the last piece's z1)
-          const double u1 = 1.0 - w1, v12 = w1 * (1.0 - w2), w12 = w1 * w2;
-          const bool p0 = piece == 0, p1 = piece == 1, p2 = piece == 2;
-          const double z = p0 ? w1 : p1 ? v12 : p2 ? -v12 : -w1;
-          const double x = p0 ? u1 : p1 ? w12 : p2 ? 1.0 : w2;
-          const double y = p0 ? w2 : p1 ? 1.0 : p2 ? w12 : u1;
-          for (int d = 0; d < 3; ++d) R[r][d] = -z * e[d] + x * av[d] - y * bv[d];
-          W[r] = i0 + 64 * r < nr ? gw[ib] * gw[ic] * ((p1 || p2) ? w1 : 1.0) : 0.0;
+          const double4 ry = reinterpret_cast<const double4*>(gl + qt_edge_rays(n))[it];
+          for (int d = 0; d < 3; ++d) R[r][d] = -ry.x * e[d] + ry.y * av[d] - ry.z * bv[d];
+          W[r] = i0 + 64 * r < nr ? ry.w : 0.0;
         }
-        radial_rays<2>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
+        radial_rays<NRAY>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
     } else
     // lanes over (piece, xi, w1); the innermost variable w2 enters the
@@ -326,22 +322,21 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     }
     const int K = radial_order(tab, a.kappa * (fmax(norm3(A0), norm3(A01)) + fmax(norm3(B0), norm3(B01))));
     if (K >= 0) {
-      // lanes over (piece, eta, t1, t2), two rays per lane; xi by the radial table
+      // lanes over (piece, eta, t1, t2), NRAY rays per lane; xi by the radial table
       const int nr = 2 * n3;
-      for (int i0 = lane; i0 < nr; i0 += 128) {
-        double R[2][3], W[2];
+      for (int i0 = lane; i0 < nr; i0 += 64 * NRAY) {
+        double R[NRAY][3], W[NRAY];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < NRAY; ++r) {
+          // the ray's s_a, s_a t1, s_b, s_b t2 and weight from the table
           const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
-          const int piece = it / n3, rem = it - piece * n3;
-          const int ib = rem / n2, ic = (rem / n) % n, id = rem % n;
-          const double eta = gx[ib], t1 = gx[ic], t2 = gx[id];
-          const double sa = piece == 0 ? 1.0 : eta;
-          const double sb = piece == 0 ? eta : 1.0;
-          for (int d = 0; d < 3; ++d) R[r][d] = sa * (A0[d] + t1 * A1[d]) - sb * (B0[d] + t2 * B1[d]);
-          W[r] = i0 + 64 * r < nr ? gw[ib] * gw[ic] * gw[id] * eta : 0.0;
+          const double* ry = gl + QT_RAY + 6 * it;
+          const double2 r01 = *reinterpret_cast<const double2*>(ry);
+          const double2 r23 = *reinterpret_cast<const double2*>(ry + 2);
+          for (int d = 0; d < 3; ++d) R[r][d] = (r01.x * A0[d] + r01.y * A1[d]) - (r23.x * B0[d] + r23.y * B1[d]);
+          W[r] = i0 + 64 * r < nr ? ry[4] : 0.0;
         }
-        radial_rays<2>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
+        radial_rays<NRAY>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
     } else
     // lanes over (piece, xi, eta, t1); the innermost t2 enters linearly

@@ -724,7 +724,7 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_HIP(hipDeviceSynchronize());
   h->free_all();
   {
-    std::vector<double> gl(QT_SIZE);
+    std::vector<double> gl(qt_size(h->prm.quad_duffy));
     quad_table(h->prm.quad_duffy, gl.data());
     FAGBI_TRY(h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double)));
   }
