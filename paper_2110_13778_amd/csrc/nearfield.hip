@@ -117,6 +117,24 @@ __device__ inline int radial_order(const double* tab, double vb) {
   return __builtin_amdgcn_readfirstlane(K);
 }
 
+// the four series of NR rays to degree K (Horner)
+template <int K, int NR>
+__device__ inline void radial_series(const double* tab, const double (&v)[NR], double (&t0)[NR],
+                                     double (&t2)[NR], double (&t5a)[NR], double (&t5b)[NR]) {
+  static_assert(K <= RAD_KMAX, "table degree");
+#pragma unroll
+  for (int k = K; k >= 0; --k) {
+    const double* c = tab + 4 * k;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      t0[r] = fma(t0[r], v[r], c[0]);
+      t2[r] = fma(t2[r], v[r], c[1]);
+      t5a[r] = fma(t5a[r], v[r], c[2]);
+      t5b[r] = fma(t5b[r], v[r], c[3]);
+    }
+  }
+}
+
 // adds the xi-rule of NR rays with weights W (the other coordinates' weights);
 // the rays share the series' coefficient reads
 template <int NR>
@@ -133,16 +151,16 @@ __device__ inline void radial_rays(const double (&R)[NR][3], const double (&W)[N
     v[r] = kappa * (r2 * ir[r]);
     t0[r] = t2[r] = t5a[r] = t5b[r] = 0.0;
   }
-#pragma unroll 2
-  for (int k = K; k >= 0; --k) {
-    const double* c = tab + 4 * k;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      t0[r] = fma(t0[r], v[r], c[0]);
-      t2[r] = fma(t2[r], v[r], c[1]);
-      t5a[r] = fma(t5a[r], v[r], c[2]);
-      t5b[r] = fma(t5b[r], v[r], c[3]);
-    }
+  // degree rounded up to a multiple of 3 (more terms only add accuracy), so
+  // that each series is unrolled with its table reads at fixed offsets
+  switch ((K + 2) / 3) {
+    case 0: case 1: case 2: radial_series<6, NR>(tab, v, t0, t2, t5a, t5b); break;
+    case 3: radial_series<9, NR>(tab, v, t0, t2, t5a, t5b); break;
+    case 4: radial_series<12, NR>(tab, v, t0, t2, t5a, t5b); break;
+    case 5: radial_series<15, NR>(tab, v, t0, t2, t5a, t5b); break;
+    case 6: radial_series<18, NR>(tab, v, t0, t2, t5a, t5b); break;
+    case 7: radial_series<21, NR>(tab, v, t0, t2, t5a, t5b); break;
+    default: radial_series<24, NR>(tab, v, t0, t2, t5a, t5b); break;
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -170,7 +188,9 @@ template <int CLS>
 __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* items, int64_t n_items,
                                                        const double* gl, int n, double4* ent,
                                                        const uint8_t* skip, double* raw) {
-  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // the wave's pair (made provably wave-uniform, so that the returns below and
+  // the loops after them stay scalar)
+  const int64_t it = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (it >= n_items) return;
   if (skip && skip[it]) return;
@@ -203,17 +223,20 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     if (K >= 0) {
       // lanes over (sector, t), NRAY rays per lane; xi by the radial table
       const int nr = 6 * n;
-      for (int p0 = lane; p0 < nr; p0 += 64 * NRAY) {
+      // (a uniform loop: lanes past the end take the last ray with weight 0,
+      // so the series loop inside keeps scalar counters and addresses)
+      for (int b0 = 0; b0 < nr; b0 += 64 * NRAY) {
         double R[NRAY][3], W[NRAY];
 #pragma unroll
         for (int r = 0; r < NRAY; ++r) {
-          const int p = p0 + 64 * r < nr ? p0 + 64 * r : p0;
+          const int p0 = b0 + 64 * r + lane;
+          const int p = p0 < nr ? p0 : nr - 1;
           const int s = p / n, ib = p - s * n;
           const double t = gx[ib];
           const double z1 = (1.0 - t) * HP[s][0] + t * HQ[s][0];
           const double z2 = (1.0 - t) * HP[s][1] + t * HQ[s][1];
           for (int d = 0; d < 3; ++d) R[r][d] = -(z1 * e1[d] + z2 * e2[d]);
-          W[r] = p0 + 64 * r < nr ? gw[ib] : 0.0;
+          W[r] = p0 < nr ? gw[ib] : 0.0;
         }
         radial_rays<NRAY>(R, W, ni, ni, nn, a.kappa, tab, K, acc);
       }
@@ -254,16 +277,17 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     if (K >= 0) {
       // lanes over (piece, w1, w2), NRAY rays per lane; xi by the radial table
       const int nr = 4 * n2;
-      for (int i0 = lane; i0 < nr; i0 += 64 * NRAY) {
+      for (int b0 = 0; b0 < nr; b0 += 64 * NRAY) {   // uniform, as above
         double R[NRAY][3], W[NRAY];
 #pragma unroll
         for (int r = 0; r < NRAY; ++r) {
           // the ray's (z1, x2, y2) / xi and weight from the table (consecutive
           // lanes, consecutive rays)
-          const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
+          const int i0 = b0 + 64 * r + lane;
+          const int it = i0 < nr ? i0 : nr - 1;
           const double4 ry = reinterpret_cast<const double4*>(gl + qt_edge_rays(n))[it];
           for (int d = 0; d < 3; ++d) R[r][d] = -ry.x * e[d] + ry.y * av[d] - ry.z * bv[d];
-          W[r] = i0 + 64 * r < nr ? ry.w : 0.0;
+          W[r] = i0 < nr ? ry.w : 0.0;
         }
         radial_rays<NRAY>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
@@ -324,17 +348,18 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     if (K >= 0) {
       // lanes over (piece, eta, t1, t2), NRAY rays per lane; xi by the radial table
       const int nr = 2 * n3;
-      for (int i0 = lane; i0 < nr; i0 += 64 * NRAY) {
+      for (int b0 = 0; b0 < nr; b0 += 64 * NRAY) {   // uniform, as above
         double R[NRAY][3], W[NRAY];
 #pragma unroll
         for (int r = 0; r < NRAY; ++r) {
           // the ray's s_a, s_a t1, s_b, s_b t2 and weight from the table
-          const int it = i0 + 64 * r < nr ? i0 + 64 * r : i0;
+          const int i0 = b0 + 64 * r + lane;
+          const int it = i0 < nr ? i0 : nr - 1;
           const double* ry = gl + QT_RAY + 6 * it;
           const double2 r01 = *reinterpret_cast<const double2*>(ry);
           const double2 r23 = *reinterpret_cast<const double2*>(ry + 2);
           for (int d = 0; d < 3; ++d) R[r][d] = (r01.x * A0[d] + r01.y * A1[d]) - (r23.x * B0[d] + r23.y * B1[d]);
-          W[r] = i0 + 64 * r < nr ? ry[4] : 0.0;
+          W[r] = i0 < nr ? ry[4] : 0.0;
         }
         radial_rays<NRAY>(R, W, ni, nj, nn, a.kappa, tab, K, acc);
       }
