@@ -171,6 +171,15 @@ void quad_table(int n, double* t) {
       r[2] = y;
       r[3] = W;
     }
+    // close rule, outer points (s1, t1, s2) of the Duffy-collapsed product
+    for (int it = 0; it < n3; ++it) {
+      const int ia = it / n2, ib = (it / n) % n, ic = it % n;
+      double* r = c.data() + qt_close_pts(n) + 4 * it;
+      r[0] = x[ia];
+      r[1] = x[ia] * x[ib];
+      r[2] = x[ic];
+      r[3] = x[ia] * w[ia] * w[ib] * x[ic] * w[ic];
+    }
   }
   std::copy(c.begin(), c.end(), t);
 }

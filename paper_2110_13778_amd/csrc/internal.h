@@ -234,7 +234,10 @@ constexpr int QT_RAD = 32;
 // the coordinates of a ray divided by its radial coordinate
 constexpr int QT_RAY = QT_RAD + 3 * RAD_STRIDE;
 __host__ __device__ inline int qt_edge_rays(int n) { return QT_RAY + 12 * n * n * n; }
-__host__ __device__ inline int qt_size(int n) { return qt_edge_rays(n) + 16 * n * n; }
+// and the outer points of the close rule ([n^3][4]: s1, s1 t1, s2, weight
+// without the areas)
+__host__ __device__ inline int qt_close_pts(int n) { return qt_edge_rays(n) + 16 * n * n; }
+__host__ __device__ inline int qt_size(int n) { return qt_close_pts(n) + 4 * n * n * n; }
 void quad_table(int n, double* t);   // t: qt_size(n) doubles
 }  // namespace fagbi
 

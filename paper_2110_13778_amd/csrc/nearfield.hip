@@ -386,14 +386,18 @@ __global__ void __launch_bounds__(256) k_near_singular(NearArgs a, const Item* i
     }
   } else {  // CLOSE
     const double tai = 2.0 * a.pa[i], taj = 2.0 * a.pa[j];
-    // lanes over (s1, t1, s2); the innermost t2 enters linearly
-    for (int it = lane; it < n3; it += 64) {
-      const int ia = it / n2, ib = (it / n) % n, ic = it % n;
-      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic];
-      const double wb = tai * s1 * gw[ia] * gw[ib] * taj * s2 * gw[ic];
+    // lanes over (s1, t1, s2) from the order's table (a uniform loop: lanes
+    // past the end take the last point with weight 0); the innermost t2
+    // enters linearly
+    const double4* cp = reinterpret_cast<const double4*>(gl + qt_close_pts(n));
+    for (int b0 = 0; b0 < n3; b0 += 64) {
+      const int it0 = b0 + lane;
+      const double4 o = cp[it0 < n3 ? it0 : n3 - 1];
+      const double s1 = o.x, s1t1 = o.y, s2 = o.z;
+      const double wb = it0 < n3 ? tai * taj * o.w : 0.0;
       double R0[3], R1[3];
       for (int d = 0; d < 3; ++d) {
-        const double x = ci[d] + s1 * (ci[3 + d] - ci[d]) + s1 * t1 * (ci[6 + d] - ci[3 + d]);
+        const double x = ci[d] + s1 * (ci[3 + d] - ci[d]) + s1t1 * (ci[6 + d] - ci[3 + d]);
         R0[d] = x - (cj[d] + s2 * (cj[3 + d] - cj[d]));
         R1[d] = -s2 * (cj[6 + d] - cj[3 + d]);
       }
