@@ -959,9 +959,10 @@ __global__ void __launch_bounds__(64) k_taylor_table(int n_off, const int32_t* _
       }
 }
 
-// the FP32 table rows of one offset of each opposite pair
-__global__ void k_half_rows(const int32_t* __restrict__ rows, int n_half, int T, const float* __restrict__ full,
-                            float* half) {
+// the table rows of one offset of each opposite pair
+template <typename R>
+__global__ void k_half_rows(const int32_t* __restrict__ rows, int n_half, int T, const R* __restrict__ full,
+                            R* half) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n_half * 2 * T) return;
   const int64_t k = i / (2 * T), r = i - k * 2 * T;
@@ -1141,6 +1142,7 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
       if (ok) {
         st.add(D.d_rows, rows.data(), rows.size() * 4);
         st.reserve(D.d_F32[1], (size_t)2 * rows.size() * D.T * 4);
+        if (D.order == 3) st.reserve(D.d_F64[1], (size_t)2 * rows.size() * D.T * 8);
         st.add(D.d_oid_map, omap.data(), omap.size() * 4);
         D.n_half = (int)rows.size();
       }
@@ -1169,8 +1171,12 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         D.d_F32[0].as<float>());
     if (D.n_half > 0) {
       const int64_t m = (int64_t)D.n_half * 2 * D.T;
-      k_half_rows<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
-                                                             D.d_F32[0].as<float>(), D.d_F32[1].as<float>());
+      k_half_rows<float><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
+                                                                    D.d_F32[0].as<float>(), D.d_F32[1].as<float>());
+      if (D.order == 3)
+        k_half_rows<double><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
+                                                                       D.d_F64[0].as<double>(),
+                                                                       D.d_F64[1].as<double>());
     }
   }
   FAGBI_HIP(hipGetLastError());
@@ -1334,6 +1340,20 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     // (order 5 in registers in FP32 only: the FP64 version would spill)
     const int preg = sizeof(R) == 4 ? 5 : 4;
     const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
+    // FP64 at order 3: the same with the FP64 half table (512 threads: 224 VGPRs)
+    if constexpr (sizeof(R) == 8)
+    if (D.n_half > 0 && D.order == 3 && D.d_F64[1].p && dbytes <= (size_t)150 * 1024) {
+      int S = 1;
+      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+      const R2* Dh = (const R2*)D.d_F64[1].p;
+      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 512>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+      k_m2l_lds<R, 3, 512><<<224, 512, dbytes, st>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
+                                                     D.d_inter_oid.as<int32_t>(), Dh, D.n_half,
+                                                     D.d_oid_map.as<int32_t>(), D.n_off, D.n, S, M(D, 0), M(D, 1),
+                                                     Lc(D, 0), Lc(D, 1));
+      return 0;
+    }
     if constexpr (sizeof(R) == 4)
     if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
       int S = 1;
