@@ -416,7 +416,8 @@ void fagbi_destroy(fagbi_handle* h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->s_near) (void)hipStreamDestroy(h->s_near);
-  for (hipEvent_t e : {h->ev_up0, h->ev_up1, h->ev_m2l, h->ev_upd})
+  if (h->hpin) (void)hipHostFree(h->hpin);
+  for (hipEvent_t e : {h->ev_up0, h->ev_up1, h->ev_m2l, h->ev_upd, h->ev_col})
     if (e) (void)hipEventDestroy(e);
   if (h->s_m2l) (void)hipStreamDestroy(h->s_m2l);
   (void)hipSetDevice(cur);

@@ -159,6 +159,9 @@ struct fagbi_handle {
   hipStream_t s_m2l = nullptr;                  // MtL of the two finest levels, default priority
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr, ev_m2l = nullptr;
   hipEvent_t ev_upd = nullptr;                  // upward pass complete (coarse MtL on the near stream)
+  double* hpin = nullptr;                       // pinned host copy of a GMRES Hessenberg column
+  size_t hpin_n = 0;
+  hipEvent_t ev_col = nullptr;
   fagbi_profile prof{};
   std::vector<fagbi::DBuf*> owned;
   int alloc(fagbi::DBuf& b, size_t bytes);

@@ -331,6 +331,19 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
   k_axpby<<<G, 256, 0, s>>>(1.0 / beta, V, 0.0, V, n);
   const int m = std::min(maxit, K.m);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), col(m + 2);
+  // the column comes back through pinned memory, waited for by polling an
+  // event (a copy into pageable memory and a stream synchronisation left the
+  // GPU idle for ~65 us per iteration)
+  const size_t need = 2 * (size_t)(K.m + 2);
+  if (h->hpin_n < need) {
+    if (h->hpin) FAGBI_HIP(hipHostFree(h->hpin));
+    h->hpin = nullptr;
+    h->hpin_n = 0;
+    FAGBI_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hpin), need * 8, hipHostMallocDefault));
+    h->hpin_n = need;
+  }
+  if (!h->ev_col) FAGBI_HIP(hipEventCreateWithFlags(&h->ev_col, hipEventDisableTiming));
+  double* hp = h->hpin;
   g[0] = beta;
   int k = 0;
   for (; k < m; ++k) {
@@ -346,11 +359,15 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
     multidot(K, V, k + 1, w, hc, 0, s);
     k_combine<<<G, 256, 0, s>>>(V, n, hc, k + 1, -1.0, n, w);
     multidot(K, w, 1, w, hc + k + 1, 0, s);
-    std::vector<double> h1(k + 1);
-    FAGBI_HIP(hipMemcpyAsync(col.data(), hc, (k + 2) * 8, hipMemcpyDeviceToHost, s));
-    FAGBI_HIP(hipMemcpyAsync(h1.data(), hc2, (k + 1) * 8, hipMemcpyDeviceToHost, s));
-    FAGBI_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i <= k; ++i) col[i] += h1[i];
+    FAGBI_HIP(hipMemcpyAsync(hp, hc, (k + 2) * 8, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipMemcpyAsync(hp + (K.m + 2), hc2, (k + 1) * 8, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipEventRecord(h->ev_col, s));
+    hipError_t q;
+    while ((q = hipEventQuery(h->ev_col)) == hipErrorNotReady) {
+    }
+    FAGBI_HIP(q);
+    for (int i = 0; i <= k + 1; ++i) col[i] = hp[i];
+    for (int i = 0; i <= k; ++i) col[i] += hp[K.m + 2 + i];
     const double hn = std::sqrt(col[k + 1]);
     if (!std::isfinite(hn)) return set_error(FAGBI_E_NUMERIC, "non-finite Krylov vector");
     col[k + 1] = hn;
