@@ -44,6 +44,20 @@ def gpu_columns(h, n2):
     return A
 
 
+def check_blocks(A, R, N):
+    """every operator block's off-diagonal and diagonal entries to 1e-12 of
+    that part's largest oracle entry"""
+    off = ~np.eye(N, dtype=bool)
+    for bi in range(2):
+        for bj in range(2):
+            G = A[bi * N:(bi + 1) * N, bj * N:(bj + 1) * N]
+            O = R[bi * N:(bi + 1) * N, bj * N:(bj + 1) * N]
+            for mask in (off, ~off):
+                scale = np.abs(O[mask]).max()
+                err = np.abs(G[mask] - O[mask]).max()
+                assert err <= 1e-12 * scale, (bi, bj, mask is off, err / scale)
+
+
 @pytest.mark.parametrize("n,kappa", [(7, 0.02), (7, 0.1257), (7, 0.2), (7, 1.0), (3, 0.1257), (4, 0.3)])
 def test_touching_pairs_entrywise(coarse_sphere, n, kappa):
     v, t, P = coarse_sphere
@@ -54,12 +68,20 @@ def test_touching_pairs_entrywise(coarse_sphere, n, kappa):
     A = gpu_columns(h, 2 * N)   # caller order, as the oracle's
     h.close()
     R = odense.assemble(P, EPS, kappa, n=n)
-    off = ~np.eye(N, dtype=bool)
-    for bi in range(2):
-        for bj in range(2):
-            G = A[bi * N:(bi + 1) * N, bj * N:(bj + 1) * N]
-            O = R[bi * N:(bi + 1) * N, bj * N:(bj + 1) * N]
-            for mask in (off, ~off):
-                scale = np.abs(O[mask]).max()
-                err = np.abs(G[mask] - O[mask]).max()
-                assert err <= 1e-12 * scale, (bi, bj, mask is off, err / scale)
+    check_blocks(A, R, N)
+
+
+@pytest.mark.parametrize("level,n,kappa", [(2, 1, 0.1257), (1, 16, 0.02)])
+def test_touching_pairs_extreme_orders(level, n, kappa):
+    """the smallest and the largest accepted rule orders (1 and 16; the
+    coarser mesh keeps the oracle's 2 n^4 vertex points affordable)"""
+    v, t = icosphere(level, 20.0)
+    P = panels(v, t)
+    N = P.n
+    print("touching pairs: level %d n %d kappa %g" % (level, n, kappa), flush=True)
+    h = F.Handle(eta0=0.0, eps_in=1.0, eps_out=EPS, kappa=kappa, quad_duffy=n)
+    h.build_tree(v, t).assemble_nearfield()
+    A = gpu_columns(h, 2 * N)
+    h.close()
+    R = odense.assemble(P, EPS, kappa, n=n)
+    check_blocks(A, R, N)
