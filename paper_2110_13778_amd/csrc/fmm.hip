@@ -1576,11 +1576,13 @@ __device__ double tc_far(bool has, double dx, double dy, double dz, double kappa
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     ir = inv_sqrt(r2);
     ir2 = ir * ir;
-    exp_expm1(-kappa * (r2 * ir), E, em1);
+    if (!RHS) exp_expm1(-kappa * (r2 * ir), E, em1);
     if (gl == 0) {
       F0[0] = ir;
-      FK[0] = E * ir;
-      HK[0] = E;
+      if (!RHS) {
+        FK[0] = E * ir;
+        HK[0] = E;
+      }
     }
   }
   wave_sync();
@@ -1772,6 +1774,52 @@ __global__ void __launch_bounds__(64) k_tc_far(TcLevels lv, int l, double kappa,
   if (has && gl == 0) unsafeAtomicAdd(V + n, v);
 }
 
+// The same particle-to-local terms (right-hand side) for a level with few
+// clusters: many charges share each cluster, so instead of one global atomic
+// per term each block accumulates into an LDS copy of the level's evaluated
+// locals ([n][T(p)], then one Coulomb coefficient row per group) and adds the
+// copy to global memory once.  Wavefronts stride over the accepted pairs.
+__global__ void __launch_bounds__(1024) k_tc_far_rhs_lds(TcLevels lv, int l, double3 corner,
+                                                        const double4* __restrict__ chg,
+                                                        const int64_t* __restrict__ list, int64_t nacc,
+                                                        const int32_t* __restrict__ pn,
+                                                        const int32_t* __restrict__ pc) {
+  extern __shared__ __align__(16) double sl[];
+  const int p = lv.pt[l], Tp = nterms(p), ncl = lv.n[l];
+  const int g = p <= 4 ? 16 : p <= 6 ? 32 : 64, ng = 64 / g;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gi = lane / g, gl = lane % g;
+  const int nwb = blockDim.x >> 6;
+  double* F0 = sl + (size_t)ncl * Tp + (size_t)wave * TC_TG;
+  for (int e = threadIdx.x; e < ncl * Tp; e += blockDim.x) sl[e] = 0.0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * nwb * ng;
+  for (int64_t wb = ((int64_t)blockIdx.x * nwb + wave) * ng; wb < nacc; wb += stride) {
+    const int64_t k = wb + gi;
+    const bool has = k < nacc;
+    int c = 0;
+    double dx = 0, dy = 0, dz = 0;
+    double4 xq = make_double4(0, 0, 0, 0);
+    if (has) {
+      const int64_t i = list[k];
+      c = pc[i];
+      xq = chg[pn[i]];
+      tc_offset(lv, l, c, corner, xq, dx, dy, dz);
+    }
+    tc_far<true>(has, dx, dy, dz, 0.0, p, Tp, g, nullptr, nullptr, sl + (size_t)c * Tp, xq.w, F0 + gi * Tp,
+                 nullptr, nullptr, nullptr, nullptr, gl);
+  }
+  __syncthreads();
+  double* lam = lv.lam[l];
+  const int TL = lv.T[l];
+  for (int e = threadIdx.x; e < ncl * Tp; e += blockDim.x) {
+    const double v = sl[e];
+    if (v != 0.0) {
+      const int c = e / Tp;
+      unsafeAtomicAdd(lam + (int64_t)c * TL + (e - c * Tp), v);
+    }
+  }
+}
+
 // children of the pairs that failed, appended in pair order
 __global__ void k_tc_expand(TcLevels lv, int l, int64_t M, const int32_t* __restrict__ pn,
                             const int32_t* __restrict__ pc, const int32_t* __restrict__ nch,
@@ -1884,8 +1932,17 @@ static int tc_visit(fagbi_handle* h, const TcLevels& lv, int l0, const double* c
       int64_t* list = W[9].as<int64_t>();
       k_tc_compact<<<gm, 256, 0, s>>>(M, acc, aoff, list);
       const int p = lv.pt[l], ng = p <= 4 ? 4 : p <= 6 ? 2 : 1;
-      k_tc_far<RHS><<<(unsigned)((nacc + ng - 1) / ng), 64, 0, s>>>(lv, l, kappa, corner, q4, list, nacc, pn, pc,
-                                                                    V);
+      const size_t lds = ((size_t)lv.n[l] * nterms(p) + (size_t)16 * TC_TG) * sizeof(double);
+      if (RHS && (size_t)lv.n[l] * nterms(p) * sizeof(double) <= (size_t)120 * 1024) {
+        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tc_far_rhs_lds),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const int64_t per_block = (int64_t)16 * ng;
+        const unsigned grid = (unsigned)std::min<int64_t>(256, (nacc + per_block - 1) / per_block);
+        k_tc_far_rhs_lds<<<grid, 1024, lds, s>>>(lv, l, corner, q4, list, nacc, pn, pc);
+      } else {
+        k_tc_far<RHS><<<(unsigned)((nacc + ng - 1) / ng), 64, 0, s>>>(lv, l, kappa, corner, q4, list, nacc, pn,
+                                                                      pc, V);
+      }
     }
     if (Mn > TC_MAX_PAIRS)
       return set_error(FAGBI_E_ARG, "treecode: too many (charge, cluster) pairs on one level (theta too small)");
