@@ -514,40 +514,63 @@ __global__ void k_map_ids(const int32_t* __restrict__ ikey, int64_t n, const int
 // leaf-level near-field layout: per leaf c, the source panels of every
 // c' in N(c) in list order, and n_c x S_c entries stored row by row
 // ---------------------------------------------------------------------------
-__global__ void k_leaf_count(const int32_t* __restrict__ nbr_off, const int32_t* __restrict__ nbr,
-                             const int32_t* __restrict__ start, const int32_t* __restrict__ end, int nl,
-                             int32_t* cnt, int64_t* nsrc, int64_t* nent, int32_t* self_col, int32_t* col) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per leaf (launched with 256 threads), lanes over its
+// neighbour leaves: each neighbour's column is the exclusive prefix sum of the
+// neighbours' panel counts in list order
+__global__ void __launch_bounds__(256) k_leaf_count(const int32_t* __restrict__ nbr_off,
+                                                   const int32_t* __restrict__ nbr,
+                                                   const int32_t* __restrict__ start,
+                                                   const int32_t* __restrict__ end, int nl, int32_t* cnt,
+                                                   int64_t* nsrc, int64_t* nent, int32_t* self_col,
+                                                   int32_t* col) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (c >= nl) return;
-  int64_t s = 0;
-  int32_t sc = -1;
-  for (int q = nbr_off[c]; q < nbr_off[c + 1]; ++q) {
-    const int c2 = nbr[q];
-    if (c2 == c) sc = (int32_t)s;
-    col[q] = (int32_t)s;
-    s += end[c2] - start[c2];
+  const int q0 = nbr_off[c], q1 = nbr_off[c + 1];
+  int base = 0, sc = -1;
+  for (int qb = q0; qb < q1; qb += 64) {
+    const int q = qb + lane;
+    const int c2 = q < q1 ? nbr[q] : -1;
+    const int m = q < q1 ? end[c2] - start[c2] : 0;
+    int x = m;   // inclusive scan over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (q < q1) {
+      col[q] = base + x - m;
+      if (c2 == c) sc = base + x - m;
+    }
+    base += __shfl(x, 63, 64);
   }
-  const int nc = end[c] - start[c];
-  cnt[c] = nc;
-  nsrc[c] = s;
-  nent[c] = s * nc;
-  self_col[c] = sc;
+  for (int o = 32; o > 0; o >>= 1) sc = max(sc, __shfl_xor(sc, o, 64));
+  if (lane == 0) {
+    const int nc = end[c] - start[c];
+    cnt[c] = nc;
+    nsrc[c] = base;
+    nent[c] = (int64_t)base * nc;
+    self_col[c] = sc;
+  }
 }
 
-__global__ void __launch_bounds__(64) k_leaf_sources(const int32_t* __restrict__ nbr_off,
+// one wavefront per leaf (256 threads), lanes over its neighbour leaves, each
+// writing that neighbour's run of panels into the leaf's source list
+__global__ void __launch_bounds__(256) k_leaf_sources(const int32_t* __restrict__ nbr_off,
                                                      const int32_t* __restrict__ nbr,
                                                      const int32_t* __restrict__ start,
                                                      const int32_t* __restrict__ end,
                                                      const int64_t* __restrict__ src_off,
-                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ col, int nl,
                                                      int32_t* src_tree, int32_t* leaf_of) {
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  for (int q = nbr_off[c]; q < nbr_off[c + 1]; ++q) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nl) return;
+  const int64_t so = src_off[c];
+  for (int q = nbr_off[c] + lane; q < nbr_off[c + 1]; q += 64) {
     const int c2 = nbr[q];
     const int j0 = start[c2], n2 = end[c2] - j0;
-    const int64_t b = src_off[c] + col[q];
-    for (int j = lane; j < n2; j += 64) src_tree[b + j] = j0 + j;
+    const int64_t b = so + col[q];
+    for (int j = 0; j < n2; ++j) src_tree[b + j] = j0 + j;
   }
   for (int i = start[c] + lane; i < end[c]; i += 64) leaf_of[i] = c;
 }
@@ -887,8 +910,9 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_TRY(h->alloc(h->d_leaf_start, (size_t)nl * 4));
   FAGBI_TRY(h->alloc(h->d_leaf_cnt, (size_t)nl * 4));
   FAGBI_HIP(hipMemcpyAsync(h->d_leaf_start.p, start[L], (size_t)nl * 4, hipMemcpyDeviceToDevice, s));
-  k_leaf_count<<<grid_of(nl), TB, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L], nl, h->d_leaf_cnt.as<int32_t>(),
-                                          nsrc, nent, h->d_self_col.as<int32_t>(), col);
+  k_leaf_count<<<(unsigned)((nl + 3) / 4), 256, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L], nl,
+                                                        h->d_leaf_cnt.as<int32_t>(), nsrc, nent,
+                                                        h->d_self_col.as<int32_t>(), col);
   FAGBI_TRY(h->alloc(h->d_src_off, ((size_t)nl + 1) * 8));
   FAGBI_TRY(h->alloc(h->d_ent_off, ((size_t)nl + 1) * 8));
   FAGBI_TRY(scan_ll(A, nsrc, nl, h->d_src_off.as<int64_t>(), s));
@@ -897,8 +921,9 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_HIP(hipMemcpy(&h->n_ent, h->d_ent_off.as<int64_t>() + nl, 8, hipMemcpyDeviceToHost));
   FAGBI_TRY(h->alloc(h->d_src_tree, (size_t)std::max<int64_t>(1, h->n_src) * 4));
   FAGBI_TRY(h->alloc(h->d_leaf_of, (size_t)N * 4));
-  k_leaf_sources<<<nl, 64, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L], h->d_src_off.as<int64_t>(), col,
-                                   h->d_src_tree.as<int32_t>(), h->d_leaf_of.as<int32_t>());
+  k_leaf_sources<<<(unsigned)((nl + 3) / 4), 256, 0, s>>>(nbr_off[L], nbr[L], start[L], end[L],
+                                                          h->d_src_off.as<int64_t>(), col, nl,
+                                                          h->d_src_tree.as<int32_t>(), h->d_leaf_of.as<int32_t>());
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(to_host(h->leaf_cnt, h->d_leaf_cnt.as<int32_t>(), nl));
   h->max_leaf = 0;
