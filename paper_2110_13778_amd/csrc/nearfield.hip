@@ -591,9 +591,25 @@ __global__ void __launch_bounds__(128) k_block_invert(const double4* __restrict_
     }
   }
   __syncthreads();
+  // elimination with each thread's share of its row (row r, columns
+  // j0 .. j0 + 31) in registers; per step only column k and the scaled pivot
+  // row pass through LDS (double-buffered: two barriers per step)
+  __shared__ double colk[2][64], prow[2][64];
+  double a[32];
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) a[jj] = (r < m && j0 + jj < m) ? A[r][j0 + jj] : 0.0;
   for (int k = 0; k < m; ++k) {
-    // pivot: largest |A[i][k]|, i >= k, smallest index on ties
-    double v = (r >= k && r < m) ? fabs(A[r][k]) : -1.0;
+    const int bk = k & 1, kh = k >> 5, kk = k & 31;
+    if (hf == kh) {   // the wavefront holding column k publishes it
+      double ck = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) ck = jj == kk ? a[jj] : ck;
+      colk[bk][r] = r < m ? ck : 0.0;
+    }
+    __syncthreads();
+    // pivot: largest |A[i][k]|, i >= k, smallest index on ties (both
+    // wavefronts find the same)
+    double v = (r >= k && r < m) ? fabs(colk[bk][r]) : -1.0;
     int vi = r;
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(v, o, 64);
@@ -605,24 +621,38 @@ __global__ void __launch_bounds__(128) k_block_invert(const double4* __restrict_
       if (threadIdx.x == 0) atomicExch(bad, 1);
       return;
     }
-    if (hf == 0 && vi != k && r < m) {
-      const double t = A[k][r];
-      A[k][r] = A[vi][r];
-      A[vi][r] = t;
+    if (vi != k) {   // interchange rows k and vi (lanes k and vi of each wavefront)
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) {
+        const double x = a[jj];
+        const double xk = __shfl(x, k, 64), xv = __shfl(x, vi, 64);
+        a[jj] = r == k ? xv : (r == vi ? xk : x);
+      }
+    }
+    const int rs = r == k ? vi : (r == vi ? k : r);   // this row's pre-interchange index
+    const double d = 1.0 / colk[bk][vi];
+    if (r == k) {
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) {
+        a[jj] = (j0 + jj == k ? 1.0 : a[jj]) * d;
+        prow[bk][j0 + jj] = a[jj];
+      }
     }
     __syncthreads();
-    const double d = 1.0 / A[k][k];
-    __syncthreads();
-    if (hf == 0 && r < m) A[k][r] = (r == k ? 1.0 : A[k][r]) * d;
-    __syncthreads();
-    const double f = (r < m && r != k) ? A[r][k] : 0.0;
-    __syncthreads();   // both halves have read column k before it is overwritten
     if (r < m && r != k) {
-      if (k >= j0 && k < j1) A[r][k] = 0.0;
-      for (int j = j0; j < j1; ++j) A[r][j] -= f * A[k][j];
+      const double f = colk[bk][rs];
+#pragma unroll
+      for (int jj = 0; jj < 32; ++jj) {
+        const double ajj = (hf == kh && jj == kk) ? 0.0 : a[jj];
+        a[jj] = ajj - f * prow[bk][j0 + jj];
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj)
+    if (r < m && j0 + jj < m) A[r][j0 + jj] = a[jj];
+  __syncthreads();
   // undo the row interchanges as column interchanges, last first
   for (int k = m - 1; k >= 0; --k) {
     const int p = swp[k];
