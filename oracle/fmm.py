@@ -79,19 +79,26 @@ def shift_matrix(dvec, p_big, p_small):
     return S
 
 
-def m2l_matrix(x0, kappa, p):
-    """T[alpha, beta] = (alpha+beta)!/(alpha! beta!) (-1)^|beta| F_{alpha+beta}(x0)/(4 pi)
-    for |alpha| + |beta| <= p (the MtL translation, x0 = x_c - x_c')."""
+def m2l_matrices(x0s, kappa, p):
+    """m2l_matrix for several offsets at once: x0s [m, 3] -> [m, T, T].  Every
+    entry is the same expression as in m2l_matrix, evaluated elementwise."""
     mi, pos = _mi(p)
-    F = taylor.coefficients(np.asarray(x0)[None, :], kappa, p)
-    T = np.zeros((len(mi), len(mi)))
+    x0s = np.atleast_2d(np.asarray(x0s, np.float64))
+    F = taylor.coefficients(x0s, kappa, p)
+    T = np.zeros((len(x0s), len(mi), len(mi)))
     for i, al in enumerate(mi):
         for j, be in enumerate(mi):
             if sum(al) + sum(be) <= p:
                 g = (al[0] + be[0], al[1] + be[1], al[2] + be[2])
-                T[i, j] = (taylor.mfact(g) / (taylor.mfact(al) * taylor.mfact(be))
-                           * (-1.0) ** sum(be) * F[g][0] / FOUR_PI)
+                c = taylor.mfact(g) / (taylor.mfact(al) * taylor.mfact(be)) * (-1.0) ** sum(be)
+                T[:, i, j] = c * F[g] / FOUR_PI
     return T
+
+
+def m2l_matrix(x0, kappa, p):
+    """T[alpha, beta] = (alpha+beta)!/(alpha! beta!) (-1)^|beta| F_{alpha+beta}(x0)/(4 pi)
+    for |alpha| + |beta| <= p (the MtL translation, x0 = x_c - x_c')."""
+    return m2l_matrices(np.asarray(x0)[None, :], kappa, p)[0]
 
 
 def setup(P, tree, eps, kappa, p_leaf=4, adaptive=False, p_max=8,
@@ -209,13 +216,12 @@ def far_field(F, phi, dphi):
         off = cl.idx[tgt] - cl.idx[src]              # x_c - x_c' = off * h
         uo, inv = np.unique(off, axis=0, return_inverse=True)
         inv = inv.ravel()
+        T0s = m2l_matrices(uo * cl.h, 0.0, pl[l])
+        Tks = m2l_matrices(uo * cl.h, kappa, pl[l])
         for k in range(len(uo)):
             sel = np.nonzero(inv == k)[0]
-            x0 = uo[k] * cl.h
-            T0 = m2l_matrix(x0, 0.0, pl[l])
-            Tk = m2l_matrix(x0, kappa, pl[l])
-            np.add.at(lam0[l], tgt[sel], M0[l][src[sel]] @ T0.T)
-            np.add.at(lamk[l], tgt[sel], Mk[l][src[sel]] @ Tk.T)
+            np.add.at(lam0[l], tgt[sel], M0[l][src[sel]] @ T0s[k].T)
+            np.add.at(lamk[l], tgt[sel], Mk[l][src[sel]] @ Tks[k].T)
     # step 5: downward pass
     downward(F, lam0, tree.lmin)
     downward(F, lamk, tree.lmin)
@@ -253,3 +259,52 @@ def coverage(tree):
             for c2 in cl.inter[c]:
                 C[np.ix_(desc[l][c], desc[l][c2])] += 1
     return C
+
+
+def far_field_rows(F, phi, dphi, leaves):
+    """The far field of far_field() at the panels of the given leaves only:
+    the full upward pass (steps 2, 3), then the interaction phase (step 4) for
+    the ancestors of these leaves alone, the downward pass (step 5) along their
+    ancestor chains and the evaluation (step 6) at their panels.  Every
+    computed local is the same sum as in far_field (one matrix per offset),
+    taken for fewer targets.  Returns (panel ids [m], f1 [m], f2 [m])."""
+    tree, eps, kappa, pl = F.tree, F.eps, F.kappa, F.orders
+    L, perm = tree.L, tree.perm
+    levels = tree.levels
+    M0, Mk = upward(F, phi, dphi)
+    anc = {L: np.unique(np.asarray(leaves, np.int64))}
+    for l in range(L - 1, tree.lmin - 1, -1):
+        anc[l] = np.unique(levels[l + 1].parent[anc[l + 1]])
+    lam0, lamk = {}, {}
+    for l in range(tree.lmin, L + 1):
+        cl = levels[l]
+        T = len(_mi(pl[l])[0])
+        lam0[l] = np.zeros((len(anc[l]), T))
+        lamk[l] = np.zeros((len(anc[l]), T))
+        for k, c in enumerate(anc[l]):
+            src = np.asarray(cl.inter[c], np.int64)
+            if len(src) == 0:
+                continue
+            x0 = (cl.idx[c][None, :] - cl.idx[src]) * cl.h
+            T0s = m2l_matrices(x0, 0.0, pl[l])
+            Tks = m2l_matrices(x0, kappa, pl[l])
+            lam0[l][k] = np.einsum("sab,sb->a", T0s, M0[l][src])
+            lamk[l][k] = np.einsum("sab,sb->a", Tks, Mk[l][src])
+    for l in range(tree.lmin, L):
+        ch = levels[l + 1]
+        where = {c: k for k, c in enumerate(anc[l])}
+        for k, c in enumerate(anc[l + 1]):
+            o = ch.idx[c] & 1
+            dvec = (o - 0.5) * ch.h
+            S = shift_matrix(dvec, pl[l], pl[l + 1])
+            p = where[ch.parent[c]]
+            lam0[l + 1][k] += lam0[l][p] @ S
+            lamk[l + 1][k] += lamk[l][p] @ S
+    leaf = levels[L]
+    ids, f1, f2 = [], [], []
+    for k, c in enumerate(anc[L]):
+        tpos = np.arange(leaf.start[c], leaf.end[c])
+        ids.append(perm[tpos])
+        f1.append(-((lam0[L][k] + lamk[L][k]) * F.ms[tpos]).sum(1))
+        f2.append(-((lam0[L][k] + lamk[L][k] / eps) * F.md[tpos]).sum(1))
+    return np.concatenate(ids), np.concatenate(f1), np.concatenate(f2)

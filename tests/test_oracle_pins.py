@@ -303,3 +303,123 @@ def test_gmres_matches_direct_solve():
     D = np.diag(A)
     x2, it2, _ = solve.gmres(lambda z: A @ z, b, 1e-12, 40, precond=lambda z: z / D)
     assert np.allclose(x2, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
+
+
+def _close_panels():
+    """three mutually non-touching, non-coplanar triangles at 1.5-2.5 h"""
+    verts = np.array([[0, 0, 0], [1.0, 0, 0], [0.4, 0.8, 0.1],
+                      [1.25, 0.1, 0.05], [2.0, 0.6, 0.3], [1.3, 0.9, -0.15],
+                      [0.2, -0.35, 0.0], [1.1, -0.5, 0.2], [0.6, -1.2, -0.1]])
+    return panels(verts, np.array([[0, 1, 2], [3, 4, 5], [7, 6, 8]]))
+
+
+@pytest.mark.parametrize("pair", [(0, 1), (0, 2), (1, 0)])
+def test_close_rule_matches_closed_forms(pair):
+    """The close-pair rule (Duffy-collapsed Gauss rule on both triangles)
+    against the Wilton single-layer and Van Oosterom-Strackee double-layer
+    closed forms integrated over the target by a fine composite rule: the
+    pairs are closer than 2 h, so the rule's class is CLOSE, and the error
+    falls geometrically with n."""
+    P = _close_panels()
+    i, j = np.array([pair[0]]), np.array([pair[1]])
+    assert pairs.classify(P, i, j, 2.0)[0] == pairs.CLOSE
+    s, d = _reference(P, pair[0], pair[1])
+    err = {}
+    for n in (3, 5, 7):
+        I = pairs.close(P, i, j, 0.0, n, kern=_g0_kernels)[0]
+        err[n] = (abs(I[0] - s) / abs(s), abs(I[1] - d) / abs(d))
+    assert err[7][0] < 1e-8 and err[7][1] < 1e-6, err
+    assert err[7][0] < 1e-2 * err[3][0] and err[7][1] < 1e-2 * err[3][1], err
+
+
+def test_touching_and_close_rules_symmetric_under_swap(sphere320):
+    """The rules applied with the two panels exchanged (no mirroring) give the
+    transposed integrals to the rules' own accuracy: I1, I6 symmetric,
+    I2 <-> I4 and I3 <-> I5 (the kernels depend on x - y only).  The mirrored
+    values the oracle stores are therefore the integrals of either order."""
+    P, _ = sphere320
+    kap = 0.1257
+    swap = [0, 3, 4, 1, 2, 5]
+    tris = P.tris
+    sh = (tris[:, None, :, None] == tris[None, :, None, :]).any(3).sum(2)
+    for rule, cnt, tol in ((pairs.edge, 2, 1e-8), (pairs.vertex, 1, 1e-8)):
+        ii, jj = np.nonzero(sh == cnt)
+        ii, jj = ii[:40], jj[:40]
+        a = rule(P, ii, jj, kap, 7)
+        b = rule(P, jj, ii, kap, 7)[:, swap]
+        scale = np.abs(a).max(0)
+        assert (np.abs(a - b) / scale).max() < tol
+    Pc = _close_panels()
+    a = pairs.close(Pc, np.array([0, 0]), np.array([1, 2]), kap, 7)
+    b = pairs.close(Pc, np.array([1, 2]), np.array([0, 0]), kap, 7)[:, swap]
+    assert (np.abs(a - b) / np.abs(a).max(0)).max() < 1e-12
+
+
+def _precond_matrix(Minv, n2):
+    """the matrix M of a preconditioner from its inverse's columns"""
+    Mi = np.stack([Minv(np.eye(n2)[k]) for k in range(n2)], 1)
+    return np.linalg.inv(Mi)
+
+
+def test_block_preconditioner_pins():
+    """Sec. 2.6 block-diagonal preconditioner against the dense operator A:
+    (1) one leaf holding every panel with eta0 = 0: M = A, so M^{-1} A x = x;
+    (2) leaf blocks: M_ij = A_ij for panels of one leaf (in both unknown
+        blocks, identity terms included), 0 elsewhere;
+    (3) groups of consecutive leaves (tree order) of at most 32 panels: M_ij =
+        A_ij for panels of one group whose leaves are neighbours, 0 elsewhere,
+        and each group is maximal (the next leaf would exceed 32 panels)."""
+    v, t = icosphere(1, 2.0)
+    P = panels(v, t)
+    N = P.n
+    eps, kap = 80.0, 0.1257
+    A = dense.assemble(P, eps, kap)
+    x = np.random.default_rng(8).standard_normal(2 * N)
+    one = otree.build(P, N, 0.0)
+    assert one.L == 0
+    Minv = solve.block_preconditioner(P, one, eps, kap)
+    assert np.linalg.norm(Minv(A @ x) - x) < 1e-12 * np.linalg.norm(x)
+    tr = otree.build(P, 8, 0.8)
+    leaf = tr.levels[tr.L]
+    lf = np.empty(N, np.int64)
+    lf[tr.perm] = np.repeat(np.arange(leaf.n), leaf.end - leaf.start)
+    same2 = lambda m: np.block([[m, m], [m, m]])
+    M = _precond_matrix(solve.block_preconditioner(P, tr, eps, kap), 2 * N)
+    keep = same2(lf[:, None] == lf[None, :])
+    scale = np.abs(A).max()
+    assert np.abs(M[keep] - A[keep]).max() < 1e-13 * scale
+    assert np.abs(M[~keep]).max() < 1e-13 * scale
+    # groups: greedy runs of consecutive leaves up to 32 panels
+    sizes = leaf.end - leaf.start
+    grp, g, cnt = np.empty(leaf.n, np.int64), 0, 0
+    for c in range(leaf.n):
+        if cnt and cnt + sizes[c] > 32:
+            g, cnt = g + 1, 0
+        grp[c] = g
+        cnt += sizes[c]
+    for k in range(g):       # maximal: the next group's first leaf does not fit
+        assert sizes[grp == k].sum() + sizes[np.nonzero(grp == k + 1)[0][0]] > 32
+    nb = np.zeros((leaf.n, leaf.n), bool)
+    for c in range(leaf.n):
+        nb[c, leaf.nbr[c]] = True
+    M = _precond_matrix(solve.block_preconditioner(P, tr, eps, kap, group_max=32), 2 * N)
+    keep = same2((grp[lf][:, None] == grp[lf][None, :]) & nb[lf][:, lf])
+    assert np.abs(M[keep] - A[keep]).max() < 1e-13 * scale
+    assert np.abs(M[~keep]).max() < 1e-13 * scale
+    assert (grp[lf][:, None] == grp[lf][None, :]).sum() > (lf[:, None] == lf[None, :]).sum()
+
+
+def test_far_field_rows_equal_far_field():
+    """The restricted far field (ancestor chains of a few leaves) equals the
+    full far field at those panels, at adaptive orders 5..8."""
+    v, t = icosphere(3, 2.0)
+    P = panels(v, t)
+    tr = otree.build(P, 4, 0.8)
+    O = fmm.setup(P, tr, 80.0, 0.1257, p_leaf=5, adaptive=1, p_max=8, with_near=False)
+    x = np.random.default_rng(9).standard_normal(2 * P.n)
+    f1, f2 = fmm.far_field(O, x[:P.n], x[P.n:])
+    leaves = np.random.default_rng(10).choice(tr.levels[tr.L].n, 10, replace=False)
+    ids, g1, g2 = fmm.far_field_rows(O, x[:P.n], x[P.n:], leaves)
+    assert len(ids) == (tr.levels[tr.L].end - tr.levels[tr.L].start)[leaves].sum()
+    assert np.abs(g1 - f1[ids]).max() < 1e-13 * np.abs(f1).max()
+    assert np.abs(g2 - f2[ids]).max() < 1e-13 * np.abs(f2).max()
