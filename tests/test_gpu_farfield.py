@@ -1,0 +1,86 @@
+"""The far field alone (FAGBI_PART_FAR: moments, MtM, MtL, LtL, LtP; no near
+field, no identity terms) against the oracle's far field (Sec. 2.4, steps 2-6)
+on trees whose interaction levels run every MtL order from 3 to 8, i.e. every
+translation kernel the benchmark dispatches (register, LDS-table and slot
+kernels, FP32 and FP64).  Tolerances: FP64 1e-11, mixed (FP32 expansions)
+1e-6, both as relative L2 over the vector and as the largest row error
+relative to the largest row (a single bad row cannot hide under the norm)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2110_13778_amd as F  # noqa: E402
+from oracle import fmm as ofmm  # noqa: E402
+from oracle import tree as otree  # noqa: E402
+from oracle.geometry import panels  # noqa: E402
+from synth import icosphere  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+EPS, KAP = 80.0, 0.1257
+DEV = "cuda:0"
+
+
+def errs(got, ref):
+    d = np.asarray(got) - np.asarray(ref)
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            float(np.abs(d).max() / np.abs(ref).max()))
+
+
+def far_gpu(h, x, prec):
+    xd = torch.tensor(x, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(xd)
+    h.matvec(xd, y, prec, F.PART_FAR)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def sphere5120():
+    v, t = icosphere(4, 2.0)
+    return v, t, panels(v, t)
+
+
+# 5,120 panels, leaf 4: levels 2..5 interact; p_leaf 3 gives MtL orders
+# 6, 5, 4, 3 and p_leaf 5 gives 8, 7, 6, 5 (adaptive, p_max 8)
+@pytest.mark.parametrize("p_leaf", [3, 5])
+def test_far_field_every_order(sphere5120, p_leaf):
+    v, t, P = sphere5120
+    prm = dict(leaf_size=4, eta0=0.8, p_leaf=p_leaf, adaptive=1, p_max=8)
+    h = F.Handle(eps_out=EPS, kappa=KAP, **prm).build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, 4, 0.8)
+    ti = h.tree_info()
+    orders = otree.orders(tr, p_leaf, 1, 8)
+    used = {orders[l] for l in range(tr.lmin, tr.L + 1) if ti.lev_pairs[l] > 0}
+    assert used == ({3, 4, 5, 6} if p_leaf == 3 else {5, 6, 7, 8}), used
+    assert [ti.lev_order[l] for l in range(tr.L + 1)] == orders
+    O = ofmm.setup(P, tr, EPS, KAP, p_leaf=p_leaf, adaptive=1, p_max=8, with_near=False)
+    rng = np.random.default_rng(30 + p_leaf)
+    for _ in range(2):
+        x = rng.standard_normal(2 * P.n)
+        ref = np.concatenate(ofmm.far_field(O, x[:P.n], x[P.n:]))
+        e64 = errs(far_gpu(h, x, F.FP64), ref)
+        e32 = errs(far_gpu(h, x, F.MIXED), ref)
+        print("p_leaf %d: FP64 rel-L2 %.2e max-row %.2e; mixed rel-L2 %.2e max-row %.2e"
+              % (p_leaf, e64[0], e64[1], e32[0], e32[1]))
+        assert e64[0] < 1e-11 and e64[1] < 1e-11, e64
+        assert e32[0] < 1e-6 and e32[1] < 1e-6, e32
+    h.close()
+
+
+def test_far_field_fixed_order8(sphere5120):
+    """fixed order 8 on every level (the slot MtM / LtL kernels at 8 -> 8)"""
+    v, t, P = sphere5120
+    h = F.Handle(eps_out=EPS, kappa=KAP, leaf_size=8, eta0=0.8, p_leaf=8, adaptive=0).build_tree(v, t)
+    h.assemble_nearfield()
+    tr = otree.build(P, 8, 0.8)
+    O = ofmm.setup(P, tr, EPS, KAP, p_leaf=8, adaptive=0, with_near=False)
+    x = np.random.default_rng(40).standard_normal(2 * P.n)
+    ref = np.concatenate(ofmm.far_field(O, x[:P.n], x[P.n:]))
+    e64 = errs(far_gpu(h, x, F.FP64), ref)
+    e32 = errs(far_gpu(h, x, F.MIXED), ref)
+    print("fixed p 8: FP64 rel-L2 %.2e max-row %.2e; mixed rel-L2 %.2e max-row %.2e"
+          % (e64[0], e64[1], e32[0], e32[1]))
+    assert e64[0] < 1e-11 and e64[1] < 1e-11, e64
+    assert e32[0] < 1e-6 and e32[1] < 1e-6, e32
+    h.close()

@@ -6,6 +6,12 @@ orders 3..8).  The oracle cannot run the whole operator at this size, so:
 * the near field: sampled rows (every panel of randomly drawn leaves) against
   the oracle's pair integrals over the oracle tree's neighbour lists, FP64 to
   1e-11 and FP32 to 1e-6;
+* the far field: rows of FAGBI_PART_FAR at every panel of 24 randomly drawn
+  leaves against the oracle's far field restricted to those leaves (its full
+  upward pass, then MtL for their ancestors, LtL down their ancestor chains
+  and LtP at their panels): every MtL order 3..8 and the benchmark's launch
+  configuration, FP64 to 1e-11 and FP32 to 1e-6 (relative L2 and the largest
+  row error relative to the largest row);
 * the whole operator: FP32 against FP64 (property: same algorithm, so the
   difference is rounding), and sampled rows against the dense oracle rows
   within a bound far above the Taylor truncation and far below what a lost
@@ -19,6 +25,7 @@ torch = pytest.importorskip("torch")
 
 import paper_2110_13778_amd as F  # noqa: E402
 from oracle import dense as odense  # noqa: E402
+from oracle import fmm as ofmm  # noqa: E402
 from oracle import tree as otree  # noqa: E402
 from oracle.geometry import panels  # noqa: E402
 from oracle.kernels import combine  # noqa: E402
@@ -90,6 +97,29 @@ def test_sampled_near_rows_match_oracle(big):
         y = gpu_matvec(h, x, prec, F.PART_NEAR)
         got = np.concatenate([y[rows], y[N + rows]])
         assert rel(got, ref) < tol, prec
+
+
+def test_sampled_far_field_rows_match_oracle(big):
+    P, tr, h, eps, w = big["P"], big["tr"], big["h"], big["eps"], big["w"]
+    N = P.n
+    orders = otree.orders(tr, PARAMS["p_leaf"], PARAMS["adaptive"], PARAMS["p_max"])
+    ti = h.tree_info()
+    assert {orders[l] for l in range(tr.lmin, tr.L + 1) if ti.lev_pairs[l] > 0} == {3, 4, 5, 6, 7, 8}
+    O = ofmm.setup(P, tr, eps, w["kappa"], p_leaf=PARAMS["p_leaf"], adaptive=PARAMS["adaptive"],
+                   p_max=PARAMS["p_max"], with_near=False)
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(2 * N)
+    leaves = rng.choice(tr.levels[tr.L].n, 24, replace=False)
+    ids, f1, f2 = ofmm.far_field_rows(O, x[:N], x[N:], leaves)
+    ref = np.concatenate([f1, f2])
+    for prec, tol in ((F.FP64, 1e-11), (F.MIXED, 1e-6)):
+        y = gpu_matvec(h, x, prec, F.PART_FAR)
+        got = np.concatenate([y[ids], y[N + ids]])
+        e = rel(got, ref)
+        em = np.abs(got - ref).max() / np.abs(ref).max()
+        print("far-field rows (%d panels), %s: rel-L2 %.2e, max-row %.2e"
+              % (len(ids), "fp64" if prec == F.FP64 else "fp32", e, em))
+        assert e < tol and em < tol, prec
 
 
 def test_full_operator_precisions_and_sampled_dense_rows(big):
