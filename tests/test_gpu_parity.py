@@ -25,6 +25,11 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
 
 
+def maxrow(a, b):
+    """largest row error relative to the largest row"""
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
 def dev(x):
     return torch.tensor(np.asarray(x), dtype=torch.float64, device=DEV)
 
@@ -85,15 +90,16 @@ def test_fmm_matches_oracle_fmm(sphere1280, cfg):
     rng = np.random.default_rng(2)
     x = rng.standard_normal(2 * P.n)
     ref = ofmm.matvec(O, x)
-    assert rel(gpu_matvec(h, x), ref) < 1e-11
-    assert rel(gpu_matvec(h, x, F.MIXED), ref) < 1e-6
+    y64, y32 = gpu_matvec(h, x), gpu_matvec(h, x, F.MIXED)
+    assert rel(y64, ref) < 1e-11 and maxrow(y64, ref) < 1e-11
+    assert rel(y32, ref) < 1e-6 and maxrow(y32, ref) < 1e-6
     # near and far parts separately: the near part carries the identity
     # terms (folded into the stored diagonal), the far part is the far field
     # alone (steps 2-6 of the FMM)
     assert rel(gpu_matvec(h, x, parts=F.PART_NEAR), ofmm.matvec(O, x, far=False)) < 1e-11
     far = np.concatenate(ofmm.far_field(O, x[:P.n], x[P.n:]))
     assert rel(gpu_matvec(h, x, parts=F.PART_FAR), far) < 1e-11
-    assert rel(gpu_matvec(h, x, F.MIXED, parts=F.PART_FAR), far) < 1e-6
+    assert rel(gpu_matvec(h, x, F.MIXED, parts=F.PART_FAR), far) < 2e-6
     h.close()
 
 
