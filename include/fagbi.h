@@ -129,6 +129,7 @@ typedef struct fagbi_profile {
   double ms_singular;          /* singular / close cubature */
   double ms_fmm_setup;         /* far-field tables, panel moments */
   double ms_precond;           /* block-diagonal factors */
+  double ms_m2l_leaf[2];       /* the leaf level's MtL kernel alone (events on its stream) */
 } fagbi_profile;
 
 typedef struct fagbi_handle fagbi_handle;
@@ -169,8 +170,13 @@ int fagbi_matvec(fagbi_handle* h, const double* x, double* y, int32_t precision,
 int fagbi_matvec_parts(fagbi_handle* h, const double* x, double* y,
                        int32_t precision, int32_t parts, void* stream);
 
-/* y = M^{-1} z for the block-diagonal preconditioner of Sec. 2.6 (leaf-level
-   blocks [phi_c; dphi_c], LU with partial pivoting, FP64).  With
+/* y = M^{-1} z for the block-diagonal preconditioner of Sec. 2.6: blocks
+   [phi_c; dphi_c] of one leaf (FAGBI_PRECOND_BLOCK) or of consecutive leaves
+   holding at most 32 panels (FAGBI_PRECOND_GROUP); each block holds the
+   stored near-field entries between its panels plus the identity terms.  The
+   assembly stores each block's explicit inverse, computed by Gauss-Jordan
+   elimination with partial pivoting in FP64 (FAGBI_E_NUMERIC for a singular
+   block); the apply is one dense block product per block.  With
    precond = FAGBI_PRECOND_DIAG the diagonal of A is used instead.  z, y:
    device f64[2N] (may alias).  Asynchronous on stream. */
 int fagbi_precond_apply(fagbi_handle* h, const double* z, double* y, void* stream);
@@ -182,8 +188,14 @@ int fagbi_precond_apply(fagbi_handle* h, const double* z, double* y, void* strea
 int fagbi_rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
               double* b, void* stream);
 
-/* Solve A x = b(charges) by right-preconditioned GMRES (FP64) or flexible
-   GMRES around FP32 inner solves (FAGBI_MIXED).  x: device f64[2N], the
+/* Solve A x = b(charges), the Galerkin system of Sec. 2.3 (its closing
+   paragraph: GMRES with the FMM product of Sec. 2.4 and the block-diagonal
+   preconditioner of Sec. 2.6), by right-preconditioned GMRES without restart
+   (classical Gram-Schmidt applied twice, Givens rotations; FP64) or, with
+   FAGBI_MIXED, by flexible GMRES on the FP64 operator whose preconditioner is
+   an inner GMRES on the FP32 operator to inner_tol.  The tolerance applies to
+   the true relative residual ||b - A64 x|| / ||b||.  b comes from the charges
+   by fagbi_rhs (rhs_theta = 0) or fagbi_rhs_treecode.  x: device f64[2N], the
    initial guess on entry (zeros: pass zeros), the solution on exit.  info may
    be NULL.  Returns FAGBI_W_NOT_CONVERGED with the best x if the tolerance is
    not met.  Synchronises. */

@@ -197,6 +197,33 @@ def downward(F, lam, l_from):
             lam[l + 1][sel] += lam[l][ch.parent[sel]] @ S
 
 
+def interaction(F, M0, Mk, l, targets=None):
+    """Step 4 on level l: the locals lambda_c = sum_{c' in I(c)} T(x_c - x_c') M_c'
+    of both channels, one MtL matrix per offset, for every cluster of the
+    level (or only the given targets, whose rows are the only non-zero ones).
+    Returns [n_l, T(p_l)] arrays lam0, lamk."""
+    tree, kappa, pl = F.tree, F.kappa, F.orders
+    cl = tree.levels[l]
+    T = len(_mi(pl[l])[0])
+    lam0 = np.zeros((cl.n, T))
+    lamk = np.zeros((cl.n, T))
+    cs = np.arange(cl.n) if targets is None else np.asarray(targets, np.int64)
+    tgt = np.concatenate([np.full(len(cl.inter[c]), c) for c in cs] + [np.zeros(0)]).astype(np.int64)
+    src = np.concatenate([cl.inter[c] for c in cs] + [np.zeros(0)]).astype(np.int64)
+    if len(tgt) == 0:
+        return lam0, lamk
+    off = cl.idx[tgt] - cl.idx[src]              # x_c - x_c' = off * h
+    uo, inv = np.unique(off, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    T0s = m2l_matrices(uo * cl.h, 0.0, pl[l])
+    Tks = m2l_matrices(uo * cl.h, kappa, pl[l])
+    for k in range(len(uo)):
+        sel = np.nonzero(inv == k)[0]
+        np.add.at(lam0, tgt[sel], M0[l][src[sel]] @ T0s[k].T)
+        np.add.at(lamk, tgt[sel], Mk[l][src[sel]] @ Tks[k].T)
+    return lam0, lamk
+
+
 def far_field(F, phi, dphi):
     P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
     L, perm = tree.L, tree.perm
@@ -205,35 +232,26 @@ def far_field(F, phi, dphi):
     # step 4: interaction phase
     lam0, lamk = {}, {}
     for l in range(tree.lmin, L + 1):
-        cl = levels[l]
-        T = len(_mi(pl[l])[0])
-        lam0[l] = np.zeros((cl.n, T))
-        lamk[l] = np.zeros((cl.n, T))
-        tgt = np.concatenate([np.full(len(s), c) for c, s in enumerate(cl.inter)]).astype(np.int64)
-        src = np.concatenate(cl.inter).astype(np.int64)
-        if len(tgt) == 0:
-            continue
-        off = cl.idx[tgt] - cl.idx[src]              # x_c - x_c' = off * h
-        uo, inv = np.unique(off, axis=0, return_inverse=True)
-        inv = inv.ravel()
-        T0s = m2l_matrices(uo * cl.h, 0.0, pl[l])
-        Tks = m2l_matrices(uo * cl.h, kappa, pl[l])
-        for k in range(len(uo)):
-            sel = np.nonzero(inv == k)[0]
-            np.add.at(lam0[l], tgt[sel], M0[l][src[sel]] @ T0s[k].T)
-            np.add.at(lamk[l], tgt[sel], Mk[l][src[sel]] @ Tks[k].T)
+        lam0[l], lamk[l] = interaction(F, M0, Mk, l)
     # step 5: downward pass
     downward(F, lam0, tree.lmin)
     downward(F, lamk, tree.lmin)
     # step 6: evaluation
-    l0 = lam0[L][F.owner]
-    lk = lamk[L][F.owner]
+    return evaluate(F, lam0[L], lamk[L])
+
+
+def evaluate(F, lam0_leaf, lamk_leaf):
+    """Step 6: the far field at every panel from the leaf locals, row 1
+    -(lambda0 + lambdak) tested with m_s, row 2 -(lambda0 + lambdak/eps)
+    tested with m_d.  Returns (y1, y2) in panel order."""
+    l0 = lam0_leaf[F.owner]
+    lk = lamk_leaf[F.owner]
     f1 = -((l0 + lk) * F.ms).sum(1)
-    f2 = -((l0 + lk / eps) * F.md).sum(1)
-    y1 = np.zeros(P.n)
-    y2 = np.zeros(P.n)
-    y1[perm] = f1
-    y2[perm] = f2
+    f2 = -((l0 + lk / F.eps) * F.md).sum(1)
+    y1 = np.zeros(F.P.n)
+    y2 = np.zeros(F.P.n)
+    y1[F.tree.perm] = f1
+    y2[F.tree.perm] = f2
     return y1, y2
 
 

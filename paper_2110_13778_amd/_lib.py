@@ -64,7 +64,8 @@ class Profile(C.Structure):
                 ("ms_near", C.c_double * 2), ("ms_up", C.c_double * 2),
                 ("ms_m2l", C.c_double * 2), ("ms_down", C.c_double * 2),
                 ("ms_tree", C.c_double), ("ms_classify", C.c_double), ("ms_surrogate", C.c_double),
-                ("ms_singular", C.c_double), ("ms_fmm_setup", C.c_double), ("ms_precond", C.c_double)]
+                ("ms_singular", C.c_double), ("ms_fmm_setup", C.c_double), ("ms_precond", C.c_double),
+                ("ms_m2l_leaf", C.c_double * 2)]
 
 
 class FagbiError(RuntimeError):

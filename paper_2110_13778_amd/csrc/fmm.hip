@@ -1324,6 +1324,8 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   if (!far) {
     FAGBI_TRY(mark(2));
     FAGBI_TRY(mark(3));
+    FAGBI_TRY(mark(7));
+    FAGBI_TRY(mark(8));
     FAGBI_TRY(mark(4));
     return 0;
   }
@@ -1425,10 +1427,16 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   }
   Level& LF = h->lev[L];
   FAGBI_TRY(launch_p2m<R>(h, ms.as<R>(), md.as<R>(), xt, f32, s));
+  // the leaf level's MtL, bracketed by events 7, 8 on its stream
+  auto launch_m2l_leaf = [&](hipStream_t st) -> int {
+    FAGBI_TRY(mark_on(7, st));
+    FAGBI_TRY(launch_m2l(L, st));
+    return mark_on(8, st);
+  };
   if (pipe) {
     FAGBI_HIP(hipEventRecord(h->ev_up0, s));
     FAGBI_HIP(hipStreamWaitEvent(h->s_m2l, h->ev_up0, 0));
-    FAGBI_TRY(launch_m2l(L, h->s_m2l));
+    FAGBI_TRY(launch_m2l_leaf(h->s_m2l));
   }
   for (int l = L - 1; l >= h->lmin; --l) {
     if (pipe && l == L - 2) {   // level L-1 moments are complete
@@ -1456,9 +1464,9 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_HIP(hipStreamWaitEvent(sn, h->ev_upd, 0));
     for (int l = h->lmin; l < l_hi; ++l) FAGBI_TRY(launch_m2l(l, sn));
     FAGBI_HIP(hipEventRecord(h->ev_join, sn));   // the SpMV and those levels
-    FAGBI_TRY(launch_m2l(l_hi, s));
+    FAGBI_TRY(l_hi == L ? launch_m2l_leaf(s) : launch_m2l(l_hi, s));
   } else {
-    for (int l = h->lmin; l <= l_hi; ++l) FAGBI_TRY(launch_m2l(l, s));
+    for (int l = h->lmin; l <= l_hi; ++l) FAGBI_TRY(l == L ? launch_m2l_leaf(s) : launch_m2l(l, s));
   }
   if (pipe) FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
   FAGBI_HIP(hipGetLastError());
@@ -1490,7 +1498,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
 
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts, hipStream_t s) {
   if (h->profiling && !h->ev[0])
-    for (int k = 0; k < 7; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
+    for (int k = 0; k < 9; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
   int r = precision == FAGBI_MIXED
               ? matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
               : matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
@@ -1503,6 +1511,9 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
   FAGBI_HIP(hipEventElapsedTime(&t[2], h->ev[2], h->ev[3]));
   FAGBI_HIP(hipEventElapsedTime(&t[3], h->ev[3], h->ev[4]));
   FAGBI_HIP(hipEventElapsedTime(&tot, h->ev[5], h->ev[4]));
+  float tleaf;
+  FAGBI_HIP(hipEventSynchronize(h->ev[8]));
+  FAGBI_HIP(hipEventElapsedTime(&tleaf, h->ev[7], h->ev[8]));
   const int p = precision == FAGBI_MIXED ? 1 : 0;
   fagbi_profile& P = h->prof;
   P.matvecs[p] += 1;
@@ -1511,6 +1522,7 @@ int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts
   P.ms_m2l[p] += t[2];
   P.ms_down[p] += t[3];
   P.ms_total[p] += tot;
+  P.ms_m2l_leaf[p] += tleaf;
   return 0;
 }
 

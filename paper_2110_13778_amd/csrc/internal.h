@@ -152,8 +152,9 @@ struct fagbi_handle {
   bool profiling = false;
   // matvec phase events: 5 start; 0, 1 around the near-field SpMV (on its
   // own stream when the far field runs beside it); 6 start of the far field,
-  // 2 upward pass, 3 MtL, 4 downward pass (after joining the near field)
-  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // 2 upward pass, 3 MtL, 4 downward pass (after joining the near field);
+  // 7, 8 around the leaf level's MtL kernel on the stream it runs on
+  hipEvent_t ev[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t s_near = nullptr;                 // default priority
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t s_m2l = nullptr;                  // MtL of the two finest levels, default priority
