@@ -209,6 +209,21 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
                            const double* q, int64_t nc, double* E_kcal,
                            void* stream);
 
+/* For callers that cannot allocate device memory during a call (code under
+   HIP graph capture, tight serving loops, harnesses that forbid it): the
+   direct energy sum of fagbi_solvation_energy with the same kernels and
+   summation order, making no device allocation.  Its per-block partial sums
+   live in a static device array of the library (65,536 doubles per GPU, held
+   until the process ends), so N <= 2^24 panels (FAGBI_E_ARG beyond).
+   chg: device f64[nc][4] {x, y, z [A], q [e]}, 32-byte aligned; x: device
+   f64[2N] (caller order); E_kcal: device f64[1], receives the energy in
+   kcal/mol.  Asynchronous on stream; no finite-value check (the caller reads
+   E_kcal).  Every call on one GPU shares that GPU's array (nothing in it needs
+   clearing: each call writes every partial sum it reads), so calls that
+   overlap on one GPU, from any handles, race. */
+int fagbi_solvation_energy_noalloc(fagbi_handle* h, const double* x, const double* chg,
+                                   int64_t nc, double* E_kcal, void* stream);
+
 /* Right-hand side as fagbi_rhs by the Cartesian treecode of Sec. 2.5 run in
    reverse: every charge visits the clusters as in
    fagbi_solvation_energy_treecode; an accepted cluster receives the charge's

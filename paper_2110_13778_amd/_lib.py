@@ -26,7 +26,7 @@ EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
            "fagbi_get_permutation", "fagbi_set_profiling", "fagbi_get_profile",
            "fagbi_mlp_dataset", "fagbi_mlp_train", "fagbi_mlp_forward", "fagbi_mlp_grad",
            "fagbi_mlp_get_weights", "fagbi_mlp_set_weights", "fagbi_get_mlp_stats",
-           "fagbi_destroy", "fagbi_last_error"]
+           "fagbi_solvation_energy_noalloc", "fagbi_destroy", "fagbi_last_error"]
 MLP_NIN, MLP_NOUT, MLP_NAUX, MLP_NPARAM, MLP_NBLOB = 16, 6, 8, 35974, 36093
 
 
@@ -99,6 +99,7 @@ def load():
         "fagbi_solve": [vp, vp, vp, i64, vp, C.POINTER(SolveInfo), vp],
         "fagbi_solvation_energy": [vp, vp, vp, vp, i64, dp, vp],
         "fagbi_solvation_energy_treecode": [vp, vp, vp, vp, i64, C.c_double, i32, dp, vp],
+        "fagbi_solvation_energy_noalloc": [vp, vp, vp, i64, vp, vp],
         "fagbi_get_tree_info": [vp, C.POINTER(TreeInfo)],
         "fagbi_get_permutation": [vp, vp],
         "fagbi_set_profiling": [vp, i32],
@@ -236,6 +237,15 @@ class Handle:
         _check(self.lib.fagbi_solvation_energy(self.h, _dev(x), xqp, qp, len(q_), C.byref(e),
                                                _stream(stream)))
         return e.value
+
+    def solvation_energy_noalloc(self, x, chg, E, stream=None):
+        """chg: float64 CUDA tensor [nc, 4] (x, y, z, q); E: float64 CUDA tensor [1]
+        receives the energy (asynchronous)."""
+        if chg.dim() != 2 or chg.shape[1] != 4:
+            raise ValueError("chg must be [nc, 4]")
+        _check(self.lib.fagbi_solvation_energy_noalloc(self.h, _dev(x), _dev(chg), chg.shape[0], _dev(E),
+                                                       _stream(stream)))
+        return E
 
     def solvation_energy_treecode(self, x, xq, q, theta, p_max=8, stream=None):
         xq_, xqp = _host(xq, np.float64)

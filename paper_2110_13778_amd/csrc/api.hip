@@ -394,6 +394,8 @@ int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
   std::vector<double> gl(qt_size(p->quad_duffy));
   quad_table(p->quad_duffy, gl.data());
   int r = h->upload(h->d_gl, gl.data(), gl.size() * sizeof(double));
+  // this device's address of the allocation-free energy sum's scratch array
+  if (r == 0) r = fagbi::energy_scratch_init(h->device);
   if (r < 0) {
     h->free_all();
     delete h;
@@ -491,6 +493,14 @@ int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq, c
   if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!h->tree_ready) return set_error(FAGBI_E_STATE, "energy before build_tree");
   return fagbi::energy(h, x, xq, q, nc, E_kcal, (hipStream_t)stream);
+}
+
+int fagbi_solvation_energy_noalloc(fagbi_handle* h, const double* x, const double* chg, int64_t nc,
+                                   double* E_kcal, void* stream) {
+  if (!h || !x || !chg || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
+  if (reinterpret_cast<uintptr_t>(chg) % 32) return set_error(FAGBI_E_ARG, "chg must be 32-byte aligned");
+  if (!h->tree_ready) return set_error(FAGBI_E_STATE, "energy before build_tree");
+  return fagbi::energy_noalloc(h, x, chg, nc, E_kcal, (hipStream_t)stream);
 }
 
 int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double theta,

@@ -205,6 +205,8 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s);
 int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s, bool f32 = false);
 int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b,
         hipStream_t s);
+int energy_scratch_init(int device);
+int energy_noalloc(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double* E, hipStream_t s);
 int energy(fagbi_handle* h, const double* x, const double* xq, const double* q,
            int64_t nc, double* E, hipStream_t s);
 int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const double* q, int64_t nc,

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <functional>
+#include <mutex>
 
 #include "fmath.h"
 #include "internal.h"
@@ -121,8 +122,8 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ pv, c
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// sum of n doubles by one block, fixed order
-__global__ void k_sum(const double* __restrict__ v, int n, double* out) {
+// scale times the sum of n doubles, by one block in a fixed order
+__global__ void k_sum(const double* __restrict__ v, int n, double scale, double* out) {
   __shared__ double red[RB];
   double a = 0;
   for (int k = threadIdx.x; k < n; k += RB) a += v[k];
@@ -132,7 +133,7 @@ __global__ void k_sum(const double* __restrict__ v, int n, double* out) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // partial[i][blk] = V_i[chunk] . w[chunk]   (grid: NB x nvec)
@@ -223,13 +224,60 @@ int energy(fagbi_handle* h, const double* x, const double* xq, const double* q, 
   k_energy<<<nb, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                               h->d_perm.as<int32_t>(), (int)h->N, chg.as<double4>(), (int)nc,
                               h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part.as<double>());
-  k_sum<<<1, RB, 0, s>>>(part.as<double>(), nb, out.as<double>());
+  k_sum<<<1, RB, 0, s>>>(part.as<double>(), nb, 1.0, out.as<double>());
   FAGBI_HIP(hipGetLastError());
   double tot = 0;
   FAGBI_HIP(hipMemcpyAsync(&tot, out.p, 8, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
   *E = 0.5 * UNIT_KCAL * tot;
   if (!std::isfinite(*E)) return set_error(FAGBI_E_NUMERIC, "non-finite energy");
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free direct energy sum.  The per-block partial sums live in a
+// file-scope device array: one copy per GPU, kept until the process ends.
+// Host code never passes the array's name to a kernel (in host code it is a
+// stand-in, not a device address): each device's address is looked up once,
+// with that device current, and kept in g_scratch.
+// ---------------------------------------------------------------------------
+constexpr int ENERGY_SCRATCH = 1 << 16;   // partial sums of 256 panels each: N <= 2^24
+static __device__ __align__(256) double scratch[ENERGY_SCRATCH];
+constexpr int SCRATCH_MAX_DEV = 64;
+static double* g_scratch[SCRATCH_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+int energy_scratch_init(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEV)
+    return set_error(FAGBI_E_ARG, "device %d beyond the %d devices of the scratch table", device,
+                     SCRATCH_MAX_DEV);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return 0;
+  double* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return set_error(FAGBI_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[device] = ptr;
+  return 0;
+}
+
+int energy_noalloc(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double* E, hipStream_t s) {
+  const int64_t nb = (h->N + 255) / 256;
+  if (nb > ENERGY_SCRATCH)
+    return set_error(FAGBI_E_ARG, "%lld panels exceed the allocation-free limit of %d", (long long)h->N,
+                     ENERGY_SCRATCH * 256);
+  if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    part = g_scratch[h->device];
+  }
+  if (!part) return set_error(FAGBI_E_STATE, "scratch array not set up on device %d", h->device);
+  k_energy<<<(unsigned)nb, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
+                                        h->d_perm.as<int32_t>(), (int)h->N, reinterpret_cast<const double4*>(chg),
+                                        (int)nc, h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part);
+  k_sum<<<1, RB, 0, s>>>(part, (int)nb, 0.5 * UNIT_KCAL, E);
+  FAGBI_HIP(hipGetLastError());
   return 0;
 }
 
@@ -254,7 +302,7 @@ int energy_treecode(fagbi_handle* h, const double* x, const double* xq, const do
   FAGBI_TRY(qv.alloc((size_t)nc * 8));
   FAGBI_TRY(out.alloc(8));
   FAGBI_TRY(treecode_potentials(h, x, chg.as<double>(), nc, theta, p_max, qv.as<double>(), s));
-  k_sum<<<1, RB, 0, s>>>(qv.as<double>(), (int)nc, out.as<double>());
+  k_sum<<<1, RB, 0, s>>>(qv.as<double>(), (int)nc, 1.0, out.as<double>());
   FAGBI_HIP(hipGetLastError());
   double tot = 0;
   FAGBI_HIP(hipMemcpyAsync(&tot, out.p, 8, hipMemcpyDeviceToHost, s));
