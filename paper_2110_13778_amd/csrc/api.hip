@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -386,6 +387,7 @@ int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
   fagbi_handle* h = new (std::nothrow) fagbi_handle();
   if (!h) return set_error(FAGBI_E_OOM, "host allocation failed");
   h->prm = *p;
+  if (const char* e = std::getenv("FAGBI_M2L_TILES")) h->m2l_tiles = std::atoi(e) != 0;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return set_error(FAGBI_E_HIP, "no HIP device");

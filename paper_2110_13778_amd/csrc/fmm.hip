@@ -680,6 +680,280 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
   }
 }
 
+// ---------------------------------------------------------------------------
+// MtL with source reuse.  Targets are taken in tiles of up to MTK consecutive
+// clusters (Morton order: a tile is a compact patch of the surface, and its
+// targets share most of their sources).  Per tile, the distinct sources are
+// staged once in LDS as scaled moments of both channels, the half derivative
+// table stays in LDS for the whole launch, and every pair reads both operands
+// from LDS into registers.  The tile's pairs are split evenly over the
+// block's threads (contiguous chunks, whatever their targets); a thread adds
+// its partial locals into the tile's LDS accumulators whenever its chunk
+// crosses into the next target.  The next tile's source rows are loaded into
+// registers while the current tile computes.  A setup pass gives each tile
+// its sorted distinct sources and each pair its packed index.
+// ---------------------------------------------------------------------------
+constexpr int MTK = 64;          // targets per tile (at most)
+constexpr int MT_S = 8;          // lanes per target
+constexpr int MT_NT = MTK * MT_S;   // threads per block
+constexpr int MT_IPT = 7;        // staged float4 chunks per thread and channel
+constexpr int MT_UMAX = 4095;    // distinct sources of one tile (12-bit slot)
+constexpr int MT_BITS = 1 << 19; // source index range of one tile the setup covers (bitmap)
+
+// setup, one block per tile (targets [tile_lo[t], tile_hi[t])): mark the
+// tile's sources in an LDS bitmap over their index range, then number them in
+// increasing order by prefix popcounts; PASS 0 reports the count (2^30 when
+// the range exceeds the bitmap, so that the tile is split), PASS 1 writes the
+// distinct sources and the packed pair indices
+template <int PASS>
+__global__ void __launch_bounds__(256) k_tile_setup(const int32_t* __restrict__ inter_off,
+                                                    const int32_t* __restrict__ inter_src,
+                                                    const int32_t* __restrict__ inter_oid,
+                                                    const int32_t* __restrict__ omap,
+                                                    const int32_t* __restrict__ tile_lo,
+                                                    const int32_t* __restrict__ tile_hi, int32_t* tile_cnt,
+                                                    const int32_t* __restrict__ tile_off, int32_t* tile_src,
+                                                    uint32_t* pack) {
+  extern __shared__ __align__(16) uint32_t bits[];       // [MT_BITS / 32] words, then their prefix counts
+  uint32_t* wpre = bits + MT_BITS / 32;
+  __shared__ int32_t red[256];
+  __shared__ int32_t smin_s, smax_s;
+  const int tid = threadIdx.x, tile = blockIdx.x;
+  const int t0 = tile_lo[tile], t1 = tile_hi[tile];
+  const int q0 = inter_off[t0], np = inter_off[t1] - q0;
+  int mn = 0x7fffffff, mx = -1;
+  for (int i = tid; i < np; i += 256) {
+    const int v = inter_src[q0 + i];
+    mn = min(mn, v);
+    mx = max(mx, v);
+  }
+  red[tid] = mn;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = min(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) smin_s = red[0];
+  __syncthreads();
+  red[tid] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = max(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) smax_s = red[0];
+  __syncthreads();
+  const int smin = smin_s, smax = smax_s;
+  if (np == 0) {
+    if (PASS == 0 && tid == 0) tile_cnt[tile] = 0;
+    return;
+  }
+  const int64_t range = (int64_t)smax - smin + 1;
+  if (range > MT_BITS) {              // uniform over the block
+    if (PASS == 0 && tid == 0) tile_cnt[tile] = 1 << 30;
+    return;
+  }
+  const int W = (int)((range + 31) / 32);
+  for (int w = tid; w < W; w += 256) bits[w] = 0u;
+  __syncthreads();
+  for (int i = tid; i < np; i += 256) {
+    const int v = inter_src[q0 + i] - smin;
+    atomicOr(&bits[v >> 5], 1u << (v & 31));
+  }
+  __syncthreads();
+  // prefix counts of the words: thread chunks of consecutive words
+  const int per = (W + 255) / 256;
+  const int w0 = tid * per, w1 = min(W, w0 + per);
+  int c = 0;
+  for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+  red[tid] = c;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < 256; ++k) {
+      const int x = red[k];
+      red[k] = acc;
+      acc += x;
+    }
+    smin_s = acc;                    // the total, reusing the slot
+  }
+  __syncthreads();
+  const int nu = smin_s;
+  if (PASS == 0) {
+    if (tid == 0) tile_cnt[tile] = nu;
+    return;
+  }
+  int acc = red[tid];
+  for (int w = w0; w < w1; ++w) {
+    wpre[w] = (uint32_t)acc;
+    acc += __popc(bits[w]);
+  }
+  __syncthreads();
+  const int u0 = tile_off[tile];
+  for (int w = tid; w < W; w += 256) {
+    uint32_t b = bits[w];
+    int k = (int)wpre[w];
+    while (b) {
+      const int j = __ffs(b) - 1;
+      tile_src[u0 + k++] = smin + 32 * w + j;
+      b &= b - 1;
+    }
+  }
+  for (int i = tid; i < np; i += 256) {
+    const int v = inter_src[q0 + i] - smin;
+    const uint32_t slot = wpre[v >> 5] + (uint32_t)__popc(bits[v >> 5] & ((1u << (v & 31)) - 1u));
+    const uint32_t m = (uint32_t)omap[inter_oid[q0 + i]];
+    pack[q0 + i] = slot | ((m & 0x3fffffffu) << 12) | ((m >> 30) << 31);
+  }
+}
+
+// the MtL itself (FP32, T(P) a multiple of 4): persistent blocks of MT_NT
+// threads, one tile at a time; XCD x (= block id mod 8) sweeps a contiguous
+// range of tiles
+template <int P>
+__global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict__ inter_off,
+                                                       const uint32_t* __restrict__ pack,
+                                                       const int32_t* __restrict__ tile_t0,
+                                                       const int32_t* __restrict__ tile_off,
+                                                       const int32_t* __restrict__ tile_src, int ntile,
+                                                       const float2* __restrict__ Dh, int n_half,
+                                                       const float* __restrict__ M0, const float* __restrict__ Mk,
+                                                       float* L0, float* Lk) {
+  constexpr TermTable<P> tt{};
+  constexpr int T = TermTable<P>::T;
+  constexpr int CPR = T / 4;              // float4 chunks per moment row and channel
+  static_assert(T % 4 == 0, "rows in float4 chunks");
+  extern __shared__ __align__(16) char smem_raw[];
+  float2* dsm = reinterpret_cast<float2*>(smem_raw);
+  float2* msm = dsm + (size_t)n_half * T;
+  __shared__ float msc[T];
+  __shared__ float acc[MTK][2 * T];       // the tile's locals, both channels
+  __shared__ int32_t qoff[MTK + 1];       // the tile's list offsets
+  for (int e = threadIdx.x; e < n_half * T; e += MT_NT) dsm[e] = Dh[e];
+  if (threadIdx.x < T) {   // (-1)^|b| / b! of term b
+    float f = 1.0f;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      if (t == (int)threadIdx.x) f = (float)tt.msc[t];
+    msc[threadIdx.x] = f;
+  }
+  const int nbx = (int)((gridDim.x + 7) / 8);
+  const int xcd = (int)(blockIdx.x & 7), bl = (int)(blockIdx.x >> 3);
+  const int per = (ntile + 8 * nbx - 1) / (8 * nbx);
+  // staged rows of a tile in registers: item i = (slot i / CPR, chunk i % CPR)
+  float4 ra[MT_IPT], rb[MT_IPT];
+  auto prefetch = [&](int tile) {
+    if (tile >= ntile) return;
+    const int u0 = tile_off[tile], ni = (tile_off[tile + 1] - u0) * CPR;
+#pragma unroll
+    for (int k = 0; k < MT_IPT; ++k) {
+      const int i = threadIdx.x + k * MT_NT;
+      if (i < ni) {
+        const int sl = i / CPR, j = i - sl * CPR;
+        const int64_t mo = (int64_t)tile_src[u0 + sl] * T + 4 * j;
+        ra[k] = *reinterpret_cast<const float4*>(M0 + mo);
+        rb[k] = *reinterpret_cast<const float4*>(Mk + mo);
+      }
+    }
+  };
+  __syncthreads();   // msc
+  prefetch(xcd * per * nbx + bl);
+  for (int it = 0; it < per; ++it) {
+    const int tile = (xcd * per + it) * nbx + bl;
+    __syncthreads();   // the previous tile's sources and locals are no longer read
+    if (tile >= ntile) continue;
+    const int t0 = tile_t0[tile], nt = tile_t0[tile + 1] - t0;
+    {
+      const int ni = (tile_off[tile + 1] - tile_off[tile]) * CPR;
+#pragma unroll
+      for (int k = 0; k < MT_IPT; ++k) {
+        const int i = threadIdx.x + k * MT_NT;
+        if (i < ni) {
+          const int sl = i / CPR, j = i - sl * CPR;
+          const float s0 = msc[4 * j], s1 = msc[4 * j + 1], s2 = msc[4 * j + 2], s3 = msc[4 * j + 3];
+          float4* dst = reinterpret_cast<float4*>(msm + (size_t)sl * T + 4 * j);
+          dst[0] = make_float4(ra[k].x * s0, rb[k].x * s0, ra[k].y * s1, rb[k].y * s1);
+          dst[1] = make_float4(ra[k].z * s2, rb[k].z * s2, ra[k].w * s3, rb[k].w * s3);
+        }
+      }
+      for (int e = threadIdx.x; e < nt * 2 * T; e += MT_NT) (&acc[0][0])[e] = 0.0f;
+      for (int e = threadIdx.x; e <= nt; e += MT_NT) qoff[e] = inter_off[t0 + e];
+    }
+    __syncthreads();
+    if (it + 1 < per) prefetch((xcd * per + it + 1) * nbx + bl);
+    // items: every target's list cut into runs of IL pairs (the last one
+    // shorter), IL = ceil(pairs / (threads - targets)), so that the tile has
+    // at most one item per thread; a thread runs its item and adds it into
+    // the target's accumulators
+    // MT_S consecutive lanes per target split its list
+    const int c = threadIdx.x / MT_S, part = threadIdx.x - c * MT_S;
+    float l0[T], lk[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0.0f;
+    if (c < nt) {
+      const int q1 = qoff[c + 1];
+      for (int q = qoff[c] + part; q < q1; q += MT_S) {
+        const uint32_t pk = pack[q];
+        const float4* dp = reinterpret_cast<const float4*>(dsm + (size_t)((pk >> 12) & 0x7ffffu) * T);
+        const float4* mp = reinterpret_cast<const float4*>(msm + (size_t)(pk & 0xfffu) * T);
+        const float sg = (pk >> 31) ? -1.0f : 1.0f;
+        float4 dr[T / 2], mr[T / 2];
+#pragma unroll
+        for (int k = 0; k < T / 2; ++k) {
+          dr[k] = dp[k];
+          mr[k] = mp[k];
+        }
+        float2 d[T], m[T];
+#pragma unroll
+        for (int k = 0; k < T / 2; ++k) {
+          d[2 * k] = make_float2(dr[k].x, dr[k].y);
+          d[2 * k + 1] = make_float2(dr[k].z, dr[k].w);
+          m[2 * k] = make_float2(mr[k].x, mr[k].y);
+          m[2 * k + 1] = make_float2(mr[k].z, mr[k].w);
+        }
+#pragma unroll
+        for (int g = 0; g < T; ++g)
+          if (tt.deg[g] & 1) {
+            d[g].x *= sg;
+            d[g].y *= sg;
+          }
+#pragma unroll
+        for (int tb = 0; tb < T; ++tb) {
+#pragma unroll
+          for (int ta = 0; ta < nterms(P - tt.deg[tb]); ++ta) {
+            const int g = midx(tt.e[ta][0] + tt.e[tb][0], tt.e[ta][1] + tt.e[tb][1], tt.e[ta][2] + tt.e[tb][2]);
+            l0[ta] += d[g].x * m[tb].x;
+            lk[ta] += d[g].y * m[tb].y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = MT_S >> 1; o > 0; o >>= 1)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        l0[t] += __shfl_xor(l0[t], o, 64);
+        lk[t] += __shfl_xor(lk[t], o, 64);
+      }
+    if (c < nt && part == 0)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        acc[c][t] = l0[t];
+        acc[c][T + t] = lk[t];
+      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt * 2 * T; e += MT_NT) {
+      const int cc = e / (2 * T), r = e - cc * 2 * T;
+      const int t = r < T ? r : r - T;
+      float lsc = 1.0f;
+#pragma unroll
+      for (int u = 0; u < T; ++u)
+        if (u == t) lsc = (float)tt.lsc[u];
+      (r < T ? L0 : Lk)[(int64_t)(t0 + cc) * T + t] = acc[cc][r] * lsc;
+    }
+  }
+}
+
 // MtM: one block per parent; slot = (a | b << 16), a parent index, b child
 // index (b <= a componentwise); coefficient rows per child octant.
 template <typename R, int SPT>
@@ -1005,6 +1279,95 @@ struct Staging {
   }
 };
 
+// source-reuse MtL tables of level l (FP32, order 3).  Tiles start as MTK
+// consecutive targets; a tile whose distinct sources do not fit the LDS left
+// beside the half table is split in halves until every tile fits.  D.n_tile
+// stays 0 when the level does not qualify (a single target whose sources do
+// not fit).
+constexpr int MT_LDS = 160 * 1024;   // a CU's LDS
+constexpr size_t MT_SETUP_LDS = (size_t)2 * (MT_BITS / 32) * 4;   // setup bitmap and word prefixes
+static int m2l_tile_setup(fagbi_handle* h, int l, hipStream_t s) {
+  Level& D = h->lev[l];
+  D.n_tile = 0;
+  if (D.order != 3 || D.n_half == 0 || D.n_half >= (1 << 19) || D.n_inter == 0 || l < h->lmin) return 0;
+  const int64_t row = (int64_t)D.T * sizeof(float2);
+  const int64_t stat_lds = (int64_t)MTK * 2 * D.T * 4 + (MTK + 1) * 4 + D.T * 4 + 256;
+  const int64_t cap = std::min<int64_t>(std::min<int64_t>(MT_UMAX, (int64_t)MT_IPT * MT_NT / (D.T / 4)),
+                                        (MT_LDS - stat_lds - (int64_t)D.n_half * row) / row);
+  if (cap < 64) return 0;
+  for (int pass = 0; pass < 2; ++pass)
+    FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(pass ? &k_tile_setup<1> : &k_tile_setup<0>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)MT_SETUP_LDS));
+  // tiles start as MTK consecutive targets; only tiles that were split are
+  // counted again (their halves), the others keep their count
+  std::vector<int32_t> t0;
+  for (int c = 0; c < D.n; c += MTK) t0.push_back(c);
+  t0.push_back(D.n);
+  const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                *id = D.d_inter_oid.as<int32_t>(), *om = D.d_oid_map.as<int32_t>();
+  std::vector<int32_t> hc(t0.size() - 1, -1);   // -1: not counted yet
+  int umax = 0;
+  Tmp dt0, cnt;
+  for (int round = 0;; ++round) {
+    // the ranges not counted yet: first targets, then last targets
+    std::vector<int32_t> todo, lohi;
+    for (size_t t = 0; t + 1 < t0.size(); ++t)
+      if (hc[t] < 0) todo.push_back((int32_t)t);
+    if (todo.empty()) break;
+    if (round == 9) return 0;
+    const int nq = (int)todo.size();
+    for (int k = 0; k < nq; ++k) lohi.push_back(t0[todo[k]]);
+    for (int k = 0; k < nq; ++k) lohi.push_back(t0[todo[k] + 1]);
+    dt0.release();
+    cnt.release();
+    FAGBI_TRY(dt0.alloc(lohi.size() * 4));
+    FAGBI_TRY(cnt.alloc((size_t)nq * 4));
+    FAGBI_HIP(hipMemcpyAsync(dt0.p, lohi.data(), lohi.size() * 4, hipMemcpyHostToDevice, s));
+    k_tile_setup<0><<<nq, 256, MT_SETUP_LDS, s>>>(io, is, id, om, dt0.as<int32_t>(), dt0.as<int32_t>() + nq,
+                                                  cnt.as<int32_t>(), nullptr, nullptr, nullptr);
+    FAGBI_HIP(hipGetLastError());
+    std::vector<int32_t> got(nq);
+    FAGBI_HIP(hipMemcpyAsync(got.data(), cnt.p, got.size() * 4, hipMemcpyDeviceToHost, s));
+    FAGBI_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nq; ++k) hc[todo[k]] = got[k];
+    // split the tiles that do not fit
+    std::vector<int32_t> nt0, nhc;
+    for (size_t t = 0; t + 1 < t0.size(); ++t) {
+      if (hc[t] > cap) {
+        if (t0[t + 1] - t0[t] < 2) return 0;
+        nt0.push_back(t0[t]);
+        nt0.push_back((t0[t] + t0[t + 1]) / 2);
+        nhc.push_back(-1);
+        nhc.push_back(-1);
+      } else {
+        nt0.push_back(t0[t]);
+        nhc.push_back(hc[t]);
+      }
+    }
+    nt0.push_back(D.n);
+    t0.swap(nt0);
+    hc.swap(nhc);
+  }
+  for (int c : hc) umax = std::max(umax, c);
+  const int nt = (int)t0.size() - 1;
+  FAGBI_TRY(h->alloc(D.d_tile_t0, t0.size() * 4));
+  FAGBI_HIP(hipMemcpyAsync(D.d_tile_t0.p, t0.data(), t0.size() * 4, hipMemcpyHostToDevice, s));
+  std::vector<int32_t> off(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) off[t + 1] = off[t] + hc[t];
+  FAGBI_TRY(h->alloc(D.d_tile_off, off.size() * 4));
+  FAGBI_HIP(hipMemcpyAsync(D.d_tile_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+  FAGBI_TRY(h->alloc(D.d_tile_src, (size_t)std::max(1, off[nt]) * 4));
+  FAGBI_TRY(h->alloc(D.d_pack, (size_t)D.n_inter * 4));
+  k_tile_setup<1><<<nt, 256, MT_SETUP_LDS, s>>>(io, is, id, om, D.d_tile_t0.as<int32_t>(),
+                                                D.d_tile_t0.as<int32_t>() + 1, nullptr, D.d_tile_off.as<int32_t>(),
+                                                D.d_tile_src.as<int32_t>(), D.d_pack.as<uint32_t>());
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_HIP(hipStreamSynchronize(s));   // the host copies above are freed on return
+  D.n_tile = nt;
+  D.tile_umax = umax;
+  return 0;
+}
+
 static int spt_of(int nslot) {
   const int s = (nslot + TB - 1) / TB;
   return s <= 1 ? 1 : s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;
@@ -1180,6 +1543,7 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
     }
   }
   FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(m2l_tile_setup(h, h->L, s));
   const unsigned grid = (unsigned)((NT + 255) / 256);
   k_panel_moments<double><<<grid, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                                                 h->d_leaf_of.as<int32_t>(), LF.d_idx.as<int32_t>(), h->corner[0],
@@ -1354,6 +1718,18 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
                                                      D.d_inter_oid.as<int32_t>(), Dh, D.n_half,
                                                      D.d_oid_map.as<int32_t>(), D.n_off, D.n, S, M(D, 0), M(D, 1),
                                                      Lc(D, 0), Lc(D, 1));
+      return 0;
+    }
+    if constexpr (sizeof(R) == 4)
+    if (D.n_tile > 0 && D.order == 3 && h->m2l_tiles) {
+      const size_t lds = ((size_t)D.n_half + D.tile_umax) * D.T * sizeof(float2);
+      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile<3>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      k_m2l_tile<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
+                                                  D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
+                                                  D.d_tile_src.as<int32_t>(), D.n_tile,
+                                                  (const float2*)D.d_F32[1].p, D.n_half, M(D, 0), M(D, 1),
+                                                  Lc(D, 0), Lc(D, 1));
       return 0;
     }
     if constexpr (sizeof(R) == 4)

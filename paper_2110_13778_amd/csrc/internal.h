@@ -94,6 +94,12 @@ struct Level {
   DBuf d_m2l_slot, d_m2l_aoff, d_m2l_c64, d_m2l_c32;
   DBuf d_up_slot, d_up_aoff, d_up_c64, d_up_c32;
   DBuf d_dn_slot, d_dn_boff, d_dn_c64, d_dn_c32;
+  // MtL with source reuse: targets in tiles of consecutive clusters; per tile
+  // its distinct sources [tile_off[t], tile_off[t + 1]) of tile_src (sorted),
+  // per interaction pair the packed index (slot of its source in the tile |
+  // half-table row << 12 | flip << 31); n_tile = 0 when not set up
+  DBuf d_tile_t0, d_tile_off, d_tile_src, d_pack;   // tile t: targets [tile_t0[t], tile_t0[t + 1])
+  int n_tile = 0, tile_umax = 0;
 };
 
 }  // namespace fagbi
@@ -148,6 +154,9 @@ struct fagbi_handle {
   fagbi::DBuf d_mlp_theta, d_mlp_m, d_mlp_v, d_mlp_norm;
   fagbi::DBuf d_mlp_skip[4];
   std::vector<float> mlp_blob;        // parameters | normalisation | calibration
+  // FP32 leaf-level MtL by the source-reuse tile kernel (when its tables fit);
+  // FAGBI_M2L_TILES=0 in the environment selects the per-pair LDS-table kernel
+  bool m2l_tiles = true;
   // per-phase profiling
   bool profiling = false;
   // matvec phase events: 5 start; 0, 1 around the near-field SpMV (on its
