@@ -58,8 +58,9 @@ def parse():
                     help="skip the secondary workloads (globule200k, ellipsoid1m)")
     ap.add_argument("--mlp-epochs", type=int, default=120,
                     help="training epochs of the near-field surrogate (before the timed steps)")
-    ap.add_argument("--mlp-pairs", type=int, default=1000000,
-                    help="training pairs drawn per training mesh (two meshes)")
+    ap.add_argument("--mlp-pairs", type=int, default=2000000,
+                    help="training pairs drawn per training mesh (two meshes; the default takes every "
+                         "near-singular pair of both)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()

@@ -86,6 +86,15 @@ __device__ inline void canonical(const NearArgs& a, int cls, int i, int j, int* 
   }
 }
 
+// centroid distance of a pair over sqrt(h_i h_j), h = sqrt(area)
+__device__ inline double pair_dratio(const NearArgs& a, int i, int j) {
+  const double* P = a.pv + 9 * i;
+  const double* Q = a.pv + 9 * j;
+  double r[3];
+  for (int d = 0; d < 3; ++d) r[d] = (P[d] + P[3 + d] + P[6 + d]) / 3.0 - (Q[d] + Q[3 + d] + Q[6 + d]) / 3.0;
+  return sqrt(dot3(r, r)) / sqrt(sqrt(a.pa[i] * a.pa[j]));
+}
+
 __device__ inline void pair_features(const NearArgs& a, int cls, int i, int j, float* X, double* hout,
                                      double* dratio) {
   int oi[3], oj[3];
@@ -123,8 +132,8 @@ __device__ inline void pair_features(const NearArgs& a, int cls, int i, int j, f
   X[14] = cls == C_VERTEX ? 1.f : 0.f;
   X[15] = cls == C_CLOSE ? 1.f : 0.f;
   *hout = h;
-  for (int d = 0; d < 3; ++d) r[d] = ci[d] - cj[d];
-  *dratio = sqrt(dot3(r, r)) / sqrt(sqrt(a.pa[i] * a.pa[j]));
+  (void)cj;
+  *dratio = pair_dratio(a, i, j);
 }
 
 // class of a feature row from its one-hot inputs (0 edge, 1 vertex, 2 close)
@@ -168,22 +177,33 @@ __global__ void k_mlp_targets(int cls_index, const double* __restrict__ Iq, cons
 }
 
 // ---------------------------------------------------------------------------
-// dense layers: C[M x N] = act(A[M x K] B[K x N] + bias), element (m,k) of A
-// at A[m*sam + k*sak], (k,n) of B at B[k*sbk + n*sbn]; 64x64 tiles, K chunks
-// of 16, 4x4 outputs per thread.  Split-K over blockIdx.z writes partial
-// sums to C + z*M*N (no bias/activation then).
+// dense layers on the matrix cores: C[M x N] = act(A[M x K] B[K x N] + bias),
+// element (m,k) of A at A[m*sam + k*sak], (k,n) of B at B[k*sbk + n*sbn].
+// 64x64 output tiles per block of four waves, each wave a 32x32 quadrant as
+// 2x2 v_mfma_f32_16x16x4f32 tiles (FP32 in, FP32 accumulation); K in chunks
+// of 16 staged through LDS.  Split-K over blockIdx.z writes partial sums to
+// C + z*M*N (no bias/activation then).  Lane layouts of the instruction:
+// A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, D[i][j] in lane
+// j + 16(i/4), element i % 4.
 // ---------------------------------------------------------------------------
 enum { ACT_NONE = 0, ACT_TANH = 1 };
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int64_t sam,
                                               int64_t sak, const float* __restrict__ B, int64_t sbk, int64_t sbn,
                                               const float* __restrict__ bias, int act, float* C, int kchunk) {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const int rb = (wave >> 1) * 32, cb = (wave & 1) * 32;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-  float acc[4][4] = {};
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       const int kk = e / 64, mm = e % 64;
@@ -194,35 +214,37 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float av[4], bv[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      float av[2], bv[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        av[u] = As[kk][ty * 4 + u];
-        bv[u] = Bs[kk][tx * 4 + u];
+      for (int t = 0; t < 2; ++t) {
+        av[t] = As[kk + kq][rb + 16 * t + i];
+        bv[t] = Bs[kk + kq][cb + 16 * t + i];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
   float* Cz = C + (int64_t)blockIdx.z * M * N;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int gm = m0 + ty * 4 + u;
-    if (gm >= M) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gn = n0 + tx * 4 + v;
+    for (int b = 0; b < 2; ++b) {
+      const int gn = n0 + cb + 16 * b + i;
       if (gn >= N) continue;
-      float x = acc[u][v];
-      if (bias) x += bias[gn];
-      if (act == ACT_TANH) x = tanhf(x);
-      Cz[(int64_t)gm * N + gn] = x;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gm = m0 + rb + 16 * a + 4 * kq + q;
+        if (gm >= M) continue;
+        float x = acc[a][b][q];
+        if (bias) x += bias[gn];
+        if (act == ACT_TANH) x = tanhf(x);
+        Cz[(int64_t)gm * N + gn] = x;
+      }
     }
-  }
 }
 
 // out[k] = sum_z part[z][k] (fixed order), k < n
@@ -253,6 +275,20 @@ __global__ void k_colsum(const float* __restrict__ D, int rows, int cols, float*
 __global__ void k_tanh_back(float* D, const float* __restrict__ H, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) D[k] *= 1.f - H[k] * H[k];
+}
+
+// out[0] = sum of the n partial sums divided by div (fixed order, one block)
+__global__ void k_loss_total(const double* __restrict__ part, int n, double div, double* out) {
+  __shared__ double red[256];
+  double a = 0;
+  for (int k = threadIdx.x; k < n; k += 256) a += part[k];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0] / div;
 }
 
 // dY = 2 (Y - T) / n  and per-block partial sums of (Y - T)^2
@@ -343,19 +379,34 @@ __device__ inline bool mlp_gated(const float* __restrict__ cal, int cls_index, f
   return est[b] <= tol;
 }
 
-// the pairs whose prediction is used (gated, or every pair with all != 0)
-__global__ void k_mlp_flag(int cls_index, int64_t n, const float* __restrict__ dr, const float* __restrict__ cal,
-                           double tol, int all, int32_t* flag) {
+// the pairs whose prediction is used (gated, or every pair with all != 0),
+// decided from the pair's class and distance ratio alone
+__global__ void k_mlp_gate(NearArgs a, int cls_index, const Item* __restrict__ items, int64_t n,
+                           const float* __restrict__ cal, double tol, int all, float* dr, int32_t* flag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) flag[t] = (all || mlp_gated(cal, cls_index, dr[t], tol)) ? 1 : 0;
+  if (t >= n) return;
+  const Item it = items[t];
+  const float d = (float)pair_dratio(a, it.i, it.j);
+  dr[t] = d;
+  flag[t] = (all || mlp_gated(cal, cls_index, d, tol)) ? 1 : 0;
 }
 
-// features of the flagged pairs, packed in pair order
-__global__ void k_mlp_pack(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
-                           const float* __restrict__ X, float* Xp) {
+// features, 3x3 integrals and h of the flagged pairs, packed in pair order
+__global__ void k_mlp_prepare_packed(NearArgs a, int cls, const Item* __restrict__ items, int64_t n,
+                                     const int32_t* __restrict__ flag, const int32_t* __restrict__ pos, float* X,
+                                     double* I3, double* hh) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n || !flag[t]) return;
-  for (int f = 0; f < NIN; ++f) Xp[(int64_t)pos[t] * NIN + f] = X[t * NIN + f];
+  const int64_t q = pos[t];
+  const Item it = items[t];
+  double h, d;
+  float f[NIN];
+  pair_features(a, cls, it.i, it.j, f, &h, &d);
+  for (int k = 0; k < NIN; ++k) X[q * NIN + k] = f[k];
+  double I[6];
+  regular_pair(a, it.i, it.j, I);
+  for (int m = 0; m < 6; ++m) I3[q * 6 + m] = I[m];
+  hh[q] = h;
 }
 
 __global__ void k_mlp_apply(NearArgs a, int cls, int cls_index, const Item* __restrict__ items, int64_t n,
@@ -373,7 +424,7 @@ __global__ void k_mlp_apply(NearArgs a, int cls, int cls_index, const Item* __re
       const int64_t q = pos[t];   // row of this pair among the predicted ones
       double I[6];
       for (int m = 0; m < 6; ++m)
-        I[m] = I3[t * 6 + m] + hpow(hh[t], m) * ((double)tn[q * NOUT + m] * norm[OUT_SD + ci * NOUT + m] +
+        I[m] = I3[q * 6 + m] + hpow(hh[q], m) * ((double)tn[q * NOUT + m] * norm[OUT_SD + ci * NOUT + m] +
                                                  norm[OUT_MU + ci * NOUT + m]);
       write_pair(a, cls, it.i, it.j, it.ent, I, ent);
     }
@@ -484,7 +535,6 @@ static int ensure_net(fagbi_handle* h) {
 // Lane layouts of the 16x16x4 FP32 instruction: A[i][k] from lane i + 16k,
 // B[k][j] from lane j + 16k, D[i][j] in lane j + 16(i/4), element i % 4.
 // ---------------------------------------------------------------------------
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int IR = 64;               // rows per block
 constexpr int AST = NH + 4;          // activation row stride (A reads: 2-way banks)
 
@@ -512,10 +562,15 @@ __device__ inline void mlp_layer(const float* act, const float* __restrict__ W, 
 
 // out[r] = network(standardised X[r]) (standardised, or in target units when
 // destd is set: times the class's output sd plus its mean)
-__global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, int64_t n,
+__global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, int64_t n_host,
+                                                   const int32_t* __restrict__ n_dev,
                                                    const float* __restrict__ th, const float* __restrict__ norm,
                                                    int destd, float* out) {
   __shared__ float act_all[4 * 16 * AST];
+  // rows: n_host, or the count in device memory (the grid covers n_host rows
+  // and the blocks beyond the count leave at once)
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  if ((int64_t)blockIdx.x * IR >= n) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* act = act_all + wave * 16 * AST;
   const int64_t r0 = (int64_t)blockIdx.x * IR + wave * 16;
@@ -557,9 +612,10 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, 
     }
 }
 
-static int infer(fagbi_handle* h, const float* Xraw, int64_t n, int destd, float* out, hipStream_t s) {
+static int infer(fagbi_handle* h, const float* Xraw, int64_t n, int destd, float* out, hipStream_t s,
+                 const int32_t* n_dev = nullptr) {
   if (n <= 0) return 0;
-  k_mlp_infer<<<(unsigned)((n + IR - 1) / IR), 256, 0, s>>>(Xraw, n, h->d_mlp_theta.as<float>(),
+  k_mlp_infer<<<(unsigned)((n + IR - 1) / IR), 256, 0, s>>>(Xraw, n, n_dev, h->d_mlp_theta.as<float>(),
                                                              h->d_mlp_norm.as<float>(), destd, out);
   FAGBI_HIP(hipGetLastError());
   return 0;
@@ -575,12 +631,14 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s) {
   FAGBI_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
   const int all = h->prm.mlp_mode == FAGBI_MLP_PRECOND ? 1 : 0;
   // one set of chunk buffers for all classes; the chunks run back to back in
-  // stream order
+  // stream order.  Per chunk: the gate of every pair (class and distance
+  // ratio), a scan of the flags, features and 3x3 integrals of the flagged
+  // pairs only (packed), inference over the packed rows (their count read on
+  // the device, so no host round trip), and the entries of the flagged pairs
   const int64_t CH = 1 << 20;
   int64_t cm = 1;
   for (int k = 1; k < 4; ++k) cm = std::max(cm, std::min<int64_t>(h->wl_n[k], CH));
-  Tmp X, Xp, I3, hh, dr, tn, flag, pos, part;
-  FAGBI_TRY(X.alloc((size_t)cm * NIN * 4));
+  Tmp Xp, I3, hh, dr, tn, flag, pos, part;
   FAGBI_TRY(Xp.alloc((size_t)cm * NIN * 4));
   FAGBI_TRY(flag.alloc((size_t)cm * 4));
   FAGBI_TRY(pos.alloc((size_t)(cm + 1) * 4));
@@ -596,18 +654,11 @@ int mlp_assembly_stage(fagbi_handle* h, hipStream_t s) {
       const int64_t c = std::min<int64_t>(CH, m - r0);
       const Item* it = h->d_wl[k].as<Item>() + r0;
       const unsigned g = (unsigned)((c + 255) / 256);
-      k_mlp_prepare<<<g, 256, 0, s>>>(a, k + 1, it, c, X.as<float>(), I3.as<double>(), hh.as<double>(),
-                                      dr.as<float>());
-      // the network runs on the pairs whose prediction is used only
-      k_mlp_flag<<<g, 256, 0, s>>>(k, c, dr.as<float>(), cal, h->prm.mlp_gate_tol, all, flag.as<int32_t>());
+      k_mlp_gate<<<g, 256, 0, s>>>(a, k, it, c, cal, h->prm.mlp_gate_tol, all, dr.as<float>(), flag.as<int32_t>());
       FAGBI_TRY((device_scan<int32_t, int32_t>(flag.as<int32_t>(), c, pos.as<int32_t>(), part.as<int32_t>(), s)));
-      int32_t np = 0;
-      FAGBI_HIP(hipMemcpyAsync(&np, pos.as<int32_t>() + c, 4, hipMemcpyDeviceToHost, s));
-      FAGBI_HIP(hipStreamSynchronize(s));
-      if (np > 0) {
-        k_mlp_pack<<<g, 256, 0, s>>>(c, flag.as<int32_t>(), pos.as<int32_t>(), X.as<float>(), Xp.as<float>());
-        FAGBI_TRY(infer(h, Xp.as<float>(), np, 0, tn.as<float>(), s));
-      }
+      k_mlp_prepare_packed<<<g, 256, 0, s>>>(a, k + 1, it, c, flag.as<int32_t>(), pos.as<int32_t>(),
+                                             Xp.as<float>(), I3.as<double>(), hh.as<double>());
+      FAGBI_TRY(infer(h, Xp.as<float>(), c, 0, tn.as<float>(), s, pos.as<int32_t>() + c));
       k_mlp_apply<<<g, 256, 0, s>>>(a, k + 1, k, it, c, pos.as<int32_t>(), tn.as<float>(), norm, I3.as<double>(),
                                     hh.as<double>(),
                                     dr.as<float>(), cal, h->prm.mlp_gate_tol, all, h->d_E64.as<double4>(),
@@ -742,34 +793,40 @@ int fagbi_mlp_train(fagbi_handle* h, const float* X, const float* T, const float
   FAGBI_HIP(hipMemsetAsync(h->d_mlp_v.p, 0, NPAR * 4, s));
   Work w;
   FAGBI_TRY(w.alloc(B));
-  Tmp xb, tb, idx;
+  Tmp xb, tb, idx, bl;
   FAGBI_TRY(xb.alloc((size_t)B * NIN * 4));
   FAGBI_TRY(tb.alloc((size_t)B * NOUT * 4));
-  FAGBI_TRY(idx.alloc((size_t)B * 8));
   const int nb = (int)(ntr / B);
+  FAGBI_TRY(idx.alloc((size_t)std::max(nb, 1) * B * 8));
+  FAGBI_TRY(bl.alloc((size_t)std::max(nb, 1) * 8));
   const int nlp = (B * NOUT + 255) / 256;
-  std::vector<double> lp(nlp);
+  std::vector<double> lb(std::max(nb, 1));
   int step = 0;
+  // the host shuffles the rows once per epoch and uploads the order in one
+  // copy; each minibatch's loss stays on the device until the epoch ends
   for (int ep = 0; ep < epochs; ++ep) {
     for (int64_t k = ntr - 1; k > 0; --k) std::swap(order[k], order[(int64_t)(uniform01(st) * (k + 1))]);
-    double lsum = 0;
     const float lr_ep = lr * (float)(0.5 * (1.0 + std::cos(3.14159265358979 * ep / epochs)));
+    FAGBI_HIP(hipStreamSynchronize(s));   // the previous epoch's kernels have read idx
+    FAGBI_HIP(hipMemcpy(idx.p, order.data(), (size_t)nb * B * 8, hipMemcpyHostToDevice));
     for (int bi = 0; bi < nb; ++bi) {
-      FAGBI_HIP(hipMemcpyAsync(idx.p, order.data() + (int64_t)bi * B, B * 8, hipMemcpyHostToDevice, s));
-      k_gather_std<<<(B + 255) / 256, 256, 0, s>>>(X, T, idx.as<int64_t>(), B, norm, xb.as<float>(), tb.as<float>());
+      k_gather_std<<<(B + 255) / 256, 256, 0, s>>>(X, T, idx.as<int64_t>() + (int64_t)bi * B, B, norm,
+                                                   xb.as<float>(), tb.as<float>());
       loss_grad(h->d_mlp_theta.as<float>(), xb.as<float>(), tb.as<float>(), w, s);
+      k_loss_total<<<1, 256, 0, s>>>(w.lpart.as<double>(), nlp, (double)B * NOUT, bl.as<double>() + bi);
       ++step;
       const float c1 = 1.f - std::pow(0.9f, (float)step), c2 = 1.f - std::pow(0.999f, (float)step);
       k_adam<<<(NPAR + 255) / 256, 256, 0, s>>>(h->d_mlp_theta.as<float>(), h->d_mlp_m.as<float>(),
                                                 h->d_mlp_v.as<float>(), w.grad.as<float>(), NPAR, lr_ep, 0.9f,
                                                 0.999f, c1, c2);
-      FAGBI_HIP(hipMemcpyAsync(lp.data(), w.lpart.p, nlp * 8, hipMemcpyDeviceToHost, s));
-      FAGBI_HIP(hipStreamSynchronize(s));
-      double l = 0;
-      for (double v : lp) l += v;
-      lsum += l / ((double)B * NOUT);
     }
-    if (loss_hist) loss_hist[ep] = (float)(lsum / std::max(nb, 1));
+    if (loss_hist && nb > 0) {
+      FAGBI_HIP(hipMemcpyAsync(lb.data(), bl.p, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+      FAGBI_HIP(hipStreamSynchronize(s));
+      double lsum = 0;
+      for (int bi = 0; bi < nb; ++bi) lsum += lb[bi];
+      loss_hist[ep] = (float)(lsum / nb);
+    }
   }
   FAGBI_HIP(hipGetLastError());
   // calibration on the held-out rows: per class, 8 bins of the distance ratio

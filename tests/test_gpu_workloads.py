@@ -4,7 +4,9 @@
   15 A ball, adaptive orders 3..8): solvation energy within 0.1 % of the
   Kirkwood series (degree 60), FP64 and mixed precision;
 * the 2,000-atom isosurface globule (~200k panels): mixed-precision and FP64
-  paths agree on the energy (the mixed path's error is stated, not assumed).
+  paths agree on the energy (the mixed path's error is stated, not assumed);
+* the 20,000-atom ellipsoidal assembly at ~1M panels: both precisions to a
+  1e-6 true residual, energies agreeing to 1e-5.
 """
 import numpy as np
 import pytest
@@ -50,4 +52,21 @@ def test_globule_mixed_against_fp64():
     assert i64.rel_residual <= 1e-6 and i32.rel_residual <= 1e-6
     print("globule200k: E fp64 %.6f mixed %.6f rel %.2e its %d / %d" % (E64, E32, abs(E32 - E64) / abs(E64),
                                                                         i64.inner_iterations, i32.inner_iterations))
+    assert abs(E32 - E64) < 1e-5 * abs(E64)
+
+
+def test_ellipsoid1m_fp64_and_mixed():
+    """the large assembly (20,000 packed atoms, ~1M panels, 20,000 charges):
+    both precisions reach a true FP64 residual of 1e-6; the mixed path's
+    energy difference from the FP64 path is stated and bounded"""
+    w = workload("ellipsoid1m")
+    N = len(w["tris"])
+    assert 950000 < N < 1200000
+    c64, i64, E64 = solve(w, F.FP64, precond=F.PRECOND_GROUP)
+    c32, i32, E32 = solve(w, F.MIXED, precond=F.PRECOND_GROUP)
+    assert c64 == 0 and c32 == 0
+    assert i64.rel_residual <= 1e-6 and i32.rel_residual <= 1e-6
+    print("ellipsoid1m (%d panels): E fp64 %.6f mixed %.6f rel %.2e its %d / %d, residuals %.2e / %.2e"
+          % (N, E64, E32, abs(E32 - E64) / abs(E64), i64.inner_iterations, i32.inner_iterations,
+             i64.rel_residual, i32.rel_residual))
     assert abs(E32 - E64) < 1e-5 * abs(E64)
