@@ -101,6 +101,8 @@ typedef struct fagbi_tree_info {
   int32_t lev_offsets[FAGBI_MAX_LEVELS];    /* distinct interaction offsets */
   int32_t lev_pad;
   int64_t lev_pairs[FAGBI_MAX_LEVELS];      /* interaction pairs (c, c' in I(c)) */
+  int64_t device_bytes;        /* device memory the handle holds (tree, near field, far-field tables and
+                                  expansions, preconditioner, Krylov and treecode workspaces) */
 } fagbi_tree_info;
 
 typedef struct fagbi_solve_info {

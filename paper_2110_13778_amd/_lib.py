@@ -49,7 +49,8 @@ class TreeInfo(C.Structure):
                 ("order_leaf", C.c_int32), ("order_root", C.c_int32),
                 ("rho_leaf", C.c_double), ("h_leaf", C.c_double),
                 ("lev_clusters", C.c_int32 * 21), ("lev_order", C.c_int32 * 21),
-                ("lev_offsets", C.c_int32 * 21), ("lev_pad", C.c_int32), ("lev_pairs", C.c_int64 * 21)]
+                ("lev_offsets", C.c_int32 * 21), ("lev_pad", C.c_int32), ("lev_pairs", C.c_int64 * 21),
+                ("device_bytes", C.c_int64)]
 
 
 class SolveInfo(C.Structure):

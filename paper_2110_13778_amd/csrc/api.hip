@@ -554,6 +554,10 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
   info->order_root = h->lev[0].order;
   info->rho_leaf = h->lev[h->L].rho;
   info->h_leaf = h->lev[h->L].h;
+  int64_t bytes = 0;
+  for (const DBuf* b : h->owned) bytes += (int64_t)b->bytes;
+  for (const Tmp& t : h->tc_ws) bytes += (int64_t)t.bytes;
+  info->device_bytes = bytes;
   return 0;
 }
 
