@@ -50,6 +50,8 @@ enum {
 enum { FAGBI_FP64 = 0, FAGBI_MIXED = 1 };
 enum { FAGBI_PRECOND_NONE = 0, FAGBI_PRECOND_DIAG = 1, FAGBI_PRECOND_BLOCK = 2, FAGBI_PRECOND_GROUP = 3 };
 enum { FAGBI_MLP_OFF = 0, FAGBI_MLP_PRECOND = 1, FAGBI_MLP_GATED = 2 };
+/* cluster radii of the separation ratio (fagbi_params.radii) */
+enum { FAGBI_RADII_LEVEL = 0, FAGBI_RADII_CLUSTER = 1 };
 /* parts of the operator for fagbi_matvec_parts */
 enum { FAGBI_PART_NEAR = 1, FAGBI_PART_FAR = 2, FAGBI_PART_ALL = 3 };
 
@@ -57,9 +59,15 @@ typedef struct fagbi_params {
   /* physics (Sec. 2.1): dielectric constants and inverse Debye length [1/A] */
   double eps_in, eps_out, kappa;
   /* cluster tree and FMM (Sec. 2.4): clusters c, c' of one level are
-     neighbours iff 2 rho_l / |x_c - x_c'| > eta0; uniform depth with at most
-     leaf_size panels per leaf cube; expansion order p_leaf at the leaves,
-     p_l = min(p_leaf + L - l, p_max) per level when adaptive != 0 */
+     neighbours iff (rho_c + rho_c') / |x_c - x_c'| > eta0, x_c the cube
+     centre; with radii = FAGBI_RADII_LEVEL every cluster of level l has the
+     radius rho_l (farthest 3-point-rule quadrature point of the level's
+     panels from their cube centres), with FAGBI_RADII_CLUSTER each cluster
+     its own rho_c (farthest vertex of its panels from its cube centre; the
+     shrink scheme of Sec. 2.4 with the centre kept on the cube lattice);
+     uniform depth with at most leaf_size panels per leaf cube; expansion
+     order p_leaf at the leaves, p_l = min(p_leaf + L - l, p_max) per level
+     when adaptive != 0 */
   double eta0;
   int32_t leaf_size, p_leaf, adaptive, p_max;
   /* near-field quadrature: Gauss points per dimension of the singular and
@@ -81,6 +89,7 @@ typedef struct fagbi_params {
      reverse treecode with this acceptance parameter (fagbi_rhs_treecode) */
   double rhs_theta;
   int32_t rhs_pmax;            /* its order cap: terms |a| <= min(p_l, rhs_pmax) */
+  int32_t radii;               /* FAGBI_RADII_LEVEL (default) or FAGBI_RADII_CLUSTER */
 } fagbi_params;
 
 #define FAGBI_MAX_LEVELS 21        /* levels 0..20 (cube keys have 20 levels) */

@@ -17,6 +17,19 @@ Readings of points the paper leaves open (one choice, used everywhere):
   * c' is a neighbour of c iff it is a child of a neighbour of c's parent and
     eta(c, c') > eta0 (c is its own neighbour); the interaction list I(c) holds
     the other children of the parent's neighbours.
+
+Shrunk radii (``radii="cluster"``), after the shrink scheme of Sec. 2.4, which
+replaces a cluster's cube by the tight box around its panels: here the
+centre stays the cube centre (so that the offsets between clusters of a level
+stay on the cube lattice and translations remain shared per offset) and each
+cluster gets its own radius rho_c, the farthest vertex of a member panel from
+that centre (the ball holds the cluster's panels whole, as the paper's box
+does).  The separation ratio becomes (rho_c + rho_c') / |x_c - x_c'|; lists
+are built by the same recursion.  Every quadrature point of c lies within
+rho_c of x_c, so the expansions converge under the same condition
+eta <= eta0 < 1; and two panels sharing a vertex v always land in
+neighbouring clusters, since |x_c - x_c'| <= |x_c - v| + |v - x_c'| <=
+rho_c + rho_c' gives eta >= 1.
 """
 import numpy as np
 from types import SimpleNamespace
@@ -42,7 +55,7 @@ def cube_index(c, corner, side, level):
     return np.clip(k, 0, 2 ** level - 1).astype(np.int64)
 
 
-def build(P, leaf_size=32, eta0=0.8, max_level=20):
+def build(P, leaf_size=32, eta0=0.8, max_level=20, radii="level"):
     V = P.verts[np.unique(P.tris)]
     lo, hi = V.min(0), V.max(0)
     center = 0.5 * (lo + hi)
@@ -75,9 +88,12 @@ def build(P, leaf_size=32, eta0=0.8, max_level=20):
         # centre (the far field only ever evaluates the 3-point rule)
         memb = np.repeat(np.arange(len(start)), end - start)
         vv = P.qp[perm]                                   # [N,3,3]
-        dist = np.linalg.norm(vv - ctr[memb][:, None, :], axis=2)
+        dist = np.linalg.norm(vv - ctr[memb][:, None, :], axis=2).max(1)
+        dvert = np.linalg.norm(P.corners[perm] - ctr[memb][:, None, :], axis=2).max(1)
+        rho_c = np.zeros(len(start))
+        np.maximum.at(rho_c, memb, dvert)
         levels.append(SimpleNamespace(level=lev, start=start, end=end, idx=idx,
-                                      h=h, center=ctr, rho=dist.max(),
+                                      h=h, center=ctr, rho=dist.max(), rho_c=rho_c,
                                       key=k[start], n=len(start)))
     # parents / children
     for lev in range(1, L + 1):
@@ -99,8 +115,14 @@ def build(P, leaf_size=32, eta0=0.8, max_level=20):
             cand = np.concatenate([np.arange(pa.child_start[q], pa.child_end[q])
                                    for q in pa.nbr[p]])
             d = np.sqrt(((cl.center[ci] - cl.center[cand]) ** 2).sum(1))
+            if radii == "cluster":
+                num = cl.rho_c[ci] + cl.rho_c[cand]
+            elif radii == "level":
+                num = cl.rho + cl.rho
+            else:
+                raise ValueError("radii must be 'level' or 'cluster'")
             with np.errstate(divide="ignore"):
-                eta = (cl.rho + cl.rho) / d
+                eta = num / d
             isn = eta > eta0
             nbr.append(cand[isn])
             inter.append(cand[~isn])
@@ -108,7 +130,8 @@ def build(P, leaf_size=32, eta0=0.8, max_level=20):
     lmin = next((l for l in range(L + 1)
                  if any(len(x) for x in levels[l].inter)), L + 1)
     return SimpleNamespace(L=L, levels=levels, perm=perm, corner=corner,
-                           side=side, lmin=lmin, leaf_size=leaf_size, eta0=eta0)
+                           side=side, lmin=lmin, leaf_size=leaf_size, eta0=eta0,
+                           radii=radii)
 
 
 def orders(tree, p_leaf, adaptive, p_max):

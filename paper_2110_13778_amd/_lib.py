@@ -17,6 +17,7 @@ W_NOT_CONVERGED = 1
 FP64, MIXED = 0, 1
 PRECOND_NONE, PRECOND_DIAG, PRECOND_BLOCK, PRECOND_GROUP = 0, 1, 2, 3
 MLP_OFF, MLP_PRECOND, MLP_GATED = 0, 1, 2
+RADII_LEVEL, RADII_CLUSTER = 0, 1
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 
 EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
@@ -39,7 +40,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_outer", C.c_int32), ("inner_tol", C.c_double),
                 ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double), ("rhs_theta", C.c_double),
-                ("rhs_pmax", C.c_int32)]
+                ("rhs_pmax", C.c_int32), ("radii", C.c_int32)]
 
 
 class TreeInfo(C.Structure):

@@ -377,6 +377,8 @@ static int check_params(const fagbi_params* p) {
   if (p->mlp_mode < 0 || p->mlp_mode > 2) return set_error(FAGBI_E_ARG, "bad mlp_mode");
   if (!(p->rhs_theta >= 0 && p->rhs_theta < 1)) return set_error(FAGBI_E_ARG, "rhs_theta must be in [0, 1)");
   if (p->rhs_pmax < 0) return set_error(FAGBI_E_ARG, "rhs_pmax must be >= 0");
+  if (p->radii != FAGBI_RADII_LEVEL && p->radii != FAGBI_RADII_CLUSTER)
+    return set_error(FAGBI_E_ARG, "radii must be FAGBI_RADII_LEVEL or FAGBI_RADII_CLUSTER");
   return 0;
 }
 

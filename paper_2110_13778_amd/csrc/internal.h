@@ -72,6 +72,7 @@ struct Level {
   int order = 0;      // expansion order p_l
   int T = 0;          // terms of order p_l
   double h = 0, rho = 0;
+  DBuf d_rho_c;                      // per-cluster radii (FAGBI_RADII_CLUSTER only)
   int64_t n_inter = 0;               // interaction pairs (c, c' in I(c))
   std::vector<int32_t> off_xyz;      // 3 * n_off distinct offsets (c - c')
   int n_off = 0;

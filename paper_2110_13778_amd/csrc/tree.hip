@@ -413,6 +413,33 @@ __global__ void __launch_bounds__(TB) k_level_rho(const double* __restrict__ pv,
   if (threadIdx.x == 0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+// farthest vertex of a member panel from its cube centre, per cluster (the
+// ball of radius rho_c around the centre holds the cluster's panels whole);
+// one wavefront per cluster, lanes over its panels (contiguous in tree order);
+// the square root is monotone and correctly rounded, so the root of the
+// largest squared distance is the largest distance
+__global__ void __launch_bounds__(256) k_cluster_rho(const double* __restrict__ pv,
+                                                     const int32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ end,
+                                                     const int32_t* __restrict__ idx, int ncl, double c0,
+                                                     double c1, double c2, double h, double* rho_c) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncl) return;
+  const double ctr[3] = {c0 + ((double)idx[3 * c] + 0.5) * h, c1 + ((double)idx[3 * c + 1] + 0.5) * h,
+                         c2 + ((double)idx[3 * c + 2] + 0.5) * h};
+  double r2 = 0;
+  for (int k = start[c] + lane; k < end[c]; k += 64) {
+    const double* cv = pv + 9 * (int64_t)k;
+    for (int v = 0; v < 3; ++v) {
+      const double s0 = cv[3 * v] - ctr[0], s1 = cv[3 * v + 1] - ctr[1], s2 = cv[3 * v + 2] - ctr[2];
+      r2 = fmax(r2, (s0 * s0 + s1 * s1) + s2 * s2);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
+  if (lane == 0) rho_c[c] = sqrt(r2);
+}
+
 __global__ void k_parents(const int32_t* __restrict__ start, int n, const int32_t* __restrict__ owner_up,
                           int32_t* parent) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,6 +469,7 @@ struct ListArgs {
   int n;
   double c0, c1, c2, h, rho, eta0;
   int W, span;
+  const double* rho_c;         // per-cluster radii, or null for rho on every cluster
 };
 
 template <int PASS>
@@ -464,7 +492,8 @@ __global__ void k_lists(ListArgs a, int32_t* ncnt, int32_t* icnt, int* reach, co
       const double s1 = xc1 - (a.c1 + ((double)jy + 0.5) * a.h);
       const double s2 = xc2 - (a.c2 + ((double)jz + 0.5) * a.h);
       const double dist = sqrt((s0 * s0 + s1 * s1) + s2 * s2);
-      const double eta = (a.rho + a.rho) / dist;   // +inf for c2 == c
+      const double num = a.rho_c ? a.rho_c[c] + a.rho_c[c2] : a.rho + a.rho;
+      const double eta = num / dist;   // +inf for c2 == c
       const int o0 = ix - jx, o1 = iy - jy, o2 = iz - jz;
       if (eta > a.eta0) {
         if (PASS == 0) {
@@ -804,6 +833,12 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
                                            D.d_idx.as<int32_t>(), start[l], end[l]);
     k_level_rho<<<grid_of(N), TB, 0, s>>>(h->d_pv.as<double>(), owner[l], D.d_idx.as<int32_t>(), N, corner[0],
                                           corner[1], corner[2], D.h, rho_bits + l);
+    if (h->prm.radii == FAGBI_RADII_CLUSTER) {
+      FAGBI_TRY(h->alloc(D.d_rho_c, (size_t)D.n * 8));
+      k_cluster_rho<<<(unsigned)((D.n + 3) / 4), 256, 0, s>>>(h->d_pv.as<double>(), start[l], end[l],
+                                                              D.d_idx.as<int32_t>(), D.n, corner[0], corner[1],
+                                                              corner[2], D.h, D.d_rho_c.as<double>());
+    }
   }
   {
     const int32_t m1 = -1;
@@ -844,7 +879,7 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
       return set_error(FAGBI_E_MESH, "build_tree: neighbour stencil too wide on level %d (reach %d)", l, reach);
     ListArgs a{C.d_idx.as<int32_t>(), C.d_parent.as<int32_t>(), nbr_off[l - 1], nbr[l - 1],
                P.d_child_start.as<int32_t>(), P.d_child_end.as<int32_t>(), C.n, corner[0], corner[1], corner[2],
-               C.h, C.rho, eta0, W, span};
+               C.h, C.rho, eta0, W, span, C.d_rho_c.p ? C.d_rho_c.as<double>() : nullptr};
     int32_t *ncnt, *icnt;
     FAGBI_TRY(A.get(ncnt, C.n));
     FAGBI_TRY(A.get(icnt, C.n));

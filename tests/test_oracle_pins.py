@@ -269,9 +269,15 @@ def test_born_surface_values():
     assert np.linalg.norm(A @ x - b) < 1e-9 * np.linalg.norm(b)
 
 
-def test_tree_coverage_and_fmm_convergence():
+@pytest.fixture(scope="module")
+def sphere1280_dense():
     v, t = icosphere(3, 2.0)
     P = panels(v, t)
+    return P, dense.assemble(P, 80.0, 0.1257)
+
+
+def test_tree_coverage_and_fmm_convergence(sphere1280_dense):
+    P, A = sphere1280_dense
     tr = otree.build(P, 32, 0.8)
     assert (fmm.coverage(tr) == 1).all()
     # a deeper tree on a smaller leaf size also covers every pair once
@@ -281,7 +287,7 @@ def test_tree_coverage_and_fmm_convergence():
     x = rng.standard_normal(2 * P.n)
     F = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=2, with_near=False)
     near = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=2)
-    ref = dense.assemble(P, 80.0, 0.1257) @ x
+    ref = A @ x
     errs = []
     for p in (2, 4, 6):
         F = fmm.setup(P, tr8, 80.0, 0.1257, p_leaf=p, with_near=False)
@@ -290,6 +296,54 @@ def test_tree_coverage_and_fmm_convergence():
     assert errs[1] < 0.5 * errs[0] and errs[2] < 0.5 * errs[1], errs
     # far field off + every pair near (eta0 = 0) is the dense operator exactly
     tr0 = otree.build(P, 32, 0.0)
+    F0 = fmm.setup(P, tr0, 80.0, 0.1257, p_leaf=2)
+    assert np.linalg.norm(fmm.matvec(F0, x) - ref) < 1e-13 * np.linalg.norm(ref)
+
+
+def test_cluster_radii_tree_pins(sphere1280_dense):
+    """Per-cluster radii (the shrink scheme of Sec. 2.4 with the cube centre
+    kept), checked from the member panels' own vertices rather than from the
+    radii the tree stores: every neighbour pair inadmissible and every
+    interaction pair admissible, every leaf pair covered once, panels that
+    share a vertex always in neighbouring leaves, the FMM converging to the
+    dense operator as p grows, and eta0 = 0 giving the dense operator."""
+    P, A = sphere1280_dense
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(2 * P.n)
+    ref = A @ x
+    # panel pairs sharing a vertex
+    inc = {}
+    for i, tri in enumerate(P.tris):
+        for v in tri:
+            inc.setdefault(int(v), []).append(i)
+    touching = {(a, b) for ps in inc.values() for a in ps for b in ps}
+    for leaf_size, eta0 in ((8, 0.8), (4, 0.6)):
+        tr = otree.build(P, leaf_size, eta0, radii="cluster")
+        assert (fmm.coverage(tr) == 1).all()
+        for l in range(1, tr.L + 1):
+            cl = tr.levels[l]
+            rad = np.array([np.linalg.norm(P.corners[tr.perm[cl.start[c]:cl.end[c]]] - cl.center[c], axis=2).max()
+                            for c in range(cl.n)])
+            for c in range(cl.n):
+                d = np.linalg.norm(cl.center[cl.inter[c]] - cl.center[c], axis=1)
+                assert (rad[c] + rad[cl.inter[c]] <= eta0 * d).all()
+                nb = cl.nbr[c][cl.nbr[c] != c]
+                d = np.linalg.norm(cl.center[nb] - cl.center[c], axis=1)
+                assert (rad[c] + rad[nb] > eta0 * d).all()
+        leaf = tr.levels[tr.L]
+        own = np.empty(P.n, np.int64)
+        own[tr.perm] = np.repeat(np.arange(leaf.n), leaf.end - leaf.start)
+        nbrs = [set(map(int, leaf.nbr[c])) for c in range(leaf.n)]
+        assert all(int(own[b]) in nbrs[own[a]] for a, b in touching)
+    tr = otree.build(P, 8, 0.8, radii="cluster")
+    near = fmm.setup(P, tr, 80.0, 0.1257, p_leaf=2)
+    errs = []
+    for p in (2, 4, 6):
+        F = fmm.setup(P, tr, 80.0, 0.1257, p_leaf=p, with_near=False)
+        F.near_i, F.near_j, F.near_B = near.near_i, near.near_j, near.near_B
+        errs.append(np.linalg.norm(fmm.matvec(F, x) - ref) / np.linalg.norm(ref))
+    assert errs[1] < 0.5 * errs[0] and errs[2] < 0.5 * errs[1], errs
+    tr0 = otree.build(P, 32, 0.0, radii="cluster")
     F0 = fmm.setup(P, tr0, 80.0, 0.1257, p_leaf=2)
     assert np.linalg.norm(fmm.matvec(F0, x) - ref) < 1e-13 * np.linalg.norm(ref)
 
