@@ -390,6 +390,7 @@ int fagbi_create(const fagbi_params* p, fagbi_handle** out) {
   if (!h) return set_error(FAGBI_E_OOM, "host allocation failed");
   h->prm = *p;
   if (const char* e = std::getenv("FAGBI_M2L_TILES")) h->m2l_tiles = std::atoi(e) != 0;
+  if (const char* e = std::getenv("FAGBI_M2L_MFMA")) h->m2l_mfma = std::atoi(e) != 0;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return set_error(FAGBI_E_HIP, "no HIP device");

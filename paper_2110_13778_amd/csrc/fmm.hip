@@ -33,6 +33,8 @@
 
 namespace fagbi {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __host__ __device__ constexpr int midx(int a, int b, int c) {
   const int d = a + b + c;
   const int below = d * (d + 1) * (d + 2) / 6;
@@ -954,6 +956,187 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
   }
 }
 
+// The same MtL on the matrix cores (order 3).  Per target and channel the
+// pairs' derivative rows D_k and scaled source moments m_k give
+//   X[g][b] = sum_k D_k[g] m_k[b],   L_a = sum over b <= g, g - b = a of X[g][b]
+// (with b <= g componentwise, |a| + |b| = |g| <= 3: exactly the truncated
+// translation).  One wavefront per target, four pairs per step,
+// v_mfma_f32_16x16x4f32 with A[i][k] = D_k[16 t + i] (derivative tile t = 0:
+// terms 0..15; t = 1: terms 16..19, rows 4..15 zero) and B[k][j] = m_k[j],
+// moments 0..15.  A moment of degree 3 only meets g = b; for b = 16..19 these
+// four diagonal products are summed on the vector units.  Each X entry of a
+// lane is then added to its local term (xdst: tile, lane and element -> term
+// a, or -1) in a per-wavefront LDS row.
+template <int P>
+__global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile_mfma(const int32_t* __restrict__ inter_off,
+                                                            const uint32_t* __restrict__ pack,
+                                                            const int32_t* __restrict__ tile_t0,
+                                                            const int32_t* __restrict__ tile_off,
+                                                            const int32_t* __restrict__ tile_src, int ntile,
+                                                            const float2* __restrict__ Dh, int n_half, int umax,
+                                                            const int8_t* __restrict__ xdst,
+                                                            const float* __restrict__ M0,
+                                                            const float* __restrict__ Mk, float* L0, float* Lk) {
+  static_assert(P == 3, "tiles of 16 derivative terms cover order 3");
+  constexpr TermTable<P> tt{};
+  constexpr int T = TermTable<P>::T;
+  constexpr int CPR = T / 4;
+  constexpr int NW = MT_NT / 64;
+  constexpr int ROWB = T * 8;                 // bytes of a row (both channels)
+  uint32_t odd = 0;
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (tt.deg[t] & 1) odd |= 1u << t;
+  // LDS: half table rows 0..n_half-1, a zero row n_half, then the staged
+  // moments, slots 0..umax-1, a zero row at slot umax and one row of slack
+  // (the lanes of terms 20..31 read past a row; their values are discarded);
+  // pairs past the end of a list point at both zero rows
+  extern __shared__ __align__(16) char smem_raw[];
+  float2* dsm = reinterpret_cast<float2*>(smem_raw);
+  float2* msm = dsm + (size_t)(n_half + 1) * T;
+  __shared__ float msc[T], lsc[T];
+  __shared__ float lred[NW][2 * T];
+  __shared__ int32_t qoff[MTK + 1];
+  for (int e = threadIdx.x; e < n_half * T; e += MT_NT) dsm[e] = Dh[e];
+  if (threadIdx.x < T) {
+    dsm[n_half * T + threadIdx.x] = make_float2(0.0f, 0.0f);
+    msm[umax * T + threadIdx.x] = make_float2(0.0f, 0.0f);
+    float f = 1.0f, g = 1.0f;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      if (t == (int)threadIdx.x) {
+        f = (float)tt.msc[t];
+        g = (float)tt.lsc[t];
+      }
+    msc[threadIdx.x] = f;
+    lsc[threadIdx.x] = g;
+  }
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int dst[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[t][e] = xdst[((t * 4 + lk) * 16 + li) * 4 + e];
+  // per-lane constants: byte offsets of the lane's terms, the sign-bit mask
+  // of its tile-0 derivative term (odd degree flips with the offset), and
+  // whether it carries one of the terms 16..19
+  const uint32_t lane_off = (uint32_t)li * 8u;
+  const uint32_t oddmask = ((odd >> li) & 1u) ? 0x80000000u : 0u;
+  const bool hi = li < 4;
+  const uint32_t dbase = (uint32_t)(reinterpret_cast<const char*>(dsm) - smem_raw);
+  const uint32_t mbase = (uint32_t)(reinterpret_cast<const char*>(msm) - smem_raw);
+  const uint32_t zpack = (uint32_t)umax | ((uint32_t)n_half << 12);
+  const int nbx = (int)((gridDim.x + 7) / 8);
+  const int xcd = (int)(blockIdx.x & 7), bl = (int)(blockIdx.x >> 3);
+  const int per = (ntile + 8 * nbx - 1) / (8 * nbx);
+  float4 ra[MT_IPT], rb[MT_IPT];
+  auto prefetch = [&](int tile) {
+    if (tile >= ntile) return;
+    const int u0 = tile_off[tile], ni = (tile_off[tile + 1] - u0) * CPR;
+#pragma unroll
+    for (int k = 0; k < MT_IPT; ++k) {
+      const int i = threadIdx.x + k * MT_NT;
+      if (i < ni) {
+        const int sl = i / CPR, j = i - sl * CPR;
+        const int64_t mo = (int64_t)tile_src[u0 + sl] * T + 4 * j;
+        ra[k] = *reinterpret_cast<const float4*>(M0 + mo);
+        rb[k] = *reinterpret_cast<const float4*>(Mk + mo);
+      }
+    }
+  };
+  __syncthreads();   // msc, lsc, zero rows
+  prefetch(xcd * per * nbx + bl);
+  for (int it = 0; it < per; ++it) {
+    const int tile = (xcd * per + it) * nbx + bl;
+    __syncthreads();   // the previous tile's sources are no longer read
+    if (tile >= ntile) continue;
+    const int t0 = tile_t0[tile], nt = tile_t0[tile + 1] - t0;
+    {
+      const int ni = (tile_off[tile + 1] - tile_off[tile]) * CPR;
+#pragma unroll
+      for (int k = 0; k < MT_IPT; ++k) {
+        const int i = threadIdx.x + k * MT_NT;
+        if (i < ni) {
+          const int sl = i / CPR, j = i - sl * CPR;
+          const float s0 = msc[4 * j], s1 = msc[4 * j + 1], s2 = msc[4 * j + 2], s3 = msc[4 * j + 3];
+          float4* dst4 = reinterpret_cast<float4*>(msm + (size_t)sl * T + 4 * j);
+          dst4[0] = make_float4(ra[k].x * s0, rb[k].x * s0, ra[k].y * s1, rb[k].y * s1);
+          dst4[1] = make_float4(ra[k].z * s2, rb[k].z * s2, ra[k].w * s3, rb[k].w * s3);
+        }
+      }
+      for (int e = threadIdx.x; e <= nt; e += MT_NT) qoff[e] = inter_off[t0 + e];
+    }
+    __syncthreads();
+    if (it + 1 < per) prefetch((xcd * per + it + 1) * nbx + bl);
+    for (int c = wv; c < nt; c += NW) {      // wave-uniform
+      const int q0 = qoff[c], q1 = qoff[c + 1];
+      f32x4 x00 = {0.f, 0.f, 0.f, 0.f}, x01 = x00, xk0 = x00, xk1 = x00;
+      float dg0 = 0.0f, dgk = 0.0f;          // the diagonal products of moments 16..19
+      // packed indices of 64 pairs at a time (one coalesced load), handed to
+      // the lanes of each step by ds_bpermute
+      for (int base = q0; base < q1; base += 64) {
+        const uint32_t pkl = base + lane < q1 ? pack[base + lane] : zpack;
+        const int ns = min(16, (q1 - base + 3) / 4);   // wave-uniform
+        int baddr = lk * 4;
+#pragma unroll 2
+        for (int s = 0; s < ns; ++s, baddr += 16) {
+          const uint32_t pk = (uint32_t)__builtin_amdgcn_ds_bpermute(baddr, (int)pkl);
+          const uint32_t da = dbase + ((pk >> 12) & 0x7ffffu) * (uint32_t)ROWB + lane_off;
+          const uint32_t ma = mbase + (pk & 0xfffu) * (uint32_t)ROWB + lane_off;
+          const float2 d0 = *reinterpret_cast<const float2*>(smem_raw + da);
+          const float2 m0 = *reinterpret_cast<const float2*>(smem_raw + ma);
+          const float2 d1 = *reinterpret_cast<const float2*>(smem_raw + da + 128);
+          const float2 m1 = *reinterpret_cast<const float2*>(smem_raw + ma + 128);
+          const uint32_t fm = pk & 0x80000000u;        // flip: odd degrees change sign
+          const uint32_t f0 = fm & oddmask;
+          const float a00 = __uint_as_float(__float_as_uint(d0.x) ^ f0);
+          const float a0k = __uint_as_float(__float_as_uint(d0.y) ^ f0);
+          const float a10 = hi ? __uint_as_float(__float_as_uint(d1.x) ^ fm) : 0.0f;
+          const float a1k = hi ? __uint_as_float(__float_as_uint(d1.y) ^ fm) : 0.0f;
+          const float c0 = hi ? m1.x : 0.0f, ck = hi ? m1.y : 0.0f;
+          x00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a00, m0.x, x00, 0, 0, 0);
+          x01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a10, m0.x, x01, 0, 0, 0);
+          xk0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0k, m0.y, xk0, 0, 0, 0);
+          xk1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1k, m0.y, xk1, 0, 0, 0);
+          dg0 += a10 * c0;
+          dgk += a1k * ck;
+        }
+      }
+      // lane (li, lk) holds X[16 t + 4 lk + e][li] in element e of tile t
+      if (lane < 2 * T) lred[wv][lane] = 0.0f;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (dst[0][e] >= 0) {
+          atomicAdd(&lred[wv][dst[0][e]], x00[e]);
+          atomicAdd(&lred[wv][T + dst[0][e]], xk0[e]);
+        }
+        if (dst[1][e] >= 0) {
+          atomicAdd(&lred[wv][dst[1][e]], x01[e]);
+          atomicAdd(&lred[wv][T + dst[1][e]], xk1[e]);
+        }
+      }
+      if (hi) {   // X[b][b] for b = 16..19: local term 0
+        atomicAdd(&lred[wv][0], dg0);
+        atomicAdd(&lred[wv][T], dgk);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < 2 * T) {
+        const int t = lane < T ? lane : lane - T;
+        (lane < T ? L0 : Lk)[(int64_t)(t0 + c) * T + t] = lred[wv][lane] * lsc[t];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
 // MtM: one block per parent; slot = (a | b << 16), a parent index, b child
 // index (b <= a componentwise); coefficient rows per child octant.
 template <typename R, int SPT>
@@ -1381,6 +1564,22 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
     for (int d = 0; d < 3; ++d) mi[3 * t + d] = (int8_t)m.a[d];
   }
   st.add(h->d_mi, mi.data(), mi.size());
+  {
+    // order-3 matrix-core MtL: X entry (derivative tile t, lane k + 16 j,
+    // element e) = X[16 t + 4 j + e][k] -> local term g - b, or -1
+    std::vector<int8_t> xd(2 * 4 * 16 * 4, -1);
+    for (int t = 0; t < 2; ++t)
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 16; ++k)
+          for (int e = 0; e < 4; ++e) {
+            const int g = 16 * t + 4 * j + e;
+            if (g >= nterms(3)) continue;
+            const MI G = mi_of(g), B = mi_of(k);
+            if (B.a[0] > G.a[0] || B.a[1] > G.a[1] || B.a[2] > G.a[2]) continue;
+            xd[((t * 4 + j) * 16 + k) * 4 + e] = (int8_t)midx(G.a[0] - B.a[0], G.a[1] - B.a[1], G.a[2] - B.a[2]);
+          }
+    st.add(h->d_xdst, xd.data(), xd.size());
+  }
   const int lo = std::min(h->lmin, h->L);
   for (int l = lo; l <= h->L; ++l) {
     Level& D = h->lev[l];
@@ -1718,6 +1917,20 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
                                                      D.d_inter_oid.as<int32_t>(), Dh, D.n_half,
                                                      D.d_oid_map.as<int32_t>(), D.n_off, D.n, S, M(D, 0), M(D, 1),
                                                      Lc(D, 0), Lc(D, 1));
+      return 0;
+    }
+    if constexpr (sizeof(R) == 4)
+    if (D.n_tile > 0 && D.order == 3 && h->m2l_tiles && h->m2l_mfma) {
+      // table + zero row, staged moments + zero row, and one row of slack:
+      // lanes past term 19 of a zero row read (and discard) up to 96 bytes beyond it
+      const size_t lds = ((size_t)D.n_half + 1 + D.tile_umax + 2) * D.T * sizeof(float2);
+      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile_mfma<3>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      k_m2l_tile_mfma<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
+                                                  D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
+                                                  D.d_tile_src.as<int32_t>(), D.n_tile,
+                                                  (const float2*)D.d_F32[1].p, D.n_half, D.tile_umax,
+                                                  h->d_xdst.as<int8_t>(), M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
       return 0;
     }
     if constexpr (sizeof(R) == 4)

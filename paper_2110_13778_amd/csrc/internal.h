@@ -135,6 +135,7 @@ struct fagbi_handle {
   fagbi::DBuf d_E64, d_E32;           // near-field entries (double4 / float4)
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
   fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]
+  fagbi::DBuf d_xdst;                 // matrix-core MtL: X entry -> local term
   fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner (block inverses, FP64)
   fagbi::DBuf d_lu32;                          // FP32 copy for the mixed path's inner solves
   fagbi::DBuf d_grp_leaf, d_grp_panel;         // its blocks: leaf and panel ranges
@@ -158,6 +159,7 @@ struct fagbi_handle {
   // FP32 leaf-level MtL by the source-reuse tile kernel (when its tables fit);
   // FAGBI_M2L_TILES=0 in the environment selects the per-pair LDS-table kernel
   bool m2l_tiles = true;
+  bool m2l_mfma = false;               // leaf-level FP32 MtL on the matrix cores
   // per-phase profiling
   bool profiling = false;
   // matvec phase events: 5 start; 0, 1 around the near-field SpMV (on its

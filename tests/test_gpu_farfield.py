@@ -95,3 +95,39 @@ def test_far_field_fixed_order8(sphere5120):
     print("  whole operator, mixed vs FP64: rel-L2 %.2e max-row %.2e" % ew)
     assert ew[0] < 1e-6 and ew[1] < 1e-6, ew
     h.close()
+
+
+@pytest.mark.parametrize("mesh", ["sphere", "globule"])
+def test_leaf_mtl_on_matrix_cores(sphere5120, mesh, monkeypatch):
+    """The order-3 leaf-level FP32 MtL on the matrix cores (FAGBI_M2L_MFMA=1,
+    v_mfma_f32_16x16x4f32) against the oracle's far field (the FP32 bounds
+    above) and against the vector-unit kernel on the same tiles (both FP32,
+    different summation order: 1e-6)."""
+    from synth import isosurface_mesh, packed_atoms_ball
+    if mesh == "sphere":
+        v, t, P = sphere5120
+        leaf = 4
+    else:
+        xa, ra, _ = packed_atoms_ball(n=40, radius=None, seed=11)
+        v, t = isosurface_mesh(xa, ra, spacing=0.9)
+        P = panels(v, t)
+        leaf = 8
+    prm = dict(eps_out=EPS, kappa=KAP, leaf_size=leaf, eta0=0.8, p_leaf=3, adaptive=1, p_max=8)
+    monkeypatch.setenv("FAGBI_M2L_MFMA", "1")
+    hm = F.Handle(**prm).build_tree(v, t).assemble_nearfield()
+    monkeypatch.setenv("FAGBI_M2L_MFMA", "0")
+    hv = F.Handle(**prm).build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, leaf, 0.8)
+    assert hm.tree_info().lev_order[tr.L] == 3
+    O = ofmm.setup(P, tr, EPS, KAP, p_leaf=3, adaptive=1, p_max=8, with_near=False)
+    rng = np.random.default_rng(44)
+    x = rng.standard_normal(2 * P.n)
+    ref = np.concatenate(ofmm.far_field(O, x[:P.n], x[P.n:]))
+    ym, yv = far_gpu(hm, x, F.MIXED), far_gpu(hv, x, F.MIXED)
+    em, ev, emv = errs(ym, ref), errs(yv, ref), errs(ym, yv)
+    print("%s (%d panels): matrix cores vs oracle %.2e / %.2e, vector units vs oracle %.2e / %.2e, "
+          "between them %.2e / %.2e" % (mesh, P.n, em[0], em[1], ev[0], ev[1], emv[0], emv[1]))
+    assert em[0] < 2e-6 and em[1] < 4e-6, em
+    assert emv[0] < 1e-6 and emv[1] < 2e-6, emv
+    hm.close()
+    hv.close()

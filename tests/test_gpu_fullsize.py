@@ -159,3 +159,27 @@ def test_full_size_solves(big):
         res[prec] = h.solvation_energy(x, w["xq"], w["q"])
         h.close()
     assert abs(res[F.MIXED] - res[F.FP64]) < 1e-5 * abs(res[F.FP64])
+
+
+def test_leaf_mtl_on_matrix_cores_full_size(big, monkeypatch):
+    """At full size the matrix-core leaf MtL (FAGBI_M2L_MFMA=1) gives the same
+    FP32 far field as the vector-unit kernel (1e-6) and stays within the FP32
+    bound of the FP64 far field (itself equal to the oracle's to 1e-11)."""
+    P, h, w = big["P"], big["h"], big["w"]
+    N = P.n
+    monkeypatch.setenv("FAGBI_M2L_MFMA", "1")
+    hm = F.Handle(eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], **PARAMS)
+    hm.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+    rng = np.random.default_rng(25)
+    x = rng.standard_normal(2 * N)
+    ym = gpu_matvec(hm, x, F.MIXED, F.PART_FAR)
+    yv = gpu_matvec(h, x, F.MIXED, F.PART_FAR)
+    y64 = gpu_matvec(h, x, F.FP64, F.PART_FAR)
+    e_mv, e_m64 = rel(ym, yv), rel(ym, y64)
+    mr = np.abs(ym - yv).max() / np.abs(yv).max()
+    print("full size far field: matrix cores vs vector units rel-L2 %.2e max-row %.2e; vs FP64 %.2e"
+          % (e_mv, mr, e_m64))
+    assert e_mv < 1e-6 and mr < 2e-6 and e_m64 < 2e-6
+    yall = gpu_matvec(hm, x, F.MIXED)
+    assert rel(yall, gpu_matvec(h, x, F.FP64)) < 1e-6
+    hm.close()
