@@ -35,6 +35,30 @@ namespace fagbi {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// lane exchanges by DPP moves (no LDS traffic): within quads lane ^ 1
+// (quad_perm 1,0,3,2) and lane ^ 2 (quad_perm 2,3,0,1); within 8 lanes the
+// mirrored lane 7 - i = i ^ 7 (row_half_mirror); within 16 lanes 15 - i = i ^ 15
+// (row_mirror)
+constexpr int DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_X7 = 0x141, DPP_X15 = 0x140;
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over aligned groups of S lanes (S = 1, 2, 4, 8 or 16), every lane of a
+// group receiving the total
+template <typename R> __device__ __forceinline__ R group_sum(R v, int S) {
+  if (S >= 2) v += dpp<DPP_X1>(v);
+  if (S >= 4) v += dpp<DPP_X2>(v);
+  if (S >= 8) v += dpp<DPP_X7>(v);
+  if (S >= 16) v += dpp<DPP_X15>(v);
+  return v;
+}
+
 __host__ __device__ constexpr int midx(int a, int b, int c) {
   const int d = a + b + c;
   const int below = d * (d + 1) * (d + 2) / 6;
@@ -396,13 +420,12 @@ __global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ int
       }
     }
   }
-  // combine the S partial sums (S divides 64, groups are lane-aligned)
-  for (int o = S >> 1; o > 0; o >>= 1)
+  // combine the S partial sums (S <= 16 divides 64, groups are lane-aligned)
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      l0[t] += __shfl_xor(l0[t], o, 64);
-      lk[t] += __shfl_xor(lk[t], o, 64);
-    }
+  for (int t = 0; t < T; ++t) {
+    l0[t] = group_sum(l0[t], S);
+    lk[t] = group_sum(lk[t], S);
+  }
   if (c < ncl && part == 0)
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -667,12 +690,11 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
         }
       }
     }
-    for (int o = S >> 1; o > 0; o >>= 1)
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        l0[t] += __shfl_xor(l0[t], o, 64);
-        lk[t] += __shfl_xor(lk[t], o, 64);
-      }
+    for (int t = 0; t < T; ++t) {
+      l0[t] = group_sum(l0[t], S);
+      lk[t] = group_sum(lk[t], S);
+    }
     if (c < ncl && part == 0)
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -828,16 +850,20 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
   extern __shared__ __align__(16) char smem_raw[];
   float2* dsm = reinterpret_cast<float2*>(smem_raw);
   float2* msm = dsm + (size_t)n_half * T;
-  __shared__ float msc[T];
+  __shared__ float msc[T], lsc[T];
   __shared__ float acc[MTK][2 * T];       // the tile's locals, both channels
   __shared__ int32_t qoff[MTK + 1];       // the tile's list offsets
   for (int e = threadIdx.x; e < n_half * T; e += MT_NT) dsm[e] = Dh[e];
-  if (threadIdx.x < T) {   // (-1)^|b| / b! of term b
-    float f = 1.0f;
+  if (threadIdx.x < T) {   // (-1)^|b| / b! of term b and 1 / a! of term a
+    float f = 1.0f, g = 1.0f;
 #pragma unroll
     for (int t = 0; t < T; ++t)
-      if (t == (int)threadIdx.x) f = (float)tt.msc[t];
+      if (t == (int)threadIdx.x) {
+        f = (float)tt.msc[t];
+        g = (float)tt.lsc[t];
+      }
     msc[threadIdx.x] = f;
+    lsc[threadIdx.x] = g;
   }
   const int nbx = (int)((gridDim.x + 7) / 8);
   const int xcd = (int)(blockIdx.x & 7), bl = (int)(blockIdx.x >> 3);
@@ -894,8 +920,11 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
     for (int t = 0; t < T; ++t) l0[t] = lk[t] = 0.0f;
     if (c < nt) {
       const int q1 = qoff[c + 1];
-      for (int q = qoff[c] + part; q < q1; q += MT_S) {
-        const uint32_t pk = pack[q];
+      int q = qoff[c] + part;
+      uint32_t pkn = q < q1 ? pack[q] : 0u;   // the packed index, loaded one pair ahead
+      for (; q < q1; q += MT_S) {
+        const uint32_t pk = pkn;
+        if (q + MT_S < q1) pkn = pack[q + MT_S];
         const float4* dp = reinterpret_cast<const float4*>(dsm + (size_t)((pk >> 12) & 0x7ffffu) * T);
         const float4* mp = reinterpret_cast<const float4*>(msm + (size_t)(pk & 0xfffu) * T);
         const float sg = (pk >> 31) ? -1.0f : 1.0f;
@@ -930,13 +959,13 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
         }
       }
     }
+    // sums over the 8 lanes of a target by DPP moves
+    static_assert(MT_S == 8, "lane groups of eight");
 #pragma unroll
-    for (int o = MT_S >> 1; o > 0; o >>= 1)
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        l0[t] += __shfl_xor(l0[t], o, 64);
-        lk[t] += __shfl_xor(lk[t], o, 64);
-      }
+    for (int t = 0; t < T; ++t) {
+      l0[t] = group_sum(l0[t], MT_S);
+      lk[t] = group_sum(lk[t], MT_S);
+    }
     if (c < nt && part == 0)
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -947,11 +976,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
     for (int e = threadIdx.x; e < nt * 2 * T; e += MT_NT) {
       const int cc = e / (2 * T), r = e - cc * 2 * T;
       const int t = r < T ? r : r - T;
-      float lsc = 1.0f;
-#pragma unroll
-      for (int u = 0; u < T; ++u)
-        if (u == t) lsc = (float)tt.lsc[u];
-      (r < T ? L0 : Lk)[(int64_t)(t0 + cc) * T + t] = acc[cc][r] * lsc;
+      (r < T ? L0 : Lk)[(int64_t)(t0 + cc) * T + t] = acc[cc][r] * lsc[t];
     }
   }
 }
@@ -1287,11 +1312,11 @@ __device__ inline double reduce_scatter8(const double* v, int lane) {
   const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
   double w[4], u[2];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = (b3 ? v[k + 4] : v[k]) + __shfl_xor(b3 ? v[k] : v[k + 4], 15, 64);
+  for (int k = 0; k < 4; ++k) w[k] = (b3 ? v[k + 4] : v[k]) + dpp<DPP_X15>(b3 ? v[k] : v[k + 4]);
 #pragma unroll
-  for (int k = 0; k < 2; ++k) u[k] = (b2 ? w[k + 2] : w[k]) + __shfl_xor(b2 ? w[k] : w[k + 2], 7, 64);
-  double z = (b1 ? u[1] : u[0]) + __shfl_xor(b1 ? u[0] : u[1], 2, 64);
-  z += __shfl_xor(z, 1, 64);
+  for (int k = 0; k < 2; ++k) u[k] = (b2 ? w[k + 2] : w[k]) + dpp<DPP_X7>(b2 ? w[k] : w[k + 2]);
+  double z = (b1 ? u[1] : u[0]) + dpp<DPP_X2>(b1 ? u[0] : u[1]);
+  z += dpp<DPP_X1>(z);
   z += __shfl_xor(z, 16, 64);
   z += __shfl_xor(z, 32, 64);
   return z;
