@@ -163,16 +163,22 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
     for (int ax = 0; ax < 3; ++ax)
       d[ax] = (2.0 / 3.0) * v[3 * k + ax] + (1.0 / 6.0) * (v[3 * ((k + 1) % 3) + ax] + v[3 * ((k + 2) % 3) + ax]) -
               ctr[ax];
-    double pw[3][PMAX + 1];
+    // d^e and d^(e-1) per axis by running products (kept in registers)
+    double pe[3], pm[3];
+#pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      pw[ax][0] = 1.0;
-      for (int q = 1; q <= e[ax]; ++q) pw[ax][q] = pw[ax][q - 1] * d[ax];
+      pe[ax] = 1.0;
+      pm[ax] = 0.0;
+      for (int q = 1; q <= e[ax]; ++q) {
+        pm[ax] = pe[ax];
+        pe[ax] *= d[ax];
+      }
     }
-    s += w * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2]];
+    s += w * pe[0] * pe[1] * pe[2];
     double g2 = 0;
-    if (e[0]) g2 += e[0] * pn[3 * i] * pw[0][e[0] - 1] * pw[1][e[1]] * pw[2][e[2]];
-    if (e[1]) g2 += e[1] * pn[3 * i + 1] * pw[0][e[0]] * pw[1][e[1] - 1] * pw[2][e[2]];
-    if (e[2]) g2 += e[2] * pn[3 * i + 2] * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2] - 1];
+    if (e[0]) g2 += e[0] * pn[3 * i] * pm[0] * pe[1] * pe[2];
+    if (e[1]) g2 += e[1] * pn[3 * i + 1] * pe[0] * pm[1] * pe[2];
+    if (e[2]) g2 += e[2] * pn[3 * i + 2] * pe[0] * pe[1] * pm[2];
     dsum += w * g2;
   }
   ms[g] = (R)s;
@@ -1393,10 +1399,28 @@ __global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restric
 // Taylor coefficients of one offset by the recurrence above (one thread per
 // offset and channel: kappa = 0 for G0), written as D_g = g! F_g / (4 pi)
 // into the interleaved {G0, Gk} tables, FP64 and FP32
-__global__ void __launch_bounds__(64) k_taylor_table(int n_off, const int32_t* __restrict__ off, double h,
-                                                     double kappa, int p, int T, double* dt, float* dt32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * n_off) return;
+struct TaylorJob {
+  const int32_t* off;
+  double* dt;
+  float* dt32;
+  double h;
+  int n_off, p, T;
+};
+struct TaylorJobs {
+  TaylorJob j[FAGBI_MAX_LEVELS];
+  int n;
+};
+// every level's tables in one launch: thread i -> (level, offset, channel)
+__global__ void __launch_bounds__(64) k_taylor_table(TaylorJobs jobs, double kappa) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int l = 0;
+  while (l < jobs.n && i >= 2 * jobs.j[l].n_off) i -= 2 * jobs.j[l].n_off, ++l;
+  if (l >= jobs.n) return;
+  const int32_t* __restrict__ off = jobs.j[l].off;
+  const double h = jobs.j[l].h;
+  const int p = jobs.j[l].p, T = jobs.j[l].T;
+  double* dt = jobs.j[l].dt;
+  float* dt32 = jobs.j[l].dt32;
   const int o = i >> 1, ch = i & 1;
   const double ka = ch ? kappa : 0.0;
   const double x0[3] = {off[3 * o] * h, off[3 * o + 1] * h, off[3 * o + 2] * h};
@@ -1750,12 +1774,21 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
   st.reserve(h->d_ms32, NT * 4);
   st.reserve(h->d_md32, NT * 4);
   FAGBI_TRY(st.commit(h, h->d_fmm_pool));
+  {
+    TaylorJobs jobs{};
+    int64_t nth = 0;
+    for (int l = std::max(lo, h->lmin); l <= h->L; ++l) {
+      Level& D = h->lev[l];
+      if (D.n_off == 0) continue;
+      jobs.j[jobs.n++] = TaylorJob{D.d_off.as<int32_t>(), D.d_F64[0].as<double>(), D.d_F32[0].as<float>(), D.h,
+                                   D.n_off, D.order, D.T};
+      nth += 2 * (int64_t)D.n_off;
+    }
+    if (jobs.n > 0) k_taylor_table<<<(unsigned)((nth + 63) / 64), 64, 0, s>>>(jobs, h->prm.kappa);
+  }
   for (int l = std::max(lo, h->lmin); l <= h->L; ++l) {
     Level& D = h->lev[l];
     if (D.n_off == 0) continue;
-    k_taylor_table<<<(unsigned)((2 * D.n_off + 63) / 64), 64, 0, s>>>(
-        D.n_off, D.d_off.as<int32_t>(), D.h, h->prm.kappa, D.order, D.T, D.d_F64[0].as<double>(),
-        D.d_F32[0].as<float>());
     if (D.n_half > 0) {
       const int64_t m = (int64_t)D.n_half * 2 * D.T;
       k_half_rows<float><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
