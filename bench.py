@@ -55,7 +55,10 @@ def parse():
     ap.add_argument("--fp64-runs", type=int, default=5, help="FP64 path solves (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the secondary workloads (globule200k, ellipsoid1m)")
+                    help="skip the secondary workloads (kirkwood2, globule200k, ellipsoid1m)")
+    ap.add_argument("--cpu-solve", action="store_true",
+                    help="only the oracle's whole solve on the 81,920-panel multi-charge sphere on the host "
+                         "(about half an hour of one core; no GPU), printed as one JSON line")
     ap.add_argument("--mlp-epochs", type=int, default=120,
                     help="training epochs of the near-field surrogate (before the timed steps)")
     ap.add_argument("--mlp-pairs", type=int, default=2000000,
@@ -256,8 +259,54 @@ def cpu_fmm_c2():
             "process_cpu_s": time.process_time() - c0, "mpanels_per_s_far_field_only": P.n / dt / 1e6}
 
 
+def cpu_solve_c2():
+    """The FP64 oracle's whole solve on the 81,920-panel multi-charge sphere
+    as it stands: tree, FMM setup with the near field (every stored pair by
+    its cubature rule), block preconditioner, right-hand side, right-
+    preconditioned GMRES to 1e-6 with the oracle's FMM matvec (adaptive orders
+    3..8, leaf 32, eta0 0.8), direct energy sum.  One process."""
+    from oracle import fmm as ofmm
+    from oracle import solve as osolve
+    from oracle import tree as otree
+    from oracle.geometry import panels
+    from synth import workload
+    w = workload("kirkwood2")
+    P = panels(w["verts"], w["tris"])
+    eps = w["eps_out"] / w["eps_in"]
+    t = {}
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    tr = otree.build(P, 32, 0.8)
+    t["tree"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F = ofmm.setup(P, tr, eps, w["kappa"], p_leaf=3, adaptive=True, p_max=8)
+    t["fmm_setup_and_near_field"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    M = osolve.block_preconditioner(P, tr, eps, w["kappa"])
+    t["preconditioner"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = osolve.rhs(P, w["xq"], w["q"], w["eps_in"])
+    t["rhs"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, its, hist = osolve.gmres(lambda z: ofmm.matvec(F, z), b, tol=1e-6, max_iter=100, precond=M)
+    t["gmres"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    E = osolve.energy(P, x, w["xq"], w["q"], eps, w["kappa"])
+    t["energy"] = time.perf_counter() - t0
+    model, ncpu, avail = host_cpu()
+    total = sum(t.values())
+    return {"workload": "kirkwood2: 81,920-panel sphere, 50 charges", "kind": "oracle",
+            "time_to_solve_s": total, "stage_s": t, "gmres_iterations": int(its),
+            "estimated_residual": float(hist[-1]), "energy_kcal": float(E), "near_pairs": int(len(F.near_i)),
+            "process_cpu_s": time.process_time() - c0, "cpu_model": model, "nproc": ncpu,
+            "threads_available": avail}
+
+
 def main():
     args = parse()
+    if args.cpu_solve:
+        print(json.dumps({"cpu_baseline_solve": cpu_solve_c2()}))
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU; --gpus %d is not supported "
               "(the path shards by contiguous Morton ranges of leaves; not built here)" % args.gpus,
@@ -483,7 +532,7 @@ def main():
     }
     if not args.no_secondary:
         sec = {}
-        for name in ("globule200k", "ellipsoid1m"):
+        for name in ("kirkwood2", "globule200k", "ellipsoid1m"):
             w2 = workload(name)
             r = {"panels": len(w2["tris"]), "charges": len(w2["q"])}
             for tag, prec, mlp in (("mixed_with_surrogate", F.MIXED, True), ("fp64", F.FP64, True)):
