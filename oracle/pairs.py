@@ -8,7 +8,8 @@ Classes (decided from shared vertex indices and centroid distance):
   REGULAR otherwise
 
 Rules (n = Gauss-Legendre points per dimension, 7 by default):
-  REGULAR  3-point x 3-point product rule (Sec. 2.3 regular quadrature).
+  REGULAR  product of the panels' regular rules (3 x 3 points; 1 x 1 with
+           the one-point panel rule), Sec. 2.3 regular quadrature.
   CLOSE    Duffy-collapsed n x n Gauss rule on each triangle (n^4 points).
   IDENT/EDGE/VERTEX: the singularity-removing relative-coordinate transforms of
   Sauter and Schwab (Sec. 2.3, "cubature"), written out below from their
@@ -79,9 +80,10 @@ def _integrate(r, wts, nx, ny, kappa, kern=None):
 
 
 def regular(P, i, j, kappa, kern=None):
+    m = P.qp.shape[1]
     r = P.qp[i][:, :, None, :] - P.qp[j][:, None, :, :]
     w = P.qw[i][:, :, None] * P.qw[j][:, None, :]
-    return _integrate(r.reshape(len(i), 9, 3), w.reshape(len(i), 9),
+    return _integrate(r.reshape(len(i), m * m, 3), w.reshape(len(i), m * m),
                       P.normal[i], P.normal[j], kappa, kern)
 
 

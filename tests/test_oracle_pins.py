@@ -251,6 +251,31 @@ def test_paper_sphere_energy_matches_table2():
     assert abs(E - g[("exact", "inf")]) < abs(g[("table1_order1", "320")] - g[("exact", "inf")])
 
 
+def test_regular_rule_reading_against_tables():
+    """Reading of the paper's regular quadrature (Sec. 2.3; Tables 1-2 print
+    energies for orders 2-4 of the touching-pair cubature): on its 320-panel
+    sphere the three-point panel rule lands within 0.05 % of the printed
+    entries for orders 3 and 4, while a one-point (centroid) rule for the
+    regular pairs, the right-hand side and the energy lands 1.6 % away from
+    them and farther than the three-point rule for every order 2-4."""
+    g = _golden("kirkwood_paper_table2.txt")
+    v, t = icosphere(2, 50.0)
+    err = {}
+    for pts in (3, 1):
+        P = panels(v, t, points=pts)
+        b = solve.rhs(P, np.zeros((1, 3)), np.array([50.0]), 1.0)
+        for n in (2, 3, 4):
+            A = dense.assemble(P, 40.0, 0.1257, n=n)
+            x = np.linalg.solve(A, b)
+            E = solve.energy(P, x, np.zeros((1, 3)), np.array([50.0]), 40.0, 0.1257)
+            ref = g[("table2_order%d" % n, "320")]
+            err[(pts, n)] = abs(E - ref) / abs(ref)
+    for n in (2, 3, 4):
+        assert err[(3, n)] < err[(1, n)], (n, err)
+        assert err[(1, n)] > 1e-2, (n, err)
+    assert err[(3, 3)] < 5e-4 and err[(3, 4)] < 5e-4, err
+
+
 def test_born_surface_values():
     """Solved surface potential/derivative vs the exact Born values on C1-like sphere."""
     v, t = icosphere(2, 2.0)
