@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile_mfma(const int32_t* __res
   float2* dsm = reinterpret_cast<float2*>(smem_raw);
   float2* msm = dsm + (size_t)(n_half + 1) * T;
   __shared__ float msc[T], lsc[T];
-  __shared__ float lred[NW][2 * T];
+  __shared__ float lred[NW][2][2 * T];   // per wavefront, alternating between its targets
   __shared__ int32_t qoff[MTK + 1];
   for (int e = threadIdx.x; e < n_half * T; e += MT_NT) dsm[e] = Dh[e];
   if (threadIdx.x < T) {
@@ -1134,36 +1134,36 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile_mfma(const int32_t* __res
           dgk += a1k * ck;
         }
       }
-      // lane (li, lk) holds X[16 t + 4 lk + e][li] in element e of tile t
-      if (lane < 2 * T) lred[wv][lane] = 0.0f;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // lane (li, lk) holds X[16 t + 4 lk + e][li] in element e of tile t.
+      // The LDS row is private to the wavefront; between its phases the
+      // wavefront waits for its own LDS operations only (lgkmcnt(0)), and
+      // consecutive targets alternate rows, so the next target's zeroing
+      // never meets this one's reads
+      float* lr = lred[wv][(c / NW) & 1];
+      if (lane < 2 * T) lr[lane] = 0.0f;
+      __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (dst[0][e] >= 0) {
-          atomicAdd(&lred[wv][dst[0][e]], x00[e]);
-          atomicAdd(&lred[wv][T + dst[0][e]], xk0[e]);
+          atomicAdd(&lr[dst[0][e]], x00[e]);
+          atomicAdd(&lr[T + dst[0][e]], xk0[e]);
         }
         if (dst[1][e] >= 0) {
-          atomicAdd(&lred[wv][dst[1][e]], x01[e]);
-          atomicAdd(&lred[wv][T + dst[1][e]], xk1[e]);
+          atomicAdd(&lr[dst[1][e]], x01[e]);
+          atomicAdd(&lr[T + dst[1][e]], xk1[e]);
         }
       }
       if (hi) {   // X[b][b] for b = 16..19: local term 0
-        atomicAdd(&lred[wv][0], dg0);
-        atomicAdd(&lred[wv][T], dgk);
+        atomicAdd(&lr[0], dg0);
+        atomicAdd(&lr[T], dgk);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (lane < 2 * T) {
         const int t = lane < T ? lane : lane - T;
-        (lane < T ? L0 : Lk)[(int64_t)(t0 + c) * T + t] = lred[wv][lane] * lsc[t];
+        (lane < T ? L0 : Lk)[(int64_t)(t0 + c) * T + t] = lr[lane] * lsc[t];
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
