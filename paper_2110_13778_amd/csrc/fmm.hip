@@ -49,14 +49,38 @@ template <int CTRL> __device__ __forceinline__ double dpp(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
-// sum over aligned groups of S lanes (S = 1, 2, 4, 8 or 16), every lane of a
-// group receiving the total
-template <typename R> __device__ __forceinline__ R group_sum(R v, int S) {
-  if (S >= 2) v += dpp<DPP_X1>(v);
-  if (S >= 4) v += dpp<DPP_X2>(v);
-  if (S >= 8) v += dpp<DPP_X7>(v);
-  if (S >= 16) v += dpp<DPP_X15>(v);
-  return v;
+// sums over aligned groups of S lanes (S = 1, 2, 4, 8 or 16) of the n values
+// of two arrays, every lane of a group receiving the totals; one branch per
+// exchange step
+template <int n, typename R> __device__ __forceinline__ void group_sum2(R* a, R* b, int S) {
+  if (S >= 2) {
+#pragma unroll
+    for (int t = 0; t < n; ++t) {
+      a[t] += dpp<DPP_X1>(a[t]);
+      b[t] += dpp<DPP_X1>(b[t]);
+    }
+  }
+  if (S >= 4) {
+#pragma unroll
+    for (int t = 0; t < n; ++t) {
+      a[t] += dpp<DPP_X2>(a[t]);
+      b[t] += dpp<DPP_X2>(b[t]);
+    }
+  }
+  if (S >= 8) {
+#pragma unroll
+    for (int t = 0; t < n; ++t) {
+      a[t] += dpp<DPP_X7>(a[t]);
+      b[t] += dpp<DPP_X7>(b[t]);
+    }
+  }
+  if (S >= 16) {
+#pragma unroll
+    for (int t = 0; t < n; ++t) {
+      a[t] += dpp<DPP_X15>(a[t]);
+      b[t] += dpp<DPP_X15>(b[t]);
+    }
+  }
 }
 
 __host__ __device__ constexpr int midx(int a, int b, int c) {
@@ -427,11 +451,7 @@ __global__ void __launch_bounds__(256) k_m2l_reg(const int32_t* __restrict__ int
     }
   }
   // combine the S partial sums (S <= 16 divides 64, groups are lane-aligned)
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    l0[t] = group_sum(l0[t], S);
-    lk[t] = group_sum(lk[t], S);
-  }
+  group_sum2<T>(l0, lk, S);
   if (c < ncl && part == 0)
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -696,11 +716,7 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
         }
       }
     }
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      l0[t] = group_sum(l0[t], S);
-      lk[t] = group_sum(lk[t], S);
-    }
+    group_sum2<T>(l0, lk, S);
     if (c < ncl && part == 0)
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -967,11 +983,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
     }
     // sums over the 8 lanes of a target by DPP moves
     static_assert(MT_S == 8, "lane groups of eight");
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      l0[t] = group_sum(l0[t], MT_S);
-      lk[t] = group_sum(lk[t], MT_S);
-    }
+    group_sum2<T>(l0, lk, MT_S);
     if (c < nt && part == 0)
 #pragma unroll
       for (int t = 0; t < T; ++t) {
