@@ -221,6 +221,9 @@ def test_error_paths():
     assert e.value.code == -2
     with pytest.raises(F.FagbiError):
         F.Handle(p_leaf=12)
+    with pytest.raises(F.FagbiError) as e:         # unknown cluster-radius mode
+        F.Handle(radii=2)
+    assert e.value.code == -1
     h.build_tree(v, t).assemble_nearfield()
     x = torch.zeros(2 * len(t), dtype=torch.float64, device=DEV)
     with pytest.raises(F.FagbiError):
