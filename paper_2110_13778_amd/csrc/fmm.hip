@@ -869,13 +869,20 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
   constexpr int T = TermTable<P>::T;
   constexpr int CPR = T / 4;              // float4 chunks per moment row and channel
   static_assert(T % 4 == 0, "rows in float4 chunks");
+  // LDS rows of both tables are TP = T + 2 float2 apart (a 176-byte stride
+  // at order 3 starts rows on twice as many banks as 160 bytes, fewer
+  // conflicts between the lanes' random rows); the last two are padding
+  constexpr int TP = T + 2;
   extern __shared__ __align__(16) char smem_raw[];
   float2* dsm = reinterpret_cast<float2*>(smem_raw);
-  float2* msm = dsm + (size_t)n_half * T;
+  float2* msm = dsm + (size_t)n_half * TP;
   __shared__ float msc[T], lsc[T];
   __shared__ float acc[MTK][2 * T];       // the tile's locals, both channels
   __shared__ int32_t qoff[MTK + 1];       // the tile's list offsets
-  for (int e = threadIdx.x; e < n_half * T; e += MT_NT) dsm[e] = Dh[e];
+  for (int e = threadIdx.x; e < n_half * T; e += MT_NT) {
+    const int rw = e / T;
+    dsm[rw * TP + (e - rw * T)] = Dh[e];
+  }
   if (threadIdx.x < T) {   // (-1)^|b| / b! of term b and 1 / a! of term a
     float f = 1.0f, g = 1.0f;
 #pragma unroll
@@ -921,7 +928,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
         if (i < ni) {
           const int sl = i / CPR, j = i - sl * CPR;
           const float s0 = msc[4 * j], s1 = msc[4 * j + 1], s2 = msc[4 * j + 2], s3 = msc[4 * j + 3];
-          float4* dst = reinterpret_cast<float4*>(msm + (size_t)sl * T + 4 * j);
+          float4* dst = reinterpret_cast<float4*>(msm + (size_t)sl * TP + 4 * j);
           dst[0] = make_float4(ra[k].x * s0, rb[k].x * s0, ra[k].y * s1, rb[k].y * s1);
           dst[1] = make_float4(ra[k].z * s2, rb[k].z * s2, ra[k].w * s3, rb[k].w * s3);
         }
@@ -947,8 +954,8 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
       for (; q < q1; q += MT_S) {
         const uint32_t pk = pkn;
         if (q + MT_S < q1) pkn = pack[q + MT_S];
-        const float4* dp = reinterpret_cast<const float4*>(dsm + (size_t)((pk >> 12) & 0x7ffffu) * T);
-        const float4* mp = reinterpret_cast<const float4*>(msm + (size_t)(pk & 0xfffu) * T);
+        const float4* dp = reinterpret_cast<const float4*>(dsm + (size_t)((pk >> 12) & 0x7ffffu) * TP);
+        const float4* mp = reinterpret_cast<const float4*>(msm + (size_t)(pk & 0xfffu) * TP);
         const float sg = (pk >> 31) ? -1.0f : 1.0f;
         float4 dr[T / 2], mr[T / 2];
 #pragma unroll
@@ -1534,7 +1541,7 @@ static int m2l_tile_setup(fagbi_handle* h, int l, hipStream_t s) {
   Level& D = h->lev[l];
   D.n_tile = 0;
   if (D.order != 3 || D.n_half == 0 || D.n_half >= (1 << 19) || D.n_inter == 0 || l < h->lmin) return 0;
-  const int64_t row = (int64_t)D.T * sizeof(float2);
+  const int64_t row = (int64_t)(D.T + 2) * sizeof(float2);   // the tile kernel's padded LDS row
   const int64_t stat_lds = (int64_t)MTK * 2 * D.T * 4 + (MTK + 1) * 4 + D.T * 4 + 256;
   const int64_t cap = std::min<int64_t>(std::min<int64_t>(MT_UMAX, (int64_t)MT_IPT * MT_NT / (D.T / 4)),
                                         (MT_LDS - stat_lds - (int64_t)D.n_half * row) / row);
@@ -2005,7 +2012,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     }
     if constexpr (sizeof(R) == 4)
     if (D.n_tile > 0 && D.order == 3 && h->m2l_tiles) {
-      const size_t lds = ((size_t)D.n_half + D.tile_umax) * D.T * sizeof(float2);
+      const size_t lds = ((size_t)D.n_half + D.tile_umax) * (D.T + 2) * sizeof(float2);
       FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile<3>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       k_m2l_tile<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
