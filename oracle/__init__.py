@@ -14,7 +14,9 @@ Everything follows the paper (Cartesian FMM Galerkin BIE for linearised PB):
   * the block-diagonal preconditioner: Sec. 2.6;
   * the solvation energy: Eq. for E_sol in Sec. 2.3 and the unit factor of
     Sec. 3;
-  * the Kirkwood reference: Sec. 3.1 (sphere with interior charges).
+  * the Kirkwood reference: Sec. 3.1 (sphere with interior charges);
+  * the continuous piecewise-linear space S^1_h of Sec. 2.3 (vertex hat
+    functions as test and trial functions; see ``p1``).
 
 Functions with no independent pin say "parity unpinned" in their docstring.
 """

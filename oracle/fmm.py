@@ -153,20 +153,29 @@ def matvec(F, x, far=True, near=True):
 def upward(F, phi, dphi):
     """Steps 2 and 3: leaf moments of the two channels and the MtM upward pass.
     Returns dicts level -> [n_l, T(p_l)] of M0 and Mk for l = l_min..L."""
-    tree, eps, pl = F.tree, F.eps, F.orders
+    tree, eps = F.tree, F.eps
     L, perm = tree.L, tree.perm
-    levels = tree.levels
     # step 2: leaf moments (two channels)
     a = phi[perm]
     b = dphi[perm]
     c0 = F.ms * b[:, None] - F.md * a[:, None]
     ck = -F.ms * b[:, None] + eps * F.md * a[:, None]
-    leaf = levels[L]
-    M0 = {L: np.zeros((leaf.n, F.ms.shape[1]))}
-    Mk = {L: np.zeros((leaf.n, F.ms.shape[1]))}
-    np.add.at(M0[L], F.owner, c0)
-    np.add.at(Mk[L], F.owner, ck)
-    # step 3: upward pass
+    leaf = tree.levels[L]
+    M0L = np.zeros((leaf.n, F.ms.shape[1]))
+    MkL = np.zeros((leaf.n, F.ms.shape[1]))
+    np.add.at(M0L, F.owner, c0)
+    np.add.at(MkL, F.owner, ck)
+    return upward_pass(F, M0L, MkL)
+
+
+def upward_pass(F, M0L, MkL):
+    """Step 3 from the leaf moments M0L, MkL [n_L, T(p_L)]: dicts level ->
+    moments for l = l_min..L."""
+    tree, pl = F.tree, F.orders
+    L = tree.L
+    levels = tree.levels
+    M0 = {L: M0L}
+    Mk = {L: MkL}
     for l in range(L - 1, tree.lmin - 1, -1):
         ch, pa = levels[l + 1], levels[l]
         T = len(_mi(pl[l])[0])
@@ -225,19 +234,22 @@ def interaction(F, M0, Mk, l, targets=None):
 
 
 def far_field(F, phi, dphi):
-    P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
-    L, perm = tree.L, tree.perm
-    levels = tree.levels
     M0, Mk = upward(F, phi, dphi)
-    # step 4: interaction phase
+    # steps 4 and 5, then step 6: evaluation
+    return evaluate(F, *leaf_locals(F, M0, Mk))
+
+
+def leaf_locals(F, M0, Mk):
+    """Steps 4 and 5: the interaction phase on every level and the downward
+    pass; returns the leaf locals (lam0, lamk) [n_L, T(p_L)]."""
+    tree = F.tree
+    L = tree.L
     lam0, lamk = {}, {}
     for l in range(tree.lmin, L + 1):
         lam0[l], lamk[l] = interaction(F, M0, Mk, l)
-    # step 5: downward pass
     downward(F, lam0, tree.lmin)
     downward(F, lamk, tree.lmin)
-    # step 6: evaluation
-    return evaluate(F, lam0[L], lamk[L])
+    return lam0[L], lamk[L]
 
 
 def evaluate(F, lam0_leaf, lamk_leaf):
