@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--cpu-solve", action="store_true",
                     help="only the oracle's whole solve on the 81,920-panel multi-charge sphere on the host "
                          "(about half an hour of one core; no GPU), printed as one JSON line")
-    ap.add_argument("--mlp-epochs", type=int, default=120,
+    ap.add_argument("--mlp-epochs", type=int, default=240,
                     help="training epochs of the near-field surrogate (before the timed steps)")
     ap.add_argument("--mlp-pairs", type=int, default=2000000,
                     help="training pairs drawn per training mesh (two meshes; the default takes every "
@@ -414,7 +414,7 @@ def main():
     runs_nm = []
     h_nm = None
     for k in range(3):
-        h, x, st = run(w, F.MIXED, False, mlp=False, keep=(k == 2))
+        h, x, st = run(w, F.MIXED, True, mlp=False, keep=(k == 2))
         runs_nm.append(st)
         if k == 2:
             h_nm = h
