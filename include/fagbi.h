@@ -20,7 +20,10 @@
  *     is per calling thread), > 0 = warning (e.g. FAGBI_W_NOT_CONVERGED);
  *   - mesh and charge arrays are HOST pointers, read during the call and not
  *     retained; solution/vector arrays are DEVICE pointers of the current HIP
- *     device, owned by the caller, of 2N doubles unless stated otherwise;
+ *     device, owned by the caller, of 2n doubles unless stated otherwise, with
+ *     n = N (panels, FAGBI_BASIS_S0: [phi_1..phi_N, dphi_1..dphi_N] in the
+ *     caller's panel order) or n = V (vertices, FAGBI_BASIS_S1: the nodal
+ *     values in the caller's vertex order);
  *   - `stream` is a hipStream_t (NULL = the default stream); asynchronous calls
  *     are ordered on it, calls documented as synchronising wait for it;
  *   - a handle owns all of its device memory, is bound to the device current
@@ -52,6 +55,15 @@ enum { FAGBI_PRECOND_NONE = 0, FAGBI_PRECOND_DIAG = 1, FAGBI_PRECOND_BLOCK = 2, 
 enum { FAGBI_MLP_OFF = 0, FAGBI_MLP_PRECOND = 1, FAGBI_MLP_GATED = 2 };
 /* cluster radii of the separation ratio (fagbi_params.radii) */
 enum { FAGBI_RADII_LEVEL = 0, FAGBI_RADII_CLUSTER = 1 };
+/* Galerkin space of phi and dphi (fagbi_params.basis), Sec. 2.3:
+   FAGBI_BASIS_S0 the piecewise-constant box functions (unknowns per panel),
+   FAGBI_BASIS_S1 the continuous piecewise-linear hat functions (unknowns per
+   vertex; on a panel the hat function of its corner a is the barycentric
+   coordinate lambda_a).  With S1 every entry of the system is the S0 entry's
+   integral with lambda_a(x) lambda_b(y) inside, summed over the panels at the
+   two vertices, the identity terms use the mass matrix int phi_i phi_j, and
+   the sources and the energy interpolate the nodal values. */
+enum { FAGBI_BASIS_S0 = 0, FAGBI_BASIS_S1 = 1 };
 /* parts of the operator for fagbi_matvec_parts */
 enum { FAGBI_PART_NEAR = 1, FAGBI_PART_FAR = 2, FAGBI_PART_ALL = 3 };
 
@@ -90,6 +102,11 @@ typedef struct fagbi_params {
   double rhs_theta;
   int32_t rhs_pmax;            /* its order cap: terms |a| <= min(p_l, rhs_pmax) */
   int32_t radii;               /* FAGBI_RADII_LEVEL (default) or FAGBI_RADII_CLUSTER */
+  /* FAGBI_BASIS_S0 (default) or FAGBI_BASIS_S1.  S1 needs every vertex to
+     belong to a triangle, mlp_mode FAGBI_MLP_OFF, precond FAGBI_PRECOND_NONE
+     or FAGBI_PRECOND_DIAG and rhs_theta 0; the treecode and allocation-free
+     entry points are not available with it (FAGBI_E_ARG). */
+  int32_t basis;
 } fagbi_params;
 
 #define FAGBI_MAX_LEVELS 21        /* levels 0..20 (cube keys have 20 levels) */
@@ -166,13 +183,18 @@ int fagbi_build_tree(fagbi_handle* h, const double* verts, int64_t nv,
    (Sec. 2.3 linear system entries; singular pairs by Sauter-Schwab-type
    relative-coordinate cubature, Sec. 2.3 last paragraph), their FP32 copy,
    the FMM translation tables and the block-diagonal preconditioner factors
-   (Sec. 2.6).  Requires fagbi_build_tree.  Synchronises. */
+   (Sec. 2.6).  With FAGBI_BASIS_S1 each stored panel pair holds the 3 x 3
+   corner integrals (singular and close pairs by the same relative-coordinate
+   and Duffy rules with the barycentric products inside, the identical and
+   edge rules' analytic inner variable replaced by exact 3- and 2-point
+   rules), and the preconditioner is the diagonal of A.  Requires
+   fagbi_build_tree.  Synchronises. */
 int fagbi_assemble_nearfield(fagbi_handle* h, void* stream);
 
 /* y = A x (Sec. 2.4 six-step FMM: near field, moments, upward pass,
    interaction phase, downward pass, evaluation).  precision FAGBI_FP64: FP64
    throughout; FAGBI_MIXED: FP32 near-field entries and FP32 expansions with
-   FP64 accumulation of y.  x, y: device f64[2N], caller order, must not
+   FP64 accumulation of y.  x, y: device f64[2n], caller order, must not
    alias.  Asynchronous on stream. */
 int fagbi_matvec(fagbi_handle* h, const double* x, double* y, int32_t precision,
                  void* stream);
@@ -189,12 +211,12 @@ int fagbi_matvec_parts(fagbi_handle* h, const double* x, double* y,
    elimination with partial pivoting in FP64 (FAGBI_E_NUMERIC for a singular
    block); the apply is one dense block product per block.  With
    precond = FAGBI_PRECOND_DIAG the diagonal of A is used instead.  z, y:
-   device f64[2N] (may alias).  Asynchronous on stream. */
+   device f64[2n] (may alias).  Asynchronous on stream. */
 int fagbi_precond_apply(fagbi_handle* h, const double* z, double* y, void* stream);
 
 /* Right-hand side b (Sec. 2.2 source terms S1, S2 tested with the box
    functions): xq host f64[nc*3] charge positions [A], q host f64[nc] charges
-   [e]; b device f64[2N].  Asynchronous on stream (arguments copied before
+   [e]; b device f64[2n].  Asynchronous on stream (arguments copied before
    return). */
 int fagbi_rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
               double* b, void* stream);
@@ -206,7 +228,7 @@ int fagbi_rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
    FAGBI_MIXED, by flexible GMRES on the FP64 operator whose preconditioner is
    an inner GMRES on the FP32 operator to inner_tol.  The tolerance applies to
    the true relative residual ||b - A64 x|| / ||b||.  b comes from the charges
-   by fagbi_rhs (rhs_theta = 0) or fagbi_rhs_treecode.  x: device f64[2N], the
+   by fagbi_rhs (rhs_theta = 0) or fagbi_rhs_treecode.  x: device f64[2n], the
    initial guess on entry (zeros: pass zeros), the solution on exit.  info may
    be NULL.  Returns FAGBI_W_NOT_CONVERGED with the best x if the tolerance is
    not met.  Synchronises. */
@@ -214,7 +236,7 @@ int fagbi_solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc,
                 double* x, fagbi_solve_info* info, void* stream);
 
 /* Solvation energy (Sec. 2.3 discrete E_sol times 4 pi 332.0716, Sec. 3) in
-   kcal/mol from a solution x (device f64[2N]).  FP64 direct sum over charges
+   kcal/mol from a solution x (device f64[2n]).  FP64 direct sum over charges
    and panel quadrature points.  Synchronises. */
 int fagbi_solvation_energy(fagbi_handle* h, const double* x, const double* xq,
                            const double* q, int64_t nc, double* E_kcal,

@@ -18,6 +18,7 @@ FP64, MIXED = 0, 1
 PRECOND_NONE, PRECOND_DIAG, PRECOND_BLOCK, PRECOND_GROUP = 0, 1, 2, 3
 MLP_OFF, MLP_PRECOND, MLP_GATED = 0, 1, 2
 RADII_LEVEL, RADII_CLUSTER = 0, 1
+BASIS_S0, BASIS_S1 = 0, 1          # box functions (per panel) / hat functions (per vertex)
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 
 EXPORTS = ["fagbi_default_params", "fagbi_create", "fagbi_build_tree",
@@ -40,7 +41,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_outer", C.c_int32), ("inner_tol", C.c_double),
                 ("mlp_mode", C.c_int32), ("mlp_gate_tol", C.c_double), ("rhs_theta", C.c_double),
-                ("rhs_pmax", C.c_int32), ("radii", C.c_int32)]
+                ("rhs_pmax", C.c_int32), ("radii", C.c_int32), ("basis", C.c_int32)]
 
 
 class TreeInfo(C.Structure):

@@ -379,6 +379,14 @@ static int check_params(const fagbi_params* p) {
   if (p->rhs_pmax < 0) return set_error(FAGBI_E_ARG, "rhs_pmax must be >= 0");
   if (p->radii != FAGBI_RADII_LEVEL && p->radii != FAGBI_RADII_CLUSTER)
     return set_error(FAGBI_E_ARG, "radii must be FAGBI_RADII_LEVEL or FAGBI_RADII_CLUSTER");
+  if (p->basis != FAGBI_BASIS_S0 && p->basis != FAGBI_BASIS_S1)
+    return set_error(FAGBI_E_ARG, "basis must be FAGBI_BASIS_S0 or FAGBI_BASIS_S1");
+  if (p->basis == FAGBI_BASIS_S1) {
+    if (p->mlp_mode != FAGBI_MLP_OFF) return set_error(FAGBI_E_ARG, "the hat-function basis needs mlp_mode OFF");
+    if (p->precond != FAGBI_PRECOND_NONE && p->precond != FAGBI_PRECOND_DIAG)
+      return set_error(FAGBI_E_ARG, "the hat-function basis takes precond NONE or DIAG");
+    if (p->rhs_theta != 0.0) return set_error(FAGBI_E_ARG, "the hat-function basis takes rhs_theta 0");
+  }
   return 0;
 }
 
@@ -504,6 +512,7 @@ int fagbi_solvation_energy_noalloc(fagbi_handle* h, const double* x, const doubl
                                    double* E_kcal, void* stream) {
   if (!h || !x || !chg || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (reinterpret_cast<uintptr_t>(chg) % 32) return set_error(FAGBI_E_ARG, "chg must be 32-byte aligned");
+  if (h->hat()) return set_error(FAGBI_E_ARG, "not available with the hat-function basis");
   if (!h->tree_ready) return set_error(FAGBI_E_STATE, "energy before build_tree");
   return fagbi::energy_noalloc(h, x, chg, nc, E_kcal, (hipStream_t)stream);
 }
@@ -513,6 +522,7 @@ int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64
   if (!h || !xq || !q || !b || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
   if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
+  if (h->hat()) return set_error(FAGBI_E_ARG, "not available with the hat-function basis");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode right-hand side before assemble_nearfield");
   return fagbi::rhs_treecode(h, xq, q, nc, theta, p_max, b, (hipStream_t)stream);
 }
@@ -522,6 +532,7 @@ int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x, const doub
   if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
   if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
+  if (h->hat()) return set_error(FAGBI_E_ARG, "not available with the hat-function basis");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode energy before assemble_nearfield");
   return fagbi::energy_treecode(h, x, xq, q, nc, theta, p_max, E_kcal, (hipStream_t)stream);
 }

@@ -165,16 +165,22 @@ static MI mi_of(int t) {
 // ---------------------------------------------------------------------------
 constexpr int TB = 256;   // threads per translation block
 
-// single/double layer moments of each panel about its leaf centre
+// single/double layer moments of each panel about its leaf centre; with
+// corners != 0 one set per panel corner (row e = 3 i + a), the rule's weights
+// times the hat function lambda_a at its points (2/3 at point a, 1/6 at the
+// others)
 template <typename R>
 __global__ void k_panel_moments(const double* __restrict__ pv, const double* __restrict__ pn,
                                 const double* __restrict__ pa, const int32_t* __restrict__ leaf_of,
                                 const int32_t* __restrict__ lidx, double cx, double cy, double cz,
-                                double hL, int N, int T, const int8_t* __restrict__ mi, R* ms, R* md) {
-  // layout [N][T]: moment t of panel i at i * T + t
+                                double hL, int N, int T, const int8_t* __restrict__ mi, R* ms, R* md,
+                                int corners) {
+  // layout [rows][T]: moment t of a row (panel i, or corner a of panel i) at row * T + t
+  const int rows = corners ? 3 * N : N;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)N * T) return;
-  const int i = (int)(g / T), t = (int)(g - (int64_t)i * T);
+  if (g >= (int64_t)rows * T) return;
+  const int row = (int)(g / T), t = (int)(g - (int64_t)row * T);
+  const int i = corners ? row / 3 : row, a = corners ? row - 3 * (row / 3) : -1;
   const int c = leaf_of[i];
   const double ctr[3] = {cx + ((double)lidx[3 * c] + 0.5) * hL, cy + ((double)lidx[3 * c + 1] + 0.5) * hL,
                          cz + ((double)lidx[3 * c + 2] + 0.5) * hL};
@@ -198,12 +204,13 @@ __global__ void k_panel_moments(const double* __restrict__ pv, const double* __r
         pe[ax] *= d[ax];
       }
     }
-    s += w * pe[0] * pe[1] * pe[2];
+    const double wk = a < 0 ? w : (k == a ? (2.0 / 3.0) : (1.0 / 6.0)) * w;
+    s += wk * pe[0] * pe[1] * pe[2];
     double g2 = 0;
     if (e[0]) g2 += e[0] * pn[3 * i] * pm[0] * pe[1] * pe[2];
     if (e[1]) g2 += e[1] * pn[3 * i + 1] * pe[0] * pm[1] * pe[2];
     if (e[2]) g2 += e[2] * pn[3 * i + 2] * pe[0] * pe[1] * pm[2];
-    dsum += w * g2;
+    dsum += wk * g2;
   }
   ms[g] = (R)s;
   md[g] = (R)dsum;
@@ -1401,12 +1408,29 @@ __global__ void __launch_bounds__(256) k_spmv(const E* __restrict__ ent, const i
   }
 }
 
-// xt = x in tree order, (phi, dphi) interleaved per panel
-__global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restrict__ perm, int64_t N, double* xt) {
+// xt = x in tree order, (phi, dphi) interleaved per row: row i takes entry
+// idx[i] of both channels of x (channel stride n_x)
+__global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restrict__ idx, int64_t n,
+                          int64_t n_x, double* xt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int64_t p = perm[i];
-  reinterpret_cast<double2*>(xt)[i] = make_double2(x[p], x[N + p]);
+  if (i >= n) return;
+  const int64_t p = idx[i];
+  reinterpret_cast<double2*>(xt)[i] = make_double2(x[p], x[n_x + p]);
+}
+
+ElemView box_view(fagbi_handle* h) {
+  ElemView v;
+  v.n = h->N;
+  v.leaf_start = h->d_leaf_start.as<int32_t>();
+  v.leaf_cnt = h->d_leaf_cnt.as<int32_t>();
+  v.leaf_of = h->d_leaf_of.as<int32_t>();
+  v.src_tree = h->d_src_tree.as<int32_t>();
+  v.src_off = h->d_src_off.as<int64_t>();
+  v.ent_off = h->d_ent_off.as<int64_t>();
+  v.in_idx = v.out_idx = h->d_perm.as<int32_t>();
+  v.in_stride = h->N;
+  v.xt = h->d_xt.as<double>();
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1784,10 +1808,11 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
       st.reserve(D.d_L32[ch], (size_t)D.n * D.T * 4);
     }
   }
-  // panel moments about the leaf centres
+  // panel (or panel-corner) moments about the leaf centres
   const Level& LF = h->lev[h->L];
   const int T = LF.T;
-  const int64_t NT = h->N * T;
+  const int corners = h->hat() ? 1 : 0;
+  const int64_t NT = (corners ? 3 : 1) * h->N * T;
   st.reserve(h->d_ms64, NT * 8);
   st.reserve(h->d_md64, NT * 8);
   st.reserve(h->d_ms32, NT * 4);
@@ -1825,12 +1850,12 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
                                                 h->d_leaf_of.as<int32_t>(), LF.d_idx.as<int32_t>(), h->corner[0],
                                                 h->corner[1], h->corner[2], LF.h, (int)h->N, T,
                                                 h->d_mi.as<int8_t>(), h->d_ms64.as<double>(),
-                                                h->d_md64.as<double>());
+                                                h->d_md64.as<double>(), corners);
   k_panel_moments<float><<<grid, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                                                h->d_leaf_of.as<int32_t>(), LF.d_idx.as<int32_t>(), h->corner[0],
                                                h->corner[1], h->corner[2], LF.h, (int)h->N, T,
                                                h->d_mi.as<int8_t>(), h->d_ms32.as<float>(),
-                                               h->d_md32.as<float>());
+                                               h->d_md32.as<float>(), corners);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }
@@ -1850,16 +1875,15 @@ static R* moments_of(Level& D, int ch, bool f32) {
   return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>();
 }
 
-// step 2: leaf moments of the two channels from x in tree order
+// step 2: leaf moments of the two channels from the rows' values xt (tree order)
 template <typename R>
-static int launch_p2m(fagbi_handle* h, const R* ms, const R* md, const double* xt, bool f32, hipStream_t s) {
+static int launch_p2m(fagbi_handle* h, const ElemView& v, const R* ms, const R* md, bool f32, hipStream_t s) {
   Level& LF = h->lev[h->L];
   const int nl = LF.n;
   const double eps = h->prm.eps_out / h->prm.eps_in;
   const int64_t tot = (int64_t)nl * LF.T;
-  k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms, md, h->d_leaf_start.as<int32_t>(),
-                                                        h->d_leaf_cnt.as<int32_t>(), h->N, nl, LF.T, eps, xt,
-                                                        moments_of<R>(LF, 0, f32), moments_of<R>(LF, 1, f32));
+  k_p2m<R><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ms, md, v.leaf_start, v.leaf_cnt, v.n, nl, LF.T, eps,
+                                                        v.xt, moments_of<R>(LF, 0, f32), moments_of<R>(LF, 1, f32));
   return 0;
 }
 
@@ -1921,9 +1945,11 @@ static int launch_l2l(fagbi_handle* h, int l, bool f32, hipStream_t s) {
 }
 
 template <typename R, typename E>
-static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipStream_t s,
+static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double* y_out, int parts, hipStream_t s,
                     const DBuf& ent, const DBuf& ms, const DBuf& md, bool f32) {
-  const int64_t N = h->N;
+  // rows: panels, or panel corners summed into the vertices at the end
+  const int64_t N = v.n;
+  double* y = v.y ? v.y : y_out;
   const int nl = h->lev[h->L].n;
   const bool prof = h->profiling;
   auto mark_on = [&](int k, hipStream_t st) -> int {
@@ -1932,8 +1958,10 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   };
   auto mark = [&](int k) { return mark_on(k, s); };
   FAGBI_TRY(mark(5));
-  double* xt = h->d_xt.as<double>();
-  k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), N, xt);
+  double* xt = v.xt;
+  k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, v.in_idx, N, v.in_stride, xt);
+  // the rows' results summed into the caller's outputs (hat functions)
+  auto gather = [&]() -> int { return v.gat_off ? hat_gather(h, y, y_out, s) : 0; };
   const bool near = parts & FAGBI_PART_NEAR;
   const bool far = (parts & FAGBI_PART_FAR) && h->lmin <= h->L;
   // the near-field SpMV (HBM bound) runs on a second stream beside the far
@@ -1952,8 +1980,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   FAGBI_TRY(mark_on(0, sn));
   if (near) {
     k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, sn>>>(
-        ent.as<E>(), h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(), h->d_src_off.as<int64_t>(),
-        h->d_ent_off.as<int64_t>(), h->d_src_tree.as<int32_t>(), h->d_perm.as<int32_t>(), N, nl, xt, y);
+        ent.as<E>(), v.leaf_start, v.leaf_cnt, v.src_off, v.ent_off, v.src_tree, v.out_idx, N, nl, xt, y);
   } else {
     FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   }
@@ -1966,6 +1993,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_TRY(mark(3));
     FAGBI_TRY(mark(7));
     FAGBI_TRY(mark(8));
+    FAGBI_TRY(gather());
     FAGBI_TRY(mark(4));
     return 0;
   }
@@ -2092,7 +2120,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     FAGBI_HIP(hipEventCreateWithFlags(&h->ev_m2l, hipEventDisableTiming));
   }
   Level& LF = h->lev[L];
-  FAGBI_TRY(launch_p2m<R>(h, ms.as<R>(), md.as<R>(), xt, f32, s));
+  FAGBI_TRY(launch_p2m<R>(h, v, ms.as<R>(), md.as<R>(), f32, s));
   // the leaf level's MtL, bracketed by events 7, 8 on its stream
   auto launch_m2l_leaf = [&](hipStream_t st) -> int {
     FAGBI_TRY(mark_on(7, st));
@@ -2147,7 +2175,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
   {
     const unsigned g = (unsigned)((N + 255) / 256);
     const R *a = ms.as<R>(), *b = md.as<R>();
-    const int32_t *lo = h->d_leaf_of.as<int32_t>(), *pm = h->d_perm.as<int32_t>();
+    const int32_t *lo = v.leaf_of, *pm = v.out_idx;
     switch (LF.order) {
       case 2: k_l2p_reg<R, 2><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), y); break;
       case 3: k_l2p_reg<R, 3><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), y); break;
@@ -2158,6 +2186,7 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
     }
   }
   FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY(gather());
   FAGBI_TRY(mark(4));
   return 0;
 }
@@ -2165,9 +2194,10 @@ static int matvec_t(fagbi_handle* h, const double* x, double* y, int parts, hipS
 int matvec(fagbi_handle* h, const double* x, double* y, int precision, int parts, hipStream_t s) {
   if (h->profiling && !h->ev[0])
     for (int k = 0; k < 9; ++k) FAGBI_HIP(hipEventCreate(&h->ev[k]));
+  const ElemView v = h->hat() ? hat_view(h) : box_view(h);
   int r = precision == FAGBI_MIXED
-              ? matvec_t<float, float4>(h, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
-              : matvec_t<double, double4>(h, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
+              ? matvec_t<float, float4>(h, v, x, y, parts, s, h->d_E32, h->d_ms32, h->d_md32, true)
+              : matvec_t<double, double4>(h, v, x, y, parts, s, h->d_E64, h->d_ms64, h->d_md64, false);
   if (r < 0 || !h->profiling) return r;
   FAGBI_HIP(hipEventSynchronize(h->ev[4]));
   float t[4], tot;
@@ -2642,9 +2672,9 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
                         double* qv, hipStream_t s) {
   const int L = h->L, l0 = std::min(h->lmin, h->L);
   // moments of x: leaf moments and the upward pass, FP64
-  double* xt = h->d_xt.as<double>();
-  k_to_tree<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(x, h->d_perm.as<int32_t>(), h->N, xt);
-  FAGBI_TRY(launch_p2m<double>(h, h->d_ms64.as<double>(), h->d_md64.as<double>(), xt, false, s));
+  const ElemView v = box_view(h);
+  k_to_tree<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(x, v.in_idx, h->N, h->N, v.xt);
+  FAGBI_TRY(launch_p2m<double>(h, v, h->d_ms64.as<double>(), h->d_md64.as<double>(), false, s));
   for (int l = L - 1; l >= l0; --l) FAGBI_TRY(launch_m2m<double>(h, l, false, s));
   TcLevels lv;
   FAGBI_TRY(tc_levels(h, l0, p_max, lv));

@@ -155,6 +155,13 @@ struct fagbi_handle {
   int64_t mlp_gated_pairs = 0;
   fagbi::DBuf d_mlp_theta, d_mlp_m, d_mlp_v, d_mlp_norm;
   fagbi::DBuf d_mlp_skip[4];
+  // hat-function basis (FAGBI_BASIS_S1): elements are the panel corners,
+  // e = 3 i + a for tree-order panel i; the near field's element layout
+  // (leaf ranges, source lists, entry offsets of the 3 x 3 blocks), the
+  // identity map of the element outputs, the leaf of each element, the
+  // elements of each vertex (CSR, ascending), the element results [2][3N]
+  fagbi::DBuf d_s1_leaf_start, d_s1_leaf_cnt, d_s1_src_off, d_s1_ent_off, d_s1_src_tree, d_s1_iota,
+      d_s1_leaf_of, d_vx_off, d_vx_el, d_ye;
   std::vector<float> mlp_blob;        // parameters | normalisation | calibration
   // FP32 leaf-level MtL by the source-reuse tile kernel (when its tables fit);
   // FAGBI_M2L_TILES=0 in the environment selects the per-pair LDS-table kernel
@@ -180,6 +187,9 @@ struct fagbi_handle {
   int alloc(fagbi::DBuf& b, size_t bytes);
   int upload(fagbi::DBuf& b, const void* host, size_t bytes);
   void free_all();
+  bool hat() const { return prm.basis == FAGBI_BASIS_S1; }
+  // unknowns per channel: panels (box functions) or vertices (hat functions)
+  int64_t n_unk() const { return hat() ? nv : N; }
 };
 
 namespace fagbi {
@@ -204,6 +214,25 @@ struct StageTimer {
   }
   ~StageTimer() { stop(); }
 };
+
+// The rows the near and far field run over, in tree order: the panels (box
+// functions) or the panel corners (hat functions).  The matvec gathers
+// xt[e] = (x[in_idx[e]], x[in_stride + in_idx[e]]), runs the SpMV, P2M and
+// LtP over the rows (row results at y[out_idx[e]] and y[n + out_idx[e]]) and,
+// with a gather list, sums the rows of each output into the caller's y.
+struct ElemView {
+  int64_t n = 0;
+  const int32_t *leaf_start = nullptr, *leaf_cnt = nullptr, *leaf_of = nullptr, *src_tree = nullptr;
+  const int64_t *src_off = nullptr, *ent_off = nullptr;
+  const int32_t *in_idx = nullptr, *out_idx = nullptr;
+  int64_t in_stride = 0;
+  double* xt = nullptr;        // [n] (phi, dphi) pairs
+  double* y = nullptr;         // row results [2n]; nullptr: the caller's y
+  const int32_t *gat_off = nullptr, *gat_el = nullptr;   // outputs' rows (CSR)
+  int64_t n_out = 0;
+};
+ElemView box_view(fagbi_handle* h);
+ElemView hat_view(fagbi_handle* h);
 
 // stages implemented in the .hip files
 int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* tris, int64_t nt);
@@ -232,6 +261,11 @@ int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, i
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x,
           fagbi_solve_info* info, hipStream_t s);
 void gauss_legendre01(int n, double* x, double* w);
+// hat-function basis: near field (entries, element layout, vertex lists),
+// diagonal preconditioner, and the element-to-vertex sum
+int hat_assemble(fagbi_handle* h, hipStream_t s);
+int hat_diag_setup(fagbi_handle* h, hipStream_t s);
+int hat_gather(fagbi_handle* h, const double* rows, double* y, hipStream_t s);
 
 // The quadrature table of the singular and close rules (device d_gl):
 // [0, 16) Gauss-Legendre nodes on [0, 1], [16, 32) weights, then one radial

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_near_classify(NearArgs a, int64_t* blk,
       // touching and close pairs are integrated once per unordered pair (for
       // the member whose target has the lower caller index) and mirrored
       if (cls >= C_EDGE && a.perm[i] > a.perm[j]) cls = -1;
-      if (PASS == 1 && cls == C_REGULAR) {
+      if (PASS == 1 && cls == C_REGULAR && ent) {
         double I[6];
         regular_pair(a, i, j, I);
         ent[eo + e] = combine(I, a.eps);
@@ -478,8 +478,10 @@ int run_singular(fagbi_handle* h, int cls_index, const uint8_t* skip, double* ra
 int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   const int nl = h->lev[h->L].n;
   NearArgs a = near_args(h);
-  FAGBI_TRY(h->alloc(h->d_E64, (size_t)h->n_ent * sizeof(double4)));
-  FAGBI_TRY(h->alloc(h->d_E32, (size_t)h->n_ent * sizeof(float4)));
+  // hat functions: a 3 x 3 block of element entries per stored panel pair
+  const int64_t n_e = (h->hat() ? 9 : 1) * h->n_ent;
+  FAGBI_TRY(h->alloc(h->d_E64, (size_t)n_e * sizeof(double4)));
+  FAGBI_TRY(h->alloc(h->d_E32, (size_t)n_e * sizeof(float4)));
   StageTimer t_cls(h, s, &h->prof.ms_classify);
   // per-leaf class counts, one scan over the flattened [class][leaf] array,
   // then the worklists at the scanned offsets
@@ -502,9 +504,23 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
     FAGBI_TRY(h->alloc(h->d_wl[k], (size_t)std::max<int64_t>(c, 1) * sizeof(Item)));
   }
   k_near_classify<1><<<nl, 256, 0, s>>>(a, off.as<int64_t>(), nl, h->d_wl[0].as<Item>(), h->d_wl[1].as<Item>(),
-                                        h->d_wl[2].as<Item>(), h->d_wl[3].as<Item>(), h->d_E64.as<double4>());
+                                        h->d_wl[2].as<Item>(), h->d_wl[3].as<Item>(),
+                                        h->hat() ? nullptr : h->d_E64.as<double4>());
   FAGBI_HIP(hipGetLastError());
   t_cls.stop();
+  if (h->hat()) {
+    h->prof.ms_surrogate = 0;
+    h->mlp_gated_pairs = 0;
+    {
+      StageTimer t_sing(h, s, &h->prof.ms_singular);
+      FAGBI_TRY(hat_assemble(h, s));
+    }
+    k_to_f32<<<2048, 256, 0, s>>>(h->d_E64.as<double4>(), h->d_E32.as<float4>(), n_e);
+    FAGBI_HIP(hipGetLastError());
+    FAGBI_HIP(hipStreamSynchronize(s));
+    h->precond_ready = false;
+    return 0;
+  }
   h->prof.ms_surrogate = 0;
   StageTimer t_sing(h, s, &h->prof.ms_singular);
   // identical pairs: always the FP64 singular cubature
@@ -722,6 +738,7 @@ __global__ void k_to_f32_1(const double* __restrict__ a, float* b, int64_t n) {
 }
 
 int precond_setup(fagbi_handle* h, hipStream_t s) {
+  if (h->hat()) return h->prm.precond == FAGBI_PRECOND_DIAG ? hat_diag_setup(h, s) : 0;
   const int nl = h->lev[h->L].n;
   FAGBI_TRY(h->alloc(h->d_diag, 2 * h->N * sizeof(double)));
   k_diag_extract<<<nl, 64, 0, s>>>(h->d_E64.as<double4>(), h->d_leaf_start.as<int32_t>(),
@@ -775,12 +792,13 @@ int precond_setup(fagbi_handle* h, hipStream_t s) {
 }
 
 int precond_apply(fagbi_handle* h, const double* z, double* y, hipStream_t s, bool f32) {
+  const int64_t n = 2 * h->n_unk();
   if (h->prm.precond == FAGBI_PRECOND_NONE) {
-    if (z != y) FAGBI_HIP(hipMemcpyAsync(y, z, 2 * h->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (z != y) FAGBI_HIP(hipMemcpyAsync(y, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     return 0;
   }
   if (h->prm.precond == FAGBI_PRECOND_DIAG) {
-    k_diag_apply<<<1024, 256, 0, s>>>(h->d_diag.as<double>(), z, y, 2 * h->N);
+    k_diag_apply<<<1024, 256, 0, s>>>(h->d_diag.as<double>(), z, y, n);
     FAGBI_HIP(hipGetLastError());
     return 0;
   }

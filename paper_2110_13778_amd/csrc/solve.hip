@@ -21,7 +21,10 @@ constexpr int RB = 256;   // reduction block
 // (quad_points) with the charges staged through LDS; charges carry q / (4 pi).
 // FP64 throughout.
 
-// b1 = (1/eps_in) sum_q w_q sum_k q_k G0(x_q, y_k); b2 likewise with dG0/dn_x
+// b1 = (1/eps_in) sum_q w_q sum_k q_k G0(x_q, y_k); b2 likewise with dG0/dn_x.
+// HAT: per panel corner a, the same sums with lambda_a(x_q) inside, written to
+// the element rows b[e], b[3N + e] (e = 3 i + a) for the sum into the vertices
+template <bool HAT = false>
 __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, const double* __restrict__ pn,
                                              const double* __restrict__ pa, const int32_t* __restrict__ perm,
                                              int N, const double4* __restrict__ chg, int nc, double inv_eps_in,
@@ -36,6 +39,7 @@ __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, cons
     w = pa[i] / 3.0;
   }
   double s1 = 0, s2 = 0;
+  double h1[3] = {0, 0, 0}, h2[3] = {0, 0, 0};   // per point (HAT)
   for (int t0 = 0; t0 < nc; t0 += 256) {
     __syncthreads();
     if (t0 + (int)threadIdx.x < nc) {
@@ -53,12 +57,31 @@ __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, cons
           const double rx = qp[3 * q] - c.x, ry = qp[3 * q + 1] - c.y, rz = qp[3 * q + 2] - c.z;
           const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
           const double g = c.w * ir;
-          s1 += g;
-          s2 -= g * (rx * n[0] + ry * n[1] + rz * n[2]) * (ir * ir);
+          if constexpr (HAT) {
+            h1[q] += g;
+            h2[q] -= g * (rx * n[0] + ry * n[1] + rz * n[2]) * (ir * ir);
+          } else {
+            s1 += g;
+            s2 -= g * (rx * n[0] + ry * n[1] + rz * n[2]) * (ir * ir);
+          }
         }
       }
   }
-  if (valid) {
+  if (!valid) return;
+  if constexpr (HAT) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double c1 = 0, c2 = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double l = q == a ? 2.0 / 3.0 : 1.0 / 6.0;
+        c1 += l * h1[q];
+        c2 += l * h2[q];
+      }
+      b[3 * i + a] = w * c1 * inv_eps_in;
+      b[3 * (int64_t)N + 3 * i + a] = w * c2 * inv_eps_in;
+    }
+  } else {
     const int p = perm[i];
     b[p] = w * s1 * inv_eps_in;
     b[N + p] = w * s2 * inv_eps_in;
@@ -67,25 +90,39 @@ __global__ void __launch_bounds__(256) k_rhs(const double* __restrict__ pv, cons
 
 // per-block partial sums of sum_i w_i sum_q sum_n q_n [K1 dphi_i + K2 phi_i]
 // with K1 = (G0 - Gk)(x_n, y), K2 = d/dn_y (eps Gk - G0)(x_n, y), y on the
-// panel
+// panel.  HAT: phi and dphi at point q interpolated from the nodal values,
+// sum_a lambda_a(x_q) x[v_a] (perm then holds the panels' vertices [N][3] and
+// N_x the vertex count)
+template <bool HAT = false>
 __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ pv, const double* __restrict__ pn,
                                                 const double* __restrict__ pa, const int32_t* __restrict__ perm,
                                                 int N, const double4* __restrict__ chg, int nc, double eps,
-                                                double kappa, const double* __restrict__ x, double* partial) {
+                                                double kappa, const double* __restrict__ x, double* partial,
+                                                int64_t N_x = 0) {
   __shared__ double4 tile[256];
   __shared__ double red[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < N;
   double qp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, n[3] = {0, 0, 0}, w = 0, phi = 0, dphi = 0;
+  double hu[3] = {0, 0, 0}, hv[3] = {0, 0, 0};   // HAT: nodal values at the corners
   if (valid) {
     quad_points(pv, i, qp);
     for (int d = 0; d < 3; ++d) n[d] = pn[3 * i + d];
     w = pa[i] / 3.0;
-    const int p = perm[i];
-    phi = x[p];
-    dphi = x[N + p];
+    if constexpr (HAT) {
+      for (int a = 0; a < 3; ++a) {
+        const int64_t v = perm[3 * i + a];
+        hu[a] = x[v];
+        hv[a] = x[N_x + v];
+      }
+    } else {
+      const int p = perm[i];
+      phi = x[p];
+      dphi = x[N + p];
+    }
   }
   double a1 = 0, a2 = 0;   // sum q K1, sum q K2
+  double b1[3] = {0, 0, 0}, b2[3] = {0, 0, 0};   // per point (HAT)
   for (int t0 = 0; t0 < nc; t0 += 256) {
     __syncthreads();
     if (t0 + (int)threadIdx.x < nc) {
@@ -108,12 +145,33 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ pv, c
           exp_expm1(-u, E, em1);
           const double rny = rx * n[0] + ry * n[1] + rz * n[2];
           const double g = c.w * ir;
-          a1 -= g * em1;
-          a2 += g * (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir);
+          if constexpr (HAT) {
+            b1[q] -= g * em1;
+            b2[q] += g * (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir);
+          } else {
+            a1 -= g * em1;
+            a2 += g * (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir);
+          }
         }
       }
   }
-  red[threadIdx.x] = valid ? w * (a1 * dphi + a2 * phi) : 0.0;
+  double tot = w * (a1 * dphi + a2 * phi);
+  if constexpr (HAT) {
+    tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double u = 0, v = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double l = q == a ? 2.0 / 3.0 : 1.0 / 6.0;
+        u += l * hu[a];
+        v += l * hv[a];
+      }
+      tot += b1[q] * v + b2[q] * u;
+    }
+    tot *= w;
+  }
+  red[threadIdx.x] = valid ? tot : 0.0;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
@@ -204,11 +262,24 @@ static int upload_charges(Tmp& buf, const double* xq, const double* q, int64_t n
 
 int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* b, hipStream_t s) {
   if (nc > (1 << 30)) return set_error(FAGBI_E_ARG, "too many charges");
+  if (h->hat() && !h->d_vx_off.p)
+    return set_error(FAGBI_E_STATE, "hat-function right-hand side before assemble_nearfield");
   Tmp chg;
   FAGBI_TRY(upload_charges(chg, xq, q, nc));
-  k_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(),
-                                                        h->d_pa.as<double>(), h->d_perm.as<int32_t>(), (int)h->N,
-                                                        chg.as<double4>(), (int)nc, 1.0 / h->prm.eps_in, b);
+  if (h->hat()) {
+    // corner sums into the element rows, then into the vertices
+    double* rows = h->d_ye.as<double>();
+    k_rhs<true><<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(),
+                                                               h->d_pa.as<double>(), nullptr, (int)h->N,
+                                                               chg.as<double4>(), (int)nc, 1.0 / h->prm.eps_in,
+                                                               rows);
+    FAGBI_HIP(hipGetLastError());
+    FAGBI_TRY(hat_gather(h, rows, b, s));
+  } else {
+    k_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(),
+                                                          h->d_pa.as<double>(), h->d_perm.as<int32_t>(), (int)h->N,
+                                                          chg.as<double4>(), (int)nc, 1.0 / h->prm.eps_in, b);
+  }
   FAGBI_HIP(hipGetLastError());
   FAGBI_HIP(hipStreamSynchronize(s));   // the charge buffer is freed on return
   return 0;
@@ -221,9 +292,14 @@ int energy(fagbi_handle* h, const double* x, const double* xq, const double* q, 
   const int nb = (int)((h->N + 255) / 256);
   FAGBI_TRY(part.alloc(nb * 8));
   FAGBI_TRY(out.alloc(8));
-  k_energy<<<nb, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
-                              h->d_perm.as<int32_t>(), (int)h->N, chg.as<double4>(), (int)nc,
-                              h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part.as<double>());
+  if (h->hat())
+    k_energy<true><<<nb, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
+                                      h->d_ptri.as<int32_t>(), (int)h->N, chg.as<double4>(), (int)nc,
+                                      h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part.as<double>(), h->nv);
+  else
+    k_energy<<<nb, 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
+                                h->d_perm.as<int32_t>(), (int)h->N, chg.as<double4>(), (int)nc,
+                                h->prm.eps_out / h->prm.eps_in, h->prm.kappa, x, part.as<double>());
   k_sum<<<1, RB, 0, s>>>(part.as<double>(), nb, 1.0, out.as<double>());
   FAGBI_HIP(hipGetLastError());
   double tot = 0;
@@ -343,6 +419,18 @@ static void multidot(Krylov& K, const double* V, int nv, const double* w, double
 
 using Op = std::function<int(const double*, double*)>;
 
+// pinned host buffer for one Hessenberg column pair of a basis of m vectors
+static int pinned_column(fagbi_handle* h, int m) {
+  const size_t need = 2 * (size_t)(m + 2);
+  if (h->hpin_n >= need) return 0;
+  if (h->hpin) FAGBI_HIP(hipHostFree(h->hpin));
+  h->hpin = nullptr;
+  h->hpin_n = 0;
+  FAGBI_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hpin), need * 8, hipHostMallocDefault));
+  h->hpin_n = need;
+  return 0;
+}
+
 // Solve A x = b, right preconditioned (flexible: P may change per step).
 // x holds x0 on entry.  Returns 0 (converged) or FAGBI_W_NOT_CONVERGED.
 static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const double* b, double* x, double tol,
@@ -381,17 +469,10 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), col(m + 2);
   // the column comes back through pinned memory, waited for by polling an
   // event (a copy into pageable memory and a stream synchronisation left the
-  // GPU idle for ~65 us per iteration)
-  const size_t need = 2 * (size_t)(K.m + 2);
-  if (h->hpin_n < need) {
-    if (h->hpin) FAGBI_HIP(hipHostFree(h->hpin));
-    h->hpin = nullptr;
-    h->hpin_n = 0;
-    FAGBI_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hpin), need * 8, hipHostMallocDefault));
-    h->hpin_n = need;
-  }
+  // GPU idle for ~65 us per iteration); solve() sizes the buffer for both
+  // levels of the flexible solve, so the inner solves never replace it
+  FAGBI_TRY(pinned_column(h, K.m));
   if (!h->ev_col) FAGBI_HIP(hipEventCreateWithFlags(&h->ev_col, hipEventDisableTiming));
-  double* hp = h->hpin;
   g[0] = beta;
   int k = 0;
   for (; k < m; ++k) {
@@ -399,6 +480,7 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
     double* zk = Z + (int64_t)k * n;
     FAGBI_TRY(P(vk, zk));
     FAGBI_TRY(A(zk, w));
+    double* hp = h->hpin;   // after P: an inner solve may have run
     // classical Gram-Schmidt, twice; the first pass's coefficients stay on
     // the device (hc2) until the one read-back per iteration
     double* hc2 = hc + (m + 2);
@@ -459,7 +541,7 @@ static int gmres(fagbi_handle* h, Krylov& K, const Op& A, const Op& P, const dou
 
 int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* x, fagbi_solve_info* info,
           hipStream_t s) {
-  const int64_t n = 2 * h->N;
+  const int64_t n = 2 * h->n_unk();
   fagbi_solve_info inf{};
   auto t0 = std::chrono::steady_clock::now();
   Tmp b, r;
@@ -491,6 +573,7 @@ int solve(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double
   Op M32 = [&](const double* in, double* out) { return precond_apply(h, in, out, s, true); };
   int status = 0, it = 0;
   double rel = 0;
+  FAGBI_TRY(pinned_column(h, std::max(h->prm.max_iter, h->prm.max_outer)));
   if (h->prm.precision == FAGBI_FP64) {
     Krylov KA;
     FAGBI_TRY(krylov_alloc(KA, h->prm.max_iter, n));

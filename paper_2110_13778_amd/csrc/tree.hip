@@ -699,6 +699,13 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
     if (tr[0] == tr[1] || tr[1] == tr[2] || tr[0] == tr[2])
       return set_error(FAGBI_E_MESH, "build_tree: triangle %lld repeats a vertex", (long long)t);
   }
+  if (h->hat()) {   // every vertex carries a hat function: it must lie on a triangle
+    std::vector<char> used(nv, 0);
+    for (int64_t k = 0; k < 3 * nt; ++k) used[tris[k]] = 1;
+    for (int64_t v = 0; v < nv; ++v)
+      if (!used[v])
+        return set_error(FAGBI_E_MESH, "build_tree: vertex %lld belongs to no triangle", (long long)v);
+  }
   hipStream_t s = 0;
   const int64_t N = nt;
   Arena A;
@@ -793,7 +800,7 @@ int build_tree(fagbi_handle* h, const double* verts, int64_t nv, const int32_t* 
   FAGBI_TRY(h->alloc(h->d_pa, N * 8));
   FAGBI_TRY(h->alloc(h->d_ptri, 3 * N * 4));
   FAGBI_TRY(h->alloc(h->d_pc, N * sizeof(double4)));
-  FAGBI_TRY(h->alloc(h->d_xt, 2 * N * sizeof(double)));
+  FAGBI_TRY(h->alloc(h->d_xt, (h->hat() ? 6 : 2) * N * sizeof(double)));   // rows: panels or corners
   int32_t* perm = h->d_perm.as<int32_t>();
   k_leaf_order<<<grid_of(N), TB, 0, s>>>(key, val, N, 3 * (DEEP - L), leaf, perm, keyL);
   k_permute<<<grid_of(N), TB, 0, s>>>(perm, N, cor, nrm, area, dt, h->d_pv.as<double>(), h->d_pn.as<double>(),

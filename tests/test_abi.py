@@ -26,8 +26,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_size_matches_header_layout():
     import ctypes
-    # 8 doubles + 10 int32 with natural alignment (see include/fagbi.h)
-    assert ctypes.sizeof(_lib.Params) == 128
+    # 8 doubles + 11 int32 with natural alignment (see include/fagbi.h): the
+    # last int32 (basis) at 128, padded to 136
+    assert ctypes.sizeof(_lib.Params) == 136
     p = F.default_params()
     assert p.eps_out == 80.0 and p.p_leaf == 4 and p.quad_duffy == 7
 

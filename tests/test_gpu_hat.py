@@ -1,0 +1,232 @@
+"""The continuous piecewise-linear basis (FAGBI_BASIS_S1, hat functions at the
+vertices; Sec. 2.3) against the oracle's hat-function discretisation.
+
+* the operator: FP64 to 1e-11 and FP32 to 1e-6 (relative L2 and largest row),
+  near part (with the mass terms) and far part separately, on the icosphere
+  and on an irregular isosurface globule with close pairs;
+* the right-hand side and the energy to 1e-12, the Jacobi divisors to 1e-12;
+* solves: with every pair near (eta0 = 0) the GPU solution equals the oracle's
+  dense solve; on the Kirkwood sphere the surface potential's L2 error falls
+  like h^2 (against h with box functions) and the FP32-inner solve agrees with
+  the FP64 one;
+* error paths of the parameters the basis excludes."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2110_13778_amd as F  # noqa: E402
+from oracle import dense, kirkwood, p1  # noqa: E402
+from oracle import solve as osolve  # noqa: E402
+from oracle import tree as otree  # noqa: E402
+from oracle.geometry import panels  # noqa: E402
+from synth import icosphere, isosurface_mesh, packed_atoms_ball  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+EPS, KAP = 80.0, 0.1257
+DEV = "cuda:0"
+HAT = F.BASIS_S1
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def maxrow(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def dev(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device=DEV)
+
+
+def gpu_matvec(h, x, precision=F.FP64, parts=F.PART_ALL):
+    xd = dev(x)
+    y = torch.empty_like(xd)
+    h.matvec(xd, y, precision, parts)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def sphere1280():
+    v, t = icosphere(3, 2.0)
+    return v, t, panels(v, t)
+
+
+@pytest.fixture(scope="module")
+def globule():
+    x, r, q = packed_atoms_ball(n=16, radius=None, seed=11)
+    v, t = isosurface_mesh(x, r, spacing=1.0)     # 2,388 panels with close pairs
+    return v, t, panels(v, t)
+
+
+@pytest.mark.parametrize("mesh,cfg", [
+    ("sphere", dict(leaf_size=8, p_leaf=3, adaptive=1, p_max=6)),
+    ("globule", dict(leaf_size=16, p_leaf=4, adaptive=0, quad_duffy=4)),
+    ("globule", dict(leaf_size=4, p_leaf=3, adaptive=1, p_max=8, quad_duffy=4)),
+])
+def test_hat_operator_matches_oracle(sphere1280, globule, mesh, cfg):
+    v, t, P = sphere1280 if mesh == "sphere" else globule
+    h = F.Handle(eta0=0.8, basis=HAT, precond=F.PRECOND_DIAG, **cfg).build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, cfg["leaf_size"], 0.8)
+    O = p1.setup(P, tr, EPS, KAP, p_leaf=cfg["p_leaf"], adaptive=cfg["adaptive"], p_max=cfg.get("p_max", 8),
+                 n_duffy=cfg.get("quad_duffy", 7))
+    V = len(v)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(2 * V)
+    ref = p1.matvec(O, x)
+    y64, y32 = gpu_matvec(h, x), gpu_matvec(h, x, F.MIXED)
+    print("%s %s: %d vertices, fp64 %.2e / %.2e, fp32 %.2e / %.2e"
+          % (mesh, cfg, V, rel(y64, ref), maxrow(y64, ref), rel(y32, ref), maxrow(y32, ref)))
+    assert rel(y64, ref) < 1e-11 and maxrow(y64, ref) < 1e-11
+    assert rel(y32, ref) < 1e-6 and maxrow(y32, ref) < 1e-6
+    assert rel(gpu_matvec(h, x, parts=F.PART_NEAR), p1.matvec(O, x, far=False)) < 1e-11
+    assert rel(gpu_matvec(h, x, parts=F.PART_FAR), np.concatenate(p1.far_field(O, x[:V], x[V:]))) < 1e-11
+    # Jacobi divisors
+    z = rng.standard_normal(2 * V)
+    y = torch.empty(2 * V, dtype=torch.float64, device=DEV)
+    h.precond_apply(dev(z), y)
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), z / p1.diagonal(O)) < 1e-12
+    h.close()
+
+
+def test_hat_rhs_and_energy(globule):
+    v, t, P = globule
+    V = len(v)
+    x_, r_, q_ = packed_atoms_ball(n=16, radius=None, seed=11)
+    h = F.Handle(leaf_size=16, basis=HAT, precond=F.PRECOND_DIAG, quad_duffy=4).build_tree(v, t)
+    h.assemble_nearfield()
+    b = torch.empty(2 * V, dtype=torch.float64, device=DEV)
+    h.rhs(x_, q_, b)
+    torch.cuda.synchronize()
+    ref = p1.rhs(P, x_, q_, 1.0)
+    assert rel(b.cpu().numpy(), ref) < 1e-12 and maxrow(b.cpu().numpy(), ref) < 1e-12
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(2 * V)
+    E = h.solvation_energy(dev(x), x_, q_)
+    Eref = p1.energy(P, x, x_, q_, EPS, KAP)
+    assert abs(E - Eref) < 1e-12 * abs(Eref)
+    h.close()
+
+
+def _kirkwood_case():
+    R, e1, e2, kap = 2.0, 1.0, 80.0, 0.1257
+    xq = np.array([[0.0, 0.0, 0.9], [0.7, -0.3, -0.5], [-0.4, 0.6, 0.2]])
+    q = np.array([1.0, -0.7, 0.5])
+    return R, e1, e2, kap, xq, q
+
+
+def test_hat_solve_equals_dense_oracle():
+    """every pair near (eta0 = 0): the GPU operator is the dense matrix, and the
+    FP64 solve to 1e-12 reproduces the oracle's direct solve and energy"""
+    R, e1, e2, kap, xq, q = _kirkwood_case()
+    v, t = icosphere(2, R)
+    P = panels(v, t)
+    V = len(v)
+    A = p1.assemble(P, e2 / e1, kap)
+    b = p1.rhs(P, xq, q, e1)
+    xref = np.linalg.solve(A, b)
+    Eref = p1.energy(P, xref, xq, q, e2 / e1, kap)
+    h = F.Handle(eps_in=e1, eps_out=e2, kappa=kap, eta0=0.0, leaf_size=8, basis=HAT,
+                 precond=F.PRECOND_DIAG, tol=1e-12, max_iter=300)
+    h.build_tree(v, t).assemble_nearfield()
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal(2 * V)
+    assert rel(gpu_matvec(h, z), A @ z) < 1e-12
+    x = torch.zeros(2 * V, dtype=torch.float64, device=DEV)
+    code, info = h.solve(xq, q, x)
+    assert code == 0 and info.rel_residual <= 1e-12
+    E = h.solvation_energy(x, xq, q)
+    print("dense hat system: %d iterations, solution rel diff %.2e, energy %.10f vs %.10f"
+          % (info.inner_iterations, rel(x.cpu().numpy(), xref), E, Eref))
+    assert rel(x.cpu().numpy(), xref) < 1e-10
+    assert abs(E - Eref) < 1e-10 * abs(Eref)
+    h.close()
+
+
+def _surface_potential(pts, R, e1, e2, kap, xq, q, nmax=60):
+    C = kirkwood.reaction_factors(R, e1, e2, kap, nmax)
+    xs = R * pts / np.linalg.norm(pts, axis=-1, keepdims=True)
+    out = np.zeros(xs.shape[:-1])
+    for k in range(len(q)):
+        rk = np.linalg.norm(xq[k])
+        d = np.linalg.norm(xs - xq[k], axis=-1)
+        Pn = kirkwood.legendre(nmax, (xs @ xq[k]) / (R * rk))
+        out += q[k] / (4 * np.pi * e1) * (1.0 / d + sum(C[n] * (rk / R) ** n * Pn[n] for n in range(nmax + 1)) / R)
+    return out
+
+
+def test_hat_kirkwood_projection_rates_on_gpu():
+    """FMM solves on the Kirkwood sphere at 320 / 1,280 / 5,120 panels: the
+    surface potential's L2 error falls like h^2 with hat functions and like h
+    with box functions; the energies converge to the series; the FP32-inner
+    solve agrees with the FP64 one.  The expansions (order 7 at the leaves,
+    eta0 0.6) keep the FMM's error far below the discretisation's (with order
+    4 at eta0 0.8 the hat error levels off near 1e-3 from 5,120 panels on)."""
+    R, e1, e2, kap, xq, q = _kirkwood_case()
+    Eref = kirkwood.energy(xq, q, R, e1, e2, kap)
+    prm = dict(eps_in=e1, eps_out=e2, kappa=kap, leaf_size=16, eta0=0.6, p_leaf=7, adaptive=1, p_max=8,
+               tol=1e-8, max_iter=300, inner_tol=5e-9)
+    e_hat, e_box, E_hat = [], [], []
+    for lev in (2, 3, 4):
+        v, t = icosphere(lev, R)
+        P = panels(v, t)
+        V, N = len(v), len(t)
+        ex = _surface_potential(P.qp, R, e1, e2, kap, xq, q)
+        nrm = np.sqrt((P.qw * ex ** 2).sum())
+        sol = {}
+        for basis, prec, pc in ((HAT, F.FP64, F.PRECOND_DIAG), (HAT, F.MIXED, F.PRECOND_DIAG),
+                                (F.BASIS_S0, F.FP64, F.PRECOND_BLOCK)):
+            print("solve: %d panels, basis %d, precision %d" % (N, basis, prec), flush=True)
+            h = F.Handle(basis=basis, precision=prec, precond=pc, **prm).build_tree(v, t).assemble_nearfield()
+            n = V if basis == HAT else N
+            x = torch.zeros(2 * n, dtype=torch.float64, device=DEV)
+            code, info = h.solve(xq, q, x)
+            assert code == 0, (basis, prec)
+            sol[(basis, prec)] = (x.cpu().numpy(), h.solvation_energy(x, xq, q), info.inner_iterations)
+            h.close()
+        xh, Eh, ith = sol[(HAT, F.FP64)]
+        xb, Eb, itb = sol[(F.BASIS_S0, F.FP64)]
+        uh = np.einsum("ka,pa->pk", p1.LAM, xh[:V][P.tris])
+        e_hat.append(np.sqrt((P.qw * (uh - ex) ** 2).sum()) / nrm)
+        e_box.append(np.sqrt((P.qw * (xb[:N, None] - ex) ** 2).sum()) / nrm)
+        E_hat.append(abs(Eh - Eref) / abs(Eref))
+        Em = sol[(HAT, F.MIXED)][1]
+        print("%d panels: L2 hat %.3e box %.3e, energy hat %.6f box %.6f series %.6f (mixed %.6f), "
+              "iterations hat %d box %d" % (N, e_hat[-1], e_box[-1], Eh, Eb, Eref, Em, ith, itb))
+        assert abs(Em - Eh) < 1e-7 * abs(Eh)
+    assert e_hat[0] / e_hat[1] > 3.5 and e_hat[1] / e_hat[2] > 3.5
+    assert e_box[0] / e_box[1] < 2.6 and e_box[1] / e_box[2] < 2.6
+    assert e_hat[2] < 0.2 * e_box[2]
+    assert E_hat[0] / E_hat[1] > 3.5 and E_hat[1] / E_hat[2] > 3.5
+
+
+def test_hat_error_paths(sphere1280):
+    v, t, P = sphere1280
+    for kw in (dict(mlp_mode=F.MLP_GATED), dict(precond=F.PRECOND_BLOCK), dict(precond=F.PRECOND_GROUP),
+               dict(rhs_theta=0.5), dict(basis=2)):
+        args = dict(basis=HAT, precond=F.PRECOND_DIAG)
+        args.update(kw)
+        with pytest.raises(F.FagbiError) as e:
+            F.Handle(**args)
+        assert e.value.code == -1, kw
+    # a vertex on no triangle carries a hat function of zero support
+    v2 = np.vstack([v, [[10.0, 0.0, 0.0]]])
+    with pytest.raises(F.FagbiError) as e:
+        F.Handle(basis=HAT, precond=F.PRECOND_DIAG).build_tree(v2, t)
+    assert e.value.code == -2
+    h = F.Handle(basis=HAT, precond=F.PRECOND_DIAG).build_tree(v, t)
+    b = torch.zeros(2 * len(v), dtype=torch.float64, device=DEV)
+    with pytest.raises(F.FagbiError) as e:      # before the assembly
+        h.rhs(np.zeros((1, 3)), np.ones(1), b)
+    assert e.value.code == -3
+    h.assemble_nearfield()
+    x = torch.zeros(2 * len(v), dtype=torch.float64, device=DEV)
+    for call in (lambda: h.solvation_energy_treecode(x, np.zeros((1, 3)), np.ones(1), 0.5),
+                 lambda: h.rhs_treecode(np.zeros((1, 3)), np.ones(1), 0.5, b)):
+        with pytest.raises(F.FagbiError) as e:
+            call()
+        assert e.value.code == -1
+    h.close()
