@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--mlp-pairs", type=int, default=2000000,
                     help="training pairs drawn per training mesh (two meshes; the default takes every "
                          "near-singular pair of both)")
+    ap.add_argument("--no-hat", action="store_true",
+                    help="skip the continuous piecewise-linear (hat-function) leg on the main workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -78,6 +80,66 @@ MLP_GATE = 0.05         # stated per-pair error tolerance of the gated near fiel
 
 def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
+    """The continuous piecewise-linear basis (hat functions at the vertices) on
+    the same workload and tree: FP32-inner flexible GMRES and FP64 GMRES with
+    the Jacobi preconditioner, the direct right-hand side and energy sums.
+    Median of `runs` whole solves per precision (build, assembly, solve,
+    energy), with the per-matvec phase times of the median run."""
+    N, V = len(w["tris"]), len(w["verts"])
+    prm = dict(PARAMS, precond=F.PRECOND_DIAG, rhs_theta=0.0, max_iter=300)
+    out = {"panels": N, "vertices": V, "precond": "Jacobi (the diagonal of A)",
+           "rhs_and_energy": "direct sums over charges and the 3-point rule's points"}
+    near_pairs = 0
+    for tag, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
+        sts = []
+        p = 1 if prec == F.MIXED else 0
+        for _ in range(runs):
+            h = F.Handle(precision=prec, eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"],
+                         basis=F.BASIS_S1, **prm)
+            h.set_profiling(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.build_tree(w["verts"], w["tris"])
+            t1 = time.perf_counter()
+            h.assemble_nearfield()
+            t2 = time.perf_counter()
+            x = torch.zeros(2 * V, dtype=torch.float64, device=dev)
+            code, info = h.solve(w["xq"], w["q"], x)
+            t3 = time.perf_counter()
+            E = h.solvation_energy(x, w["xq"], w["q"])
+            t4 = time.perf_counter()
+            pr = h.profile()
+            near_pairs = h.tree_info().near_pairs
+            mv = max(pr["matvecs"][p], 1)
+            sts.append(dict(code=code, total_ms=1e3 * (t4 - t0), tree_ms=1e3 * (t1 - t0),
+                            assemble_ms=1e3 * (t2 - t1), solve_ms=1e3 * (t3 - t2), energy_ms=1e3 * (t4 - t3),
+                            t_rhs_ms=info.t_rhs_ms, t_iterations_ms=info.t_solve_ms,
+                            iters=info.inner_iterations, outer=info.outer_iterations, res=info.rel_residual, E=E,
+                            setup_stages_ms={k: pr[k] for k in ("ms_tree", "ms_classify", "ms_singular",
+                                                                "ms_fmm_setup", "ms_precond")},
+                            matvec_ms=pr["ms_total"][p] / mv, spmv_ms=pr["ms_near"][p] / mv,
+                            m2l_leaf_ms=pr["ms_m2l_leaf"][p] / mv, matvecs=pr["matvecs"][p]))
+            h.close()
+        out[tag] = sts[int(np.argsort([s["total_ms"] for s in sts])[len(sts) // 2])]
+        out[tag]["total_ms_runs"] = [s["total_ms"] for s in sts]
+        log("hat basis %s: %.0f ms to 1e-6 (%d inner iterations), matvec %.3f ms"
+            % (tag, out[tag]["total_ms"], out[tag]["iters"], out[tag]["matvec_ms"]))
+    # the near-field SpMV over panel corners: 9 FP32 entry quadruples per stored
+    # panel pair, the corners' (phi, dphi) read and their two results written
+    spmv_bytes = 9 * near_pairs * 16 + 3 * N * 16 + 3 * N * 16
+    ach = spmv_bytes / (out["mixed"]["spmv_ms"] * 1e-3) / 1e9
+    out["spmv_fp32"] = {"kernel": "k_spmv<float4> over panel corners (one launch per matvec)", "bound": "hbm",
+                        "avg_launch_ms": out["mixed"]["spmv_ms"], "algorithmic_bytes_per_launch": spmv_bytes,
+                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    out["matvec_mvertices_per_s"] = {"mixed_fp32": V / (out["mixed"]["matvec_ms"] * 1e-3) / 1e6,
+                                     "fp64": V / (out["fp64"]["matvec_ms"] * 1e-3) / 1e6}
+    E64, Em = out["fp64"]["E"], out["mixed"]["E"]
+    out["energy_kcal"] = {"mixed": Em, "fp64": E64, "mixed_vs_fp64": abs(Em - E64) / abs(E64),
+                          "box_fp64_direct_sums": E_box_ref, "hat_vs_box": abs(E64 - E_box_ref) / abs(E_box_ref)}
+    return out
 
 
 def sha256(path):
@@ -543,6 +605,8 @@ def main():
             log("secondary %s: %d panels, mixed %.0f ms, fp64 %.0f ms" % (
                 name, r["panels"], r["mixed_with_surrogate"]["total_ms"], r["fp64"]["total_ms"]))
         line["secondary_workloads"] = sec
+    if not args.no_hat:
+        line["hat_basis"] = hat_leg(F, torch, w, dev, E_ref)
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

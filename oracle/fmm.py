@@ -298,10 +298,28 @@ def far_field_rows(F, phi, dphi, leaves):
     ancestor chains and the evaluation (step 6) at their panels.  Every
     computed local is the same sum as in far_field (one matrix per offset),
     taken for fewer targets.  Returns (panel ids [m], f1 [m], f2 [m])."""
-    tree, eps, kappa, pl = F.tree, F.eps, F.kappa, F.orders
+    tree, eps = F.tree, F.eps
     L, perm = tree.L, tree.perm
-    levels = tree.levels
     M0, Mk = upward(F, phi, dphi)
+    anc, lam0, lamk = leaf_locals_at(F, M0, Mk, leaves)
+    leaf = tree.levels[L]
+    ids, f1, f2 = [], [], []
+    for k, c in enumerate(anc):
+        tpos = np.arange(leaf.start[c], leaf.end[c])
+        ids.append(perm[tpos])
+        f1.append(-((lam0[k] + lamk[k]) * F.ms[tpos]).sum(1))
+        f2.append(-((lam0[k] + lamk[k] / eps) * F.md[tpos]).sum(1))
+    return np.concatenate(ids), np.concatenate(f1), np.concatenate(f2)
+
+
+def leaf_locals_at(F, M0, Mk, leaves):
+    """Steps 4 and 5 for the given leaves only (from the moments of every
+    level): the interaction phase at the ancestors of these leaves and the
+    downward pass along their chains.  Returns (leaves, sorted unique [m],
+    lam0 [m, T(p_L)], lamk [m, T(p_L)])."""
+    tree, kappa, pl = F.tree, F.kappa, F.orders
+    L = tree.L
+    levels = tree.levels
     anc = {L: np.unique(np.asarray(leaves, np.int64))}
     for l in range(L - 1, tree.lmin - 1, -1):
         anc[l] = np.unique(levels[l + 1].parent[anc[l + 1]])
@@ -330,11 +348,7 @@ def far_field_rows(F, phi, dphi, leaves):
             p = where[ch.parent[c]]
             lam0[l + 1][k] += lam0[l][p] @ S
             lamk[l + 1][k] += lamk[l][p] @ S
-    leaf = levels[L]
-    ids, f1, f2 = [], [], []
-    for k, c in enumerate(anc[L]):
-        tpos = np.arange(leaf.start[c], leaf.end[c])
-        ids.append(perm[tpos])
-        f1.append(-((lam0[L][k] + lamk[L][k]) * F.ms[tpos]).sum(1))
-        f2.append(-((lam0[L][k] + lamk[L][k] / eps) * F.md[tpos]).sum(1))
-    return np.concatenate(ids), np.concatenate(f1), np.concatenate(f2)
+    if tree.lmin > L:
+        T = len(_mi(pl[L])[0])
+        return anc[L], np.zeros((len(anc[L]), T)), np.zeros((len(anc[L]), T))
+    return anc[L], lam0[L], lamk[L]

@@ -403,6 +403,79 @@ def far_field(F, u, v):
     return y1, y2
 
 
+def _leaf_of_panels(F):
+    """leaf of every panel (caller order)"""
+    owner = np.empty(F.P.n, np.int64)
+    owner[F.tree.perm] = F.owner
+    return owner
+
+
+def panels_at(P, verts):
+    """the panels having a corner at one of the given vertices"""
+    return np.nonzero(np.isin(P.tris, np.asarray(verts)).any(1))[0]
+
+
+def near_rows(F, u, v, verts, near_ratio=2.0, n=7):
+    """the near part of A x (identity terms included) at the given vertices:
+    the stored pairs of the panels at those vertices (sources: every panel of
+    the neighbour leaves of their leaf), integrated pair by pair.  Returns
+    (y1 [m], y2 [m]) in the order of verts."""
+    P, tree, eps = F.P, F.tree, F.eps
+    leaf = tree.levels[tree.L]
+    owner = _leaf_of_panels(F)
+    verts = np.asarray(verts)
+    y1 = np.zeros(len(verts))
+    y2 = np.zeros(len(verts))
+    Mb = mass_diag_blocks(P)
+    for k, vx in enumerate(verts):
+        for t_ in panels_at(P, [vx]):
+            a = int(np.nonzero(P.tris[t_] == vx)[0][0])
+            c = owner[t_]
+            src = np.concatenate([tree.perm[leaf.start[c2]:leaf.end[c2]] for c2 in leaf.nbr[c]])
+            J, _ = pair_integrals(P, np.full(len(src), t_), src, F.kappa, near_ratio, n)
+            B = combine(J[:, a], eps)                  # [s, b, 4]
+            ub, vb = u[P.tris[src]], v[P.tris[src]]    # [s, b]
+            y1[k] += (B[..., 0] * ub).sum() + (B[..., 1] * vb).sum()
+            y2[k] += (B[..., 2] * ub).sum() + (B[..., 3] * vb).sum()
+            y1[k] += 0.5 * (1.0 + eps) * (Mb[t_, a] * u[P.tris[t_]]).sum()
+            y2[k] += 0.5 * (1.0 + 1.0 / eps) * (Mb[t_, a] * v[P.tris[t_]]).sum()
+    return y1, y2
+
+
+def far_rows(F, u, v, verts):
+    """the far field of A x at the given vertices: the full upward pass, the
+    locals of the leaves holding the vertices' panels only, and the corner
+    results of those panels summed into the vertices.  Returns (y1, y2)."""
+    P, tree, eps = F.P, F.tree, F.eps
+    L = tree.L
+    tri = P.tris[tree.perm]
+    a, b = u[tri], v[tri]
+    c0 = np.einsum("pat,pa->pt", F.ms3, b) - np.einsum("pat,pa->pt", F.md3, a)
+    ck = -np.einsum("pat,pa->pt", F.ms3, b) + eps * np.einsum("pat,pa->pt", F.md3, a)
+    leaf = tree.levels[L]
+    M0L = np.zeros((leaf.n, F.ms3.shape[2]))
+    MkL = np.zeros((leaf.n, F.ms3.shape[2]))
+    np.add.at(M0L, F.owner, c0)
+    np.add.at(MkL, F.owner, ck)
+    M0, Mk = fmm.upward_pass(F, M0L, MkL)
+    verts = np.asarray(verts)
+    owner = _leaf_of_panels(F)
+    pans = panels_at(P, verts)
+    anc, lam0, lamk = fmm.leaf_locals_at(F, M0, Mk, owner[pans])
+    row = {int(c): k for k, c in enumerate(anc)}
+    pos = np.empty(P.n, np.int64)
+    pos[tree.perm] = np.arange(P.n)                  # tree position of each panel
+    y1 = np.zeros(len(verts))
+    y2 = np.zeros(len(verts))
+    for k, vx in enumerate(verts):
+        for t_ in panels_at(P, [vx]):
+            a_ = int(np.nonzero(P.tris[t_] == vx)[0][0])
+            r = row[int(owner[t_])]
+            y1[k] -= ((lam0[r] + lamk[r]) * F.ms3[pos[t_], a_]).sum()
+            y2[k] -= ((lam0[r] + lamk[r] / eps) * F.md3[pos[t_], a_]).sum()
+    return y1, y2
+
+
 def near_matvec(F, u, v):
     P, V = F.P, F.V
     ti, tj = P.tris[F.near_i], P.tris[F.near_j]

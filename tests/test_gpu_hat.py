@@ -230,3 +230,86 @@ def test_hat_error_paths(sphere1280):
             call()
         assert e.value.code == -1
     h.close()
+
+
+# the benchmark's tree and expansion settings on its 491,088-panel workload
+BIG = dict(leaf_size=32, eta0=0.8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=7, near_ratio=2.0)
+
+
+@pytest.fixture(scope="module")
+def big_hat():
+    from synth import workload
+    w = workload("ellipsoid500k")
+    P = panels(w["verts"], w["tris"])
+    eps = w["eps_out"] / w["eps_in"]
+    tr = otree.build(P, BIG["leaf_size"], BIG["eta0"])
+    O = p1.setup(P, tr, eps, w["kappa"], p_leaf=BIG["p_leaf"], adaptive=BIG["adaptive"], p_max=BIG["p_max"],
+                 with_near=False)
+    h = F.Handle(eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], basis=HAT, precond=F.PRECOND_DIAG,
+                 **BIG).build_tree(w["verts"], w["tris"]).assemble_nearfield()
+    yield dict(w=w, P=P, O=O, h=h)
+    h.close()
+
+
+def test_hat_full_size_rows_and_invariant(big_hat):
+    """491,088 panels (245,546 vertices): near and far rows of 12 sampled
+    vertices against the oracle (FP64 to 1e-11, the FP32 operator to 1e-6 of
+    the largest row), and the box-function invariant: for constant nodal
+    values the sum of A x over the vertices equals the box operator's sum over
+    the panels (the hat functions of a panel sum to one)"""
+    w, P, O, h = big_hat["w"], big_hat["P"], big_hat["O"], big_hat["h"]
+    V = len(w["verts"])
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(2 * V)
+    yn = gpu_matvec(h, x, parts=F.PART_NEAR)
+    yf = gpu_matvec(h, x, parts=F.PART_FAR)
+    y32 = gpu_matvec(h, x, F.MIXED)
+    verts = rng.choice(V, 12, replace=False)
+    n1, n2 = p1.near_rows(O, x[:V], x[V:], verts)
+    f1, f2 = p1.far_rows(O, x[:V], x[V:], verts)
+    near = np.concatenate([n1, n2])
+    far = np.concatenate([f1, f2])
+    idx = np.concatenate([verts, V + verts])
+    print("491k hat rows: near %.2e, far %.2e, fp32 %.2e"
+          % (maxrow(yn[idx], near), maxrow(yf[idx], far), maxrow(y32[idx], near + far)))
+    assert maxrow(yn[idx], near) < 1e-11 and maxrow(yf[idx], far) < 1e-11
+    assert maxrow(y32[idx], near + far) < 1e-6
+    hb = F.Handle(eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], precond=F.PRECOND_DIAG, **BIG)
+    hb.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+    N = len(w["tris"])
+    for c1, c2 in ((1.0, 0.0), (0.0, 1.0), (0.7, -0.3)):
+        s_hat = gpu_matvec(h, np.concatenate([np.full(V, c1), np.full(V, c2)]))
+        s_box = gpu_matvec(hb, np.concatenate([np.full(N, c1), np.full(N, c2)]))
+        for ch in range(2):
+            a, b = s_hat[ch * V:(ch + 1) * V].sum(), s_box[ch * N:(ch + 1) * N].sum()
+            print("constant (%.1f, %.1f) channel %d: hat %.12e box %.12e" % (c1, c2, ch, a, b))
+            assert abs(a - b) < 1e-11 * np.abs(s_box[ch * N:(ch + 1) * N]).sum()
+    hb.close()
+
+
+def test_hat_full_size_solves(big_hat):
+    """both precisions to a 1e-6 true residual on the 491,088-panel workload,
+    energies within 1e-5 of each other and within 5e-3 of the box-function
+    FP64 energy: the two discretisations of the same problem, each with an
+    O(h^2) energy error (measured 1.9e-3 apart here; 3.8e-3 apart on the
+    320-panel Kirkwood sphere, 2.4e-4 at 5,120 panels)"""
+    w = big_hat["w"]
+    V, N = len(w["verts"]), len(w["tris"])
+    E = {}
+    for basis, prec, pc in ((HAT, F.FP64, F.PRECOND_DIAG), (HAT, F.MIXED, F.PRECOND_DIAG),
+                            (F.BASIS_S0, F.FP64, F.PRECOND_GROUP)):
+        print("solve: basis %d precision %d" % (basis, prec), flush=True)
+        h = F.Handle(eps_in=w["eps_in"], eps_out=w["eps_out"], kappa=w["kappa"], basis=basis, precision=prec,
+                     precond=pc, tol=1e-6, max_iter=300, max_outer=5, inner_tol=5e-7, **BIG)
+        h.build_tree(w["verts"], w["tris"]).assemble_nearfield()
+        n = V if basis == HAT else N
+        x = torch.zeros(2 * n, dtype=torch.float64, device=DEV)
+        code, info = h.solve(w["xq"], w["q"], x)
+        assert code == 0 and info.rel_residual <= 1e-6, (basis, prec)
+        E[(basis, prec)] = h.solvation_energy(x, w["xq"], w["q"])
+        print("basis %d precision %d: %d inner iterations, energy %.6f"
+              % (basis, prec, info.inner_iterations, E[(basis, prec)]))
+        h.close()
+    e64 = E[(HAT, F.FP64)]
+    assert abs(E[(HAT, F.MIXED)] - e64) < 1e-5 * abs(e64)
+    assert abs(E[(F.BASIS_S0, F.FP64)] - e64) < 5e-3 * abs(e64)
