@@ -92,7 +92,7 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
     prm = dict(PARAMS, precond=F.PRECOND_DIAG, rhs_theta=0.0, max_iter=300)
     out = {"panels": N, "vertices": V, "precond": "Jacobi (the diagonal of A)",
            "rhs_and_energy": "direct sums over charges and the 3-point rule's points"}
-    near_pairs = 0
+    near_pairs = hat_rows = hat_entries = 0
     for tag, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
         sts = []
         p = 1 if prec == F.MIXED else 0
@@ -112,7 +112,8 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
             E = h.solvation_energy(x, w["xq"], w["q"])
             t4 = time.perf_counter()
             pr = h.profile()
-            near_pairs = h.tree_info().near_pairs
+            ti = h.tree_info()
+            near_pairs, hat_rows, hat_entries = ti.near_pairs, ti.hat_rows, ti.hat_entries
             mv = max(pr["matvecs"][p], 1)
             sts.append(dict(code=code, total_ms=1e3 * (t4 - t0), tree_ms=1e3 * (t1 - t0),
                             assemble_ms=1e3 * (t2 - t1), solve_ms=1e3 * (t3 - t2), energy_ms=1e3 * (t4 - t3),
@@ -127,11 +128,14 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
         out[tag]["total_ms_runs"] = [s["total_ms"] for s in sts]
         log("hat basis %s: %.0f ms to 1e-6 (%d inner iterations), matvec %.3f ms"
             % (tag, out[tag]["total_ms"], out[tag]["iters"], out[tag]["matvec_ms"]))
-    # the near-field SpMV over panel corners: 9 FP32 entry quadruples per stored
-    # panel pair, the corners' (phi, dphi) read and their two results written
-    spmv_bytes = 9 * near_pairs * 16 + 3 * N * 16 + 3 * N * 16
+    # the near-field SpMV over vertex pairs: one FP32 entry quadruple per
+    # (leaf row vertex, source vertex), every vertex's (phi, dphi) read once and
+    # the two results of every row written
+    spmv_bytes = hat_entries * 16 + V * 16 + hat_rows * 16
     ach = spmv_bytes / (out["mixed"]["spmv_ms"] * 1e-3) / 1e9
-    out["spmv_fp32"] = {"kernel": "k_spmv<float4> over panel corners (one launch per matvec)", "bound": "hbm",
+    out["near_field"] = {"stored_panel_pairs": near_pairs, "vertex_pair_rows": hat_rows,
+                         "vertex_pair_entries": hat_entries, "corner_pair_entries": 9 * near_pairs}
+    out["spmv_fp32"] = {"kernel": "k_spmv<float4> over vertex pairs (one launch per matvec)", "bound": "hbm",
                         "avg_launch_ms": out["mixed"]["spmv_ms"], "algorithmic_bytes_per_launch": spmv_bytes,
                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
     out["matvec_mvertices_per_s"] = {"mixed_fp32": V / (out["mixed"]["matvec_ms"] * 1e-3) / 1e6,

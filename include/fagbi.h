@@ -129,6 +129,10 @@ typedef struct fagbi_tree_info {
   int64_t lev_pairs[FAGBI_MAX_LEVELS];      /* interaction pairs (c, c' in I(c)) */
   int64_t device_bytes;        /* device memory the handle holds (tree, near field, far-field tables and
                                   expansions, preconditioner, Krylov and treecode workspaces) */
+  /* FAGBI_BASIS_S1 (after assembly): the near field by vertex pairs, rows
+     (per leaf, the distinct vertices of its panels) and entries (rows times
+     the distinct vertices of the leaf's source panels); 0 otherwise */
+  int64_t hat_rows, hat_entries;
 } fagbi_tree_info;
 
 typedef struct fagbi_solve_info {

@@ -52,7 +52,7 @@ class TreeInfo(C.Structure):
                 ("rho_leaf", C.c_double), ("h_leaf", C.c_double),
                 ("lev_clusters", C.c_int32 * 21), ("lev_order", C.c_int32 * 21),
                 ("lev_offsets", C.c_int32 * 21), ("lev_pad", C.c_int32), ("lev_pairs", C.c_int64 * 21),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("hat_rows", C.c_int64), ("hat_entries", C.c_int64)]
 
 
 class SolveInfo(C.Structure):

@@ -572,6 +572,10 @@ int fagbi_get_tree_info(fagbi_handle* h, fagbi_tree_info* info) {
   for (const DBuf* b : h->owned) bytes += (int64_t)b->bytes;
   for (const Tmp& t : h->tc_ws) bytes += (int64_t)t.bytes;
   info->device_bytes = bytes;
+  if (h->hat()) {
+    info->hat_rows = h->n_vb_rows;
+    info->hat_entries = h->n_vb_ent;
+  }
   return 0;
 }
 

@@ -1420,14 +1420,14 @@ __global__ void k_to_tree(const double* __restrict__ x, const int32_t* __restric
 
 ElemView box_view(fagbi_handle* h) {
   ElemView v;
-  v.n = h->N;
-  v.leaf_start = h->d_leaf_start.as<int32_t>();
-  v.leaf_cnt = h->d_leaf_cnt.as<int32_t>();
+  v.n = v.n_near = h->N;
+  v.leaf_start = v.near_start = h->d_leaf_start.as<int32_t>();
+  v.leaf_cnt = v.near_cnt = h->d_leaf_cnt.as<int32_t>();
   v.leaf_of = h->d_leaf_of.as<int32_t>();
-  v.src_tree = h->d_src_tree.as<int32_t>();
-  v.src_off = h->d_src_off.as<int64_t>();
-  v.ent_off = h->d_ent_off.as<int64_t>();
-  v.in_idx = v.out_idx = h->d_perm.as<int32_t>();
+  v.near_src = h->d_src_tree.as<int32_t>();
+  v.near_src_off = h->d_src_off.as<int64_t>();
+  v.near_ent_off = h->d_ent_off.as<int64_t>();
+  v.in_idx = v.out_idx = v.out_near = h->d_perm.as<int32_t>();
   v.in_stride = h->N;
   v.xt = h->d_xt.as<double>();
   return v;
@@ -1950,6 +1950,7 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   // rows: panels, or panel corners summed into the vertices at the end
   const int64_t N = v.n;
   double* y = v.y ? v.y : y_out;
+  double* yn = v.y_near ? v.y_near : y;
   const int nl = h->lev[h->L].n;
   const bool prof = h->profiling;
   auto mark_on = [&](int k, hipStream_t st) -> int {
@@ -1961,7 +1962,8 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   double* xt = v.xt;
   k_to_tree<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, v.in_idx, N, v.in_stride, xt);
   // the rows' results summed into the caller's outputs (hat functions)
-  auto gather = [&]() -> int { return v.gat_off ? hat_gather(h, y, y_out, s) : 0; };
+  auto gather = [&]() -> int { return v.gather ? hat_gather(h, y, yn, y_out, s) : 0; };
+  if (v.zero_y) FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
   const bool near = parts & FAGBI_PART_NEAR;
   const bool far = (parts & FAGBI_PART_FAR) && h->lmin <= h->L;
   // the near-field SpMV (HBM bound) runs on a second stream beside the far
@@ -1980,9 +1982,10 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   FAGBI_TRY(mark_on(0, sn));
   if (near) {
     k_spmv<E><<<(unsigned)(((nl + 3) / 4 + 7) / 8 * 8), 256, 0, sn>>>(
-        ent.as<E>(), v.leaf_start, v.leaf_cnt, v.src_off, v.ent_off, v.src_tree, v.out_idx, N, nl, xt, y);
+        ent.as<E>(), v.near_start, v.near_cnt, v.near_src_off, v.near_ent_off, v.near_src, v.out_near, v.n_near,
+        nl, xt, yn);
   } else {
-    FAGBI_HIP(hipMemsetAsync(y, 0, 2 * N * sizeof(double), s));
+    FAGBI_HIP(hipMemsetAsync(yn, 0, 2 * v.n_near * sizeof(double), s));
   }
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark_on(1, sn));

@@ -160,8 +160,15 @@ struct fagbi_handle {
   // (leaf ranges, source lists, entry offsets of the 3 x 3 blocks), the
   // identity map of the element outputs, the leaf of each element, the
   // elements of each vertex (CSR, ascending), the element results [2][3N]
-  fagbi::DBuf d_s1_leaf_start, d_s1_leaf_cnt, d_s1_src_off, d_s1_ent_off, d_s1_src_tree, d_s1_iota,
-      d_s1_leaf_of, d_vx_off, d_vx_el, d_ye;
+  fagbi::DBuf d_s1_leaf_start, d_s1_leaf_cnt, d_s1_iota, d_s1_leaf_of, d_vx_off, d_vx_el, d_ye;
+  // its near field by vertex pairs: per leaf the distinct vertices of its
+  // panels (rows) and of its source panels (columns, each with one of its
+  // corners, whose tree-order input is the vertex's value), the entry blocks
+  // [rows][columns], the vertex and leaf of each row, the rows of each vertex
+  // (CSR); counts of rows and entries
+  fagbi::DBuf d_vb_row_start, d_vb_row_cnt, d_vb_col_off, d_vb_ent_off, d_vb_col_elem, d_vb_col_vert,
+      d_vb_row_vert, d_vb_row_leaf, d_vx_poff, d_vx_pr;
+  int64_t n_vb_rows = 0, n_vb_ent = 0;
   std::vector<float> mlp_blob;        // parameters | normalisation | calibration
   // FP32 leaf-level MtL by the source-reuse tile kernel (when its tables fit);
   // FAGBI_M2L_TILES=0 in the environment selects the per-pair LDS-table kernel
@@ -220,16 +227,23 @@ struct StageTimer {
 // xt[e] = (x[in_idx[e]], x[in_stride + in_idx[e]]), runs the SpMV, P2M and
 // LtP over the rows (row results at y[out_idx[e]] and y[n + out_idx[e]]) and,
 // with a gather list, sums the rows of each output into the caller's y.
+// The near field may run over rows of its own (the hat functions' vertex
+// pairs): its leaf ranges, source lists (indices into xt), entry offsets and
+// row outputs y_near[out_near[r]], y_near[n_near + ...]; zero_y clears the far
+// field's rows first (the SpMV then does not write them).
 struct ElemView {
   int64_t n = 0;
-  const int32_t *leaf_start = nullptr, *leaf_cnt = nullptr, *leaf_of = nullptr, *src_tree = nullptr;
-  const int64_t *src_off = nullptr, *ent_off = nullptr;
+  const int32_t *leaf_start = nullptr, *leaf_cnt = nullptr, *leaf_of = nullptr;
   const int32_t *in_idx = nullptr, *out_idx = nullptr;
   int64_t in_stride = 0;
   double* xt = nullptr;        // [n] (phi, dphi) pairs
   double* y = nullptr;         // row results [2n]; nullptr: the caller's y
-  const int32_t *gat_off = nullptr, *gat_el = nullptr;   // outputs' rows (CSR)
-  int64_t n_out = 0;
+  int64_t n_near = 0;
+  const int32_t *near_start = nullptr, *near_cnt = nullptr, *near_src = nullptr, *out_near = nullptr;
+  const int64_t *near_src_off = nullptr, *near_ent_off = nullptr;
+  double* y_near = nullptr;    // near rows [2 n_near]; nullptr: as y
+  bool zero_y = false;
+  bool gather = false;         // sum the rows into the vertices (hat functions)
 };
 ElemView box_view(fagbi_handle* h);
 ElemView hat_view(fagbi_handle* h);
@@ -265,7 +279,7 @@ void gauss_legendre01(int n, double* x, double* w);
 // diagonal preconditioner, and the element-to-vertex sum
 int hat_assemble(fagbi_handle* h, hipStream_t s);
 int hat_diag_setup(fagbi_handle* h, hipStream_t s);
-int hat_gather(fagbi_handle* h, const double* rows, double* y, hipStream_t s);
+int hat_gather(fagbi_handle* h, const double* rows, const double* near_rows, double* y, hipStream_t s);
 
 // The quadrature table of the singular and close rules (device d_gl):
 // [0, 16) Gauss-Legendre nodes on [0, 1], [16, 32) weights, then one radial

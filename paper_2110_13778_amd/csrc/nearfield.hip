@@ -478,10 +478,11 @@ int run_singular(fagbi_handle* h, int cls_index, const uint8_t* skip, double* ra
 int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
   const int nl = h->lev[h->L].n;
   NearArgs a = near_args(h);
-  // hat functions: a 3 x 3 block of element entries per stored panel pair
-  const int64_t n_e = (h->hat() ? 9 : 1) * h->n_ent;
-  FAGBI_TRY(h->alloc(h->d_E64, (size_t)n_e * sizeof(double4)));
-  FAGBI_TRY(h->alloc(h->d_E32, (size_t)n_e * sizeof(float4)));
+  // (hat functions: the entries by vertex pairs are allocated by their assembly)
+  if (!h->hat()) {
+    FAGBI_TRY(h->alloc(h->d_E64, (size_t)h->n_ent * sizeof(double4)));
+    FAGBI_TRY(h->alloc(h->d_E32, (size_t)h->n_ent * sizeof(float4)));
+  }
   StageTimer t_cls(h, s, &h->prof.ms_classify);
   // per-leaf class counts, one scan over the flattened [class][leaf] array,
   // then the worklists at the scanned offsets
@@ -515,7 +516,7 @@ int assemble_nearfield(fagbi_handle* h, hipStream_t s) {
       StageTimer t_sing(h, s, &h->prof.ms_singular);
       FAGBI_TRY(hat_assemble(h, s));
     }
-    k_to_f32<<<2048, 256, 0, s>>>(h->d_E64.as<double4>(), h->d_E32.as<float4>(), n_e);
+    k_to_f32<<<2048, 256, 0, s>>>(h->d_E64.as<double4>(), h->d_E32.as<float4>(), h->n_vb_ent);
     FAGBI_HIP(hipGetLastError());
     FAGBI_HIP(hipStreamSynchronize(s));
     h->precond_ready = false;

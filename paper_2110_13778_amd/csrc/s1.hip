@@ -41,6 +41,7 @@
 #include <vector>
 
 #include "near.h"
+#include "scan.h"
 
 namespace fagbi {
 
@@ -337,33 +338,167 @@ __global__ void __launch_bounds__(64) k_hat_singular(NearArgs a, const Item* ite
     }
 }
 
-// element layout of the near field and the far field's rows
+// the far field's element rows: leaf ranges, identity outputs, leaf of each
 __global__ void k_hat_layout(const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ leaf_cnt,
-                             const int64_t* __restrict__ src_off, const int64_t* __restrict__ ent_off,
-                             const int32_t* __restrict__ src_tree, const int32_t* __restrict__ leaf_of, int nl,
-                             int64_t n_src, int64_t N, int32_t* ls3, int32_t* lc3, int64_t* so3, int64_t* eo3,
-                             int32_t* st3, int32_t* iota3, int32_t* lo3) {
-  const int64_t m = max(max((int64_t)nl + 1, 3 * n_src), 3 * N);
+                             const int32_t* __restrict__ leaf_of, int nl, int64_t n_iota, int64_t N, int32_t* ls3,
+                             int32_t* lc3, int32_t* iota, int32_t* lo3) {
+  const int64_t m = max(max((int64_t)nl, n_iota), 3 * N);
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m; g += (int64_t)gridDim.x * blockDim.x) {
-    if (g <= nl) {
-      so3[g] = 3 * src_off[g];
-      eo3[g] = 9 * ent_off[g];
-      if (g < nl) {
-        ls3[g] = 3 * leaf_start[g];
-        lc3[g] = 3 * leaf_cnt[g];
-      }
+    if (g < nl) {
+      ls3[g] = 3 * leaf_start[g];
+      lc3[g] = 3 * leaf_cnt[g];
     }
-    if (g < 3 * n_src) st3[g] = 3 * src_tree[g / 3] + (int32_t)(g % 3);
-    if (g < 3 * N) {
-      iota3[g] = (int32_t)g;
-      lo3[g] = leaf_of[g / 3];
-    }
+    if (g < n_iota) iota[g] = (int32_t)g;
+    if (g < 3 * N) lo3[g] = leaf_of[g / 3];
   }
 }
 
-// y[v] = sum of the rows of the elements of vertex v (both channels)
-__global__ void k_hat_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ el, int64_t nv,
-                             int64_t n3, const double* __restrict__ rows, double* y) {
+// ---------------------------------------------------------------------------
+// Near field by vertex pairs.  For leaf c the corner rows (3 n_c) and the
+// source corners (3 S_c) are sorted by vertex (key = vertex << 20 | local
+// index, bitonic sort in LDS); each run of equal vertices is one row or one
+// column, and the entry of (row r, column k) is the sum over the corners of
+// run r and of run k of the corner entries, in run order.
+// ---------------------------------------------------------------------------
+constexpr int VB_ROWS = 128;       // >= 3 x the largest leaf (leaf_size <= 32)
+constexpr int VB_SHIFT = 20;       // local corner index bits
+
+__device__ inline void bitonic(uint64_t* k, int n) {
+  for (int size = 2; size <= n; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1)), j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint64_t a = k[i], b = k[j];
+        if ((a > b) == up) {
+          k[i] = b;
+          k[j] = a;
+        }
+      }
+    }
+  __syncthreads();
+}
+
+__device__ inline int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// sorted keys of the leaf's corner rows (rk, n_r) and source corners (ck, n_c);
+// run starts (rs, cs: run u at [rs[u], rs[u + 1])) and run counts
+struct VbLeaf {
+  int nr, nc, ur, uc;
+};
+
+__device__ inline VbLeaf vb_sort(const NearArgs& a, int c, uint64_t* rk, uint64_t* ck, int* rs, int* cs, int* cnt) {
+  const int nrow = a.leaf_cnt[c], i0 = a.leaf_start[c];
+  const int64_t so = a.src_off[c];
+  const int S = (int)(a.src_off[c + 1] - so);
+  VbLeaf L{3 * nrow, 3 * S, 0, 0};
+  const int pr = pow2_at_least(L.nr), pc = pow2_at_least(L.nc);
+  for (int t = threadIdx.x; t < pr; t += blockDim.x)
+    rk[t] = t < L.nr ? ((uint64_t)(uint32_t)a.ptri[3 * i0 + t] << VB_SHIFT) | (uint64_t)t : ~0ull;
+  for (int t = threadIdx.x; t < pc; t += blockDim.x)
+    ck[t] = t < L.nc ? ((uint64_t)(uint32_t)a.ptri[3 * a.src_tree[so + t / 3] + t % 3] << VB_SHIFT) | (uint64_t)t
+                     : ~0ull;
+  bitonic(rk, pr);
+  bitonic(ck, pc);
+  // run starts, in order, by one thread per list (a few hundred keys)
+  if (threadIdx.x == 0) {
+    int u = 0;
+    for (int t = 0; t < L.nr; ++t)
+      if (t == 0 || (rk[t] >> VB_SHIFT) != (rk[t - 1] >> VB_SHIFT)) rs[u++] = t;
+    rs[u] = L.nr;
+    cnt[0] = u;
+  } else if (threadIdx.x == 64) {
+    int u = 0;
+    for (int t = 0; t < L.nc; ++t)
+      if (t == 0 || (ck[t] >> VB_SHIFT) != (ck[t - 1] >> VB_SHIFT)) cs[u++] = t;
+    cs[u] = L.nc;
+    cnt[1] = u;
+  }
+  __syncthreads();
+  L.ur = cnt[0];
+  L.uc = cnt[1];
+  return L;
+}
+
+// pass 0: rows, columns and entries per leaf
+__global__ void __launch_bounds__(256) k_vb_count(NearArgs a, int max_pc, int64_t* nrow, int64_t* ncol,
+                                                  int64_t* nent) {
+  extern __shared__ uint64_t lds[];
+  uint64_t* rk = lds;
+  uint64_t* ck = rk + VB_ROWS;
+  int* rs = reinterpret_cast<int*>(ck + max_pc);
+  int* cs = rs + VB_ROWS + 1;
+  int* cnt = cs + max_pc + 1;
+  const int c = blockIdx.x;
+  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs, cnt);
+  if (threadIdx.x == 0) {
+    nrow[c] = L.ur;
+    ncol[c] = L.uc;
+    nent[c] = (int64_t)L.ur * L.uc;
+  }
+}
+
+// pass 1: the lists, and the entries summed from the corner entries E (FP64)
+__global__ void __launch_bounds__(256) k_vb_build(NearArgs a, int max_pc, const double4* __restrict__ E,
+                                                  const int64_t* __restrict__ row_off,
+                                                  const int64_t* __restrict__ col_off,
+                                                  const int64_t* __restrict__ ent_off, int32_t* row_start,
+                                                  int32_t* row_cnt, int32_t* col_elem, int32_t* col_vert,
+                                                  int32_t* row_vert, int32_t* row_leaf, double4* V) {
+  extern __shared__ uint64_t lds[];
+  uint64_t* rk = lds;
+  uint64_t* ck = rk + VB_ROWS;
+  int* rs = reinterpret_cast<int*>(ck + max_pc);
+  int* cs = rs + VB_ROWS + 1;
+  int* cnt = cs + max_pc + 1;
+  const int c = blockIdx.x;
+  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs, cnt);
+  const int64_t so = a.src_off[c];
+  const int S3 = L.nc;
+  const uint64_t mask = (1ull << VB_SHIFT) - 1;
+  const int64_t r0 = row_off[c], c0 = col_off[c], e0 = ent_off[c];
+  if (threadIdx.x == 0) {
+    row_start[c] = (int32_t)r0;
+    row_cnt[c] = L.ur;
+  }
+  for (int u = threadIdx.x; u < L.uc; u += blockDim.x) {
+    const int f = (int)(ck[cs[u]] & mask);
+    col_elem[c0 + u] = 3 * a.src_tree[so + f / 3] + f % 3;
+    col_vert[c0 + u] = (int32_t)(ck[cs[u]] >> VB_SHIFT);
+  }
+  for (int u = threadIdx.x; u < L.ur; u += blockDim.x) {
+    row_vert[r0 + u] = (int32_t)(rk[rs[u]] >> VB_SHIFT);
+    row_leaf[r0 + u] = c;
+  }
+  const double4* Ec = E + 9 * a.ent_off[c];
+  for (int p = threadIdx.x; p < L.ur * L.uc; p += blockDim.x) {
+    const int r = p / L.uc, k = p - r * L.uc;
+    double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int x = rs[r]; x < rs[r + 1]; ++x) {
+      const double4* row = Ec + (int64_t)(rk[x] & mask) * S3;
+      for (int y = cs[k]; y < cs[k + 1]; ++y) {
+        const double4 e = row[ck[y] & mask];
+        acc.x += e.x;
+        acc.y += e.y;
+        acc.z += e.z;
+        acc.w += e.w;
+      }
+    }
+    V[e0 + p] = acc;
+  }
+}
+
+// y[v] = the corner rows of vertex v (far field) plus its near rows (when
+// given), both channels
+__global__ void k_hat_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ el,
+                             const int32_t* __restrict__ poff, const int32_t* __restrict__ pr, int64_t nv,
+                             int64_t n3, int64_t nr, const double* __restrict__ rows,
+                             const double* __restrict__ near_rows, double* y) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   double s1 = 0, s2 = 0;
@@ -372,33 +507,38 @@ __global__ void k_hat_gather(const int32_t* __restrict__ off, const int32_t* __r
     s1 += rows[e];
     s2 += rows[n3 + e];
   }
+  if (near_rows)
+    for (int k = poff[v]; k < poff[v + 1]; ++k) {
+      const int r = pr[k];
+      s1 += near_rows[r];
+      s2 += near_rows[nr + r];
+    }
   y[v] = s1;
   y[nv + v] = s2;
 }
 
-// diagonal of A at vertex v: the stored entries between the elements of v
-__global__ void k_hat_diag(const double4* __restrict__ ent, const int32_t* __restrict__ off,
-                           const int32_t* __restrict__ el, const int32_t* __restrict__ ptri,
-                           const int32_t* __restrict__ leaf_of, const int32_t* __restrict__ leaf_start,
-                           const int64_t* __restrict__ src_off, const int64_t* __restrict__ ent_off,
-                           const int32_t* __restrict__ src_tree, int64_t nv, double* diag) {
+// diagonal of A at vertex v: in each of its near rows, the column of v
+__global__ void k_hat_diag(const double4* __restrict__ V, const int32_t* __restrict__ poff,
+                           const int32_t* __restrict__ pr, const int32_t* __restrict__ row_leaf,
+                           const int32_t* __restrict__ row_start, const int64_t* __restrict__ col_off,
+                           const int64_t* __restrict__ ent_off, const int32_t* __restrict__ col_vert, int64_t nv,
+                           double* diag) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   double d1 = 0, d2 = 0;
-  for (int k = off[v]; k < off[v + 1]; ++k) {
-    const int e = el[k], i = e / 3, a = e - 3 * i;
-    const int c = leaf_of[i];
-    const int r = i - leaf_start[c];
-    const int64_t so = src_off[c];
-    const int S = (int)(src_off[c + 1] - so);
-    const double4* row = ent + 9 * ent_off[c] + (int64_t)(3 * r + a) * (3 * S);
-    for (int col = 0; col < 3 * S; ++col) {
-      const int f = 3 * src_tree[so + col / 3] + col % 3;
-      if (ptri[f] == v) {
-        const double4 x = row[col];
-        d1 += x.x;
-        d2 += x.w;
-      }
+  for (int k = poff[v]; k < poff[v + 1]; ++k) {
+    const int r = pr[k], c = row_leaf[r];
+    const int64_t c0 = col_off[c];
+    const int nc = (int)(col_off[c + 1] - c0);
+    int lo = 0, hi = nc;   // columns ascending by vertex
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (col_vert[c0 + mid] < v) lo = mid + 1; else hi = mid;
+    }
+    if (lo < nc && col_vert[c0 + lo] == v) {
+      const double4 e = V[ent_off[c] + (int64_t)(r - row_start[c]) * nc + lo];
+      d1 += e.x;
+      d2 += e.w;
     }
   }
   diag[v] = d1;
@@ -411,33 +551,54 @@ ElemView hat_view(fagbi_handle* h) {
   v.leaf_start = h->d_s1_leaf_start.as<int32_t>();
   v.leaf_cnt = h->d_s1_leaf_cnt.as<int32_t>();
   v.leaf_of = h->d_s1_leaf_of.as<int32_t>();
-  v.src_tree = h->d_s1_src_tree.as<int32_t>();
-  v.src_off = h->d_s1_src_off.as<int64_t>();
-  v.ent_off = h->d_s1_ent_off.as<int64_t>();
-  v.in_idx = h->d_ptri.as<int32_t>();     // vertex of element e = 3 i + a
+  v.in_idx = h->d_ptri.as<int32_t>();     // vertex of corner e = 3 i + a
   v.out_idx = h->d_s1_iota.as<int32_t>();
   v.in_stride = h->nv;
   v.xt = h->d_xt.as<double>();
   v.y = h->d_ye.as<double>();
-  v.gat_off = h->d_vx_off.as<int32_t>();
-  v.gat_el = h->d_vx_el.as<int32_t>();
-  v.n_out = h->nv;
+  v.n_near = h->n_vb_rows;
+  v.near_start = h->d_vb_row_start.as<int32_t>();
+  v.near_cnt = h->d_vb_row_cnt.as<int32_t>();
+  v.near_src = h->d_vb_col_elem.as<int32_t>();
+  v.near_src_off = h->d_vb_col_off.as<int64_t>();
+  v.near_ent_off = h->d_vb_ent_off.as<int64_t>();
+  v.out_near = h->d_s1_iota.as<int32_t>();
+  v.y_near = h->d_ye.as<double>() + 6 * h->N;
+  v.zero_y = true;
+  v.gather = true;
   return v;
 }
 
-int hat_gather(fagbi_handle* h, const double* rows, double* y, hipStream_t s) {
-  k_hat_gather<<<(unsigned)((h->nv + 255) / 256), 256, 0, s>>>(h->d_vx_off.as<int32_t>(), h->d_vx_el.as<int32_t>(),
-                                                               h->nv, 3 * h->N, rows, y);
+int hat_gather(fagbi_handle* h, const double* rows, const double* near_rows, double* y, hipStream_t s) {
+  k_hat_gather<<<(unsigned)((h->nv + 255) / 256), 256, 0, s>>>(
+      h->d_vx_off.as<int32_t>(), h->d_vx_el.as<int32_t>(), h->d_vx_poff.as<int32_t>(), h->d_vx_pr.as<int32_t>(),
+      h->nv, 3 * h->N, h->n_vb_rows, rows, near_rows, y);
   FAGBI_HIP(hipGetLastError());
   return 0;
 }
 
-// entries of every stored pair (the worklists of the singular and close pairs
-// are built by the classification), the element layout and the vertex lists
+// CSR of the items of each of nv keys, items ascending
+static void key_lists(const std::vector<int32_t>& key, int64_t nv, std::vector<int32_t>& off,
+                      std::vector<int32_t>& el) {
+  off.assign(nv + 1, 0);
+  el.resize(key.size());
+  for (size_t e = 0; e < key.size(); ++e) ++off[key[e] + 1];
+  for (int64_t v = 0; v < nv; ++v) off[v + 1] += off[v];
+  std::vector<int32_t> pos(off.begin(), off.end() - 1);
+  for (size_t e = 0; e < key.size(); ++e) el[pos[key[e]]++] = (int32_t)e;
+}
+
+// corner entries of every stored pair (the worklists of the singular and
+// close pairs are built by the classification) into a temporary array, their
+// sums by vertex pairs into the handle's entries (FP64 and FP32), the element
+// layout and the vertex lists
 int hat_assemble(fagbi_handle* h, hipStream_t s) {
   const int nl = h->lev[h->L].n;
+  const int64_t N = h->N;
   NearArgs a = near_args(h);
-  double4* E = h->d_E64.as<double4>();
+  Tmp Ebuf;
+  FAGBI_TRY(Ebuf.alloc((size_t)9 * h->n_ent * sizeof(double4)));
+  double4* E = Ebuf.as<double4>();
   k_hat_regular<<<nl, 256, 0, s>>>(a, E);
   FAGBI_HIP(hipGetLastError());
   const int n = h->prm.quad_duffy;
@@ -454,44 +615,90 @@ int hat_assemble(fagbi_handle* h, hipStream_t s) {
     }
     FAGBI_HIP(hipGetLastError());
   }
-  // element layout
-  const int64_t N = h->N;
+  // vertex-pair layout: the longest source list sets the sort's LDS
+  std::vector<int64_t> soff(nl + 1);
+  FAGBI_HIP(hipMemcpyAsync(soff.data(), h->d_src_off.p, (nl + 1) * 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  int max_s = 0;
+  for (int c = 0; c < nl; ++c) max_s = std::max<int>(max_s, (int)(soff[c + 1] - soff[c]));
+  int max_pc = 1;
+  while (max_pc < 3 * max_s) max_pc <<= 1;
+  const size_t lds = (size_t)(VB_ROWS + max_pc) * 8 + (size_t)(VB_ROWS + 1 + max_pc + 1 + 2) * 4;
+  if (lds > 150 * 1024)
+    return set_error(FAGBI_E_ARG, "a leaf's source list (%d panels) is too long for the hat-function layout",
+                     max_s);
+  FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vb_count),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vb_build),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  Tmp cnt, off, part;
+  FAGBI_TRY(cnt.alloc((size_t)3 * nl * 8));
+  FAGBI_TRY(off.alloc((size_t)3 * (nl + 1) * 8));
+  FAGBI_TRY(part.alloc((size_t)scan_part_size(nl) * 8));
+  int64_t* c_row = cnt.as<int64_t>();
+  int64_t *o_row = off.as<int64_t>(), *o_col = o_row + (nl + 1), *o_ent = o_col + (nl + 1);
+  k_vb_count<<<nl, 256, lds, s>>>(a, max_pc, c_row, c_row + nl, c_row + 2 * nl);
+  FAGBI_HIP(hipGetLastError());
+  FAGBI_TRY((device_scan<int64_t, int64_t>(c_row, nl, o_row, part.as<int64_t>(), s)));
+  FAGBI_TRY((device_scan<int64_t, int64_t>(c_row + nl, nl, o_col, part.as<int64_t>(), s)));
+  FAGBI_TRY((device_scan<int64_t, int64_t>(c_row + 2 * nl, nl, o_ent, part.as<int64_t>(), s)));
+  int64_t tot[3];
+  FAGBI_HIP(hipMemcpyAsync(&tot[0], o_row + nl, 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipMemcpyAsync(&tot[1], o_col + nl, 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipMemcpyAsync(&tot[2], o_ent + nl, 8, hipMemcpyDeviceToHost, s));
+  FAGBI_HIP(hipStreamSynchronize(s));
+  h->n_vb_rows = tot[0];
+  h->n_vb_ent = tot[2];
+  FAGBI_TRY(h->alloc(h->d_vb_row_start, (size_t)nl * 4));
+  FAGBI_TRY(h->alloc(h->d_vb_row_cnt, (size_t)nl * 4));
+  FAGBI_TRY(h->alloc(h->d_vb_col_off, (size_t)(nl + 1) * 8));
+  FAGBI_TRY(h->alloc(h->d_vb_ent_off, (size_t)(nl + 1) * 8));
+  FAGBI_TRY(h->alloc(h->d_vb_col_elem, (size_t)std::max<int64_t>(1, tot[1]) * 4));
+  FAGBI_TRY(h->alloc(h->d_vb_col_vert, (size_t)std::max<int64_t>(1, tot[1]) * 4));
+  FAGBI_TRY(h->alloc(h->d_vb_row_vert, (size_t)std::max<int64_t>(1, tot[0]) * 4));
+  FAGBI_TRY(h->alloc(h->d_vb_row_leaf, (size_t)std::max<int64_t>(1, tot[0]) * 4));
+  FAGBI_TRY(h->alloc(h->d_E64, (size_t)std::max<int64_t>(1, tot[2]) * sizeof(double4)));
+  FAGBI_TRY(h->alloc(h->d_E32, (size_t)std::max<int64_t>(1, tot[2]) * sizeof(float4)));
+  FAGBI_HIP(hipMemcpyAsync(h->d_vb_col_off.p, o_col, (nl + 1) * 8, hipMemcpyDeviceToDevice, s));
+  FAGBI_HIP(hipMemcpyAsync(h->d_vb_ent_off.p, o_ent, (nl + 1) * 8, hipMemcpyDeviceToDevice, s));
+  k_vb_build<<<nl, 256, lds, s>>>(a, max_pc, E, o_row, o_col, o_ent, h->d_vb_row_start.as<int32_t>(),
+                                  h->d_vb_row_cnt.as<int32_t>(), h->d_vb_col_elem.as<int32_t>(),
+                                  h->d_vb_col_vert.as<int32_t>(), h->d_vb_row_vert.as<int32_t>(),
+                                  h->d_vb_row_leaf.as<int32_t>(), h->d_E64.as<double4>());
+  FAGBI_HIP(hipGetLastError());
+  // the far field's element rows
+  const int64_t n_iota = std::max<int64_t>(3 * N, tot[0]);
   FAGBI_TRY(h->alloc(h->d_s1_leaf_start, (size_t)nl * 4));
   FAGBI_TRY(h->alloc(h->d_s1_leaf_cnt, (size_t)nl * 4));
-  FAGBI_TRY(h->alloc(h->d_s1_src_off, (size_t)(nl + 1) * 8));
-  FAGBI_TRY(h->alloc(h->d_s1_ent_off, (size_t)(nl + 1) * 8));
-  FAGBI_TRY(h->alloc(h->d_s1_src_tree, (size_t)3 * h->n_src * 4));
-  FAGBI_TRY(h->alloc(h->d_s1_iota, (size_t)3 * N * 4));
+  FAGBI_TRY(h->alloc(h->d_s1_iota, (size_t)n_iota * 4));
   FAGBI_TRY(h->alloc(h->d_s1_leaf_of, (size_t)3 * N * 4));
-  FAGBI_TRY(h->alloc(h->d_ye, (size_t)6 * N * 8));
+  FAGBI_TRY(h->alloc(h->d_ye, (size_t)(6 * N + 2 * tot[0]) * 8));
   k_hat_layout<<<1024, 256, 0, s>>>(h->d_leaf_start.as<int32_t>(), h->d_leaf_cnt.as<int32_t>(),
-                                    h->d_src_off.as<int64_t>(), h->d_ent_off.as<int64_t>(),
-                                    h->d_src_tree.as<int32_t>(), h->d_leaf_of.as<int32_t>(), nl, h->n_src, N,
-                                    h->d_s1_leaf_start.as<int32_t>(), h->d_s1_leaf_cnt.as<int32_t>(),
-                                    h->d_s1_src_off.as<int64_t>(), h->d_s1_ent_off.as<int64_t>(),
-                                    h->d_s1_src_tree.as<int32_t>(), h->d_s1_iota.as<int32_t>(),
+                                    h->d_leaf_of.as<int32_t>(), nl, n_iota, N, h->d_s1_leaf_start.as<int32_t>(),
+                                    h->d_s1_leaf_cnt.as<int32_t>(), h->d_s1_iota.as<int32_t>(),
                                     h->d_s1_leaf_of.as<int32_t>());
   FAGBI_HIP(hipGetLastError());
-  // elements of each vertex, ascending (counting sort on the host)
-  std::vector<int32_t> ev(3 * N);
+  // corners and near rows of each vertex, ascending (counting sorts on the host)
+  std::vector<int32_t> ev(3 * N), rv(tot[0]);
   FAGBI_HIP(hipMemcpyAsync(ev.data(), h->d_ptri.p, 3 * N * 4, hipMemcpyDeviceToHost, s));
+  if (tot[0] > 0) FAGBI_HIP(hipMemcpyAsync(rv.data(), h->d_vb_row_vert.p, tot[0] * 4, hipMemcpyDeviceToHost, s));
   FAGBI_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> off(h->nv + 1, 0), el(3 * N);
-  for (int64_t e = 0; e < 3 * N; ++e) ++off[ev[e] + 1];
-  for (int64_t v = 0; v < h->nv; ++v) off[v + 1] += off[v];
-  std::vector<int32_t> pos(off.begin(), off.end() - 1);
-  for (int64_t e = 0; e < 3 * N; ++e) el[pos[ev[e]]++] = (int32_t)e;
-  FAGBI_TRY(h->upload(h->d_vx_off, off.data(), off.size() * 4));
-  FAGBI_TRY(h->upload(h->d_vx_el, el.data(), el.size() * 4));
+  std::vector<int32_t> voff, vel, poff, pel;
+  key_lists(ev, h->nv, voff, vel);
+  key_lists(rv, h->nv, poff, pel);
+  FAGBI_TRY(h->upload(h->d_vx_off, voff.data(), voff.size() * 4));
+  FAGBI_TRY(h->upload(h->d_vx_el, vel.data(), vel.size() * 4));
+  FAGBI_TRY(h->upload(h->d_vx_poff, poff.data(), poff.size() * 4));
+  FAGBI_TRY(h->upload(h->d_vx_pr, pel.data(), std::max<size_t>(1, pel.size()) * 4));
   return 0;
 }
 
 int hat_diag_setup(fagbi_handle* h, hipStream_t s) {
   FAGBI_TRY(h->alloc(h->d_diag, 2 * h->nv * sizeof(double)));
   k_hat_diag<<<(unsigned)((h->nv + 255) / 256), 256, 0, s>>>(
-      h->d_E64.as<double4>(), h->d_vx_off.as<int32_t>(), h->d_vx_el.as<int32_t>(), h->d_ptri.as<int32_t>(),
-      h->d_leaf_of.as<int32_t>(), h->d_leaf_start.as<int32_t>(), h->d_src_off.as<int64_t>(),
-      h->d_ent_off.as<int64_t>(), h->d_src_tree.as<int32_t>(), h->nv, h->d_diag.as<double>());
+      h->d_E64.as<double4>(), h->d_vx_poff.as<int32_t>(), h->d_vx_pr.as<int32_t>(), h->d_vb_row_leaf.as<int32_t>(),
+      h->d_vb_row_start.as<int32_t>(), h->d_vb_col_off.as<int64_t>(), h->d_vb_ent_off.as<int64_t>(),
+      h->d_vb_col_vert.as<int32_t>(), h->nv, h->d_diag.as<double>());
   FAGBI_HIP(hipGetLastError());
   return 0;
 }

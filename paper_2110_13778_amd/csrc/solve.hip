@@ -274,7 +274,7 @@ int rhs(fagbi_handle* h, const double* xq, const double* q, int64_t nc, double* 
                                                                chg.as<double4>(), (int)nc, 1.0 / h->prm.eps_in,
                                                                rows);
     FAGBI_HIP(hipGetLastError());
-    FAGBI_TRY(hat_gather(h, rows, b, s));
+    FAGBI_TRY(hat_gather(h, rows, nullptr, b, s));
   } else {
     k_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_pv.as<double>(), h->d_pn.as<double>(),
                                                           h->d_pa.as<double>(), h->d_perm.as<int32_t>(), (int)h->N,
