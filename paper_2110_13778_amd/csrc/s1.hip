@@ -32,6 +32,9 @@
 //           the product, a quadratic in x1, by 2-point Gauss-Legendre.
 //  VERTEX:  Duffy on each triangle and the collapsed square, 2 n^4 points.
 //  CLOSE:   Duffy n x n on each triangle, n^4 points.
+//  In both the innermost coordinate moves the source point along a line with
+//  the target point fixed, so each lane sums lambda_b k over it first (18
+//  sums) and multiplies by lambda_a once per line.
 // Reference coordinates chi(x) = u + x1 (v - u) + x2 (w - v) on
 // {0 <= x2 <= x1 <= 1}: lambda_u = 1 - x1, lambda_v = x1 - x2, lambda_w = x2.
 // One wavefront per singular or close pair, fixed-order reductions: FP64
@@ -265,37 +268,86 @@ __global__ void __launch_bounds__(64) k_hat_singular(NearArgs a, const Item* ite
       B0[d] = cj[3 * oj[1] + d] - S;
       B1[d] = cj[3 * oj[2] + d] - cj[3 * oj[1] + d];
     }
-    for (int p = lane; p < 2 * n4; p += 64) {
-      const int half = p / n4, rem = p - half * n4;
-      const int ia = rem / n3, ib = (rem / n2) % n, ic = (rem / n) % n, id = rem % n;
-      const double xi = gx[ia], eta = gx[ib], t1 = gx[ic], t2 = gx[id];
-      const double w = gw[ia] * gw[ib] * gw[ic] * gw[id] * xi * xi * xi * eta;
+    // lanes over (half, xi, eta, t1); the innermost t2 moves the source point
+    // linearly (r = R0 + t2 R1) with the target's barycentrics fixed: its
+    // products with lambda_b are summed over t2 first
+    const double nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
+    for (int p = lane; p < 2 * n3; p += 64) {
+      const int half = p / n3, rem = p - half * n3;
+      const int ia = rem / n2, ib = (rem / n) % n, ic = rem % n;
+      const double xi = gx[ia], eta = gx[ib], t1 = gx[ic];
+      const double wb = gw[ia] * gw[ib] * gw[ic] * xi * xi * xi * eta;
       const double x1 = half == 0 ? xi : xi * eta;
       const double y1 = half == 0 ? xi * eta : xi;
-      double r[3];
-      for (int d = 0; d < 3; ++d) r[d] = x1 * (A0[d] + t1 * A1[d]) - y1 * (B0[d] + t2 * B1[d]);
-      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
+      double R0[3], R1[3];
+      for (int d = 0; d < 3; ++d) {
+        R0[d] = x1 * (A0[d] + t1 * A1[d]) - y1 * B0[d];
+        R1[d] = -y1 * B1[d];
+      }
+      const LinSep L = lin_sep(R0, R1, ni, nj);
+      double sb[3][6];
+#pragma unroll
+      for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) sb[y][m] = 0.0;
+      for (int id = 0; id < n; ++id) {
+        const double t2 = gx[id], w = wb * gw[id];
+        kernel6s(fma(t2, fma(t2, L.c, L.b), L.a), fma(t2, L.p1, L.p0), fma(t2, L.q1, L.q0), nn, a.kappa, k6);
+        bary(y1, y1 * t2, lb);
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+          const double wy = w * lb[y];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) sb[y][m] += wy * k6[m];
+        }
+      }
       bary(x1, x1 * t1, la);
-      bary(y1, y1 * t2, lb);
-      add_outer<0, 6>(acc, w, la, lb, k6);
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+          for (int m = 0; m < 6; ++m) acc[x][y][m] += la[x] * sb[y][m];
     }
     scale = 4.0 * a.pa[i] * a.pa[j];
   } else {  // CLOSE
     const double wij = 4.0 * a.pa[i] * a.pa[j];
-    for (int p = lane; p < n4; p += 64) {
-      const int ia = p / n3, ib = (p / n2) % n, ic = (p / n) % n, id = p % n;
-      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic], t2 = gx[id];
-      const double w = wij * gw[ia] * gw[ib] * s1 * gw[ic] * gw[id] * s2;
-      double r[3];
+    const double nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
+    // lanes over (s1, t1, s2), the innermost t2 as in the vertex rule
+    for (int p = lane; p < n3; p += 64) {
+      const int ia = p / n2, ib = (p / n) % n, ic = p % n;
+      const double s1 = gx[ia], t1 = gx[ib], s2 = gx[ic];
+      const double wb = wij * gw[ia] * gw[ib] * s1 * gw[ic] * s2;
+      double R0[3], R1[3];
       for (int d = 0; d < 3; ++d) {
         const double x = ci[d] + s1 * (ci[3 + d] - ci[d]) + s1 * t1 * (ci[6 + d] - ci[3 + d]);
-        const double y = cj[d] + s2 * (cj[3 + d] - cj[d]) + s2 * t2 * (cj[6 + d] - cj[3 + d]);
-        r[d] = x - y;
+        R0[d] = x - (cj[d] + s2 * (cj[3 + d] - cj[d]));
+        R1[d] = -s2 * (cj[6 + d] - cj[3 + d]);
       }
-      kernel6(r[0], r[1], r[2], ni, nj, a.kappa, k6);
+      const LinSep L = lin_sep(R0, R1, ni, nj);
+      double sb[3][6];
+#pragma unroll
+      for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) sb[y][m] = 0.0;
+      for (int id = 0; id < n; ++id) {
+        const double t2 = gx[id], w = wb * gw[id];
+        kernel6s(fma(t2, fma(t2, L.c, L.b), L.a), fma(t2, L.p1, L.p0), fma(t2, L.q1, L.q0), nn, a.kappa, k6);
+        bary(s2, s2 * t2, lb);
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+          const double wy = w * lb[y];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) sb[y][m] += wy * k6[m];
+        }
+      }
       bary(s1, s1 * t1, la);
-      bary(s2, s2 * t2, lb);
-      add_outer<0, 6>(acc, w, la, lb, k6);
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+          for (int m = 0; m < 6; ++m) acc[x][y][m] += la[x] * sb[y][m];
     }
   }
 #pragma unroll
