@@ -66,6 +66,8 @@ def parse():
                          "near-singular pair of both)")
     ap.add_argument("--no-hat", action="store_true",
                     help="skip the continuous piecewise-linear (hat-function) leg on the main workload")
+    ap.add_argument("--hat-only", action="store_true",
+                    help="run only the hat-function leg (for per-kernel profiles of that path) and print it")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -142,7 +144,8 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
                                      "fp64": V / (out["fp64"]["matvec_ms"] * 1e-3) / 1e6}
     E64, Em = out["fp64"]["E"], out["mixed"]["E"]
     out["energy_kcal"] = {"mixed": Em, "fp64": E64, "mixed_vs_fp64": abs(Em - E64) / abs(E64),
-                          "box_fp64_direct_sums": E_box_ref, "hat_vs_box": abs(E64 - E_box_ref) / abs(E_box_ref)}
+                          "box_fp64_direct_sums": E_box_ref,
+                          "hat_vs_box": None if E_box_ref is None else abs(E64 - E_box_ref) / abs(E_box_ref)}
     return out
 
 
@@ -388,6 +391,9 @@ def main():
     dev = "cuda:0"
 
     log("workload %s: %d panels, %d charges" % (args.workload, N, len(w["q"])))
+    if args.hat_only:
+        print(json.dumps({"workload": args.workload, "hat_basis": hat_leg(F, torch, w, dev, None)}))
+        return
     blob, mlp_info = train_surrogate(F, torch, args.mlp_pairs, args.mlp_epochs)
     log("surrogate trained on %d pairs in %.1f s" % (mlp_info["pairs"], mlp_info["train_s"]))
 
