@@ -87,14 +87,17 @@ def log(msg):
 def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
     """The continuous piecewise-linear basis (hat functions at the vertices) on
     the same workload and tree: FP32-inner flexible GMRES and FP64 GMRES with
-    the Jacobi preconditioner, the direct right-hand side and energy sums.
-    Median of `runs` whole solves per precision (build, assembly, solve,
-    energy), with the per-matvec phase times of the median run."""
+    the Jacobi preconditioner, right-hand side and energy by the treecodes as
+    in the box-function step.  Median of `runs` whole solves per precision
+    (build, assembly, solve, energy), with the per-matvec phase times of the
+    median run; the energy of the last FP64 solve also by the direct sum."""
     N, V = len(w["tris"]), len(w["verts"])
-    prm = dict(PARAMS, precond=F.PRECOND_DIAG, rhs_theta=0.0, max_iter=300)
+    prm = dict(PARAMS, precond=F.PRECOND_DIAG, max_iter=300)
     out = {"panels": N, "vertices": V, "precond": "Jacobi (the diagonal of A)",
-           "rhs_and_energy": "direct sums over charges and the 3-point rule's points"}
+           "rhs_and_energy": "treecodes, theta %.2f / %.2f, order cap %d / %d" % (
+               PARAMS["rhs_theta"], ENERGY_THETA, PARAMS["rhs_pmax"], ENERGY_PMAX)}
     near_pairs = hat_rows = hat_entries = 0
+    E_direct = None
     for tag, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
         sts = []
         p = 1 if prec == F.MIXED else 0
@@ -111,8 +114,10 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
             x = torch.zeros(2 * V, dtype=torch.float64, device=dev)
             code, info = h.solve(w["xq"], w["q"], x)
             t3 = time.perf_counter()
-            E = h.solvation_energy(x, w["xq"], w["q"])
+            E = h.solvation_energy_treecode(x, w["xq"], w["q"], ENERGY_THETA, p_max=ENERGY_PMAX)
             t4 = time.perf_counter()
+            if prec == F.FP64:
+                E_direct = h.solvation_energy(x, w["xq"], w["q"])
             pr = h.profile()
             ti = h.tree_info()
             near_pairs, hat_rows, hat_entries = ti.near_pairs, ti.hat_rows, ti.hat_entries
@@ -144,8 +149,9 @@ def hat_leg(F, torch, w, dev, E_box_ref, runs=3):
                                      "fp64": V / (out["fp64"]["matvec_ms"] * 1e-3) / 1e6}
     E64, Em = out["fp64"]["E"], out["mixed"]["E"]
     out["energy_kcal"] = {"mixed": Em, "fp64": E64, "mixed_vs_fp64": abs(Em - E64) / abs(E64),
+                          "fp64_direct_sum": E_direct, "treecode_vs_direct": abs(E64 - E_direct) / abs(E_direct),
                           "box_fp64_direct_sums": E_box_ref,
-                          "hat_vs_box": None if E_box_ref is None else abs(E64 - E_box_ref) / abs(E_box_ref)}
+                          "hat_vs_box": None if E_box_ref is None else abs(E_direct - E_box_ref) / abs(E_box_ref)}
     return out
 
 

@@ -103,9 +103,9 @@ typedef struct fagbi_params {
   int32_t rhs_pmax;            /* its order cap: terms |a| <= min(p_l, rhs_pmax) */
   int32_t radii;               /* FAGBI_RADII_LEVEL (default) or FAGBI_RADII_CLUSTER */
   /* FAGBI_BASIS_S0 (default) or FAGBI_BASIS_S1.  S1 needs every vertex to
-     belong to a triangle, mlp_mode FAGBI_MLP_OFF, precond FAGBI_PRECOND_NONE
-     or FAGBI_PRECOND_DIAG and rhs_theta 0; the treecode and allocation-free
-     entry points are not available with it (FAGBI_E_ARG). */
+     belong to a triangle, mlp_mode FAGBI_MLP_OFF and precond
+     FAGBI_PRECOND_NONE or FAGBI_PRECOND_DIAG; the allocation-free energy is
+     not available with it (FAGBI_E_ARG). */
   int32_t basis;
 } fagbi_params;
 
@@ -268,8 +268,10 @@ int fagbi_solvation_energy_noalloc(fagbi_handle* h, const double* x, const doubl
    p_max >= 8 evaluates the full orders), a leaf that
    fails receives the direct 3-point sums; the far field's LtL then takes the
    local expansions to the leaves and LtP tests them with each panel's single-
-   and double-layer moments.  theta in [0, 1) (theta = 0: the direct sum).  xq: host f64[nc][3]; q:
-   host f64[nc]; b: device f64[2N] (caller order), overwritten.  Requires
+   and double-layer moments (FAGBI_BASIS_S1: the leaf sums and LtP per panel
+   corner with lambda_a, summed into the vertices).  theta in [0, 1) (theta =
+   0: the direct sum).  xq: host f64[nc][3]; q:
+   host f64[nc]; b: device f64[2n] (caller order), overwritten.  Requires
    fagbi_assemble_nearfield.  The expansions are accumulated with device
    atomics: results agree between runs to rounding, not bit for bit.  Uses
    the far field's local-expansion buffers (not concurrently with a matvec of
@@ -285,10 +287,11 @@ int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q,
    with rho_l / R <= theta (rho_l the level's cluster radius, R the distance
    of the charge from the cube centre); clusters failing the criterion pass
    it to their children, from level min(l_min, L) down; leaves failing it are
-   summed directly as in fagbi_solvation_energy.  All charges advance level
-   by level together (one list of (charge, cluster) pairs per level).
-   theta in [0, 1); theta = 0 gives the direct sum.
-   x: device f64[2N] (caller order); xq: host f64[nc][3]; q: host f64[nc].
+   summed directly as in fagbi_solvation_energy (FAGBI_BASIS_S1: the moments
+   from the corner moments, the leaf sums with the nodal values interpolated).
+   All charges advance level by level together (one list of (charge, cluster)
+   pairs per level).  theta in [0, 1); theta = 0 gives the direct sum.
+   x: device f64[2n] (caller order); xq: host f64[nc][3]; q: host f64[nc].
    Requires fagbi_assemble_nearfield (the far-field tables); orders above 8
    are rejected.  FAGBI_E_ARG when a level would hold more than 2^26
    (charge, cluster) pairs (theta too small for the tree and the charges).

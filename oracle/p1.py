@@ -559,3 +559,129 @@ def energy(P, x, xq, q, eps, kappa):
         k2 = (eps * E * (1.0 + uu) - 1.0) * rny / (FOUR_PI * rr ** 3)
         total += q[n] * (P.qw * (k1 * dphi + k2 * phi)).sum()
     return 0.5 * UNIT_KCAL * total
+
+
+# ---------------------------------------------------------------------------
+# The Cartesian treecode (Sec. 2.5) with hat functions: the visit of
+# ``treecode`` with the moments of the hat-function far field (corner moments,
+# MtM) and, at leaves that fail the criterion, the direct sums with the nodal
+# values interpolated at the 3-point rule's points (energy), or the per-point
+# source terms distributed to the panel's corners with lambda_a (RHS; the far
+# part by LtL and LtP with the corner moments).
+# ---------------------------------------------------------------------------
+def _hat_moments(F, u, v):
+    P, tree, eps = F.P, F.tree, F.eps
+    tri = P.tris[tree.perm]
+    a, b = u[tri], v[tri]
+    c0 = np.einsum("pat,pa->pt", F.ms3, b) - np.einsum("pat,pa->pt", F.md3, a)
+    ck = -np.einsum("pat,pa->pt", F.ms3, b) + eps * np.einsum("pat,pa->pt", F.md3, a)
+    leaf = tree.levels[tree.L]
+    M0L = np.zeros((leaf.n, F.ms3.shape[2]))
+    MkL = np.zeros((leaf.n, F.ms3.shape[2]))
+    np.add.at(M0L, F.owner, c0)
+    np.add.at(MkL, F.owner, ck)
+    return fmm.upward_pass(F, M0L, MkL)
+
+
+def treecode_energy(F, x, xq, q, theta, p_max=None):
+    """E_sol (kcal/mol) by the treecode with hat functions (theta = 0: the
+    direct sum of ``energy``)."""
+    from .treecode import _far
+    from . import taylor
+    P, tree, eps, kappa, pl = F.P, F.tree, F.eps, F.kappa, F.orders
+    V = F.V
+    u, v = x[:V], x[V:]
+    M0, Mk = _hat_moments(F, u, v)
+    phi = np.einsum("ka,pa->pk", LAM, u[P.tris])          # [N, 3 points]
+    dphi = np.einsum("ka,pa->pk", LAM, v[P.tris])
+    L, levels, perm = tree.L, tree.levels, tree.perm
+    l0 = min(tree.lmin, L)
+    xq = np.atleast_2d(np.asarray(xq, np.float64))
+    Vn = np.zeros(len(xq))
+    th2 = theta * theta
+    for n in range(len(xq)):
+        xn = xq[n]
+        front = np.arange(levels[l0].n)
+        for l in range(l0, L + 1):
+            if len(front) == 0:
+                break
+            cl = levels[l]
+            d = xn[None, :] - cl.center[front]
+            R2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+            acc = cl.rho * cl.rho <= th2 * R2
+            if acc.any():
+                a = front[acc]
+                p = pl[l] if p_max is None else min(pl[l], p_max)
+                T = len(taylor.multi_indices(p))
+                Vn[n] += _far(d[acc], M0[l][a][:, :T], Mk[l][a][:, :T], kappa, p).sum()
+            rest = front[~acc]
+            if l < L:
+                front = np.concatenate([np.arange(cl.child_start[c], cl.child_end[c]) for c in rest]) \
+                    if len(rest) else rest
+            else:
+                for c in rest:
+                    ids = perm[cl.start[c]:cl.end[c]]
+                    r = xn[None, None, :] - P.qp[ids]
+                    rr = np.sqrt((r * r).sum(-1))
+                    uu = kappa * rr
+                    em1 = np.expm1(-uu)
+                    E = em1 + 1.0
+                    rny = (r * P.normal[ids][:, None, :]).sum(-1)
+                    k1 = -em1 / (FOUR_PI * rr)
+                    k2 = (eps * E * (1.0 + uu) - 1.0) * rny / (FOUR_PI * rr ** 3)
+                    Vn[n] += float((P.qw[ids] * (k1 * dphi[ids] + k2 * phi[ids])).sum())
+    return 0.5 * UNIT_KCAL * float(np.dot(np.asarray(q, np.float64), Vn))
+
+
+def treecode_rhs(F, xq, q, theta, eps_in, p_max=None):
+    """b = [b1; b2] (vertex order) by the reverse treecode with hat functions
+    (theta = 0: the direct sum of ``rhs``)."""
+    from . import taylor
+    P, tree, pl = F.P, F.tree, F.orders
+    N, V = P.n, F.V
+    L, levels, perm = tree.L, tree.levels, tree.perm
+    l0 = min(tree.lmin, L)
+    xq = np.atleast_2d(np.asarray(xq, np.float64))
+    q = np.asarray(q, np.float64)
+    lam = {l: np.zeros((levels[l].n, len(taylor.multi_indices(pl[l])))) for l in range(l0, L + 1)}
+    c1 = np.zeros((N, 3))          # per panel corner (caller order)
+    c2 = np.zeros((N, 3))
+    th2 = theta * theta
+    for n in range(len(xq)):
+        xn = xq[n]
+        front = np.arange(levels[l0].n)
+        for l in range(l0, L + 1):
+            if len(front) == 0:
+                break
+            cl = levels[l]
+            d = xn[None, :] - cl.center[front]
+            R2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+            acc = cl.rho * cl.rho <= th2 * R2
+            if acc.any():
+                a = front[acc]
+                p = pl[l] if p_max is None else min(pl[l], p_max)
+                Fc = taylor.coefficients(-d[acc], 0.0, p)
+                for t, k in enumerate(taylor.multi_indices(p)):
+                    lam[l][a, t] += q[n] * Fc[k] / FOUR_PI
+            rest = front[~acc]
+            if l < L:
+                front = np.concatenate([np.arange(cl.child_start[c], cl.child_end[c]) for c in rest]) \
+                    if len(rest) else rest
+            else:
+                for c in rest:
+                    ids = perm[cl.start[c]:cl.end[c]]
+                    r = P.qp[ids] - xn[None, None, :]
+                    rr = np.sqrt((r * r).sum(-1))
+                    g0 = 1.0 / (FOUR_PI * rr)
+                    dg0 = -(r * P.normal[ids][:, None, :]).sum(-1) / (FOUR_PI * rr ** 3)
+                    c1[ids] += q[n] * np.einsum("pk,ka->pa", P.qw[ids] * g0, LAM)
+                    c2[ids] += q[n] * np.einsum("pk,ka->pa", P.qw[ids] * dg0, LAM)
+    fmm.downward(F, lam, l0)
+    f = lam[L][F.owner]                                             # tree order
+    c1[perm] += np.einsum("pt,pat->pa", f, F.ms3)
+    c2[perm] += np.einsum("pt,pat->pa", f, F.md3)
+    b1 = np.zeros(V)
+    b2 = np.zeros(V)
+    np.add.at(b1, P.tris, c1)
+    np.add.at(b2, P.tris, c2)
+    return np.concatenate([b1, b2]) / eps_in

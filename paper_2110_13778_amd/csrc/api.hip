@@ -385,7 +385,6 @@ static int check_params(const fagbi_params* p) {
     if (p->mlp_mode != FAGBI_MLP_OFF) return set_error(FAGBI_E_ARG, "the hat-function basis needs mlp_mode OFF");
     if (p->precond != FAGBI_PRECOND_NONE && p->precond != FAGBI_PRECOND_DIAG)
       return set_error(FAGBI_E_ARG, "the hat-function basis takes precond NONE or DIAG");
-    if (p->rhs_theta != 0.0) return set_error(FAGBI_E_ARG, "the hat-function basis takes rhs_theta 0");
   }
   return 0;
 }
@@ -522,7 +521,6 @@ int fagbi_rhs_treecode(fagbi_handle* h, const double* xq, const double* q, int64
   if (!h || !xq || !q || !b || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
   if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
-  if (h->hat()) return set_error(FAGBI_E_ARG, "not available with the hat-function basis");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode right-hand side before assemble_nearfield");
   return fagbi::rhs_treecode(h, xq, q, nc, theta, p_max, b, (hipStream_t)stream);
 }
@@ -532,7 +530,6 @@ int fagbi_solvation_energy_treecode(fagbi_handle* h, const double* x, const doub
   if (!h || !x || !xq || !q || !E_kcal || nc < 1) return set_error(FAGBI_E_ARG, "bad argument");
   if (!(theta >= 0.0 && theta < 1.0)) return set_error(FAGBI_E_ARG, "theta outside [0, 1)");
   if (p_max < 0) return set_error(FAGBI_E_ARG, "p_max must be >= 0");
-  if (h->hat()) return set_error(FAGBI_E_ARG, "not available with the hat-function basis");
   if (!h->near_ready) return set_error(FAGBI_E_STATE, "treecode energy before assemble_nearfield");
   return fagbi::energy_treecode(h, x, xq, q, nc, theta, p_max, E_kcal, (hipStream_t)stream);
 }

@@ -2393,7 +2393,7 @@ __global__ void __launch_bounds__(256) k_tc_classify(TcLevels lv, int l, int L, 
                                                      const int32_t* __restrict__ leaf_start,
                                                      const int32_t* __restrict__ leaf_cnt, int64_t N,
                                                      const double* __restrict__ x, double* V, double* b, int32_t* acc,
-                                                     int32_t* nch) {
+                                                     int32_t* nch, const int32_t* __restrict__ ptri, int64_t nv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   const int n = pn[i], c = pc[i];
@@ -2405,7 +2405,10 @@ __global__ void __launch_bounds__(256) k_tc_classify(TcLevels lv, int l, int L, 
   acc[i] = a;
   nch[i] = (!a && l < L) ? lv.ce[l][c] - lv.cs[l][c] : 0;
   if (a || l < L) return;
-  // direct sum over the leaf's panels (tree order)
+  // direct sum over the leaf's panels (tree order).  Hat functions (ptri set):
+  // the values at the rule's points interpolate the nodal values of the
+  // panel's vertices (x: channel stride nv), and the source terms go to the
+  // panel's corners e = 3 i + a with lambda_a (b: corner rows, stride 3N)
   const int i0 = leaf_start[c], i1 = i0 + leaf_cnt[c];
   double v = 0;
   for (int ii = i0; ii < i1; ++ii) {
@@ -2416,18 +2419,58 @@ __global__ void __launch_bounds__(256) k_tc_classify(TcLevels lv, int l, int L, 
     const double w = pa[ii] / 3.0;
     if (RHS) {
       // b1 += qs sum_q w / r, b2 += -qs sum_q w (y_q - x_n) . n / r^3
-      double a1 = 0, a2 = 0;
+      double a1 = 0, a2 = 0, g1[3], g2[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const double rx = qp[3 * q] - xq.x, ry = qp[3 * q + 1] - xq.y, rz = qp[3 * q + 2] - xq.z;
         const double ir = inv_sqrt(rx * rx + ry * ry + rz * rz);
-        a1 += ir;
-        a2 -= (rx * nx + ry * ny + rz * nz) * (ir * ir * ir);
+        g1[q] = ir;
+        g2[q] = -(rx * nx + ry * ny + rz * nz) * (ir * ir * ir);
+        a1 += g1[q];
+        a2 += g2[q];
       }
-      unsafeAtomicAdd(b + p, xq.w * w * a1);
-      unsafeAtomicAdd(b + N + p, xq.w * w * a2);
+      if (ptri) {
+        const int64_t N3 = 3 * N;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double c1 = 0, c2 = 0;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const double l = q == k ? 2.0 / 3.0 : 1.0 / 6.0;
+            c1 += l * g1[q];
+            c2 += l * g2[q];
+          }
+          unsafeAtomicAdd(b + 3 * (int64_t)ii + k, xq.w * w * c1);
+          unsafeAtomicAdd(b + N3 + 3 * (int64_t)ii + k, xq.w * w * c2);
+        }
+      } else {
+        unsafeAtomicAdd(b + p, xq.w * w * a1);
+        unsafeAtomicAdd(b + N + p, xq.w * w * a2);
+      }
     } else {
-      const double ph = x[p], dph = x[N + p];
+      double ph[3], dph[3];
+      if (ptri) {
+        double hu[3], hv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int64_t vx = ptri[3 * (int64_t)ii + k];
+          hu[k] = x[vx];
+          hv[k] = x[nv + vx];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          ph[q] = dph[q] = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double l = q == k ? 2.0 / 3.0 : 1.0 / 6.0;
+            ph[q] += l * hu[k];
+            dph[q] += l * hv[k];
+          }
+        }
+      } else {
+        ph[0] = ph[1] = ph[2] = x[p];
+        dph[0] = dph[1] = dph[2] = x[N + p];
+      }
       double s = 0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -2438,7 +2481,7 @@ __global__ void __launch_bounds__(256) k_tc_classify(TcLevels lv, int l, int L, 
         double E, em1;
         exp_expm1(-u, E, em1);
         const double rny = rx * nx + ry * ny + rz * nz;
-        s += ir * (-em1 * dph + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph);
+        s += ir * (-em1 * dph[q] + (eps * E * (1.0 + u) - 1.0) * rny * (ir * ir) * ph[q]);
       }
       v += w * s;
     }
@@ -2630,7 +2673,8 @@ static int tc_visit(fagbi_handle* h, const TcLevels& lv, int l0, const double* c
     k_tc_classify<RHS><<<gm, 256, 0, s>>>(lv, l, L, theta * theta, kappa, eps, corner, q4, M, pn, pc,
                                           h->d_pv.as<double>(), h->d_pn.as<double>(), h->d_pa.as<double>(),
                                           h->d_perm.as<int32_t>(), h->d_leaf_start.as<int32_t>(),
-                                          h->d_leaf_cnt.as<int32_t>(), h->N, x, V, b, acc, nch);
+                                          h->d_leaf_cnt.as<int32_t>(), h->N, x, V, b, acc, nch,
+                                          h->hat() ? h->d_ptri.as<int32_t>() : nullptr, h->nv);
     FAGBI_TRY((device_scan<int32_t, int64_t>(acc, M, aoff, part, s)));
     FAGBI_TRY((device_scan<int32_t, int64_t>(nch, M, koff, part, s)));
     int64_t tot[2];
@@ -2674,9 +2718,9 @@ static int tc_visit(fagbi_handle* h, const TcLevels& lv, int l0, const double* c
 int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int64_t nc, double theta, int p_max,
                         double* qv, hipStream_t s) {
   const int L = h->L, l0 = std::min(h->lmin, h->L);
-  // moments of x: leaf moments and the upward pass, FP64
-  const ElemView v = box_view(h);
-  k_to_tree<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(x, v.in_idx, h->N, h->N, v.xt);
+  // moments of x: leaf moments (from panel or corner moments) and the upward pass, FP64
+  const ElemView v = h->hat() ? hat_view(h) : box_view(h);
+  k_to_tree<<<(unsigned)((v.n + 255) / 256), 256, 0, s>>>(x, v.in_idx, v.n, v.in_stride, v.xt);
   FAGBI_TRY(launch_p2m<double>(h, v, h->d_ms64.as<double>(), h->d_md64.as<double>(), false, s));
   for (int l = L - 1; l >= l0; --l) FAGBI_TRY(launch_m2m<double>(h, l, false, s));
   TcLevels lv;
@@ -2692,25 +2736,32 @@ int treecode_potentials(fagbi_handle* h, const double* x, const double* chg, int
   return 0;
 }
 
-// b (caller order, f64[2N]) by the reverse treecode; chg holds x, y, z and
+// b (caller order, f64[2n]) by the reverse treecode; chg holds x, y, z and
 // q / (4 pi eps_in) per charge
 int treecode_rhs(fagbi_handle* h, const double* chg, int64_t nc, double theta, int p_max, double* b, hipStream_t s) {
   const int L = h->L, l0 = std::min(h->lmin, h->L);
   TcLevels lv;
   FAGBI_TRY(tc_levels(h, l0, p_max, lv));
-  FAGBI_HIP(hipMemsetAsync(b, 0, (size_t)2 * h->N * sizeof(double), s));
+  // rows: the panels (caller order, b itself), or the panel corners (the
+  // matvec's corner rows, summed into the vertices of b at the end)
+  const bool hat = h->hat();
+  const int64_t nrow = hat ? 3 * h->N : h->N;
+  double* rows = hat ? h->d_ye.as<double>() : b;
+  FAGBI_HIP(hipMemsetAsync(rows, 0, (size_t)2 * nrow * sizeof(double), s));
   for (int l = l0; l <= L; ++l) {
     Level& D = h->lev[l];
     for (int ch = 0; ch < 2; ++ch)
       FAGBI_HIP(hipMemsetAsync(D.d_L64[ch].p, 0, (size_t)D.n * D.T * sizeof(double), s));
   }
-  FAGBI_TRY(tc_visit<true>(h, lv, l0, chg, nc, theta, nullptr, nullptr, b, s));
+  FAGBI_TRY(tc_visit<true>(h, lv, l0, chg, nc, theta, nullptr, nullptr, rows, s));
   for (int l = l0; l < L; ++l) FAGBI_TRY(launch_l2l<double>(h, l, false, s));
   Level& LF = h->lev[L];
-  k_l2p_rhs<<<(unsigned)((h->N + 255) / 256), 256, 0, s>>>(h->d_ms64.as<double>(), h->d_md64.as<double>(),
-                                                          h->d_leaf_of.as<int32_t>(), h->d_perm.as<int32_t>(), h->N,
-                                                          LF.T, LF.d_L64[0].as<double>(), b);
+  const int32_t* lo = hat ? h->d_s1_leaf_of.as<int32_t>() : h->d_leaf_of.as<int32_t>();
+  const int32_t* pm = hat ? h->d_s1_iota.as<int32_t>() : h->d_perm.as<int32_t>();
+  k_l2p_rhs<<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(h->d_ms64.as<double>(), h->d_md64.as<double>(), lo, pm,
+                                                          nrow, LF.T, LF.d_L64[0].as<double>(), rows);
   FAGBI_HIP(hipGetLastError());
+  if (hat) FAGBI_TRY(hat_gather(h, rows, nullptr, b, s));
   FAGBI_HIP(hipStreamSynchronize(s));
   return 0;
 }

@@ -9,6 +9,7 @@ vertices; Sec. 2.3) against the oracle's hat-function discretisation.
   dense solve; on the Kirkwood sphere the surface potential's L2 error falls
   like h^2 (against h with box functions) and the FP32-inner solve agrees with
   the FP64 one;
+* the treecode energy and RHS with hat functions against the oracle's;
 * error paths of the parameters the basis excludes."""
 import numpy as np
 import pytest
@@ -206,7 +207,7 @@ def test_hat_kirkwood_projection_rates_on_gpu():
 def test_hat_error_paths(sphere1280):
     v, t, P = sphere1280
     for kw in (dict(mlp_mode=F.MLP_GATED), dict(precond=F.PRECOND_BLOCK), dict(precond=F.PRECOND_GROUP),
-               dict(rhs_theta=0.5), dict(basis=2)):
+               dict(basis=2)):
         args = dict(basis=HAT, precond=F.PRECOND_DIAG)
         args.update(kw)
         with pytest.raises(F.FagbiError) as e:
@@ -224,11 +225,44 @@ def test_hat_error_paths(sphere1280):
     assert e.value.code == -3
     h.assemble_nearfield()
     x = torch.zeros(2 * len(v), dtype=torch.float64, device=DEV)
-    for call in (lambda: h.solvation_energy_treecode(x, np.zeros((1, 3)), np.ones(1), 0.5),
-                 lambda: h.rhs_treecode(np.zeros((1, 3)), np.ones(1), 0.5, b)):
-        with pytest.raises(F.FagbiError) as e:
-            call()
-        assert e.value.code == -1
+    chg = torch.zeros((1, 4), dtype=torch.float64, device=DEV)
+    E = torch.zeros(1, dtype=torch.float64, device=DEV)
+    with pytest.raises(F.FagbiError) as e:      # the allocation-free energy is box-only
+        h.solvation_energy_noalloc(x, chg, E)
+    assert e.value.code == -1
+    h.close()
+
+
+def test_hat_treecodes_match_oracle(globule):
+    """treecode energy and RHS with hat functions (theta 0.5, order cap 6, and
+    theta 0 = the direct sums) against the oracle's hat treecodes, and a solve
+    with the treecode right-hand side"""
+    v, t, P = globule
+    V = len(v)
+    x_, r_, q_ = packed_atoms_ball(n=16, radius=None, seed=11)
+    cfg = dict(leaf_size=16, p_leaf=4, adaptive=1, p_max=8, quad_duffy=4)
+    h = F.Handle(eta0=0.8, basis=HAT, precond=F.PRECOND_DIAG, rhs_theta=0.5, rhs_pmax=6, **cfg)
+    h.build_tree(v, t).assemble_nearfield()
+    O = p1.setup(P, otree.build(P, 16, 0.8), EPS, KAP, p_leaf=4, adaptive=1, p_max=8, with_near=False)
+    c = v.mean(0)
+    x = np.concatenate([np.cos(0.3 * (v - c) @ np.array([1.0, 0.5, -0.2])),
+                        np.sin(0.25 * (v - c) @ np.array([-0.3, 1.0, 0.4]))])
+    for theta, pmax in ((0.5, 6), (0.3, 8), (0.0, 8)):
+        E = h.solvation_energy_treecode(dev(x), x_, q_, theta, p_max=pmax)
+        Eref = p1.treecode_energy(O, x, x_, q_, theta, p_max=pmax)
+        b = torch.empty(2 * V, dtype=torch.float64, device=DEV)
+        h.rhs_treecode(x_, q_, theta, b, p_max=pmax)
+        torch.cuda.synchronize()
+        bref = p1.treecode_rhs(O, x_, q_, theta, 1.0, p_max=pmax)
+        print("theta %.1f: energy %.3e, rhs %.3e / %.3e" % (theta, abs(E - Eref) / abs(Eref),
+                                                           rel(b.cpu().numpy(), bref), maxrow(b.cpu().numpy(), bref)))
+        assert abs(E - Eref) < 1e-11 * abs(Eref)
+        assert rel(b.cpu().numpy(), bref) < 1e-11 and maxrow(b.cpu().numpy(), bref) < 1e-11
+    Ed = h.solvation_energy(dev(x), x_, q_)
+    assert abs(h.solvation_energy_treecode(dev(x), x_, q_, 0.0) - Ed) < 1e-12 * abs(Ed)
+    xs = torch.zeros(2 * V, dtype=torch.float64, device=DEV)
+    code, info = h.solve(x_, q_, xs)
+    assert code == 0 and info.rel_residual <= 1e-6
     h.close()
 
 
@@ -309,6 +343,11 @@ def test_hat_full_size_solves(big_hat):
         E[(basis, prec)] = h.solvation_energy(x, w["xq"], w["q"])
         print("basis %d precision %d: %d inner iterations, energy %.6f"
               % (basis, prec, info.inner_iterations, E[(basis, prec)]))
+        if basis == HAT and prec == F.FP64:
+            # the treecode energy (theta 0.5, order cap 6) against the direct sum
+            Et = h.solvation_energy_treecode(x, w["xq"], w["q"], 0.5, p_max=6)
+            print("hat treecode energy %.6f (rel. diff %.2e)" % (Et, abs(Et - E[(basis, prec)]) / abs(E[(basis, prec)])))
+            assert abs(Et - E[(basis, prec)]) < 1e-5 * abs(E[(basis, prec)])
         h.close()
     e64 = E[(HAT, F.FP64)]
     assert abs(E[(HAT, F.MIXED)] - e64) < 1e-5 * abs(e64)

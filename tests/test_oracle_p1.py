@@ -270,3 +270,42 @@ def test_fmm_converges_to_dense_operator():
     assert np.linalg.norm(p1.matvec(F, x) - ref) < 1e-13 * np.linalg.norm(ref)
     # the Jacobi divisors are the dense diagonal
     assert np.abs(p1.diagonal(F) - np.diag(A)).max() < 1e-13 * np.abs(np.diag(A)).max()
+
+
+def test_hat_treecodes():
+    """Treecode energy and RHS with hat functions (Sec. 2.5): theta = 0 gives the
+    direct sums; the error falls with theta for smooth nodal values; constant
+    nodal values give the box-function treecode's energy and the same total
+    right-hand side (the hat functions of a panel sum to one)."""
+    from oracle import fmm, treecode
+    x_, r_, q_ = packed_atoms_ball(n=16, radius=None, seed=11)
+    v, t = isosurface_mesh(x_, r_, spacing=1.0)
+    P = panels(v, t)
+    V = len(v)
+    tr = otree.build(P, 16, 0.8)
+    F1 = p1.setup(P, tr, 80.0, 0.1257, p_leaf=4, adaptive=1, p_max=8, with_near=False)
+    c = v.mean(0)
+    u = np.cos(0.3 * (v - c) @ np.array([1.0, 0.5, -0.2]))
+    w = np.sin(0.25 * (v - c) @ np.array([-0.3, 1.0, 0.4]))
+    x = np.concatenate([u, w])
+    Ed = p1.energy(P, x, x_, q_, 80.0, 0.1257)
+    bd = p1.rhs(P, x_, q_, 1.0)
+    assert abs(p1.treecode_energy(F1, x, x_, q_, 0.0) - Ed) < 1e-13 * abs(Ed)
+    assert np.linalg.norm(p1.treecode_rhs(F1, x_, q_, 0.0, 1.0) - bd) < 1e-13 * np.linalg.norm(bd)
+    eE = [abs(p1.treecode_energy(F1, x, x_, q_, th) - Ed) / abs(Ed) for th in (0.7, 0.5, 0.3)]
+    eb = [np.linalg.norm(p1.treecode_rhs(F1, x_, q_, th, 1.0) - bd) / np.linalg.norm(bd) for th in (0.7, 0.5, 0.3)]
+    print("hat treecode energy errors %s, rhs errors %s" % (eE, eb))
+    assert eE[0] > eE[1] > eE[2] and eE[2] < 5e-5
+    assert eb[0] > eb[1] > eb[2] and eb[2] < 1e-4
+    F0 = fmm.setup(P, tr, 80.0, 0.1257, p_leaf=4, adaptive=1, p_max=8, with_near=False)
+    for c1, c2 in ((1.0, 0.0), (0.3, -0.8)):
+        xh = np.concatenate([np.full(V, c1), np.full(V, c2)])
+        xb = np.concatenate([np.full(P.n, c1), np.full(P.n, c2)])
+        Eh = p1.treecode_energy(F1, xh, x_, q_, 0.5, p_max=6)
+        Eb = treecode.energy(F0, xb, x_, q_, 0.5, p_max=6)
+        assert abs(Eh - Eb) < 1e-12 * abs(Eb), (Eh, Eb)
+    bh = p1.treecode_rhs(F1, x_, q_, 0.5, 1.0, p_max=6)
+    bb = treecode.rhs(F0, x_, q_, 0.5, 1.0, p_max=6)
+    for ch in range(2):
+        sh, sb = bh[ch * V:(ch + 1) * V].sum(), bb[ch * P.n:(ch + 1) * P.n].sum()
+        assert abs(sh - sb) < 1e-12 * np.abs(bb[ch * P.n:(ch + 1) * P.n]).sum()
