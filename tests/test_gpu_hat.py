@@ -3,7 +3,8 @@ vertices; Sec. 2.3) against the oracle's hat-function discretisation.
 
 * the operator: FP64 to 1e-11 and FP32 to 1e-6 (relative L2 and largest row),
   near part (with the mass terms) and far part separately, on the icosphere
-  and on an irregular isosurface globule with close pairs;
+  and on an irregular isosurface globule with close pairs (one tree with
+  per-cluster radii);
 * the right-hand side and the energy to 1e-12, the Jacobi divisors to 1e-12;
 * solves: with every pair near (eta0 = 0) the GPU solution equals the oracle's
   dense solve; on the Kirkwood sphere the surface potential's L2 error falls
@@ -66,11 +67,12 @@ def globule():
     ("sphere", dict(leaf_size=8, p_leaf=3, adaptive=1, p_max=6)),
     ("globule", dict(leaf_size=16, p_leaf=4, adaptive=0, quad_duffy=4)),
     ("globule", dict(leaf_size=4, p_leaf=3, adaptive=1, p_max=8, quad_duffy=4)),
+    ("globule", dict(leaf_size=8, p_leaf=3, adaptive=1, p_max=8, quad_duffy=4, radii=F.RADII_CLUSTER)),
 ])
 def test_hat_operator_matches_oracle(sphere1280, globule, mesh, cfg):
     v, t, P = sphere1280 if mesh == "sphere" else globule
     h = F.Handle(eta0=0.8, basis=HAT, precond=F.PRECOND_DIAG, **cfg).build_tree(v, t).assemble_nearfield()
-    tr = otree.build(P, cfg["leaf_size"], 0.8)
+    tr = otree.build(P, cfg["leaf_size"], 0.8, radii="cluster" if cfg.get("radii") else "level")
     O = p1.setup(P, tr, EPS, KAP, p_leaf=cfg["p_leaf"], adaptive=cfg["adaptive"], p_max=cfg.get("p_max", 8),
                  n_duffy=cfg.get("quad_duffy", 7))
     V = len(v)
