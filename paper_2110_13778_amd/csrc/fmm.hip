@@ -279,23 +279,25 @@ template <typename R> struct Pair;
 template <> struct Pair<float> { using T = float2; };
 template <> struct Pair<double> { using T = double2; };
 
+// one block's work (blk: the block's index within its level; smem_raw: the
+// block's dynamic LDS); SPT slot rounds per thread, SPT * TB >= nslot
 template <typename R, int SPT>
-__global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_off, const int32_t* __restrict__ inter_src,
-                                            const int32_t* __restrict__ inter_oid,
-                                            const typename Pair<R>::T* __restrict__ Dt,
-                                            const int32_t* __restrict__ slot, const R* __restrict__ mscale,
-                                            const R* __restrict__ lscale, const int32_t* __restrict__ aoff,
-                                            int nslot, int T, int batch, int cpb, int ncl,
-                                            const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
+__device__ __forceinline__ void m2l_slot_block(char* smem_raw, int blk, const int32_t* __restrict__ inter_off,
+                                               const int32_t* __restrict__ inter_src,
+                                               const int32_t* __restrict__ inter_oid,
+                                               const typename Pair<R>::T* __restrict__ Dt,
+                                               const int32_t* __restrict__ slot, const R* __restrict__ mscale,
+                                               const R* __restrict__ lscale, const int32_t* __restrict__ aoff,
+                                               int nslot, int T, int batch, int cpb, int ncl,
+                                               const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
   // cpb targets per block when a translation has few slots: group g of
-  // nslot threads (SPT == 1) owns target blockIdx.x * cpb + g
+  // nslot threads (SPT == 1) owns target blk * cpb + g
   using R2 = typename Pair<R>::T;
-  extern __shared__ __align__(16) char smem_raw[];
   const int tid = threadIdx.x;
   const int gsz = SPT == 1 ? nslot : TB;
   const int g = SPT == 1 ? tid / nslot : 0;
   const int lt = SPT == 1 ? tid - g * nslot : tid;   // thread within the group
-  const int c = blockIdx.x * cpb + g;
+  const int c = blk * cpb + g;
   const bool active = g < cpb && c < ncl;
   R2* sm = reinterpret_cast<R2*>(smem_raw) + (size_t)(active ? g : 0) * batch * 2 * T;
   int sg[SPT], sb[SPT];
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
   // the block iterates over the longest list among its targets
   int maxlen = 0;
   for (int gg = 0; gg < cpb; ++gg) {
-    const int cc = blockIdx.x * cpb + gg;
+    const int cc = blk * cpb + gg;
     if (cc < ncl) maxlen = max(maxlen, inter_off[cc + 1] - inter_off[cc]);
   }
   const int W = 2 * T;   // one staged source: D (T pairs) then Mt (T pairs)
@@ -370,6 +372,70 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
     L0[(int64_t)c * T + t] = s0 * lscale[t];
     Lk[(int64_t)c * T + t] = sk * lscale[t];
   }
+}
+
+// the block with the exact number of slot rounds of its level for the orders
+// 7 and 8 (ceil(nslot / TB) = 7, 12) when at most SPT; SPT rounds otherwise
+// (the slots past nslot read slot 0 and are not stored)
+template <typename R, int SPT>
+__device__ __forceinline__ void m2l_slot_dispatch(char* smem_raw, int blk, const int32_t* __restrict__ inter_off,
+                                                  const int32_t* __restrict__ inter_src,
+                                                  const int32_t* __restrict__ inter_oid,
+                                                  const typename Pair<R>::T* __restrict__ Dt,
+                                                  const int32_t* __restrict__ slot, const R* __restrict__ mscale,
+                                                  const R* __restrict__ lscale, const int32_t* __restrict__ aoff,
+                                                  int nslot, int T, int batch, int cpb, int ncl,
+                                                  const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
+#define FAGBI_SLOT_BLOCK(NJ)                                                                                   \
+  m2l_slot_block<R, NJ>(smem_raw, blk, inter_off, inter_src, inter_oid, Dt, slot, mscale, lscale, aoff, nslot, T, \
+                        batch, cpb, ncl, M0, Mk, L0, Lk)
+  const int nj = (nslot + TB - 1) / TB;   // uniform over the block
+  if constexpr (SPT >= 12) if (nj == 12) { FAGBI_SLOT_BLOCK(12); return; }
+  if constexpr (SPT >= 7) if (nj == 7) { FAGBI_SLOT_BLOCK(7); return; }
+  FAGBI_SLOT_BLOCK(SPT);
+#undef FAGBI_SLOT_BLOCK
+}
+
+template <typename R, int SPT>
+__global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_off, const int32_t* __restrict__ inter_src,
+                                            const int32_t* __restrict__ inter_oid,
+                                            const typename Pair<R>::T* __restrict__ Dt,
+                                            const int32_t* __restrict__ slot, const R* __restrict__ mscale,
+                                            const R* __restrict__ lscale, const int32_t* __restrict__ aoff,
+                                            int nslot, int T, int batch, int cpb, int ncl,
+                                            const R* __restrict__ M0, const R* __restrict__ Mk, R* L0, R* Lk) {
+  extern __shared__ __align__(16) char smem_raw[];
+  m2l_slot_block<R, SPT>(smem_raw, (int)blockIdx.x, inter_off, inter_src, inter_oid, Dt, slot, mscale, lscale, aoff,
+                         nslot, T, batch, cpb, ncl, M0, Mk, L0, Lk);
+}
+
+// Several levels' slot MtL in one launch (the levels are independent): the
+// coarse levels have few clusters each, so one launch per level leaves the
+// GPU mostly idle while a long chain of short launches runs.  Level i owns
+// blocks [b0_i, b0_{i+1}), one target cluster per block.
+constexpr int MTL_MAXL = 16;
+template <typename R>
+struct MtlLevels {
+  struct Lv {
+    const int32_t *off, *src, *oid, *slot, *aoff;
+    const typename Pair<R>::T* Dt;
+    const R* msc;   // (-1)^|b| / b! for the moments, then 1 / a! for the locals
+    const R *M0, *Mk;
+    R *L0, *Lk;
+    int nslot, T, batch, ncl, b0;
+  } lv[MTL_MAXL];
+  int n;
+};
+
+template <typename R, int SPT>
+__global__ void __launch_bounds__(TB) k_m2l_multi(const MtlLevels<R> ls) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int b = (int)blockIdx.x;
+  int i = 0;
+  while (i + 1 < ls.n && b >= ls.lv[i + 1].b0) ++i;
+  const typename MtlLevels<R>::Lv& v = ls.lv[i];
+  m2l_slot_dispatch<R, SPT>(smem_raw, b - v.b0, v.off, v.src, v.oid, v.Dt, v.slot, v.msc, v.msc + v.T, v.aoff,
+                            v.nslot, v.T, v.batch, 1, v.ncl, v.M0, v.Mk, v.L0, v.Lk);
 }
 
 // MtL for low orders with the whole expansion in registers: S consecutive
@@ -2004,113 +2070,187 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   const int L = h->L;
   auto M = [&](Level& D, int ch) { return f32 ? D.d_M32[ch].as<R>() : D.d_M64[ch].as<R>(); };
   auto Lc = [&](Level& D, int ch) { return f32 ? D.d_L32[ch].as<R>() : D.d_L64[ch].as<R>(); };
-  // MtL of one level (levels are independent of each other)
+  // MtL of one level (levels are independent of each other): which kernel
+  // serves level l
+  enum { K_LDS64, K_TILE_MFMA, K_TILE, K_LDS32, K_REG, K_EMPTY, K_SLOT };
+  // register-blocked kernels for the low orders (up to p = 4, FP32 up to 5)
+  // (order 5 in registers in FP32 only: the FP64 version would spill)
+  const int preg = sizeof(R) == 4 ? 5 : 4;
+  auto dbytes_of = [&](const Level& D) {
+    return (size_t)D.n_half * D.T * sizeof(typename Pair<R>::T) + (size_t)D.n_off * 4;
+  };
+  auto kind_of = [&](const Level& D) -> int {
+    const bool small = dbytes_of(D) <= (size_t)150 * 1024;
+    // FP64 at order 3: the LDS kernel with the FP64 half table (512 threads: 224 VGPRs)
+    if (sizeof(R) == 8 && D.n_half > 0 && D.order == 3 && D.d_F64[1].p && small) return K_LDS64;
+    if (sizeof(R) == 4 && D.n_tile > 0 && D.order == 3 && h->m2l_tiles) return h->m2l_mfma ? K_TILE_MFMA : K_TILE;
+    if (sizeof(R) == 4 && D.n_half > 0 && (D.order == 3 || D.order == 4) && small) return K_LDS32;
+    if (D.n_off > 0 && D.order <= preg && D.order >= 1) return K_REG;
+    if (D.n_off == 0) return K_EMPTY;   // no interactions: LtL adds into zero locals
+    return K_SLOT;
+  };
+  // the slot kernel's staging batch and LDS bytes for one target per block
+  auto slot_batch = [&](const Level& D) {
+    return std::max(1, std::min(16, (int)(16384 / (2 * D.T * sizeof(typename Pair<R>::T)))));
+  };
+  auto slot_lds = [&](const Level& D, int cpb) {
+    return (size_t)cpb * std::max<size_t>((size_t)slot_batch(D) * 2 * D.T * sizeof(typename Pair<R>::T),
+                                          (size_t)2 * D.m2l_nslot * sizeof(R));
+  };
   auto launch_m2l = [&](int l, hipStream_t st) -> int {
     Level& D = h->lev[l];
     using R2 = typename Pair<R>::T;
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
-    // register-blocked kernels for the low orders (up to p = 4, FP32 up to 5)
-    // (order 5 in registers in FP32 only: the FP64 version would spill)
-    const int preg = sizeof(R) == 4 ? 5 : 4;
-    const size_t dbytes = (size_t)D.n_half * D.T * sizeof(R2) + (size_t)D.n_off * 4;
-    // FP64 at order 3: the same with the FP64 half table (512 threads: 224 VGPRs)
-    if constexpr (sizeof(R) == 8)
-    if (D.n_half > 0 && D.order == 3 && D.d_F64[1].p && dbytes <= (size_t)150 * 1024) {
-      int S = 1;
-      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      const R2* Dh = (const R2*)D.d_F64[1].p;
-      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 512>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-      k_m2l_lds<R, 3, 512><<<224, 512, dbytes, st>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
-                                                     D.d_inter_oid.as<int32_t>(), Dh, D.n_half,
-                                                     D.d_oid_map.as<int32_t>(), D.n_off, D.n, S, M(D, 0), M(D, 1),
-                                                     Lc(D, 0), Lc(D, 1));
-      return 0;
-    }
-    if constexpr (sizeof(R) == 4)
-    if (D.n_tile > 0 && D.order == 3 && h->m2l_tiles && h->m2l_mfma) {
-      // table + zero row, staged moments + zero row, and one row of slack:
-      // lanes past term 19 of a zero row read (and discard) up to 96 bytes beyond it
-      const size_t lds = ((size_t)D.n_half + 1 + D.tile_umax + 2) * D.T * sizeof(float2);
-      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile_mfma<3>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      k_m2l_tile_mfma<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
-                                                  D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
-                                                  D.d_tile_src.as<int32_t>(), D.n_tile,
-                                                  (const float2*)D.d_F32[1].p, D.n_half, D.tile_umax,
-                                                  h->d_xdst.as<int8_t>(), M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
-      return 0;
-    }
-    if constexpr (sizeof(R) == 4)
-    if (D.n_tile > 0 && D.order == 3 && h->m2l_tiles) {
-      const size_t lds = ((size_t)D.n_half + D.tile_umax) * (D.T + 2) * sizeof(float2);
-      FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile<3>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      k_m2l_tile<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
-                                                  D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
-                                                  D.d_tile_src.as<int32_t>(), D.n_tile,
-                                                  (const float2*)D.d_F32[1].p, D.n_half, M(D, 0), M(D, 1),
-                                                  Lc(D, 0), Lc(D, 1));
-      return 0;
-    }
-    if constexpr (sizeof(R) == 4)
-    if (D.n_half > 0 && (D.order == 3 || D.order == 4) && dbytes <= (size_t)150 * 1024) {
-      int S = 1;
-      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      const R2* Dh = (const R2*)D.d_F32[1].p;
-      const int32_t* om = D.d_oid_map.as<int32_t>();
-      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
-                    *id = D.d_inter_oid.as<int32_t>();
-      if (D.order == 3) {
-        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 1024>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-        // 28 of each XCD's 32 CUs: the persistent blocks hold most of a CU's
-        // LDS, and the free CUs keep the main stream's coarse-level MtL from
-        // waiting for the whole kernel (measured 1.24 -> 1.20 ms per FP32 matvec)
-        k_m2l_lds<R, 3, 1024><<<224, 1024, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
-                                                        M(D, 1), Lc(D, 0), Lc(D, 1));
-      } else {
-        FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
-        k_m2l_lds<R, 4, 768><<<256, 768, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
-                                                      M(D, 1), Lc(D, 0), Lc(D, 1));
+    const size_t dbytes = dbytes_of(D);
+    switch (kind_of(D)) {
+      case K_LDS64:
+        if constexpr (sizeof(R) == 8) {
+          int S = 1;
+          while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+          const R2* Dh = (const R2*)D.d_F64[1].p;
+          FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 512>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+          k_m2l_lds<R, 3, 512><<<224, 512, dbytes, st>>>(D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
+                                                         D.d_inter_oid.as<int32_t>(), Dh, D.n_half,
+                                                         D.d_oid_map.as<int32_t>(), D.n_off, D.n, S, M(D, 0),
+                                                         M(D, 1), Lc(D, 0), Lc(D, 1));
+        }
+        return 0;
+      case K_TILE_MFMA:
+        if constexpr (sizeof(R) == 4) {
+          // table + zero row, staged moments + zero row, and one row of slack:
+          // lanes past term 19 of a zero row read (and discard) up to 96 bytes beyond it
+          const size_t lds = ((size_t)D.n_half + 1 + D.tile_umax + 2) * D.T * sizeof(float2);
+          FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile_mfma<3>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+          k_m2l_tile_mfma<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
+                                                      D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
+                                                      D.d_tile_src.as<int32_t>(), D.n_tile,
+                                                      (const float2*)D.d_F32[1].p, D.n_half, D.tile_umax,
+                                                      h->d_xdst.as<int8_t>(), M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
+        }
+        return 0;
+      case K_TILE:
+        if constexpr (sizeof(R) == 4) {
+          const size_t lds = ((size_t)D.n_half + D.tile_umax) * (D.T + 2) * sizeof(float2);
+          FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_tile<3>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+          k_m2l_tile<3><<<224, MT_NT, lds, st>>>(D.d_inter_off.as<int32_t>(), D.d_pack.as<uint32_t>(),
+                                                 D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
+                                                 D.d_tile_src.as<int32_t>(), D.n_tile,
+                                                 (const float2*)D.d_F32[1].p, D.n_half, M(D, 0), M(D, 1),
+                                                 Lc(D, 0), Lc(D, 1));
+        }
+        return 0;
+      case K_LDS32:
+        if constexpr (sizeof(R) == 4) {
+          int S = 1;
+          while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+          const R2* Dh = (const R2*)D.d_F32[1].p;
+          const int32_t* om = D.d_oid_map.as<int32_t>();
+          const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                        *id = D.d_inter_oid.as<int32_t>();
+          if (D.order == 3) {
+            FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 3, 1024>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+            // 28 of each XCD's 32 CUs: the persistent blocks hold most of a CU's
+            // LDS, and the free CUs keep the main stream's coarse-level MtL from
+            // waiting for the whole kernel (measured 1.24 -> 1.20 ms per FP32 matvec)
+            k_m2l_lds<R, 3, 1024><<<224, 1024, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                            M(D, 1), Lc(D, 0), Lc(D, 1));
+          } else {
+            FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+            k_m2l_lds<R, 4, 768><<<256, 768, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
+                                                          M(D, 1), Lc(D, 0), Lc(D, 1));
+          }
+        }
+        return 0;
+      case K_REG: {
+        int S = 1;
+        while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
+        const unsigned grid = (unsigned)((((int64_t)D.n * S + 255) / 256 + 7) / 8 * 8);
+        const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
+                      *id = D.d_inter_oid.as<int32_t>();
+        switch (D.order) {
+          case 1: k_m2l_reg<R, 1><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+          case 2: k_m2l_reg<R, 2><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+          case 3: k_m2l_reg<R, 3><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+          case 4: k_m2l_reg<R, 4><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
+          default:
+            if constexpr (sizeof(R) == 4)
+              k_m2l_reg<R, 5><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
+            break;
+        }
+        return 0;
       }
-      return 0;
-    }
-    if (D.n_off > 0 && D.order <= preg && D.order >= 1) {
-      int S = 1;
-      while (S < 16 && (int64_t)D.n * S < (int64_t)512 * 1024) S <<= 1;
-      const unsigned grid = (unsigned)((((int64_t)D.n * S + 255) / 256 + 7) / 8 * 8);
-      const int32_t *io = D.d_inter_off.as<int32_t>(), *is = D.d_inter_src.as<int32_t>(),
-                    *id = D.d_inter_oid.as<int32_t>();
-      switch (D.order) {
-        case 1: k_m2l_reg<R, 1><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        case 2: k_m2l_reg<R, 2><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        case 3: k_m2l_reg<R, 3><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        case 4: k_m2l_reg<R, 4><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1)); break;
-        default:
-          if constexpr (sizeof(R) == 4)
-            k_m2l_reg<R, 5><<<grid, 256, 0, st>>>(io, is, id, Dt, D.n, S, M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
-          break;
+      case K_EMPTY:
+        FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), st));
+        FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), st));
+        return 0;
+      default: {
+        const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
+        const int spt = spt_of(D.m2l_nslot);
+        const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
+        const unsigned grid = (unsigned)((D.n + cpb - 1) / cpb);
+        FAGBI_SPT_SWITCH(spt, k_m2l, grid, slot_lds(D, cpb), st, D.d_inter_off.as<int32_t>(),
+                         D.d_inter_src.as<int32_t>(), D.d_inter_oid.as<int32_t>(), Dt, D.d_m2l_slot.as<int32_t>(),
+                         sc, sc + D.T, D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, slot_batch(D), cpb, D.n,
+                         M(D, 0), M(D, 1), Lc(D, 0), Lc(D, 1));
+        return 0;
       }
-      return 0;
     }
-    if (D.n_off == 0) {   // no interactions: LtL adds into zero locals
-      FAGBI_HIP(hipMemsetAsync(Lc(D, 0), 0, (size_t)D.n * D.T * sizeof(R), st));
-      FAGBI_HIP(hipMemsetAsync(Lc(D, 1), 0, (size_t)D.n * D.T * sizeof(R), st));
-      return 0;
+  };
+  // MtL of the levels [l0, l1): in FP32 the levels served by the slot kernel
+  // at orders 7 and 8 (at least 8 slots per thread: the coarsest, with few
+  // clusters each) in one launch, coarsest (longest lists) first, the others
+  // one by one after it.  The FP32 matvec waits for this chain (measured
+  // 1.057 -> 1.032 ms per matvec at 491k panels); in FP64 the finest levels'
+  // MtL is the longest path, and the grouped launch only takes CUs from it
+  // (2.276 -> 2.316 ms), so there every level has its own launch.
+  auto launch_m2l_range = [&](int l0, int l1, hipStream_t st) -> int {
+    MtlLevels<R> ls{};
+    int spt = 1;
+    size_t sh = 0;
+    int64_t nb = 0;
+    std::vector<int> rest;
+    for (int l = l0; l < l1; ++l) {
+      Level& D = h->lev[l];
+      const int sp = kind_of(D) == K_SLOT ? spt_of(D.m2l_nslot) : 0;
+      if (!f32 || sp < 8 || ls.n == MTL_MAXL) {
+        rest.push_back(l);
+        continue;
+      }
+      const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
+      auto& v = ls.lv[ls.n++];
+      v.off = D.d_inter_off.as<int32_t>();
+      v.src = D.d_inter_src.as<int32_t>();
+      v.oid = D.d_inter_oid.as<int32_t>();
+      v.slot = D.d_m2l_slot.as<int32_t>();
+      v.aoff = D.d_m2l_aoff.as<int32_t>();
+      v.Dt = f32 ? (const typename Pair<R>::T*)D.d_F32[0].p : (const typename Pair<R>::T*)D.d_F64[0].p;
+      v.msc = sc;
+      v.M0 = M(D, 0);
+      v.Mk = M(D, 1);
+      v.L0 = Lc(D, 0);
+      v.Lk = Lc(D, 1);
+      v.nslot = D.m2l_nslot;
+      v.T = D.T;
+      v.batch = slot_batch(D);
+      v.ncl = D.n;
+      v.b0 = (int)nb;
+      nb += D.n;
+      spt = std::max(spt, spt_of(D.m2l_nslot));
+      sh = std::max(sh, slot_lds(D, 1));
     }
-    const R* sc = f32 ? D.d_m2l_c32.as<R>() : D.d_m2l_c64.as<R>();
-    const int spt = spt_of(D.m2l_nslot);
-    const int cpb = spt == 1 ? std::max(1, std::min(8, TB / D.m2l_nslot)) : 1;
-    const int batch = std::max(1, std::min(16, (int)(16384 / (cpb * 2 * D.T * sizeof(R2)))));
-    const size_t sh = (size_t)cpb * std::max<size_t>((size_t)batch * 2 * D.T * sizeof(R2),
-                                                     (size_t)2 * D.m2l_nslot * sizeof(R));
-    const unsigned grid = (unsigned)((D.n + cpb - 1) / cpb);
-    FAGBI_SPT_SWITCH(spt, k_m2l, grid, sh, st, D.d_inter_off.as<int32_t>(), D.d_inter_src.as<int32_t>(),
-                     D.d_inter_oid.as<int32_t>(), Dt, D.d_m2l_slot.as<int32_t>(), sc, sc + D.T,
-                     D.d_m2l_aoff.as<int32_t>(), D.m2l_nslot, D.T, batch, cpb, D.n, M(D, 0), M(D, 1), Lc(D, 0),
-                     Lc(D, 1));
+    if (ls.n > 0) {
+      if (nb > INT32_MAX) return set_error(FAGBI_E_ARG, "too many clusters for one MtL launch");
+      if (spt == 8)
+        k_m2l_multi<R, 8><<<(unsigned)nb, TB, sh, st>>>(ls);
+      else
+        k_m2l_multi<R, 16><<<(unsigned)nb, TB, sh, st>>>(ls);
+    }
+    for (int l : rest) FAGBI_TRY(launch_m2l(l, st));
     return 0;
   };
   // pipelined MtL: the two finest levels (most of the pairs) run on a second
@@ -2159,11 +2299,12 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
     if (!h->ev_upd) FAGBI_HIP(hipEventCreateWithFlags(&h->ev_upd, hipEventDisableTiming));
     FAGBI_HIP(hipEventRecord(h->ev_upd, s));
     FAGBI_HIP(hipStreamWaitEvent(sn, h->ev_upd, 0));
-    for (int l = h->lmin; l < l_hi; ++l) FAGBI_TRY(launch_m2l(l, sn));
+    FAGBI_TRY(launch_m2l_range(h->lmin, l_hi, sn));
     FAGBI_HIP(hipEventRecord(h->ev_join, sn));   // the SpMV and those levels
     FAGBI_TRY(l_hi == L ? launch_m2l_leaf(s) : launch_m2l(l_hi, s));
   } else {
-    for (int l = h->lmin; l <= l_hi; ++l) FAGBI_TRY(l == L ? launch_m2l_leaf(s) : launch_m2l(l, s));
+    FAGBI_TRY(launch_m2l_range(h->lmin, std::min(l_hi + 1, L), s));
+    if (l_hi == L) FAGBI_TRY(launch_m2l_leaf(s));
   }
   if (pipe) FAGBI_HIP(hipEventRecord(h->ev_m2l, h->s_m2l));
   FAGBI_HIP(hipGetLastError());
