@@ -714,11 +714,39 @@ __global__ void __launch_bounds__(256) k_m2m_reg(const int32_t* __restrict__ chi
   }
 }
 
-// the same with the level's derivative table staged in LDS: only one of each
-// pair of opposite offsets is stored (D_g(-o) = (-1)^|g| D_g(o), the kernels
-// being even), omap[oid] = row | flip << 30.  One persistent block per CU,
-// each block a contiguous range of targets (XCD-contiguous as above), so only
-// the source moments come from the caches.
+// Dynamic tile claims of the persistent MtL kernels.  Tiles [0, n) form 8
+// contiguous ranges, one per XCD (block id mod 8), each with a claim counter
+// ctr[x]; a block (or wavefront) claims the next tile of its own XCD's range
+// and, once that range is used up, of the following XCDs' ranges.  A block
+// whose CU is shared with other kernels simply claims fewer tiles, so the
+// launch does not wait for its slowest block.  *vx is the caller's cursor over
+// the ranges (0 at the start); -1 when every range is used up.  ctr[8] counts
+// finished blocks and the last one clears all nine, so every launch starts
+// from zero (the counters are zero when allocated).
+__device__ __forceinline__ int claim_tile(int* ctr, int xcd, int* vx, int n) {
+  const int per = (n + 7) / 8;
+  while (*vx < 8) {
+    const int x = (xcd + *vx) & 7;
+    const int k = atomicAdd(&ctr[x], 1);
+    if (k < per && x * per + k < n) return x * per + k;
+    ++*vx;
+  }
+  return -1;
+}
+// one thread per block, after the block's last claim
+__device__ __forceinline__ void claims_done(int* ctr) {
+  __threadfence();
+  if (atomicAdd(&ctr[8], 1) == (int)gridDim.x - 1) {
+    for (int x = 0; x < 9; ++x) atomicExch(&ctr[x], 0);
+    __threadfence();
+  }
+}
+
+// the register-blocked MtL (k_m2l_reg) with the level's derivative table
+// staged in LDS: only one of each pair of opposite offsets is stored
+// (D_g(-o) = (-1)^|g| D_g(o), the kernels being even), omap[oid] = row |
+// flip << 30.  One persistent block per CU, each block a contiguous range of
+// targets, so only the source moments come from the caches.
 template <typename R, int P, int NT>
 __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inter_off,
                                                 const int32_t* __restrict__ inter_src,
@@ -737,7 +765,9 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
   __syncthreads();
   // XCD x (= block id mod 8) owns a contiguous range of tiles; its blocks
   // sweep that range together (tile it * nbx + local block), so the sources
-  // in use at any time stay within the XCD's L2
+  // in use at any time stay within the XCD's L2.  (Claimed tiles, as in the
+  // leaf tile kernel, keep every block and its LDS until the last tile and
+  // starved the kernels beside it: 1.03 -> 1.26 ms per FP32 matvec.)
   const int nbx = (int)((gridDim.x + 7) / 8);
   const int64_t xcd = blockIdx.x & 7, bl = blockIdx.x >> 3;
   const int64_t ntile = ((int64_t)ncl * S + NT - 1) / NT;
@@ -927,8 +957,8 @@ __global__ void __launch_bounds__(256) k_tile_setup(const int32_t* __restrict__ 
 }
 
 // the MtL itself (FP32, T(P) a multiple of 4): persistent blocks of MT_NT
-// threads, one tile at a time; XCD x (= block id mod 8) sweeps a contiguous
-// range of tiles
+// threads, one tile at a time, claimed from the block's XCD's range of tiles
+// first (claim_tile)
 template <int P>
 __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict__ inter_off,
                                                        const uint32_t* __restrict__ pack,
@@ -937,7 +967,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
                                                        const int32_t* __restrict__ tile_src, int ntile,
                                                        const float2* __restrict__ Dh, int n_half,
                                                        const float* __restrict__ M0, const float* __restrict__ Mk,
-                                                       float* L0, float* Lk) {
+                                                       float* L0, float* Lk, int* ctr) {
   constexpr TermTable<P> tt{};
   constexpr int T = TermTable<P>::T;
   constexpr int CPR = T / 4;              // float4 chunks per moment row and channel
@@ -952,6 +982,7 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
   __shared__ float msc[T], lsc[T];
   __shared__ float acc[MTK][2 * T];       // the tile's locals, both channels
   __shared__ int32_t qoff[MTK + 1];       // the tile's list offsets
+  __shared__ int32_t s_tile;              // the tile claimed next
   for (int e = threadIdx.x; e < n_half * T; e += MT_NT) {
     const int rw = e / T;
     dsm[rw * TP + (e - rw * T)] = Dh[e];
@@ -967,13 +998,11 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
     msc[threadIdx.x] = f;
     lsc[threadIdx.x] = g;
   }
-  const int nbx = (int)((gridDim.x + 7) / 8);
-  const int xcd = (int)(blockIdx.x & 7), bl = (int)(blockIdx.x >> 3);
-  const int per = (ntile + 8 * nbx - 1) / (8 * nbx);
+  const int xcd = (int)(blockIdx.x & 7);
+  int vx = 0;   // thread 0's cursor over the XCDs' ranges
   // staged rows of a tile in registers: item i = (slot i / CPR, chunk i % CPR)
   float4 ra[MT_IPT], rb[MT_IPT];
   auto prefetch = [&](int tile) {
-    if (tile >= ntile) return;
     const int u0 = tile_off[tile], ni = (tile_off[tile + 1] - u0) * CPR;
 #pragma unroll
     for (int k = 0; k < MT_IPT; ++k) {
@@ -986,12 +1015,14 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
       }
     }
   };
-  __syncthreads();   // msc
-  prefetch(xcd * per * nbx + bl);
-  for (int it = 0; it < per; ++it) {
-    const int tile = (xcd * per + it) * nbx + bl;
-    __syncthreads();   // the previous tile's sources and locals are no longer read
-    if (tile >= ntile) continue;
+  if (threadIdx.x == 0) s_tile = claim_tile(ctr, xcd, &vx, ntile);
+  __syncthreads();   // msc, s_tile
+  int tile = s_tile;
+  if (tile >= 0) prefetch(tile);
+  while (tile >= 0) {
+    // the previous tile's sources and locals are no longer read, and every
+    // thread has read s_tile
+    __syncthreads();
     const int t0 = tile_t0[tile], nt = tile_t0[tile + 1] - t0;
     {
       const int ni = (tile_off[tile + 1] - tile_off[tile]) * CPR;
@@ -1009,8 +1040,10 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
       for (int e = threadIdx.x; e < nt * 2 * T; e += MT_NT) (&acc[0][0])[e] = 0.0f;
       for (int e = threadIdx.x; e <= nt; e += MT_NT) qoff[e] = inter_off[t0 + e];
     }
+    if (threadIdx.x == 0) s_tile = claim_tile(ctr, xcd, &vx, ntile);
     __syncthreads();
-    if (it + 1 < per) prefetch((xcd * per + it + 1) * nbx + bl);
+    const int next = s_tile;
+    if (next >= 0) prefetch(next);
     // items: every target's list cut into runs of IL pairs (the last one
     // shorter), IL = ceil(pairs / (threads - targets)), so that the tile has
     // at most one item per thread; a thread runs its item and adds it into
@@ -1076,7 +1109,9 @@ __global__ void __launch_bounds__(MT_NT, 1) k_m2l_tile(const int32_t* __restrict
       const int t = r < T ? r : r - T;
       (r < T ? L0 : Lk)[(int64_t)(t0 + cc) * T + t] = acc[cc][r] * lsc[t];
     }
+    tile = next;
   }
+  if (threadIdx.x == 0) claims_done(ctr);
 }
 
 // The same MtL on the matrix cores (order 3).  Per target and channel the
@@ -1738,6 +1773,10 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
           }
     st.add(h->d_xdst, xd.data(), xd.size());
   }
+  {
+    const std::vector<int32_t> zero((size_t)16 * (h->L + 1), 0);
+    st.add(h->d_mtl_ctr, zero.data(), zero.size() * sizeof(int32_t));
+  }
   const int lo = std::min(h->lmin, h->L);
   for (int l = lo; l <= h->L; ++l) {
     Level& D = h->lev[l];
@@ -2102,6 +2141,7 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
     using R2 = typename Pair<R>::T;
     const R2* Dt = f32 ? (const R2*)D.d_F32[0].p : (const R2*)D.d_F64[0].p;
     const size_t dbytes = dbytes_of(D);
+    int* ctr = h->d_mtl_ctr.as<int32_t>() + 16 * l;   // the persistent kernels' tile claims
     switch (kind_of(D)) {
       case K_LDS64:
         if constexpr (sizeof(R) == 8) {
@@ -2139,7 +2179,7 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
                                                  D.d_tile_t0.as<int32_t>(), D.d_tile_off.as<int32_t>(),
                                                  D.d_tile_src.as<int32_t>(), D.n_tile,
                                                  (const float2*)D.d_F32[1].p, D.n_half, M(D, 0), M(D, 1),
-                                                 Lc(D, 0), Lc(D, 1));
+                                                 Lc(D, 0), Lc(D, 1), ctr);
         }
         return 0;
       case K_LDS32:

@@ -136,6 +136,7 @@ struct fagbi_handle {
   fagbi::DBuf d_ms64, d_md64, d_ms32, d_md32;  // panel moments [N][T(p_L)]
   fagbi::DBuf d_mi;                   // multi-index table [TMAX][3]
   fagbi::DBuf d_xdst;                 // matrix-core MtL: X entry -> local term
+  fagbi::DBuf d_mtl_ctr;              // MtL tile claim counters, 16 ints per level (zero between launches)
   fagbi::DBuf d_lu, d_lu_off, d_piv, d_diag;    // preconditioner (block inverses, FP64)
   fagbi::DBuf d_lu32;                          // FP32 copy for the mixed path's inner solves
   fagbi::DBuf d_grp_leaf, d_grp_panel;         // its blocks: leaf and panel ranges
