@@ -1435,6 +1435,55 @@ __global__ void __launch_bounds__(256) k_l2p_reg(const R* __restrict__ ms, const
   y[N + p] -= (double)y2;
 }
 
+// LtP with the leaf level's LtL folded in: a row's leaf local is the leaf's
+// MtL part plus its parent's local shifted to the leaf centre (the products
+// of k_l2l_reg in its order, so the same values), then dotted with the row's
+// moments as in k_l2p_reg.  Each row repeats its leaf's shift (2 x 195
+// multiply-adds from order 4 to 3, next to the row's own 2 x 20); the leaf
+// level's LtL launch and its pass over the leaf locals disappear from the
+// end of the matvec.
+template <typename R, int PP, int P>
+__global__ void __launch_bounds__(256) k_l2p_shift(const R* __restrict__ ms, const R* __restrict__ md,
+                                                   const int32_t* __restrict__ leaf_of,
+                                                   const int32_t* __restrict__ perm, int N, double eps,
+                                                   const R* __restrict__ L0, const R* __restrict__ Lk,
+                                                   const int32_t* __restrict__ parent,
+                                                   const int32_t* __restrict__ cidx, R hc,
+                                                   const R* __restrict__ P0, const R* __restrict__ Pk, double* y) {
+  constexpr ShiftPairs<PP, P> sp{};
+  constexpr int T = nterms(P), TP = nterms(PP);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int c = leaf_of[i];
+  const int64_t par = parent[c];
+  R mono[TP], p0[TP], pk[TP], s0[T], sk[T];
+  shift_monomials<R, PP>(cidx, c, hc, mono);
+#pragma unroll
+  for (int t = 0; t < TP; ++t) {
+    p0[t] = P0[par * TP + t];
+    pk[t] = Pk[par * TP + t];
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) s0[t] = sk[t] = 0;
+#pragma unroll
+  for (int k = 0; k < ShiftPairs<PP, P>::N; ++k) {
+    const R w = (R)sp.coef[k] * mono[sp.g[k]];
+    s0[sp.tb[k]] += w * p0[sp.ta[k]];
+    sk[sp.tb[k]] += w * pk[sp.ta[k]];
+  }
+  const R ie = (R)(1.0 / eps);
+  R y1 = 0, y2 = 0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const R l0 = L0[(int64_t)c * T + t] + s0[t], lk = Lk[(int64_t)c * T + t] + sk[t];
+    y1 += (l0 + lk) * ms[(int64_t)i * T + t];
+    y2 += (l0 + lk * ie) * md[(int64_t)i * T + t];
+  }
+  const int p = perm[i];
+  y[p] -= (double)y1;
+  y[N + p] -= (double)y2;
+}
+
 // Sum of eight per-lane values over the wavefront, scattered: recursive
 // halving over lane bits 3, 2, 1 (each lane keeps the half of its values
 // selected by the bit and adds the other half of its partner's, the partner
@@ -2350,13 +2399,32 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   FAGBI_HIP(hipGetLastError());
   FAGBI_TRY(mark(3));
   if (side) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
-  for (int l = h->lmin; l < L; ++l) {
+  // the LtL into the leaf level is folded into the LtP for the register
+  // orders (parent 4 or 3, leaves 3)
+  const bool fold = L > h->lmin && LF.order == 3 && (h->lev[L - 1].order == 4 || h->lev[L - 1].order == 3);
+  bool joined = false;
+  for (int l = h->lmin; l < (fold ? L - 1 : L); ++l) {
     // LtL into the two finest levels adds to their MtL results
-    if (pipe && l + 1 == std::max(L - 1, h->lmin + 1)) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
+    if (pipe && l + 1 == std::max(L - 1, h->lmin + 1)) {
+      FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
+      joined = true;
+    }
     FAGBI_TRY(launch_l2l<R>(h, l, f32, s));
   }
+  if (pipe && !joined) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_m2l, 0));
   if (sn != s && !side) FAGBI_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
-  {
+  if (fold) {
+    Level& PL = h->lev[L - 1];
+    const unsigned g = (unsigned)((N + 255) / 256);
+    const R *a = ms.as<R>(), *b = md.as<R>();
+    const int32_t *lo = v.leaf_of, *pm = v.out_idx, *par = LF.d_parent.as<int32_t>(), *cix = LF.d_idx.as<int32_t>();
+    if (PL.order == 4)
+      k_l2p_shift<R, 4, 3><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), par, cix, (R)LF.h,
+                                              Lc(PL, 0), Lc(PL, 1), y);
+    else
+      k_l2p_shift<R, 3, 3><<<g, 256, 0, s>>>(a, b, lo, pm, (int)N, eps, Lc(LF, 0), Lc(LF, 1), par, cix, (R)LF.h,
+                                              Lc(PL, 0), Lc(PL, 1), y);
+  } else {
     const unsigned g = (unsigned)((N + 255) / 256);
     const R *a = ms.as<R>(), *b = md.as<R>();
     const int32_t *lo = v.leaf_of, *pm = v.out_idx;
