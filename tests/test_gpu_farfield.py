@@ -76,6 +76,33 @@ def test_far_field_every_order(sphere5120, p_leaf):
     h.close()
 
 
+def test_far_field_grouped_coarse_levels(sphere5120):
+    """leaf 2, p_leaf 4: L = 6, interactions from level 2, orders 8, 7, 6, 5, 4
+    on levels 2..6.  The finest two levels' MtL run on their own stream, level
+    4 on the main one, and in FP32 the coarse levels 2 and 3 (orders 8 and 7)
+    are one launch of the multi-level slot kernel (two levels with different
+    slot rounds); FP64 runs them one launch per level."""
+    v, t, P = sphere5120
+    prm = dict(leaf_size=2, eta0=0.8, p_leaf=4, adaptive=1, p_max=8)
+    h = F.Handle(eps_out=EPS, kappa=KAP, **prm).build_tree(v, t).assemble_nearfield()
+    tr = otree.build(P, 2, 0.8)
+    ti = h.tree_info()
+    orders = otree.orders(tr, 4, 1, 8)
+    assert (tr.L, tr.lmin) == (6, 2) and orders == [8, 8, 8, 7, 6, 5, 4], (tr.L, tr.lmin, orders)
+    assert [ti.lev_order[l] for l in range(tr.L + 1)] == orders
+    assert all(ti.lev_pairs[l] > 0 for l in range(2, 7))
+    O = ofmm.setup(P, tr, EPS, KAP, p_leaf=4, adaptive=1, p_max=8, with_near=False)
+    x = np.random.default_rng(50).standard_normal(2 * P.n)
+    ref = np.concatenate(ofmm.far_field(O, x[:P.n], x[P.n:]))
+    e64 = errs(far_gpu(h, x, F.FP64), ref)
+    e32 = errs(far_gpu(h, x, F.MIXED), ref)
+    print("grouped coarse levels: FP64 rel-L2 %.2e max-row %.2e; mixed rel-L2 %.2e max-row %.2e"
+          % (e64[0], e64[1], e32[0], e32[1]))
+    assert e64[0] < 1e-11 and e64[1] < 1e-11, e64
+    assert e32[0] < 2e-6 and e32[1] < 4e-6, e32
+    h.close()
+
+
 def test_far_field_fixed_order8(sphere5120):
     """fixed order 8 on every level (the slot MtM / LtL kernels at 8 -> 8)"""
     v, t, P = sphere5120
