@@ -78,9 +78,12 @@ def test_nearfield_all_pairs_equals_dense(sphere1280, dense1280):
     h.close()
 
 
+# (leaf 4 at fixed order 3: the LtL into the leaves folded into the LtP with
+# parents of order 3; the adaptive trees fold it from order 4)
 @pytest.mark.parametrize("cfg", [dict(leaf_size=32, p_leaf=4, adaptive=0),
                                  dict(leaf_size=8, p_leaf=3, adaptive=1, p_max=6),
-                                 dict(leaf_size=4, p_leaf=2, adaptive=1, p_max=5)])
+                                 dict(leaf_size=4, p_leaf=2, adaptive=1, p_max=5),
+                                 dict(leaf_size=4, p_leaf=3, adaptive=0)])
 def test_fmm_matches_oracle_fmm(sphere1280, cfg):
     v, t, P = sphere1280
     h = F.Handle(eta0=0.8, **cfg).build_tree(v, t).assemble_nearfield()
