@@ -16,6 +16,8 @@ orders 3..8).  The oracle cannot run the whole operator at this size, so:
   difference is rounding), and sampled rows against the dense oracle rows
   within a bound far above the Taylor truncation and far below what a lost
   level, list or sign gives;
+* repeated FP32 products with alternating inputs: bitwise equal (the leaf
+  MtL's claimed tiles are each processed once per launch);
 * the solve: true residuals and the energy of both precisions.
 """
 import numpy as np
@@ -143,6 +145,24 @@ def test_full_operator_precisions_and_sampled_dense_rows(big):
     err = rel(got, ref)
     print("sampled dense rows: relative difference %.2e" % err)
     assert err < 1e-2
+
+
+def test_repeated_fp32_products_reproduce_bit_for_bit(big):
+    """The leaf MtL's blocks claim tiles through counters that the launch's
+    last block clears for the next launch; which block takes a tile does not
+    change its arithmetic, so repeated products are bitwise equal.  Inputs
+    alternate (and an FP64 product runs in between), so a tile skipped or
+    left from the launch before would show as a changed row."""
+    P, h = big["P"], big["h"]
+    rng = np.random.default_rng(26)
+    xs = [rng.standard_normal(2 * P.n) for _ in range(2)]
+    first = [gpu_matvec(h, x, F.MIXED) for x in xs]
+    for k in range(12):
+        y = gpu_matvec(h, xs[k % 2], F.MIXED)
+        assert np.array_equal(y, first[k % 2]), (k, int(np.sum(y != first[k % 2])))
+        if k == 5:
+            gpu_matvec(h, xs[0], F.FP64)
+    assert not np.array_equal(first[0], first[1])
 
 
 def test_full_size_solves(big):
