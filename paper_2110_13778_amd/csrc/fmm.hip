@@ -414,6 +414,7 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
 // GPU mostly idle while a long chain of short launches runs.  Level i owns
 // blocks [b0_i, b0_{i+1}), one target cluster per block.
 constexpr int MTL_MAXL = 16;
+constexpr int MTL_OCT_BLOCKS = 512;
 template <typename R>
 struct MtlLevels {
   struct Lv {
@@ -745,9 +746,11 @@ __device__ __forceinline__ void claims_done(int* ctr) {
 // the register-blocked MtL (k_m2l_reg) with the level's derivative table
 // staged in LDS: only one of each pair of opposite offsets is stored
 // (D_g(-o) = (-1)^|g| D_g(o), the kernels being even), omap[oid] = row |
-// flip << 30.  One persistent block per CU, each block a contiguous range of
-// targets, so only the source moments come from the caches.
-template <typename R, int P, int NT>
+// flip << 30; with OCT one offset of each class equal up to the signs of the
+// components (D_g(o) = (-1)^(g . s) D_g(|o|)), omap[oid] = row | s << 29.
+// Persistent blocks, each a contiguous range of targets, so only the source
+// moments come from the caches.
+template <typename R, int P, int NT, bool OCT = false>
 __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inter_off,
                                                 const int32_t* __restrict__ inter_src,
                                                 const int32_t* __restrict__ inter_oid,
@@ -789,20 +792,38 @@ __global__ void __launch_bounds__(NT) k_m2l_lds(const int32_t* __restrict__ inte
       }
       for (; q < q1; q += S) {
         const int64_t src = src_n;
-        const int mo = smap[oid_n];
+        const uint32_t mo = (uint32_t)smap[oid_n];
         if (q + S < q1) {
           src_n = inter_src[q + S];
           oid_n = inter_oid[q + S];
         }
-        const R2* dp = dsm + (mo & 0x3fffffff) * T;
-        const R sg = (mo >> 30) ? (R)-1 : (R)1;
         R2 d[T];
+        if constexpr (OCT) {
+          // the sign of term g: the product of the flipped axes' signs over
+          // its odd exponents (sp indexed by those axes, bit a for axis a)
+          const R2* dp = dsm + (mo & 0x1fffffffu) * T;
+          const R sx = (mo >> 29) & 1u ? (R)-1 : (R)1, sy = (mo >> 30) & 1u ? (R)-1 : (R)1,
+                  sz = (mo >> 31) ? (R)-1 : (R)1;
+          const R sp[8] = {(R)1, sx, sy, sx * sy, sz, sx * sz, sy * sz, sx * sy * sz};
 #pragma unroll
-        for (int g = 0; g < T; ++g) {
-          d[g] = dp[g];
-          if (tt.deg[g] & 1) {
-            d[g].x *= sg;
-            d[g].y *= sg;
+          for (int g = 0; g < T; ++g) {
+            d[g] = dp[g];
+            const int par = (tt.e[g][0] & 1) | (tt.e[g][1] & 1) << 1 | (tt.e[g][2] & 1) << 2;
+            if (par) {
+              d[g].x *= sp[par];
+              d[g].y *= sp[par];
+            }
+          }
+        } else {
+          const R2* dp = dsm + (mo & 0x3fffffffu) * T;
+          const R sg = (mo >> 30) ? (R)-1 : (R)1;
+#pragma unroll
+          for (int g = 0; g < T; ++g) {
+            d[g] = dp[g];
+            if (tt.deg[g] & 1) {
+              d[g].x *= sg;
+              d[g].y *= sg;
+            }
           }
         }
         const R* m0p = M0 + src * T;
@@ -1668,6 +1689,21 @@ __global__ void k_half_rows(const int32_t* __restrict__ rows, int n_half, int T,
   half[i] = full[(int64_t)rows[k] * 2 * T + r];
 }
 
+// the octant table: row k is D(|o|) of its class, from the representative
+// offset o by D_g(|o|) = (-1)^(g . s) D_g(o); mi: the terms' exponents
+__global__ void k_oct_rows(const int32_t* __restrict__ rows8, int n_oct, int T, const int8_t* __restrict__ mi,
+                           const float* __restrict__ full, float* oct) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_oct * 2 * T) return;
+  const int64_t k = i / (2 * T), r = i - k * 2 * T;
+  const int g = (int)(r >> 1);
+  const uint32_t v = (uint32_t)rows8[k], sg = v >> 29;
+  const int odd = ((mi[3 * g] & 1) & (int)(sg & 1)) ^ ((mi[3 * g + 1] & 1) & (int)((sg >> 1) & 1)) ^
+                  ((mi[3 * g + 2] & 1) & (int)((sg >> 2) & 1));
+  const float f = full[(int64_t)(v & 0x1fffffffu) * 2 * T + r];
+  oct[i] = odd ? -f : f;
+}
+
 struct Staging {
   struct Item {
     DBuf* b;
@@ -1954,6 +1990,32 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         st.add(D.d_oid_map, omap.data(), omap.size() * 4);
         D.n_half = (int)rows.size();
       }
+      // octant classes for the order-4 LDS kernel: the kernels are even in
+      // each coordinate, D_g(o) = (-1)^(g . s) D_g(|o|) with s the signs of o
+      D.n_oct = 0;
+      if (D.order == 4 && D.n_off < (1 << 29)) {
+        std::vector<int32_t> omap8(D.n_off), rows8;
+        std::vector<std::pair<int64_t, int>> cls;   // (class key, row), sorted by key
+        for (int o = 0; o < D.n_off; ++o) {
+          const int x = D.off_xyz[3 * o], y = D.off_xyz[3 * o + 1], z = D.off_xyz[3 * o + 2];
+          const uint32_t sg = (uint32_t)(x < 0) | (uint32_t)(y < 0) << 1 | (uint32_t)(z < 0) << 2;
+          const int64_t k = ((int64_t)std::abs(x) * 2048 + std::abs(y)) * 2048 + std::abs(z);
+          auto it = std::lower_bound(cls.begin(), cls.end(), std::make_pair(k, -1));
+          int row;
+          if (it != cls.end() && it->first == k) {
+            row = it->second;
+          } else {
+            row = (int)rows8.size();
+            cls.insert(it, {k, row});
+            rows8.push_back((int32_t)((uint32_t)o | sg << 29));
+          }
+          omap8[o] = (int32_t)((uint32_t)row | sg << 29);
+        }
+        st.add(D.d_rows8, rows8.data(), rows8.size() * 4);
+        st.reserve(D.d_F32o, (size_t)2 * rows8.size() * D.T * 4);
+        st.add(D.d_oid_map8, omap8.data(), omap8.size() * 4);
+        D.n_oct = (int)rows8.size();
+      }
     }
     for (int ch = 0; ch < 2; ++ch) {
       st.reserve(D.d_M64[ch], (size_t)D.n * D.T * 8);
@@ -1995,6 +2057,12 @@ int fmm_setup(fagbi_handle* h, hipStream_t s) {
         k_half_rows<double><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows.as<int32_t>(), D.n_half, D.T,
                                                                        D.d_F64[0].as<double>(),
                                                                        D.d_F64[1].as<double>());
+    }
+    if (D.n_oct > 0) {
+      const int64_t m = (int64_t)D.n_oct * 2 * D.T;
+      k_oct_rows<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(D.d_rows8.as<int32_t>(), D.n_oct, D.T,
+                                                             h->d_mi.as<int8_t>(), D.d_F32[0].as<float>(),
+                                                             D.d_F32o.as<float>());
     }
   }
   FAGBI_HIP(hipGetLastError());
@@ -2164,15 +2232,17 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
   // register-blocked kernels for the low orders (up to p = 4, FP32 up to 5)
   // (order 5 in registers in FP32 only: the FP64 version would spill)
   const int preg = sizeof(R) == 4 ? 5 : 4;
+  // FP32 order 4 stages the octant table, the other LDS kernels the half table
+  auto oct = [&](const Level& D) { return sizeof(R) == 4 && D.order == 4 && D.n_oct > 0; };
   auto dbytes_of = [&](const Level& D) {
-    return (size_t)D.n_half * D.T * sizeof(typename Pair<R>::T) + (size_t)D.n_off * 4;
+    return (size_t)(oct(D) ? D.n_oct : D.n_half) * D.T * sizeof(typename Pair<R>::T) + (size_t)D.n_off * 4;
   };
   auto kind_of = [&](const Level& D) -> int {
     const bool small = dbytes_of(D) <= (size_t)150 * 1024;
     // FP64 at order 3: the LDS kernel with the FP64 half table (512 threads: 224 VGPRs)
     if (sizeof(R) == 8 && D.n_half > 0 && D.order == 3 && D.d_F64[1].p && small) return K_LDS64;
     if (sizeof(R) == 4 && D.n_tile > 0 && D.order == 3 && h->m2l_tiles) return h->m2l_mfma ? K_TILE_MFMA : K_TILE;
-    if (sizeof(R) == 4 && D.n_half > 0 && (D.order == 3 || D.order == 4) && small) return K_LDS32;
+    if (sizeof(R) == 4 && (D.n_half > 0 || oct(D)) && (D.order == 3 || D.order == 4) && small) return K_LDS32;
     if (D.n_off > 0 && D.order <= preg && D.order >= 1) return K_REG;
     if (D.n_off == 0) return K_EMPTY;   // no interactions: LtL adds into zero locals
     return K_SLOT;
@@ -2247,6 +2317,12 @@ static int matvec_t(fagbi_handle* h, const ElemView& v, const double* x, double*
             // waiting for the whole kernel (measured 1.24 -> 1.20 ms per FP32 matvec)
             k_m2l_lds<R, 3, 1024><<<224, 1024, dbytes, st>>>(io, is, id, Dh, D.n_half, om, D.n_off, D.n, S, M(D, 0),
                                                             M(D, 1), Lc(D, 0), Lc(D, 1));
+          } else if (oct(D)) {
+            FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768, true>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));
+            k_m2l_lds<R, 4, 768, true><<<MTL_OCT_BLOCKS, 768, dbytes, st>>>(
+                io, is, id, (const R2*)D.d_F32o.p, D.n_oct, D.d_oid_map8.as<int32_t>(), D.n_off, D.n, S, M(D, 0),
+                M(D, 1), Lc(D, 0), Lc(D, 1));
           } else {
             FAGBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_lds<R, 4, 768>),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dbytes));

@@ -85,6 +85,12 @@ struct Level {
   DBuf d_F64[2], d_F32[2], d_oid_map;
   DBuf d_off, d_rows;   // offsets [n_off][3] and the half table's rows, for the table kernels
   int n_half = 0;
+  // octant table (FP32, order 4): one row per class of offsets equal up to
+  // the signs of their components, (|x|, |y|, |z|); rows8[k] = representative
+  // oid | its signs << 29, oid_map8[oid] = row | signs << 29 (bit 29 + a: the
+  // component a is negative)
+  DBuf d_F32o, d_rows8, d_oid_map8;
+  int n_oct = 0;
   DBuf d_M64[2], d_L64[2];           // moments / locals [n][T], channel 0 (G0), 1 (Gk)
   DBuf d_M32[2], d_L32[2];
   // slot tables (one slot per coupled pair of multi-indices) of the
