@@ -130,6 +130,25 @@ def test_taylor_recurrence_matches_sympy(kappa):
         assert abs(F[k][0] - ref) < 1e-12 * max(abs(ref), 1e-8), k
 
 
+def test_taylor_coefficients_reflect_with_the_axes():
+    """Both kernels depend on |r| only, so reflecting axis a multiplies the
+    coefficient of k by (-1)^k_a: F_k(x0) = (-1)^(k . s) F_k(|x0|) with s the
+    signs of x0's components (the octant tables of the GPU's order-4 MtL rest
+    on this).  An index mixed up between axes in the recurrence breaks it; the
+    values themselves are pinned against sympy above."""
+    rng = np.random.default_rng(8)
+    x0 = rng.uniform(-4.0, 4.0, (40, 3))
+    x0[np.abs(x0) < 0.3] = 0.7
+    for kappa in (0.0, 0.1257):
+        F = taylor.coefficients(x0, kappa, 7)
+        Fa = taylor.coefficients(np.abs(x0), kappa, 7)
+        neg = (x0 < 0).astype(int)
+        for k in taylor.multi_indices(7):
+            sign = (-1.0) ** (neg @ np.array(k))
+            scale = np.abs(Fa[k]).max()
+            assert np.abs(F[k] - sign * Fa[k]).max() <= 1e-14 * scale, (kappa, k)
+
+
 def test_shift_matrices_are_exact_translations():
     """MtM of moments equals the moments taken about the new centre, and LtL
     of a local expansion evaluates to the same polynomial (binomial formula)."""
