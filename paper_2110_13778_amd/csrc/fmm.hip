@@ -414,6 +414,8 @@ __global__ void __launch_bounds__(TB) k_m2l(const int32_t* __restrict__ inter_of
 // GPU mostly idle while a long chain of short launches runs.  Level i owns
 // blocks [b0_i, b0_{i+1}), one target cluster per block.
 constexpr int MTL_MAXL = 16;
+// persistent blocks of the order-4 LDS MtL with the octant table: two per CU
+// (its table leaves room for a second block's LDS; one per CU measured slower)
 constexpr int MTL_OCT_BLOCKS = 512;
 template <typename R>
 struct MtlLevels {
