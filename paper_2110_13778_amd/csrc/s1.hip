@@ -444,7 +444,34 @@ struct VbLeaf {
   int nr, nc, ur, uc;
 };
 
-__device__ inline VbLeaf vb_sort(const NearArgs& a, int c, uint64_t* rk, uint64_t* ck, int* rs, int* cs, int* cnt) {
+// the first index of every run of equal vertices in key[0..n) (sorted),
+// starts[runs] = n; flags per thread chunk, a block scan of their counts,
+// then each thread writes its chunk's starts (blockDim.x threads, sc: as many
+// ints of LDS)
+__device__ inline int vb_runs(const uint64_t* key, int n, int* starts, int* sc) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int t0 = min(n, tid * per), t1 = min(n, t0 + per);
+  int f = 0;
+  for (int t = t0; t < t1; ++t) f += (t == 0 || (key[t] >> VB_SHIFT) != (key[t - 1] >> VB_SHIFT)) ? 1 : 0;
+  sc[tid] = f;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {   // inclusive scan
+    const int v = tid >= o ? sc[tid - o] : 0;
+    __syncthreads();
+    sc[tid] += v;
+    __syncthreads();
+  }
+  int u = sc[tid] - f;
+  for (int t = t0; t < t1; ++t)
+    if (t == 0 || (key[t] >> VB_SHIFT) != (key[t - 1] >> VB_SHIFT)) starts[u++] = t;
+  const int runs = sc[nt - 1];
+  if (tid == 0) starts[runs] = n;
+  __syncthreads();   // starts written; sc free again
+  return runs;
+}
+
+__device__ inline VbLeaf vb_sort(const NearArgs& a, int c, uint64_t* rk, uint64_t* ck, int* rs, int* cs) {
   const int nrow = a.leaf_cnt[c], i0 = a.leaf_start[c];
   const int64_t so = a.src_off[c];
   const int S = (int)(a.src_off[c + 1] - so);
@@ -457,23 +484,9 @@ __device__ inline VbLeaf vb_sort(const NearArgs& a, int c, uint64_t* rk, uint64_
                      : ~0ull;
   bitonic(rk, pr);
   bitonic(ck, pc);
-  // run starts, in order, by one thread per list (a few hundred keys)
-  if (threadIdx.x == 0) {
-    int u = 0;
-    for (int t = 0; t < L.nr; ++t)
-      if (t == 0 || (rk[t] >> VB_SHIFT) != (rk[t - 1] >> VB_SHIFT)) rs[u++] = t;
-    rs[u] = L.nr;
-    cnt[0] = u;
-  } else if (threadIdx.x == 64) {
-    int u = 0;
-    for (int t = 0; t < L.nc; ++t)
-      if (t == 0 || (ck[t] >> VB_SHIFT) != (ck[t - 1] >> VB_SHIFT)) cs[u++] = t;
-    cs[u] = L.nc;
-    cnt[1] = u;
-  }
-  __syncthreads();
-  L.ur = cnt[0];
-  L.uc = cnt[1];
+  __shared__ int sc[256];
+  L.ur = vb_runs(rk, L.nr, rs, sc);
+  L.uc = vb_runs(ck, L.nc, cs, sc);
   return L;
 }
 
@@ -485,9 +498,8 @@ __global__ void __launch_bounds__(256) k_vb_count(NearArgs a, int max_pc, int64_
   uint64_t* ck = rk + VB_ROWS;
   int* rs = reinterpret_cast<int*>(ck + max_pc);
   int* cs = rs + VB_ROWS + 1;
-  int* cnt = cs + max_pc + 1;
   const int c = blockIdx.x;
-  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs, cnt);
+  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs);
   if (threadIdx.x == 0) {
     nrow[c] = L.ur;
     ncol[c] = L.uc;
@@ -507,9 +519,8 @@ __global__ void __launch_bounds__(256) k_vb_build(NearArgs a, int max_pc, const 
   uint64_t* ck = rk + VB_ROWS;
   int* rs = reinterpret_cast<int*>(ck + max_pc);
   int* cs = rs + VB_ROWS + 1;
-  int* cnt = cs + max_pc + 1;
   const int c = blockIdx.x;
-  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs, cnt);
+  const VbLeaf L = vb_sort(a, c, rk, ck, rs, cs);
   const int64_t so = a.src_off[c];
   const int S3 = L.nc;
   const uint64_t mask = (1ull << VB_SHIFT) - 1;
